@@ -1,0 +1,66 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each mutation below is a plausible slip (a dropped term, a wrong sign, index or constant,
+a transposed operand) applied to a copy of oracle.c; the copy is built into a temporary
+library and the pin suite is run against it in a subprocess.  The suite must fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = [
+    ("changeover denominator", "2.0 * y * y - 2.0 * y + 1.0", "2.0 * y * y - y + 1.0"),
+    ("changeover inner edge", "double y = (r - 0.1 * rc) / (0.9 * rc);", "double y = (r - 0.2 * rc) / (0.8 * rc);"),
+    ("pair radius min instead of max",
+     "double rcij = rc[i] > rc[j] ? rc[i] : rc[j];\n        double k = pair_weight",
+     "double rcij = rc[i] < rc[j] ? rc[i] : rc[j];\n        double k = pair_weight"),
+    ("force sign", "double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n        double r2 = sep2(dx, dy, dz);\n        double rcij",
+     "double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];\n        double r2 = sep2(dx, dy, dz);\n        double rcij"),
+    ("r^-3 -> r^-2", "double s = m[j] * k / (r2 * r);", "double s = m[j] * k / (r2);"),
+    ("source mass index", "double s = m[j] * k / (r2 * r);", "double s = m[i] * k / (r2 * r);"),
+    ("transposed y/z in force", "sy += s * dy;\n        sz += s * dz;", "sy += s * dz;\n        sz += s * dy;"),
+    ("energy pair mass index", "s += m[j] / sqrt(sep2(dx, dy, dz));", "s += m[i] / sqrt(sep2(dx, dy, dz));"),
+    ("energy kinetic factor", "kin += 0.5 * m[i]", "kin += 1.0 * m[i]"),
+    ("energy drops sun term", "out[0] = kin + (px * px + py * py + pz * pz) / (2.0 * mstar) + pot_sun - pot_pair;",
+     "out[0] = kin + pot_sun - pot_pair;"),
+    ("L cross-product sign", "lx += m[i] * (y[i] * vz[i] - z[i] * vy[i]);", "lx += m[i] * (y[i] * vz[i] + z[i] * vy[i]);"),
+    ("Kepler fdot sign", "fd = -a * a * nm * sX / (r * r0);", "fd = a * a * nm * sX / (r * r0);"),
+    ("Kepler g term", "g = dt - (X - sX) / nm;", "g = dt - (X + sX) / nm;"),
+    ("Kepler equation term", "double F = X - c * sin(X) + s * (1.0 - cos(X)) - target;",
+     "double F = X - c * sin(X) - s * (1.0 - cos(X)) - target;"),
+    ("hyperbolic fdot", "fd = -A * A * nm * shX / (r * r0);", "fd = A * A * nm * shX / (r * r0);"),
+    ("sun drift index", "y[i] += tau * py / mstar;", "y[i] += tau * px / mstar;"),
+    ("BS uses K instead of 1-K", "double w = 1.0 - pair_weight(r2, rcij);", "double w = pair_weight(r2, rcij);"),
+    # (a wrong extrapolation coefficient only costs work: the accepted result is still held
+    # to the tolerance by the error estimate, so it is not listed here)
+    ("BS acceptance tolerance", "if (err <= tol) done = k;", "if (err <= 1e-5) done = k;"),
+    ("BS midpoint end correction", "out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);", "out[q] = 0.5 * (zm[q] + zc[q]);"),
+    ("drift full sun step", "oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, 0.5 * dt);\n    int64_t *gid",
+     "oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, dt);\n    int64_t *gid"),
+    ("first half-kick length", "kick(n, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);\n        int64_t np",
+     "kick(n, x, y, z, vx, vy, vz, m, rc, dt, ax, ay, az);\n        int64_t np"),
+    ("Hill radius factor 3", "double rh = a * cbrt(m[i] / (3.0 * mstar));", "double rh = a * cbrt(m[i] / mstar);"),
+    ("encounter self pairs", "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i + 1;",
+     "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, old, new, tmp_path):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique/found: {name}"
+    mutated = tmp_path / "oracle_mut.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-w",
+                           "-o", str(lib), str(mutated), "-lm"])
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation '{name}' survived the pins:\n{r.stdout[-2000:]}"
