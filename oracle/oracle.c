@@ -235,11 +235,11 @@ static int kepler_one(double *rx, double *ry, double *rz, double *wx, double *wy
             double F = X - c * sin(X) + s * (1.0 - cos(X)) - target;
             double Fp = 1.0 - c * cos(X) + s * sin(X);
             if (F > 0.0) hi = X; else lo = X;
-            double Xn = X - F / Fp;
+            double step = F / Fp;
+            if (fabs(step) <= 1e-15 * (1.0 + fabs(X))) { X -= step; ok = 1; break; }
+            double Xn = X - step;
             if (!(Xn > lo && Xn < hi)) Xn = 0.5 * (lo + hi);
-            double d = fabs(Xn - X);
             X = Xn;
-            if (d <= 1e-15 * (1.0 + fabs(X))) { ok = 1; break; }
         }
         double sX = sin(X), cX = cos(X);
         double r = a * (1.0 - c * cX + s * sX);
@@ -259,11 +259,11 @@ static int kepler_one(double *rx, double *ry, double *rz, double *wx, double *wy
             double G = c * sinh(X) + s * (cosh(X) - 1.0) - X - target;
             double Gp = c * cosh(X) + s * sinh(X) - 1.0;
             if (G > 0.0) hi = X; else lo = X;
-            double Xn = X - G / Gp;
+            double step = G / Gp;
+            if (fabs(step) <= 1e-15 * (1.0 + fabs(X))) { X -= step; ok = 1; break; }
+            double Xn = X - step;
             if (!(Xn > lo && Xn < hi)) Xn = 0.5 * (lo + hi);
-            double d = fabs(Xn - X);
             X = Xn;
-            if (d <= 1e-15 * (1.0 + fabs(X))) { ok = 1; break; }
         }
         double shX = sinh(X), chX = cosh(X);
         double r = A * (c * chX + s * shX - 1.0);

@@ -416,3 +416,21 @@ def test_step_conserves_L_and_bounds_E_on_disc():
     L = np.linalg.norm(e[:, 1:], axis=1)
     assert np.max(np.abs(L / L[0] - 1)) < 1e-13
     assert np.max(np.abs(e[:, 0] / e[0, 0] - 1)) < 1e-6
+
+
+def test_kepler_strongly_hyperbolic_converges():
+    """A fast unbound orbit whose Newton iterates approach the root from one side only
+    (the converged iterate lands on the bracket edge)."""
+    from scipy.integrate import solve_ivp
+    x0 = np.array([0.9, 0.44, 0.01])
+    v0 = np.array([-1.2, 2.9, 0.05])
+    st = state([x0], [v0], [0.0])
+    for dt in (3.0, 0.2, 12.0):
+        s = oracle.kepler_drift(st, MU, dt)
+        got = np.concatenate([vec(s)[0], vec(s, ("vx", "vy", "vz"))[0]])
+
+        def rhs(t, y):
+            r = np.linalg.norm(y[:3])
+            return np.concatenate([y[3:], -MU * y[:3] / r**3])
+        ref = solve_ivp(rhs, (0, dt), np.concatenate([x0, v0]), rtol=1e-13, atol=1e-15, method="DOP853").y[:, -1]
+        assert np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))) < 1e-11
