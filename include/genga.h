@@ -1,0 +1,162 @@
+/*
+ * genga.h - C ABI of the MI355X (gfx950) kick library.
+ *
+ * The library implements the data-parallel hot path of a GENGA-style hybrid symplectic
+ * N-body step (Brasser, Grimm, Hatalova & Stadel 2023): the all-pairs long-range gravity
+ * kick weighted by a changeover function, the close-encounter pair list it produces, the
+ * FP64 Kepler drift with a minimal FP64 close-encounter step, and FP64 energy /
+ * angular-momentum diagnostics.  One process, one GPU.
+ *
+ * Conventions that hold for every entry point:
+ *  - Units: G = 1.  Positions are heliocentric, velocities barycentric (democratic
+ *    heliocentric coordinates).
+ *  - Every array argument named in genga_bodies and every output array is a DEVICE
+ *    pointer owned by the caller; the library never frees or retains it beyond the call
+ *    (calls are asynchronous: the caller keeps the memory alive until the stream has
+ *    finished the work).  Host arrays are marked "host".
+ *  - Body arrays are structure-of-arrays float64, length n_total, systems stored one after
+ *    the other in the order given to genga_set_systems (CSR offsets).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and never
+ *    synchronises the host, except genga_set_systems, genga_poll_status, genga_autotune and
+ *    the graph calls as documented.  Every launch sequence is capturable into a HIP graph
+ *    (no memset nodes, no host round trips).
+ *  - Return value: GENGA_OK (0) or a negative genga_status.  Errors knowable on the host
+ *    (null pointer, bad enum, no layout set) return at once and enqueue nothing.
+ *    Conditions found on the device (pair-list overflow, non-finite acceleration,
+ *    non-converged Kepler or Bulirsch-Stoer solve) raise flags in the context that
+ *    genga_poll_status reports later.  genga_last_error() gives a message for the last
+ *    failing call on the calling thread.
+ *  - A context is not thread-safe; calls that use one context must not overlap in time
+ *    from several host threads.  Calls that share a context must be issued on one stream
+ *    (or be ordered by the caller), because they share its scratch buffers.
+ */
+#ifndef GENGA_H
+#define GENGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct genga_ctx genga_ctx;
+
+typedef enum {
+    GENGA_OK = 0,
+    GENGA_ERR_ARG = -1,         /* invalid argument (host check) */
+    GENGA_ERR_HIP = -2,         /* a HIP runtime call failed */
+    GENGA_ERR_CAPACITY = -3,    /* encounter list, group or workspace capacity exceeded */
+    GENGA_ERR_NONFINITE = -4,   /* a non-finite acceleration was produced */
+    GENGA_ERR_NOCONVERGE = -5,  /* Kepler or Bulirsch-Stoer solve did not converge */
+    GENGA_ERR_STATE = -6        /* call not valid in the context's state (e.g. no layout) */
+} genga_status;
+
+/* Precision of the long-range pair arithmetic (the paper's "Do Kick in single precision"
+ * switch, Sect. 4).  FP32: coordinate differences are formed in FP64 and rounded to FP32,
+ * the pair term is FP32, partial sums over blocks of 64 sources are FP32 and are folded into
+ * an FP64 accumulator.  FP64: everything FP64.  Pairs inside the changeover region are
+ * always evaluated in FP64 (Sect. 1: encounter forces are always FP64). */
+typedef enum { GENGA_KICK_FP64 = 0, GENGA_KICK_FP32 = 1 } genga_kick_prec;
+
+/* State of all bodies (device SoA, float64, length n_total). */
+typedef struct {
+    double *x, *y, *z;      /* heliocentric positions [au] */
+    double *vx, *vy, *vz;   /* barycentric velocities [au / (day/k)] */
+    const double *m;        /* masses [M_sun] */
+    const double *rcrit;    /* critical radius r_crit,i of eq. (1) [au]; constant over a run */
+} genga_bodies;
+
+/* Create a context on HIP device `device` (it becomes current on the calling thread for
+ * every later call with this context).  *out is NULL on failure. */
+int genga_create(genga_ctx **out, int device);
+
+/* Release the context, its scratch memory and any captured graph.  NULL is accepted. */
+int genga_destroy(genga_ctx *ctx);
+
+/* Set the system layout: n_sys >= 1 systems, host CSR offsets sys_off_host[n_sys+1]
+ * (sys_off_host[0] = 0, non-decreasing, every system non-empty or empty), host central
+ * masses mstar_host[n_sys] > 0, and the capacity of the encounter pair list (pairs kept
+ * per kick; <= 0 selects 16 * n_total + 1024).  Allocates device scratch sized for the
+ * layout, builds the launch plan, and synchronises the device.  Must precede every call
+ * below except genga_last_error; may be called again to change the layout. */
+int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host,
+                      const double *mstar_host, int32_t pair_capacity);
+
+/* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
+ * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
+ * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).
+ * Reads b->x..b->m (b->rcrit is ignored); writes rc_out[n_total] (device). */
+int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, double dt,
+                double *rc_out, void *stream);
+
+/* Long-range accelerations only (no velocity update), Sect. 1:
+ *   a_i = sum_{j != i, same system} m_j K(r_ij) (r_j - r_i) / r_ij^3
+ * with the changeover weight K of Chambers (1999), y = (r - 0.1 r_crit,ij)/(0.9 r_crit,ij),
+ * r_crit,ij = max(r_crit,i, r_crit,j).  Writes ax, ay, az [n_total] (device).  Also
+ * refreshes the context's encounter list for these positions. */
+int genga_accel(genga_ctx *ctx, const genga_bodies *b, int prec, double *ax, double *ay,
+                double *az, void *stream);
+
+/* The kick (Sect. 1, level 0): v_i += tau * a_i with a_i as in genga_accel, in the given
+ * precision.  The same launch records every pair (i < j) with r_ij^2 < r_crit,ij^2
+ * (decided in FP64) into the context's encounter list, which the next genga_drift uses. */
+int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, void *stream);
+
+/* Copy the encounter list of the last kick/accel into pairs[cap][2] (device int32, global
+ * body indices, i < j), sorted lexicographically, and its full length into *d_count
+ * (device int32; may exceed cap, or the context's capacity, in which case the list is
+ * incomplete and GENGA_ERR_CAPACITY is also flagged). */
+int genga_encounter_list(genga_ctx *ctx, int32_t *pairs, int32_t cap, int32_t *d_count,
+                         void *stream);
+
+/* The drift over dt (Sect. 1): Sun drift dt/2 (r_i += dt/2 * sum_j m_j v_j / Mstar), then the
+ * FP64 Kepler drift about Mstar for bodies outside encounter groups and an FP64
+ * Bulirsch-Stoer integration over dt of each group (connected component of the context's
+ * encounter list) under the Sun's force plus the (1 - K) share of the members' mutual
+ * forces, then Sun drift dt/2.  Groups larger than 64 bodies or more than 8192 bodies in
+ * encounters raise GENGA_ERR_CAPACITY (those bodies are then only Kepler-drifted). */
+int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream);
+
+/* Energy and angular momentum per system (Sect. 3.1 diagnostics), FP64:
+ *   E = sum m v^2/2 + |sum m v|^2 / (2 Mstar) - sum Mstar m / r - sum_{i<j} m_i m_j / r_ij
+ *   L = sum m r x v
+ * Writes d_out[n_sys][4] = (E, Lx, Ly, Lz) (device). */
+int genga_energy(genga_ctx *ctx, const genga_bodies *b, double *d_out, void *stream);
+
+/* nsteps full steps of the split Kick(dt/2) Drift(dt) Kick(dt/2), adjacent half-kicks
+ * merged (nsteps + 1 force evaluations).  Velocities are synchronised on entry and exit.
+ * If energy_cadence > 0 and d_energy != NULL, record k (k = 0, 1, ...) of
+ * d_energy[nsteps / energy_cadence][n_sys][4] receives (E, Lx, Ly, Lz) after
+ * (k + 1) * energy_cadence steps, for the synchronised velocities (the half-kicked
+ * velocities minus dt/2 times the accelerations of the last kick). */
+int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec,
+               int energy_cadence, double *d_energy, void *stream);
+
+/* Capture genga_step(ctx, b, dt, nsteps, prec, 0, NULL) into a HIP graph held by the
+ * context (replacing any earlier one).  Synchronises `stream` before capture. */
+int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec,
+                        void *stream);
+
+/* Launch the captured graph `repeats` times on `stream`. */
+int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream);
+
+/* Time the kick kernel's launch shapes on the current layout and keep the fastest for
+ * `prec` (synchronises the device; the bodies are read, velocities are restored). */
+int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream);
+
+/* Waves per workgroup of the kick for `prec` (4, 8 or 16); 0 resets to the default. */
+int genga_set_kick_waves(genga_ctx *ctx, int prec, int waves);
+int genga_get_kick_waves(genga_ctx *ctx, int prec);
+
+/* Synchronise the device, then return and clear the deferred device status:
+ * GENGA_ERR_CAPACITY, GENGA_ERR_NONFINITE, GENGA_ERR_NOCONVERGE or GENGA_OK. */
+int genga_poll_status(genga_ctx *ctx);
+
+/* Message for the last failing call on this thread ("" if none).  Owned by the library. */
+const char *genga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENGA_H */

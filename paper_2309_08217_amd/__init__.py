@@ -1,0 +1,263 @@
+"""Python binding of the gfx950 kick library (libgenga.so).
+
+Argument marshalling only: every step of the kick path (pair forces, encounter list, drift,
+close-encounter step, energy) runs in the HIP kernels behind the C ABI declared in
+include/genga.h.  PyTorch provides device memory and streams.  There is no CPU fallback:
+if libgenga.so is missing or no GPU is present, the calls raise.
+
+The functions carry the C names (genga_create, genga_kick, ...) and take the same
+arguments, with torch tensors in place of device pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgenga.so")
+
+GENGA_OK = 0
+GENGA_ERR_ARG = -1
+GENGA_ERR_HIP = -2
+GENGA_ERR_CAPACITY = -3
+GENGA_ERR_NONFINITE = -4
+GENGA_ERR_NOCONVERGE = -5
+GENGA_ERR_STATE = -6
+
+GENGA_KICK_FP64 = 0
+GENGA_KICK_FP32 = 1
+
+# every entry point of include/genga.h
+ENTRY_POINTS = (
+    "genga_create", "genga_destroy", "genga_set_systems", "genga_rcrit", "genga_accel",
+    "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
+    "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_waves",
+    "genga_get_kick_waves", "genga_poll_status", "genga_last_error",
+)
+
+
+class GengaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"genga status {status}: {message}")
+        self.status = status
+
+
+class genga_bodies(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rcrit")]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgenga.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2309_08217_amd.build` "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    bp = ctypes.POINTER(genga_bodies)
+    sig = {
+        "genga_create": [ctypes.POINTER(vp), ctypes.c_int],
+        "genga_destroy": [vp],
+        "genga_set_systems": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32],
+        "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
+        "genga_accel": [vp, bp, ctypes.c_int, vp, vp, vp, vp],
+        "genga_kick": [vp, bp, dbl, ctypes.c_int, vp],
+        "genga_encounter_list": [vp, vp, i32, vp, vp],
+        "genga_drift": [vp, bp, dbl, vp],
+        "genga_energy": [vp, bp, vp, vp],
+        "genga_step": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
+        "genga_graph_capture": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, vp],
+        "genga_graph_launch": [vp, ctypes.c_int, vp],
+        "genga_autotune": [vp, bp, ctypes.c_int, vp],
+        "genga_set_kick_waves": [vp, ctypes.c_int, ctypes.c_int],
+        "genga_get_kick_waves": [vp, ctypes.c_int],
+        "genga_poll_status": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.genga_last_error.argtypes = []
+    L.genga_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        msg = load_library().genga_last_error().decode(errors="replace")
+        raise GengaError(status, msg)
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Bodies:
+    """Device SoA state (float64 CUDA tensors, length n_total) and its C view."""
+
+    KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "rcrit")
+
+    def __init__(self, **tensors):
+        import torch
+        for k in self.KEYS:
+            t = tensors.get(k)
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda):
+                raise TypeError(f"{k} must be a float64 CUDA tensor")
+            setattr(self, k, t)
+
+    @classmethod
+    def from_numpy(cls, state: dict, rcrit=None, device: str = "cuda"):
+        import torch
+        t = {k: torch.as_tensor(np.ascontiguousarray(state[k], dtype=np.float64), device=device)
+             for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+        if rcrit is not None:
+            t["rcrit"] = torch.as_tensor(np.ascontiguousarray(rcrit, dtype=np.float64), device=device)
+        return cls(**t)
+
+    def to_numpy(self) -> dict:
+        return {k: getattr(self, k).cpu().numpy() for k in ("x", "y", "z", "vx", "vy", "vz", "m")}
+
+    def c(self) -> genga_bodies:
+        return genga_bodies(*[_ptr(getattr(self, k)) for k in self.KEYS])
+
+
+# ----------------------------------------------------------------------------------------------
+# Entry points, same names and argument order as include/genga.h
+# ----------------------------------------------------------------------------------------------
+
+def genga_create(device: int = 0) -> int:
+    L = load_library()
+    h = ctypes.c_void_p()
+    _check(L.genga_create(ctypes.byref(h), int(device)))
+    return h.value
+
+
+def genga_destroy(ctx: int) -> None:
+    _check(load_library().genga_destroy(ctx))
+
+
+def genga_set_systems(ctx: int, sys_off: Sequence[int], mstar: Sequence[float], pair_capacity: int = 0) -> None:
+    off = np.ascontiguousarray(sys_off, dtype=np.int32)
+    ms = np.ascontiguousarray(mstar, dtype=np.float64)
+    if len(off) != len(ms) + 1:
+        raise ValueError("sys_off must have n_sys + 1 entries")
+    _check(load_library().genga_set_systems(ctx, len(ms), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(pair_capacity)))
+
+
+def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_rcrit(ctx, ctypes.byref(cb), float(n1), float(n2), float(dt), _ptr(rc_out),
+                                      _stream(stream)))
+
+
+def genga_accel(ctx: int, b: Bodies, prec: int, ax, ay, az, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_accel(ctx, ctypes.byref(cb), int(prec), _ptr(ax), _ptr(ay), _ptr(az),
+                                      _stream(stream)))
+
+
+def genga_kick(ctx: int, b: Bodies, tau: float, prec: int, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_kick(ctx, ctypes.byref(cb), float(tau), int(prec), _stream(stream)))
+
+
+def genga_encounter_list(ctx: int, pairs, cap: int, d_count, stream=None) -> None:
+    _check(load_library().genga_encounter_list(ctx, _ptr(pairs), int(cap), _ptr(d_count), _stream(stream)))
+
+
+def genga_drift(ctx: int, b: Bodies, dt: float, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_drift(ctx, ctypes.byref(cb), float(dt), _stream(stream)))
+
+
+def genga_energy(ctx: int, b: Bodies, d_out, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_energy(ctx, ctypes.byref(cb), _ptr(d_out), _stream(stream)))
+
+
+def genga_step(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, energy_cadence: int = 0,
+               d_energy=None, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_step(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec),
+                                     int(energy_cadence), _ptr(d_energy), _stream(stream)))
+
+
+def genga_graph_capture(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_graph_capture(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec),
+                                              _stream(stream)))
+
+
+def genga_graph_launch(ctx: int, repeats: int, stream=None) -> None:
+    _check(load_library().genga_graph_launch(ctx, int(repeats), _stream(stream)))
+
+
+def genga_autotune(ctx: int, b: Bodies, prec: int, stream=None) -> None:
+    cb = b.c()
+    _check(load_library().genga_autotune(ctx, ctypes.byref(cb), int(prec), _stream(stream)))
+
+
+def genga_set_kick_waves(ctx: int, prec: int, waves: int) -> None:
+    _check(load_library().genga_set_kick_waves(ctx, int(prec), int(waves)))
+
+
+def genga_get_kick_waves(ctx: int, prec: int) -> int:
+    return _check(load_library().genga_get_kick_waves(ctx, int(prec)))
+
+
+def genga_poll_status(ctx: int) -> int:
+    """Returns the deferred device status (0 or a negative genga_status) without raising."""
+    return load_library().genga_poll_status(ctx)
+
+
+def genga_last_error() -> str:
+    return load_library().genga_last_error().decode(errors="replace")
+
+
+class Context:
+    """Owns one genga_ctx; thin convenience wrapper over the entry points."""
+
+    def __init__(self, device: int = 0):
+        self.handle = genga_create(device)
+
+    def close(self):
+        if self.handle:
+            genga_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

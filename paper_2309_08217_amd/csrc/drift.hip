@@ -1,0 +1,577 @@
+// Drift part of the hybrid symplectic step (Brasser et al. 2023, Sect. 1), all FP64:
+//  * Sun drift: r_i += tau * (sum_j m_j v_j) / Mstar (democratic heliocentric split);
+//  * Kepler drift of every body not in a close encounter, by universal variables
+//    (Stumpff functions, safeguarded Newton on the universal Kepler equation);
+//  * close-encounter step: the encounter pairs are joined into groups (connected components,
+//    one workgroup, union-find in global memory, members sorted in LDS), and each group is
+//    integrated over dt by Gragg-Bulirsch-Stoer under the Sun's force plus the (1 - K) share
+//    of the members' mutual forces; the Kepler kernel then writes the group results back.
+#include "genga_internal.h"
+
+namespace genga {
+
+namespace {
+
+__device__ __forceinline__ double sep2_rn(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+__device__ __forceinline__ double sq_rn(double a)
+{
+#pragma clang fp contract(off)
+    return a * a;
+}
+
+__device__ __forceinline__ double changeover_k(double y)
+{
+    if (y <= 0.0) return 0.0;
+    if (y >= 1.0) return 1.0;
+    double y2 = y * y;
+    return y2 / (2.0 * y2 - 2.0 * y + 1.0);
+}
+
+// ------------------------------------------------------------------------------------------
+// Sun drift: one workgroup per system, fixed-order reduction of the momentum, then the shift.
+// ------------------------------------------------------------------------------------------
+constexpr int SUN_THREADS = 1024;
+
+__global__ __launch_bounds__(SUN_THREADS) void sun_drift_kernel(const int32_t *sys_off,
+                                                                const double *mstar, double *x,
+                                                                double *y, double *z,
+                                                                const double *vx, const double *vy,
+                                                                const double *vz, const double *m,
+                                                                double tau)
+{
+    __shared__ double red[3][SUN_THREADS / 64];
+    const int s = blockIdx.x;
+    const int b = sys_off[s], e = sys_off[s + 1];
+    double px = 0.0, py = 0.0, pz = 0.0;
+    for (int i = b + threadIdx.x; i < e; i += SUN_THREADS) {
+        px += m[i] * vx[i];
+        py += m[i] * vy[i];
+        pz += m[i] * vz[i];
+    }
+    // wave reduction (fixed butterfly order), then across waves in LDS
+    for (int o = 32; o > 0; o >>= 1) {
+        px += __shfl_xor(px, o, 64);
+        py += __shfl_xor(py, o, 64);
+        pz += __shfl_xor(pz, o, 64);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        red[0][wave] = px;
+        red[1][wave] = py;
+        red[2][wave] = pz;
+    }
+    __syncthreads();
+    double Px = 0.0, Py = 0.0, Pz = 0.0;
+    for (int w = 0; w < SUN_THREADS / 64; ++w) {
+        Px += red[0][w];
+        Py += red[1][w];
+        Pz += red[2][w];
+    }
+    const double f = tau / mstar[s];
+    const double sx = f * Px, sy = f * Py, sz = f * Pz;
+    for (int i = b + threadIdx.x; i < e; i += SUN_THREADS) {
+        x[i] += sx;
+        y[i] += sy;
+        z[i] += sz;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Kepler drift by universal variables.
+// ------------------------------------------------------------------------------------------
+
+// Stumpff functions c2(z) = (1 - cos sqrt z)/z, c3(z) = (sqrt z - sin sqrt z)/z^(3/2)
+// (hyperbolic forms for z < 0); series for |z| < 1.
+__device__ void stumpff(double zz, double &c2, double &c3)
+{
+    if (fabs(zz) < 1.0) {
+        // c2 = sum (-z)^k / (2k+2)!, c3 = sum (-z)^k / (2k+3)!
+        double t2 = 0.5, t3 = 1.0 / 6.0;
+        double s2 = t2, s3 = t3;
+        for (int k = 1; k < 14; ++k) {
+            t2 *= -zz / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+            t3 *= -zz / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+            s2 += t2;
+            s3 += t3;
+        }
+        c2 = s2;
+        c3 = s3;
+    } else if (zz > 0.0) {
+        double sz = sqrt(zz);
+        double h = sin(0.5 * sz);
+        c2 = 2.0 * h * h / zz;
+        c3 = (sz - sin(sz)) / (zz * sz);
+    } else {
+        double sz = sqrt(-zz);
+        double h = sinh(0.5 * sz);
+        c2 = 2.0 * h * h / (-zz);
+        c3 = (sinh(sz) - sz) / (-zz * sz);
+    }
+}
+
+// Advance (r, v) on the two-body orbit about mu by dt; returns false if not converged.
+__device__ bool kepler_universal(double &x, double &y, double &z, double &vx, double &vy,
+                                 double &vz, double mu, double dt)
+{
+    if (dt == 0.0) return true;
+    const double r0 = sqrt(x * x + y * y + z * z);
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    const double sig = (x * vx + y * vy + z * vz) / sqrt(mu); // r0 . v0 / sqrt(mu)
+    const double alpha = 2.0 / r0 - v2 / mu;                   // 1 / a
+    const double smu = sqrt(mu);
+    // universal Kepler equation F(chi) = sig chi^2 c2 + (1 - alpha r0) chi^3 c3 + r0 chi - sqrt(mu) dt
+    // F'(chi) = r(chi) > 0.  Bracket the root, then safeguarded Newton.
+    double chi = (alpha > 0.0) ? smu * dt * alpha : smu * dt / r0;
+    double lo, hi;
+    {
+        // expand a bracket around the first guess
+        double step = fabs(chi) + (alpha > 0.0 ? 1.0 / sqrt(alpha) : r0);
+        lo = chi - step;
+        hi = chi + step;
+        for (int k = 0; k < 200; ++k) {
+            double c2, c3, zz = alpha * lo * lo;
+            stumpff(zz, c2, c3);
+            double F = sig * lo * lo * c2 + (1.0 - alpha * r0) * lo * lo * lo * c3 + r0 * lo - smu * dt;
+            if (F <= 0.0) break;
+            lo -= step;
+            step *= 2.0;
+        }
+        step = fabs(hi - chi) + 1e-300;
+        for (int k = 0; k < 200; ++k) {
+            double c2, c3, zz = alpha * hi * hi;
+            stumpff(zz, c2, c3);
+            double F = sig * hi * hi * c2 + (1.0 - alpha * r0) * hi * hi * hi * c3 + r0 * hi - smu * dt;
+            if (F >= 0.0) break;
+            hi += step;
+            step *= 2.0;
+        }
+    }
+    bool ok = false;
+    double c2 = 0.5, c3 = 1.0 / 6.0, rr = r0;
+    for (int it = 0; it < 100; ++it) {
+        const double zz = alpha * chi * chi;
+        stumpff(zz, c2, c3);
+        const double chi2 = chi * chi;
+        const double F = sig * chi2 * c2 + (1.0 - alpha * r0) * chi2 * chi * c3 + r0 * chi - smu * dt;
+        rr = sig * chi * (1.0 - zz * c3) + (1.0 - alpha * r0) * chi2 * c2 + r0;
+        if (F > 0.0) hi = chi; else lo = chi;
+        const double step = F / rr;
+        if (fabs(step) <= 1e-15 * fabs(chi) || hi - lo <= 4e-16 * fabs(chi)) {
+            // converged: take the last Newton correction (it may sit on the bracket edge)
+            chi -= step;
+            ok = true;
+            break;
+        }
+        double nx = chi - step;
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        chi = nx;
+    }
+    const double zz = alpha * chi * chi;
+    stumpff(zz, c2, c3);
+    const double chi2 = chi * chi;
+    const double f = 1.0 - chi2 / r0 * c2;
+    const double g = dt - chi2 * chi / smu * c3;
+    const double nxp = f * x + g * vx, nyp = f * y + g * vy, nzp = f * z + g * vz;
+    const double r = sqrt(nxp * nxp + nyp * nyp + nzp * nzp);
+    const double fd = smu / (r * r0) * chi * (zz * c3 - 1.0);
+    const double gd = 1.0 - chi2 / r * c2;
+    const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
+    x = nxp;
+    y = nyp;
+    z = nzp;
+    vx = nvx;
+    vy = nvy;
+    vz = nvz;
+    return ok;
+}
+
+__global__ __launch_bounds__(256) void kepler_kernel(int n_total, const int32_t *sys_of,
+                                                     const double *mstar, double *x, double *y,
+                                                     double *z, double *vx, double *vy,
+                                                     double *vz, double dt, int32_t *member_slot,
+                                                     const double *bs_out, int32_t *flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const int slot = member_slot[i];
+    if (slot >= 0) {
+        // body integrated by the encounter step: take its result, clear the slot
+        const double *o = bs_out + 6 * (size_t)slot;
+        x[i] = o[0];
+        y[i] = o[1];
+        z[i] = o[2];
+        vx[i] = o[3];
+        vy[i] = o[4];
+        vz[i] = o[5];
+        member_slot[i] = -1;
+        return;
+    }
+    double px = x[i], py = y[i], pz = z[i], ux = vx[i], uy = vy[i], uz = vz[i];
+    const bool ok = kepler_universal(px, py, pz, ux, uy, uz, mstar[sys_of[i]], dt);
+    if (!ok) atomicOr(flags, FLAG_NOCONVERGE);
+    x[i] = px;
+    y[i] = py;
+    z[i] = pz;
+    vx[i] = ux;
+    vy[i] = uy;
+    vz[i] = uz;
+}
+
+// ------------------------------------------------------------------------------------------
+// Encounter groups: one workgroup.  lab[] (init -1) and mark[] (init 0) are global arrays
+// over all bodies that this kernel leaves clean again for the next step.
+// Output: members[] sorted by (group root, body), group_start[g] (g < n_groups, plus an end
+// sentinel), member_slot[body] = position in members[].
+// ------------------------------------------------------------------------------------------
+constexpr int CE_THREADS = 1024;
+
+__device__ __forceinline__ int find_root(const int32_t *lab, int a)
+{
+    int r = lab[a];
+    while (r != a) {
+        a = r;
+        r = lab[a];
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
+    const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab, int32_t *mark,
+    int32_t *members, int32_t *group_start, int32_t *n_groups, int32_t *member_slot, int32_t *flags)
+{
+    __shared__ uint64_t keys[CE_MAX_MEMBERS];
+    __shared__ int32_t s_nmem;
+    __shared__ int32_t s_changed;
+    __shared__ int32_t s_ng;
+    const int tid = threadIdx.x;
+    const int np = min(*pair_count, pair_cap);
+    if (tid == 0) {
+        s_nmem = 0;
+        s_ng = 0;
+    }
+    __syncthreads();
+    if (np <= 0) {
+        if (tid == 0) *n_groups = 0;
+        return;
+    }
+    // collect distinct member bodies; each becomes its own root
+    for (int p = tid; p < np; p += CE_THREADS) {
+        for (int e = 0; e < 2; ++e) {
+            const int b = pairs[2 * p + e];
+            if (atomicCAS(&mark[b], 0, 1) == 0) {
+                const int k = atomicAdd(&s_nmem, 1);
+                if (k < CE_MAX_MEMBERS) keys[k] = (uint64_t)(uint32_t)b;
+                lab[b] = b;
+            }
+        }
+    }
+    __syncthreads();
+    const int nmem_all = s_nmem;
+    const int nmem = min(nmem_all, CE_MAX_MEMBERS);
+    if (nmem_all > CE_MAX_MEMBERS) {
+        if (tid == 0) atomicOr(flags, FLAG_CAPACITY);
+    }
+    __threadfence_block();
+    // union by hooking the larger root under the smaller until no pair spans two roots
+    for (int round = 0; round < 4096; ++round) {
+        if (tid == 0) s_changed = 0;
+        __syncthreads();
+        for (int p = tid; p < np; p += CE_THREADS) {
+            int a = find_root(lab, pairs[2 * p]);
+            int b = find_root(lab, pairs[2 * p + 1]);
+            if (a != b) {
+                const int lo = min(a, b), hi = max(a, b);
+                atomicMin(&lab[hi], lo);
+                s_changed = 1;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (!s_changed) break;
+        __syncthreads();
+    }
+    // sort members by (root, body) so each group is contiguous and in ascending order
+    for (int k = tid; k < nmem; k += CE_THREADS) {
+        const int b = (int)(keys[k] & 0xffffffffu);
+        const int r = find_root(lab, b);
+        keys[k] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)b;
+    }
+    int npow = 1;
+    while (npow < nmem) npow <<= 1;
+    for (int k = nmem + tid; k < npow; k += CE_THREADS) keys[k] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= npow; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int k = tid; k < npow; k += CE_THREADS) {
+                const int partner = k ^ stride;
+                if (partner > k) {
+                    const bool up = (k & size) == 0;
+                    const uint64_t a = keys[k], b = keys[partner];
+                    if ((a > b) == up) {
+                        keys[k] = b;
+                        keys[partner] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // write members and slots; number the groups with a chunked scan of the start flags
+    __shared__ int32_t s_cnt[CE_THREADS];
+    const int per = (nmem + CE_THREADS - 1) / CE_THREADS;
+    const int kb = min(tid * per, nmem), ke = min(kb + per, nmem);
+    int nstart = 0;
+    for (int k = kb; k < ke; ++k) {
+        const int b = (int)(keys[k] & 0xffffffffu);
+        members[k] = b;
+        member_slot[b] = k;
+        if (k == 0 || (keys[k - 1] >> 32) != (keys[k] >> 32)) ++nstart;
+    }
+    s_cnt[tid] = nstart;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int t = 0; t < CE_THREADS; ++t) {
+            const int c = s_cnt[t];
+            s_cnt[t] = acc;
+            acc += c;
+        }
+        s_ng = acc;
+    }
+    __syncthreads();
+    int g = s_cnt[tid];
+    for (int k = kb; k < ke; ++k)
+        if (k == 0 || (keys[k - 1] >> 32) != (keys[k] >> 32)) group_start[g++] = k;
+    if (tid == 0) {
+        group_start[s_ng] = nmem;
+        *n_groups = s_ng;
+    }
+    // leave the marks clear for the next step (roots are re-initialised on marking)
+    for (int p = tid; p < np; p += CE_THREADS) {
+        mark[pairs[2 * p]] = 0;
+        mark[pairs[2 * p + 1]] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Bulirsch-Stoer over dt for one group per thread.
+// ------------------------------------------------------------------------------------------
+struct GroupView {
+    int nb;
+    const int32_t *idx;
+    const double *m;
+    const double *rc;
+    double mstar;
+};
+
+// D = dY/dt for the group state Y (6 doubles per member: x y z vx vy vz)
+__device__ void group_deriv(const GroupView &g, const double *Y, double *D)
+{
+    for (int a = 0; a < g.nb; ++a) {
+        const double *ya = Y + 6 * a;
+        const double r2 = ya[0] * ya[0] + ya[1] * ya[1] + ya[2] * ya[2];
+        const double r = sqrt(r2);
+        const double s = -g.mstar / (r2 * r);
+        double ax = s * ya[0], ay = s * ya[1], az = s * ya[2];
+        const double rca = g.rc[g.idx[a]];
+        for (int b = 0; b < g.nb; ++b) {
+            if (b == a) continue;
+            const double *yb = Y + 6 * b;
+            const double dx = yb[0] - ya[0], dy = yb[1] - ya[1], dz = yb[2] - ya[2];
+            const double q = sep2_rn(dx, dy, dz);
+            const double rcij = fmax(rca, g.rc[g.idx[b]]);
+            double w = 0.0;
+            if (q < sq_rn(rcij)) {
+                const double rr = sqrt(q);
+                w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
+            }
+            if (w == 0.0) continue;
+            const double rr = sqrt(q);
+            const double t = g.m[g.idx[b]] * w / (q * rr);
+            ax += t * dx;
+            ay += t * dy;
+            az += t * dz;
+        }
+        D[6 * a + 0] = ya[3];
+        D[6 * a + 1] = ya[4];
+        D[6 * a + 2] = ya[5];
+        D[6 * a + 3] = ax;
+        D[6 * a + 4] = ay;
+        D[6 * a + 5] = az;
+    }
+}
+
+// Gragg's modified midpoint rule: Y0 over H in nsub sub-steps -> out
+__device__ void midpoint(const GroupView &g, const double *Y0, double H, int nsub, double *out,
+                         double *zm, double *zc, double *dd)
+{
+    const int dim = 6 * g.nb;
+    const double h = H / nsub;
+    group_deriv(g, Y0, dd);
+    for (int q = 0; q < dim; ++q) {
+        zm[q] = Y0[q];
+        zc[q] = Y0[q] + h * dd[q];
+    }
+    for (int k = 1; k < nsub; ++k) {
+        group_deriv(g, zc, dd);
+        for (int q = 0; q < dim; ++q) {
+            const double t = zm[q] + 2.0 * h * dd[q];
+            zm[q] = zc[q];
+            zc[q] = t;
+        }
+    }
+    group_deriv(g, zc, dd);
+    for (int q = 0; q < dim; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
+}
+
+// Workspace per group: Y, tab[BS_KMAX], est, zm, zc, dd  => (BS_KMAX + 5) * dim doubles
+__device__ bool bs_integrate(const GroupView &g, double *Y, double *work, double dt, double tol)
+{
+    const int dim = 6 * g.nb;
+    double *tab = work;                       // BS_KMAX rows of dim
+    double *est = tab + (size_t)BS_KMAX * dim; // newest midpoint estimate
+    double *zm = est + dim, *zc = zm + dim, *dd = zc + dim;
+    double t = 0.0, H = dt;
+    int halvings = 0;
+    while (t < dt) {
+        if (H > dt - t) H = dt - t;
+        double sr = 0.0, sv = 0.0;
+        for (int a = 0; a < g.nb; ++a) {
+            const double *ya = Y + 6 * a;
+            sr = fmax(sr, sqrt(ya[0] * ya[0] + ya[1] * ya[1] + ya[2] * ya[2]));
+            sv = fmax(sv, sqrt(ya[3] * ya[3] + ya[4] * ya[4] + ya[5] * ya[5]));
+        }
+        int done = -1;
+        for (int k = 0; k < BS_KMAX && done < 0; ++k) {
+            midpoint(g, Y, H, 2 * (k + 1), est, zm, zc, dd);
+            // Neville update of the row: tab[l] <- T(k, l), in place
+            double err = 0.0;
+            for (int q = 0; q < dim; ++q) {
+                double prev = tab[q];           // T(k-1, 0)
+                double cur = est[q];            // T(k, 0)
+                tab[q] = cur;
+                double last = cur;
+                for (int l = 1; l <= k; ++l) {
+                    const double ratio = (double)(k + 1) / (double)(k + 1 - l);
+                    const double nxt = cur + (cur - prev) / (ratio * ratio - 1.0);
+                    prev = tab[(size_t)l * dim + q]; // T(k-1, l)
+                    last = cur;
+                    cur = nxt;
+                    tab[(size_t)l * dim + q] = cur; // T(k, l)
+                }
+                if (k > 0) {
+                    const double sc = ((q % 6) < 3) ? sr : sv;
+                    err = fmax(err, fabs(cur - last) / sc);
+                }
+            }
+            if (k > 0 && err <= tol) done = k;
+        }
+        if (done >= 0) {
+            for (int q = 0; q < dim; ++q) Y[q] = tab[(size_t)done * dim + q];
+            t += H;
+            H = 2.0 * H;
+        } else {
+            H = 0.5 * H;
+            if (++halvings > 60) return false;
+        }
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(64) void ce_bs_kernel(const int32_t *sys_of, const double *mstar,
+                                                   const double *x, const double *y,
+                                                   const double *z, const double *vx,
+                                                   const double *vy, const double *vz,
+                                                   const double *m, const double *rc, double dt,
+                                                   const int32_t *members,
+                                                   const int32_t *group_start,
+                                                   const int32_t *n_groups, double *bs_out,
+                                                   double *bs_work, int32_t *flags)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= *n_groups) return;
+    const int k0 = group_start[g], k1 = group_start[g + 1];
+    const int nb = k1 - k0;
+    const int32_t *idx = members + k0;
+    double *Y = bs_out + 6 * (size_t)k0;
+    for (int a = 0; a < nb; ++a) {
+        const int b = idx[a];
+        Y[6 * a + 0] = x[b];
+        Y[6 * a + 1] = y[b];
+        Y[6 * a + 2] = z[b];
+        Y[6 * a + 3] = vx[b];
+        Y[6 * a + 4] = vy[b];
+        Y[6 * a + 5] = vz[b];
+    }
+    if (nb > CE_MAX_GROUP) {
+        // too large for this step: Kepler-drift the members instead and flag it
+        atomicOr(flags, FLAG_CAPACITY);
+        const double ms = mstar[sys_of[idx[0]]];
+        for (int a = 0; a < nb; ++a) {
+            double *ya = Y + 6 * a;
+            if (!kepler_universal(ya[0], ya[1], ya[2], ya[3], ya[4], ya[5], ms, dt))
+                atomicOr(flags, FLAG_NOCONVERGE);
+        }
+        return;
+    }
+    GroupView gv{nb, idx, m, rc, mstar[sys_of[idx[0]]]};
+    double *work = bs_work + (size_t)(BS_KMAX + 5) * 6 * (size_t)k0;
+    if (!bs_integrate(gv, Y, work, dt, 1e-12)) atomicOr(flags, FLAG_NOCONVERGE);
+}
+
+} // namespace
+
+hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
+                            const double *vy, const double *vz, const double *m, double tau,
+                            hipStream_t stream)
+{
+    if (L.n_sys == 0) return hipSuccess;
+    sun_drift_kernel<<<L.n_sys, SUN_THREADS, 0, stream>>>(L.sys_off, L.mstar, x, y, z, vx, vy, vz, m,
+                                                         tau);
+    return hipGetLastError();
+}
+
+hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
+                            int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
+                            int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
+                            int32_t *flags, hipStream_t stream)
+{
+    (void)L;
+    ce_groups_kernel<<<1, CE_THREADS, 0, stream>>>(pairs, pair_count, pair_cap, lab, mark, members,
+                                                   group_start, n_groups, member_slot, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *m,
+                        const double *rc, double dt, const int32_t *members,
+                        const int32_t *group_start, const int32_t *n_groups, double *bs_out,
+                        double *bs_work, int32_t *flags, hipStream_t stream)
+{
+    // at most CE_MAX_MEMBERS / 2 groups (every group has >= 2 members)
+    const int grid = (CE_MAX_MEMBERS / 2 + 63) / 64;
+    ce_bs_kernel<<<grid, 64, 0, stream>>>(L.sys_of, L.mstar, x, y, z, vx, vy, vz, m, rc, dt, members,
+                                          group_start, n_groups, bs_out, bs_work, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
+                         double *vz, double dt, int32_t *member_slot, const double *bs_out,
+                         int32_t *flags, hipStream_t stream)
+{
+    if (L.n_total == 0) return hipSuccess;
+    kepler_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, L.sys_of, L.mstar, x, y, z,
+                                                               vx, vy, vz, dt, member_slot, bs_out,
+                                                               flags);
+    return hipGetLastError();
+}
+
+} // namespace genga

@@ -1,0 +1,520 @@
+// C ABI of the kick library: argument checks, the context (layout, scratch, launch plan,
+// deferred device status), the step sequence and HIP graph capture.  Host code.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "genga_internal.h"
+
+using namespace genga;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(GENGA_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+hipError_t dalloc(T *&p, size_t count)
+{
+    dfree(p);
+    if (count == 0) count = 1;
+    return hipMalloc((void **)&p, count * sizeof(T));
+}
+
+} // namespace
+
+struct genga_ctx {
+    int device = 0;
+    int n_cu = 256;
+    Layout L;
+    std::vector<int32_t> sys_off_h;
+    // launch plan
+    WorkItem *items = nullptr;  // kick items, largest systems first
+    int32_t n_items = 0;
+    WorkItem *eitems = nullptr; // energy items, in system order
+    int32_t *item_first = nullptr;
+    int waves[2] = {8, 8};      // [prec] waves per workgroup of the kick
+    int grid[2] = {0, 0};       // 0: one workgroup per item
+    // scratch
+    uint8_t *jrec = nullptr;    // 32 B per body
+    double *rc2max = nullptr;
+    double *acc = nullptr;      // a_i of the last kick: [3][n_total]
+    int32_t *pairs = nullptr;
+    int32_t *pair_count = nullptr;
+    int32_t pair_cap = 0;
+    uint64_t *sort_keys = nullptr;
+    int32_t *flags = nullptr;
+    int32_t *lab = nullptr, *mark = nullptr, *members = nullptr, *group_start = nullptr;
+    int32_t *n_groups = nullptr, *member_slot = nullptr;
+    double *bs_out = nullptr, *bs_work = nullptr;
+    double *epartial = nullptr;
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    void release()
+    {
+        dfree(L.sys_off);
+        dfree(L.sys_of);
+        dfree(L.mstar);
+        dfree(items);
+        dfree(eitems);
+        dfree(item_first);
+        dfree(jrec);
+        dfree(rc2max);
+        dfree(acc);
+        dfree(pairs);
+        dfree(pair_count);
+        dfree(sort_keys);
+        dfree(flags);
+        dfree(lab);
+        dfree(mark);
+        dfree(members);
+        dfree(group_start);
+        dfree(n_groups);
+        dfree(member_slot);
+        dfree(bs_out);
+        dfree(bs_work);
+        dfree(epartial);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        L.n_sys = L.n_total = 0;
+        n_items = 0;
+    }
+};
+
+namespace {
+
+int check_ctx(genga_ctx *ctx, bool need_layout = true)
+{
+    if (!ctx) return fail(GENGA_ERR_ARG, "null context");
+    if (need_layout && ctx->L.n_sys <= 0) return fail(GENGA_ERR_STATE, "no layout: call genga_set_systems first");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(GENGA_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+    return GENGA_OK;
+}
+
+int check_bodies(const genga_ctx *ctx, const genga_bodies *b, bool need_v, bool need_rc)
+{
+    if (!b) return fail(GENGA_ERR_ARG, "null bodies");
+    if (ctx->L.n_total == 0) return GENGA_OK;
+    if (!b->x || !b->y || !b->z || !b->m) return fail(GENGA_ERR_ARG, "null position or mass array");
+    if (need_v && (!b->vx || !b->vy || !b->vz)) return fail(GENGA_ERR_ARG, "null velocity array");
+    if (need_rc && !b->rcrit) return fail(GENGA_ERR_ARG, "null rcrit array");
+    return GENGA_OK;
+}
+
+int check_prec(int prec)
+{
+    if (prec != GENGA_KICK_FP32 && prec != GENGA_KICK_FP64) return fail(GENGA_ERR_ARG, "bad precision %d", prec);
+    return GENGA_OK;
+}
+
+int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v, int prec, double *ax,
+                 double *ay, double *az, hipStream_t s)
+{
+    const Layout &L = ctx->L;
+    if (L.n_total == 0) return GENGA_OK;
+    const int fp32 = prec == GENGA_KICK_FP32;
+    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2max, ctx->pair_count, s));
+    KickArgs a;
+    a.items = ctx->items;
+    a.n_items = ctx->n_items;
+    a.sys_off = L.sys_off;
+    a.x = b->x;
+    a.y = b->y;
+    a.z = b->z;
+    a.vx = b->vx;
+    a.vy = b->vy;
+    a.vz = b->vz;
+    a.m = b->m;
+    a.rc = b->rcrit;
+    a.jrec = ctx->jrec;
+    a.rc2max = ctx->rc2max;
+    a.ax = ax;
+    a.ay = ay;
+    a.az = az;
+    a.tau = tau;
+    a.update_v = update_v;
+    a.pairs = ctx->pairs;
+    a.pair_count = ctx->pair_count;
+    a.pair_cap = ctx->pair_cap;
+    a.flags = ctx->flags;
+    HIP_TRY(launch_kick(a, fp32, ctx->waves[fp32], ctx->grid[fp32], s));
+    return GENGA_OK;
+}
+
+int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+{
+    const Layout &L = ctx->L;
+    if (L.n_total == 0) return GENGA_OK;
+    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, s));
+    HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
+                             ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
+    HIP_TRY(launch_ce_bs(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
+                         ctx->group_start, ctx->n_groups, ctx->bs_out, ctx->bs_work, ctx->flags, s));
+    HIP_TRY(launch_kepler(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, dt, ctx->member_slot, ctx->bs_out,
+                          ctx->flags, s));
+    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, s));
+    return GENGA_OK;
+}
+
+int enqueue_energy(genga_ctx *ctx, const genga_bodies *b, double vshift, double *out, hipStream_t s)
+{
+    const Layout &L = ctx->L;
+    const size_t n = (size_t)L.n_total;
+    HIP_TRY(launch_energy(L, ctx->eitems, ctx->n_items, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, ctx->acc,
+                          ctx->acc + n, ctx->acc + 2 * n, vshift, ctx->epartial, ctx->item_first, out, s));
+    return GENGA_OK;
+}
+
+int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int cadence, double *d_energy,
+                 hipStream_t s)
+{
+    const size_t n = (size_t)ctx->L.n_total;
+    double *ax = ctx->acc, *ay = ctx->acc + n, *az = ctx->acc + 2 * n;
+    int rc = enqueue_kick(ctx, b, 0.5 * dt, 1, prec, ax, ay, az, s);
+    if (rc) return rc;
+    int rec = 0;
+    for (int k = 1; k <= nsteps; ++k) {
+        rc = enqueue_drift(ctx, b, dt, s);
+        if (rc) return rc;
+        const bool last = k == nsteps;
+        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s);
+        if (rc) return rc;
+        if (cadence > 0 && d_energy && k % cadence == 0) {
+            rc = enqueue_energy(ctx, b, last ? 0.0 : 0.5 * dt, d_energy + (size_t)rec * 4 * ctx->L.n_sys, s);
+            if (rc) return rc;
+            ++rec;
+        }
+    }
+    return GENGA_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *genga_last_error(void) { return g_last_error.c_str(); }
+
+int genga_create(genga_ctx **out, int device)
+{
+    if (!out) return fail(GENGA_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(GENGA_ERR_ARG, "device %d out of range (%d devices)", device, ndev);
+    HIP_TRY(hipSetDevice(device));
+    genga_ctx *c = new genga_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return GENGA_OK;
+}
+
+int genga_destroy(genga_ctx *ctx)
+{
+    if (!ctx) return GENGA_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->release();
+    delete ctx;
+    return GENGA_OK;
+}
+
+int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host, const double *mstar_host,
+                      int32_t pair_capacity)
+{
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    if (n_sys < 1) return fail(GENGA_ERR_ARG, "n_sys must be >= 1 (got %d)", n_sys);
+    if (!sys_off_host || !mstar_host) return fail(GENGA_ERR_ARG, "null sys_off or mstar");
+    if (sys_off_host[0] != 0) return fail(GENGA_ERR_ARG, "sys_off[0] must be 0");
+    for (int s = 0; s < n_sys; ++s) {
+        if (sys_off_host[s + 1] < sys_off_host[s]) return fail(GENGA_ERR_ARG, "sys_off not non-decreasing at %d", s);
+        if (!(mstar_host[s] > 0.0)) return fail(GENGA_ERR_ARG, "mstar[%d] must be > 0", s);
+    }
+    const int64_t n_total64 = sys_off_host[n_sys];
+    if (n_total64 > (int64_t)1 << 30) return fail(GENGA_ERR_ARG, "too many bodies");
+    const int32_t n_total = (int32_t)n_total64;
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->release();
+    ctx->sys_off_h.assign(sys_off_host, sys_off_host + n_sys + 1);
+
+    // work items: 64 consecutive bodies of one system
+    std::vector<WorkItem> it;
+    std::vector<int32_t> first(n_sys + 1, 0);
+    for (int s = 0; s < n_sys; ++s) {
+        first[s] = (int32_t)it.size();
+        const int b = sys_off_host[s], e = sys_off_host[s + 1];
+        for (int i0 = b; i0 < e; i0 += 64) it.push_back(WorkItem{s, i0, std::min(64, e - i0), e - b});
+    }
+    first[n_sys] = (int32_t)it.size();
+    std::vector<WorkItem> kit = it;
+    std::stable_sort(kit.begin(), kit.end(), [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
+    ctx->n_items = (int32_t)it.size();
+
+    std::vector<int32_t> sys_of(n_total);
+    for (int s = 0; s < n_sys; ++s)
+        for (int i = sys_off_host[s]; i < sys_off_host[s + 1]; ++i) sys_of[i] = s;
+
+    int32_t cap = pair_capacity > 0 ? pair_capacity : (int32_t)std::min<int64_t>(16 * (int64_t)n_total + 1024, INT32_MAX / 4);
+    ctx->pair_cap = cap;
+    int64_t npow = 1;
+    while (npow < cap) npow <<= 1;
+    const size_t nt = (size_t)n_total;
+
+    HIP_TRY(dalloc(ctx->L.sys_off, n_sys + 1));
+    HIP_TRY(dalloc(ctx->L.sys_of, nt));
+    HIP_TRY(dalloc(ctx->L.mstar, n_sys));
+    HIP_TRY(dalloc(ctx->items, it.size()));
+    HIP_TRY(dalloc(ctx->eitems, it.size()));
+    HIP_TRY(dalloc(ctx->item_first, n_sys + 1));
+    HIP_TRY(dalloc(ctx->jrec, nt * 32));
+    HIP_TRY(dalloc(ctx->rc2max, n_sys));
+    HIP_TRY(dalloc(ctx->acc, 3 * nt));
+    HIP_TRY(dalloc(ctx->pairs, 2 * (size_t)cap));
+    HIP_TRY(dalloc(ctx->pair_count, 1));
+    HIP_TRY(dalloc(ctx->sort_keys, (size_t)npow));
+    HIP_TRY(dalloc(ctx->flags, 1));
+    HIP_TRY(dalloc(ctx->lab, nt));
+    HIP_TRY(dalloc(ctx->mark, nt));
+    HIP_TRY(dalloc(ctx->members, CE_MAX_MEMBERS));
+    HIP_TRY(dalloc(ctx->group_start, CE_MAX_MEMBERS + 1));
+    HIP_TRY(dalloc(ctx->n_groups, 1));
+    HIP_TRY(dalloc(ctx->member_slot, nt));
+    HIP_TRY(dalloc(ctx->bs_out, 6 * (size_t)CE_MAX_MEMBERS));
+    HIP_TRY(dalloc(ctx->bs_work, (size_t)(BS_KMAX + 5) * 6 * CE_MAX_MEMBERS));
+    HIP_TRY(dalloc(ctx->epartial, 9 * it.size()));
+
+    HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (nt) HIP_TRY(hipMemcpy(ctx->L.sys_of, sys_of.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->L.mstar, mstar_host, n_sys * sizeof(double), hipMemcpyHostToDevice));
+    if (!it.empty()) {
+        HIP_TRY(hipMemcpy(ctx->items, kit.data(), kit.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->eitems, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(ctx->item_first, first.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(ctx->pair_count, 0, sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->flags, 0, sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->n_groups, 0, sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->lab, 0xff, nt * sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->mark, 0, nt * sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->member_slot, 0xff, nt * sizeof(int32_t)));
+    HIP_TRY(hipMemset(ctx->acc, 0, 3 * nt * sizeof(double)));
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->L.n_sys = n_sys;
+    ctx->L.n_total = n_total;
+    return GENGA_OK;
+}
+
+int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, double dt, double *rc_out,
+                void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_bodies(ctx, b, true, false))) return rc;
+    if (!rc_out && ctx->L.n_total) return fail(GENGA_ERR_ARG, "null rc_out");
+    if (!(n1 >= 0.0) || !(n2 >= 0.0)) return fail(GENGA_ERR_ARG, "n1, n2 must be >= 0");
+    HIP_TRY(launch_rcrit(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, n1, n2, dt, rc_out,
+                         (hipStream_t)stream));
+    return GENGA_OK;
+}
+
+int genga_accel(genga_ctx *ctx, const genga_bodies *b, int prec, double *ax, double *ay, double *az, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, false, true))) return rc;
+    if (ctx->L.n_total && (!ax || !ay || !az)) return fail(GENGA_ERR_ARG, "null acceleration output");
+    return enqueue_kick(ctx, b, 0.0, 0, prec, ax, ay, az, (hipStream_t)stream);
+}
+
+int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    const size_t n = (size_t)ctx->L.n_total;
+    return enqueue_kick(ctx, b, tau, 1, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, (hipStream_t)stream);
+}
+
+int genga_encounter_list(genga_ctx *ctx, int32_t *pairs, int32_t cap, int32_t *d_count, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!d_count) return fail(GENGA_ERR_ARG, "null d_count");
+    if (cap < 0 || (cap > 0 && !pairs)) return fail(GENGA_ERR_ARG, "bad pairs buffer");
+    HIP_TRY(launch_sort_pairs(ctx->pairs, ctx->pair_count, ctx->pair_cap, pairs, cap, d_count, ctx->sort_keys,
+                              ctx->flags, (hipStream_t)stream));
+    return GENGA_OK;
+}
+
+int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_bodies(ctx, b, true, true))) return rc;
+    return enqueue_drift(ctx, b, dt, (hipStream_t)stream);
+}
+
+int genga_energy(genga_ctx *ctx, const genga_bodies *b, double *d_out, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_bodies(ctx, b, true, false))) return rc;
+    if (!d_out) return fail(GENGA_ERR_ARG, "null d_out");
+    return enqueue_energy(ctx, b, 0.0, d_out, (hipStream_t)stream);
+}
+
+int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int energy_cadence,
+               double *d_energy, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if (nsteps < 0) return fail(GENGA_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps == 0) return GENGA_OK;
+    return enqueue_step(ctx, b, dt, nsteps, prec, energy_cadence, d_energy, (hipStream_t)stream);
+}
+
+int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if (nsteps < 1) return fail(GENGA_ERR_ARG, "nsteps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(GENGA_ERR_ARG, "graph capture needs a non-default stream");
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_step(ctx, b, dt, nsteps, prec, 0, nullptr, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(GENGA_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    ctx->graph = g;
+    HIP_TRY(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    return GENGA_OK;
+}
+
+int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!ctx->graph_exec) return fail(GENGA_ERR_STATE, "no captured graph");
+    if (repeats < 0) return fail(GENGA_ERR_ARG, "repeats must be >= 0");
+    for (int r = 0; r < repeats; ++r) HIP_TRY(hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream));
+    return GENGA_OK;
+}
+
+int genga_set_kick_waves(genga_ctx *ctx, int prec, int waves)
+{
+    if (!ctx) return fail(GENGA_ERR_ARG, "null context");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    if (waves == 0) waves = 8;
+    if (waves != 4 && waves != 8 && waves != 16) return fail(GENGA_ERR_ARG, "waves must be 4, 8 or 16");
+    ctx->waves[prec == GENGA_KICK_FP32] = waves;
+    return GENGA_OK;
+}
+
+int genga_get_kick_waves(genga_ctx *ctx, int prec)
+{
+    if (!ctx) return fail(GENGA_ERR_ARG, "null context");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    return ctx->waves[prec == GENGA_KICK_FP32];
+}
+
+int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, false, true))) return rc;
+    if (ctx->L.n_total == 0) return GENGA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int fp32 = prec == GENGA_KICK_FP32;
+    const size_t n = (size_t)ctx->L.n_total;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cand[3] = {4, 8, 16};
+    float best = 1e30f;
+    int best_w = ctx->waves[fp32];
+    for (int w : cand) {
+        ctx->waves[fp32] = w;
+        // accelerations only (velocities untouched); one warm-up then five timed launches
+        rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 5 && !rc; ++r)
+            rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_w = w;
+        }
+    }
+    ctx->waves[fp32] = best_w;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int genga_poll_status(genga_ctx *ctx)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipDeviceSynchronize());
+    int32_t f = 0;
+    HIP_TRY(hipMemcpy(&f, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(ctx->flags, 0, sizeof(int32_t)));
+    HIP_TRY(hipDeviceSynchronize());
+    if (f & FLAG_NONFINITE) return fail(GENGA_ERR_NONFINITE, "non-finite acceleration");
+    if (f & FLAG_NOCONVERGE) return fail(GENGA_ERR_NOCONVERGE, "Kepler or Bulirsch-Stoer solve did not converge");
+    if (f & FLAG_CAPACITY) return fail(GENGA_ERR_CAPACITY, "encounter capacity exceeded");
+    return GENGA_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP sources of the kick library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "genga.h"
+
+namespace genga {
+
+// One unit of kick / energy work: up to 64 consecutive bodies (one per lane) of one system.
+struct WorkItem {
+    int32_t sys;
+    int32_t i0;   // first body (global index)
+    int32_t ni;   // number of bodies, 1..64
+    int32_t cost; // sources to visit (system size), used for ordering
+};
+
+// Source ("j") records, rebuilt from the SoA state before each kick; 32 bytes so that one
+// scalar load brings a whole record into SGPRs for the wave-uniform inner loop.
+struct JRec32 {
+    double x, y, z;
+    float m;
+    float pad;
+};
+struct JRec64 {
+    double x, y, z, m;
+};
+
+enum DeviceFlag : int32_t {
+    FLAG_CAPACITY = 1,
+    FLAG_NONFINITE = 2,
+    FLAG_NOCONVERGE = 4,
+};
+
+// Maximum sizes of the close-encounter step (one workgroup builds the groups in LDS).
+constexpr int CE_MAX_MEMBERS = 8192;
+constexpr int CE_MAX_GROUP = 64;
+constexpr int BS_KMAX = 8;
+
+struct Layout {
+    int32_t n_sys = 0;
+    int32_t n_total = 0;
+    int32_t *sys_off = nullptr;  // device [n_sys + 1]
+    int32_t *sys_of = nullptr;   // device [n_total], system of each body
+    double *mstar = nullptr;     // device [n_sys]
+};
+
+struct KickArgs {
+    const WorkItem *items;
+    int32_t n_items;
+    const int32_t *sys_off;
+    const double *x, *y, *z;
+    double *vx, *vy, *vz;         // updated when update_v != 0
+    const double *m, *rc;
+    const void *jrec;             // JRec32[] or JRec64[]
+    const double *rc2max;         // [n_sys] max r_crit^2 per system
+    double *ax, *ay, *az;         // a_i out (FP64), always written
+    double tau;
+    int32_t update_v;
+    int32_t *pairs;               // [pair_cap][2]
+    int32_t *pair_count;
+    int32_t pair_cap;
+    int32_t *flags;
+};
+
+// Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
+hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
+                       const double *m, const double *rc, void *jrec, int fp32, double *rc2max,
+                       int32_t *pair_count, hipStream_t stream);
+hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream);
+hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *m,
+                        double n1, double n2, double dt, double *rc, hipStream_t stream);
+hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
+                            const double *vy, const double *vz, const double *m, double tau,
+                            hipStream_t stream);
+hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
+                            int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
+                            int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
+                            int32_t *flags, hipStream_t stream);
+hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *m,
+                        const double *rc, double dt, const int32_t *members,
+                        const int32_t *group_start, const int32_t *n_groups, double *bs_out,
+                        double *bs_work, int32_t *flags, hipStream_t stream);
+hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
+                         double *vz, double dt, int32_t *member_slot, const double *bs_out,
+                         int32_t *flags, hipStream_t stream);
+hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
+                         const double *y, const double *z, const double *vx, const double *vy,
+                         const double *vz, const double *m, const double *ax, const double *ay,
+                         const double *az, double vshift, double *partial,
+                         const int32_t *item_first, double *out, hipStream_t stream);
+hipError_t launch_sort_pairs(const int32_t *src, const int32_t *src_count, int32_t src_cap,
+                             int32_t *dst, int32_t dst_cap, int32_t *dst_count, uint64_t *keys,
+                             int32_t *flags, hipStream_t stream);
+
+} // namespace genga

@@ -1,0 +1,413 @@
+// Long-range kick of the hybrid symplectic step (Brasser et al. 2023, Sect. 1): direct
+// O(N^2) summation of Newtonian pair accelerations weighted by the changeover function,
+// in FP32 pair arithmetic (coordinate differences formed in FP64) or in FP64, with the
+// close-encounter pairs recorded by the same launch.  gfx950, wave64.
+//
+// Design (vector-ALU bound; no MFMA: a pair force is not a dense contraction):
+//  * one workgroup = up to 64 target bodies i (one per lane, FP64 position in VGPRs) and
+//    W waves; wave w visits a contiguous slice of the system's sources j, so a launch over
+//    N/64 workgroups still fills the chip.  Partial sums of the W waves are added in LDS in
+//    a fixed order, so results are deterministic.
+//  * sources are read as 32-byte records through the scalar data path: the j index is
+//    wave-uniform, so every lane's pair arithmetic takes x_j, y_j, z_j, m_j from SGPRs and
+//    no LDS traffic or barrier is needed in the inner loop.
+//  * four sources per step; the changeover test is a single compare against the system's
+//    largest r_crit^2 per pair, and only a group of four that has a candidate takes the
+//    slow path, which decides "inside r_crit,ij" in FP64 exactly as the definition states,
+//    evaluates K and the pair term in FP64 and appends (i, j) to the encounter list.
+//  * FP32 path: FP32 partial sums over blocks of 64 sources, folded into FP64 accumulators.
+//    FP64 path: v_rsq_f64 (about 2^-24) refined by one third-order correction.
+#include "genga_internal.h"
+
+namespace genga {
+
+namespace {
+
+using CJ32 = const __attribute__((address_space(4))) JRec32;
+using CJ64 = const __attribute__((address_space(4))) JRec64;
+
+// Source records are read through the constant address space: the index is wave-uniform, so
+// the loads become scalar loads into SGPRs.
+__device__ __forceinline__ JRec32 ldj(CJ32 *J, int j)
+{
+    JRec32 r;
+    r.x = J[j].x;
+    r.y = J[j].y;
+    r.z = J[j].z;
+    r.m = J[j].m;
+    r.pad = 0.f;
+    return r;
+}
+
+__device__ __forceinline__ JRec64 ldj(CJ64 *J, int j)
+{
+    JRec64 r;
+    r.x = J[j].x;
+    r.y = J[j].y;
+    r.z = J[j].z;
+    r.m = J[j].m;
+    return r;
+}
+
+// separation^2 and squares without contraction: the encounter decision uses exactly the
+// rounding of the definition ((dx*dx + dy*dy) + dz*dz, then compare with rc*rc)
+__device__ __forceinline__ double sep2_rn(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+__device__ __forceinline__ double sq_rn(double a)
+{
+#pragma clang fp contract(off)
+    return a * a;
+}
+
+// Changeover weight of Chambers (1999), cited in Sect. 1: K(y) = y^2 / (2y^2 - 2y + 1) on
+// [0, 1], 0 below, 1 above.
+__device__ __forceinline__ double changeover_k(double y)
+{
+    if (y <= 0.0) return 0.0;
+    if (y >= 1.0) return 1.0;
+    double y2 = y * y;
+    return y2 / (2.0 * y2 - 2.0 * y + 1.0);
+}
+
+__device__ __forceinline__ void emit_pair(const KickArgs &a, int i, int j)
+{
+    int idx = atomicAdd(a.pair_count, 1);
+    if (idx < a.pair_cap) {
+        a.pairs[2 * idx] = i;
+        a.pairs[2 * idx + 1] = j;
+    } else {
+        atomicOr(a.flags, FLAG_CAPACITY);
+    }
+}
+
+// Pair inside the candidate radius: exact FP64 decision; inside r_crit,ij the weighted
+// term is added in FP64 and the pair recorded; returns true when handled here.
+__device__ __forceinline__ bool close_pair(const KickArgs &a, double xj, double yj, double zj,
+                                           int j, int i, bool valid, double xi, double yi,
+                                           double zi, double rci, double &sx, double &sy,
+                                           double &sz)
+{
+    if (j == i) return true;
+    double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    double r2 = sep2_rn(dx, dy, dz);
+    double rcij = fmax(rci, a.rc[j]);
+    if (!(r2 < sq_rn(rcij))) return false;
+    double r = sqrt(r2);
+    double k = changeover_k((r - 0.1 * rcij) / (0.9 * rcij));
+    if (k > 0.0) {
+        double s = a.m[j] * k / (r2 * r);
+        sx += s * dx;
+        sy += s * dy;
+        sz += s * dz;
+    }
+    if (valid && i < j) emit_pair(a, i, j);
+    return true;
+}
+
+struct Acc32 {
+    float fx, fy, fz;
+};
+
+__device__ __forceinline__ void far32(float mj, float dx, float dy, float dz, float q, Acc32 &c)
+{
+    float ri = __builtin_amdgcn_rsqf(q);
+    float s = mj * (ri * ri) * ri;
+    c.fx = fmaf(s, dx, c.fx);
+    c.fy = fmaf(s, dy, c.fy);
+    c.fz = fmaf(s, dz, c.fz);
+}
+
+__device__ __forceinline__ void far64(double mj, double dx, double dy, double dz, double q,
+                                      double &sx, double &sy, double &sz)
+{
+    double y0 = __builtin_amdgcn_rsq(q);
+    // one third-order step: rsqrt(q) = y0 (1 - e)^(-1/2), e = 1 - q y0^2
+    double t = q * y0;
+    double e = fma(-t, y0, 1.0);
+    double p = fma(0.375, e, 0.5);
+    double y = fma(y0 * e, p, y0);
+    double s = mj * (y * y) * y;
+    sx = fma(s, dx, sx);
+    sy = fma(s, dy, sy);
+    sz = fma(s, dz, sz);
+}
+
+template <int W>
+__device__ __forceinline__ void finish(const KickArgs &a, double (*red)[W][64], int wave,
+                                       int lane, bool valid, int i, double sx, double sy,
+                                       double sz)
+{
+    red[0][wave][lane] = sx;
+    red[1][wave][lane] = sy;
+    red[2][wave][lane] = sz;
+    __syncthreads();
+    if (wave == 0) {
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            tx += red[0][w][lane];
+            ty += red[1][w][lane];
+            tz += red[2][w][lane];
+        }
+        if (valid) {
+            a.ax[i] = tx;
+            a.ay[i] = ty;
+            a.az[i] = tz;
+            if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) atomicOr(a.flags, FLAG_NONFINITE);
+            if (a.update_v) {
+                a.vx[i] += a.tau * tx;
+                a.vy[i] += a.tau * ty;
+                a.vz[i] += a.tau * tz;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
+{
+    __shared__ double red[3][W][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    CJ32 *J = (CJ32 *)a.jrec;
+    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const WorkItem w = a.items[it];
+        const int j0 = a.sys_off[w.sys], j1 = a.sys_off[w.sys + 1];
+        const bool valid = lane < w.ni;
+        const int i = w.i0 + (valid ? lane : 0);
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
+        // candidate threshold: the system's largest r_crit^2 with a margin that covers the
+        // FP32 rounding of r^2; never zero, so the self pair always takes the exact path
+        const float T = (float)(a.rc2max[w.sys] * 1.0001) + 1e-30f;
+        const int chunk = (j1 - j0 + W - 1) / W;
+        const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        Acc32 c{0.f, 0.f, 0.f};
+        int j = jb;
+        while (j < je) {
+            const int jend = min(j + 64, je);
+            for (; j + 4 <= jend; j += 4) {
+                const JRec32 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
+                float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
+                float dx1 = (float)(r1.x - xi), dy1 = (float)(r1.y - yi), dz1 = (float)(r1.z - zi);
+                float dx2 = (float)(r2.x - xi), dy2 = (float)(r2.y - yi), dz2 = (float)(r2.z - zi);
+                float dx3 = (float)(r3.x - xi), dy3 = (float)(r3.y - yi), dz3 = (float)(r3.z - zi);
+                float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
+                float q1 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
+                float q2 = fmaf(dx2, dx2, fmaf(dy2, dy2, dz2 * dz2));
+                float q3 = fmaf(dx3, dx3, fmaf(dy3, dy3, dz3 * dz3));
+                const bool near = (q0 < T) | (q1 < T) | (q2 < T) | (q3 < T);
+                if (__builtin_expect(near, 0)) {
+                    if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r0.m, dx0, dy0, dz0, q0, c);
+                    if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r1.m, dx1, dy1, dz1, q1, c);
+                    if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r2.m, dx2, dy2, dz2, q2, c);
+                    if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r3.m, dx3, dy3, dz3, q3, c);
+                } else {
+                    far32(r0.m, dx0, dy0, dz0, q0, c);
+                    far32(r1.m, dx1, dy1, dz1, q1, c);
+                    far32(r2.m, dx2, dy2, dz2, q2, c);
+                    far32(r3.m, dx3, dy3, dz3, q3, c);
+                }
+            }
+            for (; j < jend; ++j) {
+                const JRec32 r0 = ldj(J, j);
+                float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
+                float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far32(r0.m, dx0, dy0, dz0, q0, c);
+            }
+            // fold the block's FP32 partial sums into the FP64 accumulators
+            sx += (double)c.fx;
+            sy += (double)c.fy;
+            sz += (double)c.fz;
+            c.fx = c.fy = c.fz = 0.f;
+        }
+        finish<W>(a, red, wave, lane, valid, i, sx, sy, sz);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
+{
+    __shared__ double red[3][W][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    CJ64 *J = (CJ64 *)a.jrec;
+    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const WorkItem w = a.items[it];
+        const int j0 = a.sys_off[w.sys], j1 = a.sys_off[w.sys + 1];
+        const bool valid = lane < w.ni;
+        const int i = w.i0 + (valid ? lane : 0);
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
+        const double T = a.rc2max[w.sys] + 1e-300;
+        const int chunk = (j1 - j0 + W - 1) / W;
+        const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        int j = jb;
+        for (; j + 4 <= je; j += 4) {
+            const JRec64 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
+            double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
+            double dx1 = r1.x - xi, dy1 = r1.y - yi, dz1 = r1.z - zi;
+            double dx2 = r2.x - xi, dy2 = r2.y - yi, dz2 = r2.z - zi;
+            double dx3 = r3.x - xi, dy3 = r3.y - yi, dz3 = r3.z - zi;
+            double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
+            double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
+            double q2 = fma(dx2, dx2, fma(dy2, dy2, dz2 * dz2));
+            double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
+            const bool near = (q0 < T) | (q1 < T) | (q2 < T) | (q3 < T);
+            if (__builtin_expect(near, 0)) {
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
+                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
+                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
+                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
+            } else {
+                far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
+                far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
+                far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
+                far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
+            }
+        }
+        for (; j < je; ++j) {
+            const JRec64 r0 = ldj(J, j);
+            double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
+            double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
+            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
+        }
+        finish<W>(a, red, wave, lane, valid, i, sx, sy, sz);
+    }
+}
+
+// Source records and the per-system largest r_crit^2 (and a cleared pair counter).
+template <bool F32>
+__global__ __launch_bounds__(256) void prep_kernel(int n_total, int body_blocks,
+                                                   const int32_t *sys_off, const double *x,
+                                                   const double *y, const double *z,
+                                                   const double *m, const double *rc, void *jrec,
+                                                   double *rc2max, int32_t *pair_count)
+{
+    if ((int)blockIdx.x < body_blocks) {
+        int i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i < n_total) {
+            if (F32) {
+                JRec32 r;
+                r.x = x[i];
+                r.y = y[i];
+                r.z = z[i];
+                r.m = (float)m[i];
+                r.pad = 0.f;
+                ((JRec32 *)jrec)[i] = r;
+            } else {
+                JRec64 r;
+                r.x = x[i];
+                r.y = y[i];
+                r.z = z[i];
+                r.m = m[i];
+                ((JRec64 *)jrec)[i] = r;
+            }
+        }
+        return;
+    }
+    const int s = blockIdx.x - body_blocks;
+    const int b = sys_off[s], e = sys_off[s + 1];
+    double mx = 0.0;
+    for (int i = b + threadIdx.x; i < e; i += blockDim.x) mx = fmax(mx, rc[i] * rc[i]);
+    __shared__ double red[256];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rc2max[s] = red[0];
+        if (s == 0) *pair_count = 0;
+    }
+}
+
+// eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i)
+__global__ __launch_bounds__(256) void rcrit_kernel(int n_total, const int32_t *sys_of,
+                                                    const double *mstar, const double *x,
+                                                    const double *y, const double *z,
+                                                    const double *vx, const double *vy,
+                                                    const double *vz, const double *m, double n1,
+                                                    double n2, double dt, double *rc)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    double ms = mstar[sys_of[i]];
+    double r = sqrt(x[i] * x[i] + y[i] * y[i] + z[i] * z[i]);
+    double v2 = vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+    double inv_a = 2.0 / r - v2 / ms;
+    double a = inv_a > 0.0 ? 1.0 / inv_a : r;
+    double rh = a * cbrt(m[i] / (3.0 * ms));
+    double vk = sqrt(ms / a);
+    rc[i] = fmax(n1 * rh, n2 * dt * vk);
+}
+
+} // namespace
+
+hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
+                       const double *m, const double *rc, void *jrec, int fp32, double *rc2max,
+                       int32_t *pair_count, hipStream_t stream)
+{
+    const int body_blocks = (L.n_total + 255) / 256;
+    const int grid = body_blocks + L.n_sys;
+    if (fp32)
+        prep_kernel<true><<<grid, 256, 0, stream>>>(L.n_total, body_blocks, L.sys_off, x, y, z, m, rc,
+                                                    jrec, rc2max, pair_count);
+    else
+        prep_kernel<false><<<grid, 256, 0, stream>>>(L.n_total, body_blocks, L.sys_off, x, y, z, m,
+                                                     rc, jrec, rc2max, pair_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream)
+{
+    if (a.n_items == 0) return hipSuccess;
+    if (grid <= 0 || grid > a.n_items) grid = a.n_items;
+#define GENGA_KICK_CASE(Wv)                                                                   \
+    case Wv:                                                                                  \
+        if (fp32)                                                                             \
+            kick32_kernel<Wv><<<grid, 64 * Wv, 0, stream>>>(a);                              \
+        else                                                                                  \
+            kick64_kernel<Wv><<<grid, 64 * Wv, 0, stream>>>(a);                              \
+        break;
+    switch (waves) {
+        GENGA_KICK_CASE(4)
+        GENGA_KICK_CASE(8)
+        GENGA_KICK_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GENGA_KICK_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
+                        const double *vx, const double *vy, const double *vz, const double *m,
+                        double n1, double n2, double dt, double *rc, hipStream_t stream)
+{
+    if (L.n_total == 0) return hipSuccess;
+    rcrit_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, L.sys_of, L.mstar, x, y, z,
+                                                              vx, vy, vz, m, n1, n2, dt, rc);
+    return hipGetLastError();
+}
+
+} // namespace genga
