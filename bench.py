@@ -1,0 +1,255 @@
+"""Benchmark of the changeover-weighted kick path on one MI355X.
+
+Workload: a single synthetic planetesimal disc, N = 40000 equal-mass bodies (5 Earth
+masses, 0.5-4 au, Sigma ~ a^-1.5, Rayleigh e and i), r_crit = 3 Hill radii, dt = 6 days.
+A step is the whole hot path: the FP32-pair-arithmetic kick with its encounter list, the
+Sun drift, the FP64 Kepler drift and close-encounter step, and the FP64 energy /
+angular-momentum diagnostic every 10 steps.  `value` is pair interactions N(N-1) per step
+times steps per second, for state already resident in HBM.
+
+Also reported: the FP64 kick path, kick-only rates and their ratio, the roofline of the
+kick kernel (HIP events on the launch stream), a batched run of 64 uneven discs in one
+launch per kernel vs a loop of single-disc launches, Delta E/E and Delta L/L over the
+timed steps, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import discs  # noqa: E402
+import paper_2309_08217_amd as genga  # noqa: E402
+
+FLOP_PER_PAIR = 18            # 3 sub + 5 (r^2) + 1 rsqrt + 2 (r^-3) + 1 (m) + 6 (3 FMA)
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (packed FMA)
+PEAK_FP32_NONPACKED = 78.6    # 256 CU x 64 lanes x 2.4 GHz x 2 flop (unpacked FMA)
+PEAK_FP64_TFLOPS = 78.6
+CADENCE = 10
+N1, N2 = 3.0, 0.0
+DT = discs.DT_6_DAYS
+
+
+def rcrit_device(ctx, b, torch):
+    rc = torch.zeros_like(b.x)
+    genga.genga_rcrit(ctx, b, N1, N2, DT, rc)
+    b.rcrit = rc
+    return rc
+
+
+def setup(disc_list, torch):
+    st, off, mstar = discs.concat(disc_list)
+    ctx = genga.Context(0)
+    genga.genga_set_systems(ctx.handle, off, mstar)
+    b = genga.Bodies.from_numpy(st, device="cuda:0")
+    rcrit_device(ctx.handle, b, torch)
+    torch.cuda.synchronize()
+    return ctx, b, st, off
+
+
+def time_kicks(ctx, b, prec, reps, torch, stream):
+    """Average duration of one genga_kick (prep + kick kernel) over `reps` launches,
+    measured with HIP events on the launch stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            genga.genga_kick(ctx.handle, b, 0.0, prec, stream=stream)
+        e0.record(stream)
+        for _ in range(reps):
+            genga.genga_kick(ctx.handle, b, 0.0, prec, stream=stream)
+        e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def time_steps(ctx, b, prec, steps, warmup, n_sys, torch, stream):
+    """Run warmup then `steps` timed steps (energy every CADENCE steps); returns
+    (seconds, energy records, initial energy)."""
+    with torch.cuda.stream(stream):
+        if warmup > 0:
+            genga.genga_step(ctx.handle, b, DT, warmup, prec, stream=stream)
+        e_init = torch.zeros(4 * n_sys, dtype=torch.float64, device="cuda:0")
+        genga.genga_energy(ctx.handle, b, e_init, stream=stream)
+        nrec = max(steps // CADENCE, 0)
+        e_rec = torch.zeros(max(nrec, 1) * 4 * n_sys, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        genga.genga_step(ctx.handle, b, DT, steps, prec, CADENCE, e_rec, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    status = genga.genga_poll_status(ctx.handle)
+    return t1 - t0, e_rec.cpu().numpy().reshape(-1, n_sys, 4)[:nrec], e_init.cpu().numpy().reshape(n_sys, 4), status
+
+
+def drift_stats(e_init, e_rec):
+    E0 = e_init[:, 0]
+    L0 = np.linalg.norm(e_init[:, 1:], axis=1)
+    if len(e_rec) == 0:
+        return {"max_abs_dE_over_E": None, "max_abs_dL_over_L": None}
+    dE = e_rec[:, :, 0] / E0[None, :] - 1.0
+    dL = np.linalg.norm(e_rec[:, :, 1:], axis=2) / L0[None, :] - 1.0
+    return {"max_abs_dE_over_E": float(np.max(np.abs(dE))), "final_dE_over_E": float(dE[-1].mean()),
+            "max_abs_dL_over_L": float(np.max(np.abs(dL))), "final_dL_over_L": float(dL[-1].mean()),
+            "records": int(len(e_rec)), "cadence": CADENCE}
+
+
+def kick_traffic(pairs):
+    """HBM bytes per kick launch from committed rocprofv3 counter runs, if they were taken
+    on the current kick source (else null)."""
+    path = os.path.join(ROOT, "profiles", "kick32_c3_traffic.json")
+    src = os.path.join(ROOT, "paper_2309_08217_amd", "csrc", "kick.hip")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("kick_hip_sha256") != sha:
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(st, n):
+    """The FP64 oracle's kick on the same disc, timed on the host cores over whole kicks
+    (about 10-30 s of CPU work), in the metric's unit."""
+    import oracle
+    rc = oracle.rcrit(st, 1.0, N1, N2, DT)
+    oracle.accel({k: v[:512] for k, v in st.items()}, rc[:512])  # load / warm the library
+    reps, t_total = 0, 0.0
+    while reps < 8 and (t_total < 10.0 or reps < 1):
+        t0 = time.perf_counter()
+        oracle.accel(st, rc)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    pairs = float(n) * (n - 1) * reps
+    return {"value": pairs / t_total / 1e9, "unit": "G pair-interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} full FP64 oracle kick(s) of the N={n} disc ({pairs:.3e} pair interactions, "
+                      f"{t_total:.1f} s); the oracle's drift is O(N) and not included"}
+
+
+def batched(torch, stream, steps=10, warmup=2):
+    """64 discs, N uniform in [2000, 8000]: one launch per kernel for all discs vs a loop of
+    64 single-disc contexts."""
+    ds = discs.batch_c4()
+    ctx, b, st, off = setup(ds, torch)
+    genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
+    t, e_rec, e_init, status = time_steps(ctx, b, genga.GENGA_KICK_FP32, steps, warmup, len(ds), torch, stream)
+    pairs = float(sum(d.n * (d.n - 1) for d in ds))
+    # the same discs stepped one context after another (64 launches per kernel per step)
+    singles = []
+    for d in ds:
+        c1, b1, _, _ = setup([d], torch)
+        genga.genga_set_kick_waves(c1.handle, genga.GENGA_KICK_FP32, genga.genga_get_kick_waves(ctx.handle, genga.GENGA_KICK_FP32))
+        singles.append((c1, b1))
+    with torch.cuda.stream(stream):
+        for c1, b1 in singles:
+            genga.genga_step(c1.handle, b1, DT, warmup, genga.GENGA_KICK_FP32, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            for c1, b1 in singles:
+                genga.genga_step(c1.handle, b1, DT, 1, genga.GENGA_KICK_FP32, stream=stream)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    for c1, _ in singles:
+        c1.close()
+    ctx.close()
+    return {"workload": "64 discs, N uniform in [2000, 8000] (seeds 1000+s), 2.5 Earth masses each",
+            "n_total": int(off[-1]), "steps": steps, "steps_per_s": steps / t,
+            "pair_interactions_per_s_G": pairs * steps / t / 1e9,
+            "loop_of_single_disc_launches_steps_per_s": steps / t_loop,
+            "speedup_vs_loop": t_loop / t, "status": status, **drift_stats(e_init, e_rec)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--kick-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the kick of one disc "
+              "fits one MI355X, and sharding across GPUs is not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP GPU", file=sys.stderr)
+        sys.exit(2)
+    genga.load_library()
+    stream = torch.cuda.Stream()
+    d = discs.disc_c3()
+    n = d.n
+    pairs = float(n) * (n - 1)
+    result = {}
+    for name, prec in (("fp32", genga.GENGA_KICK_FP32), ("fp64", genga.GENGA_KICK_FP64)):
+        ctx, b, st, _ = setup([d], torch)
+        genga.genga_autotune(ctx.handle, b, prec)
+        kick_ms = time_kicks(ctx, b, prec, args.kick_reps, torch, stream)
+        t, e_rec, e_init, status = time_steps(ctx, b, prec, args.steps, args.warmup, 1, torch, stream)
+        result[name] = {"step_seconds": t, "ms_per_step": 1e3 * t / args.steps,
+                        "value": pairs * args.steps / t / 1e9,
+                        "kick_ms": kick_ms, "kick_G_pairs_per_s": pairs / (kick_ms * 1e-3) / 1e9,
+                        "kick_tflops": FLOP_PER_PAIR * pairs / (kick_ms * 1e-3) / 1e12,
+                        "waves": genga.genga_get_kick_waves(ctx.handle, prec), "status": status,
+                        **drift_stats(e_init, e_rec)}
+        ctx.close()
+    f32, f64 = result["fp32"], result["fp64"]
+    out = {
+        "metric": "G pair-interactions/s of the FP32-pair-arithmetic kick step at N=40000 (full step: kick, "
+                  "encounter list, drift, close-encounter step, energy every 10 steps)",
+        "value": f32["value"],
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single disc N=40000, 5 Earth masses, 0.5-4 au, Sigma~a^-1.5, e~R(0.01), "
+                               "i~R(0.005), r_crit = 3 R_H, dt = 6 d, seed 3",
+                   "n": n, "dt_days": 6.0, "energy_cadence": CADENCE, "kick_waves": f32["waves"]},
+        "roofline": {"bound": "alu", "kernel": "kick32_kernel",
+                     "achieved": f32["kick_tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": f32["kick_tflops"] / PEAK_FP32_TFLOPS,
+                     "frac_of_unpacked_fp32_peak": f32["kick_tflops"] / PEAK_FP32_NONPACKED,
+                     "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs,
+                     "launch_ms": f32["kick_ms"], "traffic": kick_traffic(pairs)},
+        "fp32_kick": {"G_pair_interactions_per_s": f32["kick_G_pairs_per_s"], "kick_ms": f32["kick_ms"]},
+        "fp64": {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
+                 "G_pair_interactions_per_s_kick": f64["kick_G_pairs_per_s"], "kick_ms": f64["kick_ms"],
+                 "roofline": {"bound": "alu", "achieved": f64["kick_tflops"], "peak": PEAK_FP64_TFLOPS,
+                              "unit": "TFLOP/s", "frac": f64["kick_tflops"] / PEAK_FP64_TFLOPS},
+                 "waves": f64["waves"]},
+        "fp32_over_fp64": {"kick": f64["kick_ms"] / f32["kick_ms"], "step": f64["ms_per_step"] / f32["ms_per_step"]},
+        "energy": {"fp32": {k: v for k, v in f32.items() if "dE" in k or "dL" in k or k in ("records", "cadence")},
+                   "fp64": {k: v for k, v in f64.items() if "dE" in k or "dL" in k or k in ("records", "cadence")}},
+        "status": {"fp32": f32["status"], "fp64": f64["status"]},
+    }
+    if not args.no_batched:
+        out["batched"] = batched(torch, stream)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d.state(), n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,6 +51,8 @@ def lib() -> ctypes.CDLL:
             L = ctypes.CDLL(_LIB)
         d = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_num_threads.argtypes = []
         L.oracle_changeover.restype = ctypes.c_double
         L.oracle_changeover.argtypes = [ctypes.c_double]
         L.oracle_rcrit.argtypes = [i64] + [d] * 7 + [ctypes.c_double] * 4 + [d]
@@ -90,6 +92,11 @@ def _f64(a) -> np.ndarray:
 # Functions on one system (the Sun plus n bodies).  State dicts hold float64 arrays
 # x, y, z, vx, vy, vz, m (heliocentric positions, barycentric velocities).
 # -------------------------------------------------------------------------------------------
+
+def num_threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(lib().oracle_num_threads())
+
 
 def changeover(y: float) -> float:
     """K(y) of the changeover (Sect. 1, the Chambers 1999 function the paper cites)."""

@@ -32,9 +32,16 @@
  *    the kick used.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Number of OpenMP threads the parallel loops use (reported with CPU timings). */
+int oracle_num_threads(void)
+{
+    return omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------------------
  * Changeover function (Sect. 1; the Chambers 1999 form cited there).

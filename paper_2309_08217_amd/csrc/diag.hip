@@ -115,21 +115,34 @@ __global__ __launch_bounds__(64 * EW) void energy_kernel(
     }
 }
 
-// One thread per system: fixed-order sum of the system's item partials.
-__global__ void energy_finish_kernel(int n_sys, const int32_t *item_first, const double *mstar,
-                                     const double *partial, double *out)
+// One workgroup per system: each thread sums a strided subset of the system's item partials
+// in order, then a fixed tree in LDS combines the threads.
+constexpr int EF_THREADS = 256;
+
+__global__ __launch_bounds__(EF_THREADS) void energy_finish_kernel(const int32_t *item_first,
+                                                                   const double *mstar,
+                                                                   const double *partial, double *out)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_sys) return;
+    __shared__ double red[NPART][EF_THREADS];
+    const int s = blockIdx.x;
     double t[NPART];
     for (int k = 0; k < NPART; ++k) t[k] = 0.0;
-    for (int it = item_first[s]; it < item_first[s + 1]; ++it)
+    for (int it = item_first[s] + threadIdx.x; it < item_first[s + 1]; it += EF_THREADS)
         for (int k = 0; k < NPART; ++k) t[k] += partial[(size_t)it * NPART + k];
-    const double p2 = t[3] * t[3] + t[4] * t[4] + t[5] * t[5];
-    out[4 * s + 0] = t[1] + p2 / (2.0 * mstar[s]) + t[2] - t[0];
-    out[4 * s + 1] = t[6];
-    out[4 * s + 2] = t[7];
-    out[4 * s + 3] = t[8];
+    for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] = t[k];
+    __syncthreads();
+    for (int o = EF_THREADS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double p2 = red[3][0] * red[3][0] + red[4][0] * red[4][0] + red[5][0] * red[5][0];
+        out[4 * s + 0] = red[1][0] + p2 / (2.0 * mstar[s]) + red[2][0] - red[0][0];
+        out[4 * s + 1] = red[6][0];
+        out[4 * s + 2] = red[7][0];
+        out[4 * s + 3] = red[8][0];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -203,8 +216,7 @@ hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items
     if (n_items > 0)
         energy_kernel<<<n_items, 64 * EW, 0, stream>>>(items, n_items, L.sys_off, L.mstar, x, y, z, vx,
                                                        vy, vz, m, ax, ay, az, vshift, partial);
-    energy_finish_kernel<<<(L.n_sys + 63) / 64, 64, 0, stream>>>(L.n_sys, item_first, L.mstar, partial,
-                                                                 out);
+    energy_finish_kernel<<<L.n_sys, EF_THREADS, 0, stream>>>(item_first, L.mstar, partial, out);
     return hipGetLastError();
 }
 

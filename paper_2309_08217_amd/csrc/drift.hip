@@ -36,27 +36,24 @@ __device__ __forceinline__ double changeover_k(double y)
 }
 
 // ------------------------------------------------------------------------------------------
-// Sun drift: one workgroup per system, fixed-order reduction of the momentum, then the shift.
+// Sun drift in two launches over chunks of one system: partial momenta per chunk (fixed-order
+// block reduction), then every chunk adds its system's partials in chunk order and shifts
+// its positions.  Deterministic.
 // ------------------------------------------------------------------------------------------
-constexpr int SUN_THREADS = 1024;
+constexpr int SUN_THREADS = 256;
 
-__global__ __launch_bounds__(SUN_THREADS) void sun_drift_kernel(const int32_t *sys_off,
-                                                                const double *mstar, double *x,
-                                                                double *y, double *z,
-                                                                const double *vx, const double *vy,
-                                                                const double *vz, const double *m,
-                                                                double tau)
+__global__ __launch_bounds__(SUN_THREADS) void momentum_kernel(const Chunk *chunks, const double *m,
+                                                               const double *vx, const double *vy,
+                                                               const double *vz, double *mom_part)
 {
     __shared__ double red[3][SUN_THREADS / 64];
-    const int s = blockIdx.x;
-    const int b = sys_off[s], e = sys_off[s + 1];
+    const Chunk c = chunks[blockIdx.x];
     double px = 0.0, py = 0.0, pz = 0.0;
-    for (int i = b + threadIdx.x; i < e; i += SUN_THREADS) {
+    for (int i = c.b + threadIdx.x; i < c.e; i += SUN_THREADS) {
         px += m[i] * vx[i];
         py += m[i] * vy[i];
         pz += m[i] * vz[i];
     }
-    // wave reduction (fixed butterfly order), then across waves in LDS
     for (int o = 32; o > 0; o >>= 1) {
         px += __shfl_xor(px, o, 64);
         py += __shfl_xor(py, o, 64);
@@ -69,15 +66,30 @@ __global__ __launch_bounds__(SUN_THREADS) void sun_drift_kernel(const int32_t *s
         red[2][wave] = pz;
     }
     __syncthreads();
-    double Px = 0.0, Py = 0.0, Pz = 0.0;
-    for (int w = 0; w < SUN_THREADS / 64; ++w) {
-        Px += red[0][w];
-        Py += red[1][w];
-        Pz += red[2][w];
+    if (threadIdx.x == 0) {
+        double P[3] = {0.0, 0.0, 0.0};
+        for (int w = 0; w < SUN_THREADS / 64; ++w)
+            for (int q = 0; q < 3; ++q) P[q] += red[q][w];
+        for (int q = 0; q < 3; ++q) mom_part[3 * (size_t)blockIdx.x + q] = P[q];
     }
-    const double f = tau / mstar[s];
+}
+
+__global__ __launch_bounds__(SUN_THREADS) void sun_shift_kernel(const Chunk *chunks,
+                                                                const int32_t *chunk_first,
+                                                                const double *mstar,
+                                                                const double *mom_part, double tau,
+                                                                double *x, double *y, double *z)
+{
+    const Chunk c = chunks[blockIdx.x];
+    double Px = 0.0, Py = 0.0, Pz = 0.0;
+    for (int k = chunk_first[c.sys]; k < chunk_first[c.sys + 1]; ++k) {
+        Px += mom_part[3 * (size_t)k];
+        Py += mom_part[3 * (size_t)k + 1];
+        Pz += mom_part[3 * (size_t)k + 2];
+    }
+    const double f = tau / mstar[c.sys];
     const double sx = f * Px, sy = f * Py, sz = f * Pz;
-    for (int i = b + threadIdx.x; i < e; i += SUN_THREADS) {
+    for (int i = c.b + threadIdx.x; i < c.e; i += SUN_THREADS) {
         x[i] += sx;
         y[i] += sy;
         z[i] += sz;
@@ -362,120 +374,135 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
 }
 
 // ------------------------------------------------------------------------------------------
-// Bulirsch-Stoer over dt for one group per thread.
+// Bulirsch-Stoer over dt: one wavefront per group, one member per lane.  Each lane keeps its
+// member's state, midpoint sub-step values and extrapolation tableau in registers; the
+// members' positions are exchanged through LDS for the pair forces; step decisions use
+// wave-wide maxima, so the control flow is uniform.  Same method as the oracle: modified
+// midpoint with n_k = 2k sub-steps (k = 1..8), polynomial extrapolation in h^2, accept when
+// the last two diagonal entries agree to tol on the group's position / velocity scales,
+// otherwise halve the step; after an accepted step the next one is twice as long.
 // ------------------------------------------------------------------------------------------
-struct GroupView {
-    int nb;
-    const int32_t *idx;
-    const double *m;
-    const double *rc;
-    double mstar;
+constexpr int BS_LANES = 64;
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct LaneGroup {
+    int a, nb;
+    bool act;
+    double m, rc, mstar;
+    double (*sp)[BS_LANES]; // [3][64] positions of the members
+    const double *sm, *src; // [64] masses and critical radii of the members
 };
 
-// D = dY/dt for the group state Y (6 doubles per member: x y z vx vy vz)
-__device__ void group_deriv(const GroupView &g, const double *Y, double *D)
+// dY/dt for this lane's member: Kepler term about the Sun plus the (1 - K) share of the
+// Newtonian forces from the other members.  Every lane of the wave must call it.
+__device__ void lane_deriv(const LaneGroup &g, const double y[6], double d[6])
 {
-    for (int a = 0; a < g.nb; ++a) {
-        const double *ya = Y + 6 * a;
-        const double r2 = ya[0] * ya[0] + ya[1] * ya[1] + ya[2] * ya[2];
-        const double r = sqrt(r2);
-        const double s = -g.mstar / (r2 * r);
-        double ax = s * ya[0], ay = s * ya[1], az = s * ya[2];
-        const double rca = g.rc[g.idx[a]];
-        for (int b = 0; b < g.nb; ++b) {
-            if (b == a) continue;
-            const double *yb = Y + 6 * b;
-            const double dx = yb[0] - ya[0], dy = yb[1] - ya[1], dz = yb[2] - ya[2];
-            const double q = sep2_rn(dx, dy, dz);
-            const double rcij = fmax(rca, g.rc[g.idx[b]]);
-            double w = 0.0;
-            if (q < sq_rn(rcij)) {
-                const double rr = sqrt(q);
-                w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
-            }
-            if (w == 0.0) continue;
-            const double rr = sqrt(q);
-            const double t = g.m[g.idx[b]] * w / (q * rr);
-            ax += t * dx;
-            ay += t * dy;
-            az += t * dz;
-        }
-        D[6 * a + 0] = ya[3];
-        D[6 * a + 1] = ya[4];
-        D[6 * a + 2] = ya[5];
-        D[6 * a + 3] = ax;
-        D[6 * a + 4] = ay;
-        D[6 * a + 5] = az;
+    g.sp[0][g.a] = y[0];
+    g.sp[1][g.a] = y[1];
+    g.sp[2][g.a] = y[2];
+    __syncthreads();
+    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const double r = sqrt(r2);
+    const double s = -g.mstar / (r2 * r);
+    double ax = s * y[0], ay = s * y[1], az = s * y[2];
+    for (int b = 0; b < g.nb; ++b) {
+        if (b == g.a) continue;
+        const double dx = g.sp[0][b] - y[0], dy = g.sp[1][b] - y[1], dz = g.sp[2][b] - y[2];
+        const double q = sep2_rn(dx, dy, dz);
+        const double rcij = fmax(g.rc, g.src[b]);
+        if (!(q < sq_rn(rcij))) continue;
+        const double rr = sqrt(q);
+        const double w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
+        if (w == 0.0) continue;
+        const double t = g.sm[b] * w / (q * rr);
+        ax += t * dx;
+        ay += t * dy;
+        az += t * dz;
+    }
+    __syncthreads();
+    if (g.act) {
+        d[0] = y[3];
+        d[1] = y[4];
+        d[2] = y[5];
+        d[3] = ax;
+        d[4] = ay;
+        d[5] = az;
+    } else {
+        for (int q = 0; q < 6; ++q) d[q] = 0.0;
     }
 }
 
-// Gragg's modified midpoint rule: Y0 over H in nsub sub-steps -> out
-__device__ void midpoint(const GroupView &g, const double *Y0, double H, int nsub, double *out,
-                         double *zm, double *zc, double *dd)
+__device__ void lane_midpoint(const LaneGroup &g, const double y0[6], double H, int nsub, double out[6])
 {
-    const int dim = 6 * g.nb;
     const double h = H / nsub;
-    group_deriv(g, Y0, dd);
-    for (int q = 0; q < dim; ++q) {
-        zm[q] = Y0[q];
-        zc[q] = Y0[q] + h * dd[q];
+    double zm[6], zc[6], dd[6];
+    lane_deriv(g, y0, dd);
+    for (int q = 0; q < 6; ++q) {
+        zm[q] = y0[q];
+        zc[q] = y0[q] + h * dd[q];
     }
     for (int k = 1; k < nsub; ++k) {
-        group_deriv(g, zc, dd);
-        for (int q = 0; q < dim; ++q) {
+        lane_deriv(g, zc, dd);
+        for (int q = 0; q < 6; ++q) {
             const double t = zm[q] + 2.0 * h * dd[q];
             zm[q] = zc[q];
             zc[q] = t;
         }
     }
-    group_deriv(g, zc, dd);
-    for (int q = 0; q < dim; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
+    lane_deriv(g, zc, dd);
+    for (int q = 0; q < 6; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
-// Workspace per group: Y, tab[BS_KMAX], est, zm, zc, dd  => (BS_KMAX + 5) * dim doubles
-__device__ bool bs_integrate(const GroupView &g, double *Y, double *work, double dt, double tol)
+// Integrate this lane's member over dt; returns false (uniformly) if the step had to be
+// halved more than 60 times.
+__device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
 {
-    const int dim = 6 * g.nb;
-    double *tab = work;                       // BS_KMAX rows of dim
-    double *est = tab + (size_t)BS_KMAX * dim; // newest midpoint estimate
-    double *zm = est + dim, *zc = zm + dim, *dd = zc + dim;
     double t = 0.0, H = dt;
     int halvings = 0;
     while (t < dt) {
         if (H > dt - t) H = dt - t;
-        double sr = 0.0, sv = 0.0;
-        for (int a = 0; a < g.nb; ++a) {
-            const double *ya = Y + 6 * a;
-            sr = fmax(sr, sqrt(ya[0] * ya[0] + ya[1] * ya[1] + ya[2] * ya[2]));
-            sv = fmax(sv, sqrt(ya[3] * ya[3] + ya[4] * ya[4] + ya[5] * ya[5]));
-        }
-        int done = -1;
-        for (int k = 0; k < BS_KMAX && done < 0; ++k) {
-            midpoint(g, Y, H, 2 * (k + 1), est, zm, zc, dd);
-            // Neville update of the row: tab[l] <- T(k, l), in place
+        const double sr = wave_max(g.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
+        const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        double T[BS_KMAX][6];
+        bool accepted = false;
+#pragma unroll
+        for (int k = 0; k < BS_KMAX; ++k) {
+            double est[6];
+            lane_midpoint(g, Y, H, 2 * (k + 1), est);
             double err = 0.0;
-            for (int q = 0; q < dim; ++q) {
-                double prev = tab[q];           // T(k-1, 0)
-                double cur = est[q];            // T(k, 0)
-                tab[q] = cur;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                double prev = T[0][q]; // T(k-1, 0)
+                double cur = est[q];   // T(k, 0)
+                T[0][q] = cur;
                 double last = cur;
+#pragma unroll
                 for (int l = 1; l <= k; ++l) {
                     const double ratio = (double)(k + 1) / (double)(k + 1 - l);
                     const double nxt = cur + (cur - prev) / (ratio * ratio - 1.0);
-                    prev = tab[(size_t)l * dim + q]; // T(k-1, l)
+                    prev = T[l][q];
                     last = cur;
                     cur = nxt;
-                    tab[(size_t)l * dim + q] = cur; // T(k, l)
+                    T[l][q] = cur;
                 }
-                if (k > 0) {
-                    const double sc = ((q % 6) < 3) ? sr : sv;
-                    err = fmax(err, fabs(cur - last) / sc);
+                if (k > 0) err = fmax(err, fabs(cur - last) / (q < 3 ? sr : sv));
+            }
+            if (k > 0) {
+                err = wave_max(g.act ? err : 0.0);
+                if (err <= tol) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) Y[q] = T[k][q];
+                    accepted = true;
+                    break;
                 }
             }
-            if (k > 0 && err <= tol) done = k;
         }
-        if (done >= 0) {
-            for (int q = 0; q < dim; ++q) Y[q] = tab[(size_t)done * dim + q];
+        if (accepted) {
             t += H;
             H = 2.0 * H;
         } else {
@@ -486,56 +513,65 @@ __device__ bool bs_integrate(const GroupView &g, double *Y, double *work, double
     return true;
 }
 
-__global__ __launch_bounds__(64) void ce_bs_kernel(const int32_t *sys_of, const double *mstar,
-                                                   const double *x, const double *y,
-                                                   const double *z, const double *vx,
-                                                   const double *vy, const double *vz,
-                                                   const double *m, const double *rc, double dt,
-                                                   const int32_t *members,
-                                                   const int32_t *group_start,
-                                                   const int32_t *n_groups, double *bs_out,
-                                                   double *bs_work, int32_t *flags)
+__global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, const double *mstar,
+                                                         const double *x, const double *y,
+                                                         const double *z, const double *vx,
+                                                         const double *vy, const double *vz,
+                                                         const double *m, const double *rc, double dt,
+                                                         const int32_t *members,
+                                                         const int32_t *group_start,
+                                                         const int32_t *n_groups, double *bs_out,
+                                                         int32_t *flags)
 {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sp[3][BS_LANES];
+    __shared__ double sm[BS_LANES], src[BS_LANES];
+    const int g = blockIdx.x;
     if (g >= *n_groups) return;
-    const int k0 = group_start[g], k1 = group_start[g + 1];
-    const int nb = k1 - k0;
-    const int32_t *idx = members + k0;
-    double *Y = bs_out + 6 * (size_t)k0;
-    for (int a = 0; a < nb; ++a) {
-        const int b = idx[a];
-        Y[6 * a + 0] = x[b];
-        Y[6 * a + 1] = y[b];
-        Y[6 * a + 2] = z[b];
-        Y[6 * a + 3] = vx[b];
-        Y[6 * a + 4] = vy[b];
-        Y[6 * a + 5] = vz[b];
-    }
-    if (nb > CE_MAX_GROUP) {
-        // too large for this step: Kepler-drift the members instead and flag it
-        atomicOr(flags, FLAG_CAPACITY);
-        const double ms = mstar[sys_of[idx[0]]];
-        for (int a = 0; a < nb; ++a) {
-            double *ya = Y + 6 * a;
-            if (!kepler_universal(ya[0], ya[1], ya[2], ya[3], ya[4], ya[5], ms, dt))
-                atomicOr(flags, FLAG_NOCONVERGE);
+    const int k0 = group_start[g], nb = group_start[g + 1] - k0;
+    const int a = threadIdx.x;
+    const double ms = mstar[sys_of[members[k0]]];
+    if (nb > BS_LANES) {
+        // larger than one wave: Kepler-drift the members instead and flag it
+        if (a == 0) atomicOr(flags, FLAG_CAPACITY);
+        for (int k = a; k < nb; k += BS_LANES) {
+            const int b = members[k0 + k];
+            double px = x[b], py = y[b], pz = z[b], ux = vx[b], uy = vy[b], uz = vz[b];
+            if (!kepler_universal(px, py, pz, ux, uy, uz, ms, dt)) atomicOr(flags, FLAG_NOCONVERGE);
+            double *o = bs_out + 6 * (size_t)(k0 + k);
+            o[0] = px;
+            o[1] = py;
+            o[2] = pz;
+            o[3] = ux;
+            o[4] = uy;
+            o[5] = uz;
         }
         return;
     }
-    GroupView gv{nb, idx, m, rc, mstar[sys_of[idx[0]]]};
-    double *work = bs_work + (size_t)(BS_KMAX + 5) * 6 * (size_t)k0;
-    if (!bs_integrate(gv, Y, work, dt, 1e-12)) atomicOr(flags, FLAG_NOCONVERGE);
+    const bool act = a < nb;
+    const int b = members[k0 + (act ? a : 0)];
+    sm[a] = act ? m[b] : 0.0;
+    src[a] = act ? rc[b] : 0.0;
+    __syncthreads();
+    LaneGroup lg{a, nb, act, m[b], rc[b], ms, sp, sm, src};
+    double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
+    const bool ok = lane_bs(lg, Y, dt, 1e-12);
+    if (act) {
+        double *o = bs_out + 6 * (size_t)(k0 + a);
+        for (int q = 0; q < 6; ++q) o[q] = Y[q];
+        if (!ok && a == 0) atomicOr(flags, FLAG_NOCONVERGE);
+    }
 }
 
 } // namespace
 
 hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
                             const double *vy, const double *vz, const double *m, double tau,
-                            hipStream_t stream)
+                            double *mom_part, hipStream_t stream)
 {
-    if (L.n_sys == 0) return hipSuccess;
-    sun_drift_kernel<<<L.n_sys, SUN_THREADS, 0, stream>>>(L.sys_off, L.mstar, x, y, z, vx, vy, vz, m,
-                                                         tau);
+    if (L.n_chunks == 0) return hipSuccess;
+    momentum_kernel<<<L.n_chunks, SUN_THREADS, 0, stream>>>(L.chunks, m, vx, vy, vz, mom_part);
+    sun_shift_kernel<<<L.n_chunks, SUN_THREADS, 0, stream>>>(L.chunks, L.chunk_first, L.mstar, mom_part,
+                                                             tau, x, y, z);
     return hipGetLastError();
 }
 
@@ -554,12 +590,12 @@ hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const
                         const double *vx, const double *vy, const double *vz, const double *m,
                         const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, double *bs_out,
-                        double *bs_work, int32_t *flags, hipStream_t stream)
+                        int32_t *flags, hipStream_t stream)
 {
-    // at most CE_MAX_MEMBERS / 2 groups (every group has >= 2 members)
-    const int grid = (CE_MAX_MEMBERS / 2 + 63) / 64;
-    ce_bs_kernel<<<grid, 64, 0, stream>>>(L.sys_of, L.mstar, x, y, z, vx, vy, vz, m, rc, dt, members,
-                                          group_start, n_groups, bs_out, bs_work, flags);
+    // one wave per group; at most CE_MAX_MEMBERS / 2 groups (every group has >= 2 members)
+    ce_bs_kernel<<<CE_MAX_MEMBERS / 2, BS_LANES, 0, stream>>>(L.sys_of, L.mstar, x, y, z, vx, vy, vz, m, rc,
+                                                              dt, members, group_start, n_groups, bs_out,
+                                                              flags);
     return hipGetLastError();
 }
 

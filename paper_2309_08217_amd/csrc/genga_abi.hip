@@ -65,7 +65,8 @@ struct genga_ctx {
     int grid[2] = {0, 0};       // 0: one workgroup per item
     // scratch
     uint8_t *jrec = nullptr;    // 32 B per body
-    double *rc2max = nullptr;
+    double *rc2_part = nullptr;   // [n_chunks]
+    double *mom_part = nullptr;   // [n_chunks][3]
     double *acc = nullptr;      // a_i of the last kick: [3][n_total]
     int32_t *pairs = nullptr;
     int32_t *pair_count = nullptr;
@@ -74,7 +75,7 @@ struct genga_ctx {
     int32_t *flags = nullptr;
     int32_t *lab = nullptr, *mark = nullptr, *members = nullptr, *group_start = nullptr;
     int32_t *n_groups = nullptr, *member_slot = nullptr;
-    double *bs_out = nullptr, *bs_work = nullptr;
+    double *bs_out = nullptr;
     double *epartial = nullptr;
     // graph
     hipGraph_t graph = nullptr;
@@ -89,7 +90,10 @@ struct genga_ctx {
         dfree(eitems);
         dfree(item_first);
         dfree(jrec);
-        dfree(rc2max);
+        dfree(rc2_part);
+        dfree(mom_part);
+        dfree(L.chunks);
+        dfree(L.chunk_first);
         dfree(acc);
         dfree(pairs);
         dfree(pair_count);
@@ -102,13 +106,12 @@ struct genga_ctx {
         dfree(n_groups);
         dfree(member_slot);
         dfree(bs_out);
-        dfree(bs_work);
         dfree(epartial);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         graph_exec = nullptr;
         graph = nullptr;
-        L.n_sys = L.n_total = 0;
+        L.n_sys = L.n_total = L.n_chunks = 0;
         n_items = 0;
     }
 };
@@ -145,7 +148,7 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
     const int fp32 = prec == GENGA_KICK_FP32;
-    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2max, ctx->pair_count, s));
+    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->pair_count, s));
     KickArgs a;
     a.items = ctx->items;
     a.n_items = ctx->n_items;
@@ -159,7 +162,8 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     a.m = b->m;
     a.rc = b->rcrit;
     a.jrec = ctx->jrec;
-    a.rc2max = ctx->rc2max;
+    a.rc2_part = ctx->rc2_part;
+    a.chunk_first = L.chunk_first;
     a.ax = ax;
     a.ay = ay;
     a.az = az;
@@ -177,14 +181,14 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
 {
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
-    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, s));
+    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
                              ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
     HIP_TRY(launch_ce_bs(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
-                         ctx->group_start, ctx->n_groups, ctx->bs_out, ctx->bs_work, ctx->flags, s));
+                         ctx->group_start, ctx->n_groups, ctx->bs_out, ctx->flags, s));
     HIP_TRY(launch_kepler(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, dt, ctx->member_slot, ctx->bs_out,
                           ctx->flags, s));
-    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, s));
+    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     return GENGA_OK;
 }
 
@@ -280,6 +284,14 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
         for (int i0 = b; i0 < e; i0 += 64) it.push_back(WorkItem{s, i0, std::min(64, e - i0), e - b});
     }
     first[n_sys] = (int32_t)it.size();
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> cfirst(n_sys + 1, 0);
+    for (int s = 0; s < n_sys; ++s) {
+        cfirst[s] = (int32_t)chunks.size();
+        for (int b = sys_off_host[s]; b < sys_off_host[s + 1]; b += CHUNK)
+            chunks.push_back(Chunk{s, b, std::min(b + CHUNK, sys_off_host[s + 1]), 0});
+    }
+    cfirst[n_sys] = (int32_t)chunks.size();
     std::vector<WorkItem> kit = it;
     std::stable_sort(kit.begin(), kit.end(), [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
     ctx->n_items = (int32_t)it.size();
@@ -301,7 +313,10 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->eitems, it.size()));
     HIP_TRY(dalloc(ctx->item_first, n_sys + 1));
     HIP_TRY(dalloc(ctx->jrec, nt * 32));
-    HIP_TRY(dalloc(ctx->rc2max, n_sys));
+    HIP_TRY(dalloc(ctx->L.chunks, chunks.size()));
+    HIP_TRY(dalloc(ctx->L.chunk_first, n_sys + 1));
+    HIP_TRY(dalloc(ctx->rc2_part, chunks.size()));
+    HIP_TRY(dalloc(ctx->mom_part, 3 * chunks.size()));
     HIP_TRY(dalloc(ctx->acc, 3 * nt));
     HIP_TRY(dalloc(ctx->pairs, 2 * (size_t)cap));
     HIP_TRY(dalloc(ctx->pair_count, 1));
@@ -314,7 +329,6 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->n_groups, 1));
     HIP_TRY(dalloc(ctx->member_slot, nt));
     HIP_TRY(dalloc(ctx->bs_out, 6 * (size_t)CE_MAX_MEMBERS));
-    HIP_TRY(dalloc(ctx->bs_work, (size_t)(BS_KMAX + 5) * 6 * CE_MAX_MEMBERS));
     HIP_TRY(dalloc(ctx->epartial, 9 * it.size()));
 
     HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -325,6 +339,9 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
         HIP_TRY(hipMemcpy(ctx->eitems, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(ctx->item_first, first.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (!chunks.empty())
+        HIP_TRY(hipMemcpy(ctx->L.chunks, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->L.chunk_first, cfirst.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(ctx->pair_count, 0, sizeof(int32_t)));
     HIP_TRY(hipMemset(ctx->flags, 0, sizeof(int32_t)));
     HIP_TRY(hipMemset(ctx->n_groups, 0, sizeof(int32_t)));
@@ -335,6 +352,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(hipDeviceSynchronize());
     ctx->L.n_sys = n_sys;
     ctx->L.n_total = n_total;
+    ctx->L.n_chunks = (int32_t)chunks.size();
     return GENGA_OK;
 }
 

@@ -38,12 +38,22 @@ constexpr int CE_MAX_MEMBERS = 8192;
 constexpr int CE_MAX_GROUP = 64;
 constexpr int BS_KMAX = 8;
 
+// A run of at most CHUNK consecutive bodies of one system: the unit of the O(N) kernels
+// (source records, momentum sums, Sun drift), so block reductions never mix systems.
+constexpr int CHUNK = 1024;
+struct Chunk {
+    int32_t sys, b, e, pad;
+};
+
 struct Layout {
     int32_t n_sys = 0;
     int32_t n_total = 0;
-    int32_t *sys_off = nullptr;  // device [n_sys + 1]
-    int32_t *sys_of = nullptr;   // device [n_total], system of each body
-    double *mstar = nullptr;     // device [n_sys]
+    int32_t n_chunks = 0;
+    int32_t *sys_off = nullptr;     // device [n_sys + 1]
+    int32_t *sys_of = nullptr;      // device [n_total], system of each body
+    double *mstar = nullptr;        // device [n_sys]
+    Chunk *chunks = nullptr;        // device [n_chunks], systems in order
+    int32_t *chunk_first = nullptr; // device [n_sys + 1]
 };
 
 struct KickArgs {
@@ -54,7 +64,8 @@ struct KickArgs {
     double *vx, *vy, *vz;         // updated when update_v != 0
     const double *m, *rc;
     const void *jrec;             // JRec32[] or JRec64[]
-    const double *rc2max;         // [n_sys] max r_crit^2 per system
+    const double *rc2_part;       // [n_chunks] max r_crit^2 per chunk
+    const int32_t *chunk_first;   // [n_sys + 1]
     double *ax, *ay, *az;         // a_i out (FP64), always written
     double tau;
     int32_t update_v;
@@ -66,7 +77,7 @@ struct KickArgs {
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
-                       const double *m, const double *rc, void *jrec, int fp32, double *rc2max,
+                       const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
                        int32_t *pair_count, hipStream_t stream);
 hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream);
 hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
@@ -74,7 +85,7 @@ hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const
                         double n1, double n2, double dt, double *rc, hipStream_t stream);
 hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
                             const double *vy, const double *vz, const double *m, double tau,
-                            hipStream_t stream);
+                            double *mom_part, hipStream_t stream);
 hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
                             int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
@@ -83,7 +94,7 @@ hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const
                         const double *vx, const double *vy, const double *vz, const double *m,
                         const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, double *bs_out,
-                        double *bs_work, int32_t *flags, hipStream_t stream);
+                        int32_t *flags, hipStream_t stream);
 hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                          double *vz, double dt, int32_t *member_slot, const double *bs_out,
                          int32_t *flags, hipStream_t stream);

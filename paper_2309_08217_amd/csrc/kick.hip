@@ -111,6 +111,14 @@ __device__ __forceinline__ bool close_pair(const KickArgs &a, double xj, double 
     return true;
 }
 
+// largest r_crit^2 of system s (wave-uniform loop over its chunks)
+__device__ __forceinline__ double system_rc2max(const KickArgs &a, int s)
+{
+    double mx = 0.0;
+    for (int k = a.chunk_first[s]; k < a.chunk_first[s + 1]; ++k) mx = fmax(mx, a.rc2_part[k]);
+    return mx;
+}
+
 struct Acc32 {
     float fx, fy, fz;
 };
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
         // candidate threshold: the system's largest r_crit^2 with a margin that covers the
         // FP32 rounding of r^2; never zero, so the self pair always takes the exact path
-        const float T = (float)(a.rc2max[w.sys] * 1.0001) + 1e-30f;
+        const float T = (float)(system_rc2max(a, w.sys) * 1.0001) + 1e-30f;
         const int chunk = (j1 - j0 + W - 1) / W;
         const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
         double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -251,7 +259,7 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
-        const double T = a.rc2max[w.sys] + 1e-300;
+        const double T = system_rc2max(a, w.sys) + 1e-300;
         const int chunk = (j1 - j0 + W - 1) / W;
         const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
         double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -294,50 +302,41 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
     }
 }
 
-// Source records and the per-system largest r_crit^2 (and a cleared pair counter).
+// Source records, the largest r_crit^2 of every chunk, and a cleared pair counter.
 template <bool F32>
-__global__ __launch_bounds__(256) void prep_kernel(int n_total, int body_blocks,
-                                                   const int32_t *sys_off, const double *x,
+__global__ __launch_bounds__(256) void prep_kernel(const Chunk *chunks, const double *x,
                                                    const double *y, const double *z,
                                                    const double *m, const double *rc, void *jrec,
-                                                   double *rc2max, int32_t *pair_count)
+                                                   double *rc2_part, int32_t *pair_count)
 {
-    if ((int)blockIdx.x < body_blocks) {
-        int i = blockIdx.x * blockDim.x + threadIdx.x;
-        if (i < n_total) {
-            if (F32) {
-                JRec32 r;
-                r.x = x[i];
-                r.y = y[i];
-                r.z = z[i];
-                r.m = (float)m[i];
-                r.pad = 0.f;
-                ((JRec32 *)jrec)[i] = r;
-            } else {
-                JRec64 r;
-                r.x = x[i];
-                r.y = y[i];
-                r.z = z[i];
-                r.m = m[i];
-                ((JRec64 *)jrec)[i] = r;
-            }
-        }
-        return;
-    }
-    const int s = blockIdx.x - body_blocks;
-    const int b = sys_off[s], e = sys_off[s + 1];
+    const Chunk c = chunks[blockIdx.x];
     double mx = 0.0;
-    for (int i = b + threadIdx.x; i < e; i += blockDim.x) mx = fmax(mx, rc[i] * rc[i]);
-    __shared__ double red[256];
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-        __syncthreads();
+    for (int i = c.b + threadIdx.x; i < c.e; i += 256) {
+        if (F32) {
+            JRec32 r;
+            r.x = x[i];
+            r.y = y[i];
+            r.z = z[i];
+            r.m = (float)m[i];
+            r.pad = 0.f;
+            ((JRec32 *)jrec)[i] = r;
+        } else {
+            JRec64 r;
+            r.x = x[i];
+            r.y = y[i];
+            r.z = z[i];
+            r.m = m[i];
+            ((JRec64 *)jrec)[i] = r;
+        }
+        mx = fmax(mx, rc[i] * rc[i]);
     }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        rc2max[s] = red[0];
-        if (s == 0) *pair_count = 0;
+        rc2_part[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        if (blockIdx.x == 0) *pair_count = 0;
     }
 }
 
@@ -364,17 +363,16 @@ __global__ __launch_bounds__(256) void rcrit_kernel(int n_total, const int32_t *
 } // namespace
 
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
-                       const double *m, const double *rc, void *jrec, int fp32, double *rc2max,
+                       const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
                        int32_t *pair_count, hipStream_t stream)
 {
-    const int body_blocks = (L.n_total + 255) / 256;
-    const int grid = body_blocks + L.n_sys;
+    if (L.n_chunks == 0) return hipSuccess;
     if (fp32)
-        prep_kernel<true><<<grid, 256, 0, stream>>>(L.n_total, body_blocks, L.sys_off, x, y, z, m, rc,
-                                                    jrec, rc2max, pair_count);
+        prep_kernel<true><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
+                                                          pair_count);
     else
-        prep_kernel<false><<<grid, 256, 0, stream>>>(L.n_total, body_blocks, L.sys_off, x, y, z, m,
-                                                     rc, jrec, rc2max, pair_count);
+        prep_kernel<false><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
+                                                           pair_count);
     return hipGetLastError();
 }
 
