@@ -151,7 +151,8 @@ def batched(torch, stream, steps=10, warmup=2):
     singles = []
     for d in ds:
         c1, b1, _, _ = setup([d], torch)
-        genga.genga_set_kick_waves(c1.handle, genga.GENGA_KICK_FP32, genga.genga_get_kick_waves(ctx.handle, genga.GENGA_KICK_FP32))
+        w, _ = genga.genga_get_kick_shape(ctx.handle, genga.GENGA_KICK_FP32)
+        genga.genga_set_kick_shape(c1.handle, genga.GENGA_KICK_FP32, w, 0)
         singles.append((c1, b1))
     with torch.cuda.stream(stream):
         for c1, b1 in singles:
@@ -159,9 +160,8 @@ def batched(torch, stream, steps=10, warmup=2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        for _ in range(steps):
-            for c1, b1 in singles:
-                genga.genga_step(c1.handle, b1, DT, 1, genga.GENGA_KICK_FP32, stream=stream)
+        for c1, b1 in singles:
+            genga.genga_step(c1.handle, b1, DT, steps, genga.GENGA_KICK_FP32, stream=stream)
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
     for c1, _ in singles:
@@ -182,6 +182,11 @@ def main():
     ap.add_argument("--kick-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-kick", type=int, default=0,
+                    help="profiling aid: run this many FP32 kicks of the N=40000 disc and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling aid: copy a 256 MiB buffer 4 times (a plain copy of known size, "
+                         "to scale HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the kick of one disc "
@@ -193,7 +198,25 @@ def main():
         sys.exit(2)
     genga.load_library()
     stream = torch.cuda.Stream()
+    if args.copy_calibration:
+        src = torch.ones(256 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 4}))
+        return
     d = discs.disc_c3()
+    if args.only_kick > 0:
+        ctx, b, st, _ = setup([d], torch)
+        genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
+        with torch.cuda.stream(stream):
+            for _ in range(args.only_kick):
+                genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32, stream=stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"kicks": args.only_kick, "shape": genga.genga_get_kick_shape(ctx.handle, genga.GENGA_KICK_FP32)}))
+        ctx.close()
+        return
     n = d.n
     pairs = float(n) * (n - 1)
     result = {}
@@ -206,7 +229,7 @@ def main():
                         "value": pairs * args.steps / t / 1e9,
                         "kick_ms": kick_ms, "kick_G_pairs_per_s": pairs / (kick_ms * 1e-3) / 1e9,
                         "kick_tflops": FLOP_PER_PAIR * pairs / (kick_ms * 1e-3) / 1e12,
-                        "waves": genga.genga_get_kick_waves(ctx.handle, prec), "status": status,
+                        "shape": genga.genga_get_kick_shape(ctx.handle, prec), "status": status,
                         **drift_stats(e_init, e_rec)}
         ctx.close()
     f32, f64 = result["fp32"], result["fp64"]
@@ -226,7 +249,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single disc N=40000, 5 Earth masses, 0.5-4 au, Sigma~a^-1.5, e~R(0.01), "
                                "i~R(0.005), r_crit = 3 R_H, dt = 6 d, seed 3",
-                   "n": n, "dt_days": 6.0, "energy_cadence": CADENCE, "kick_waves": f32["waves"]},
+                   "n": n, "dt_days": 6.0, "energy_cadence": CADENCE,
+                   "kick_waves_split": f32["shape"]},
         "roofline": {"bound": "alu", "kernel": "kick32_kernel",
                      "achieved": f32["kick_tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": f32["kick_tflops"] / PEAK_FP32_TFLOPS,
@@ -238,7 +262,7 @@ def main():
                  "G_pair_interactions_per_s_kick": f64["kick_G_pairs_per_s"], "kick_ms": f64["kick_ms"],
                  "roofline": {"bound": "alu", "achieved": f64["kick_tflops"], "peak": PEAK_FP64_TFLOPS,
                               "unit": "TFLOP/s", "frac": f64["kick_tflops"] / PEAK_FP64_TFLOPS},
-                 "waves": f64["waves"]},
+                 "kick_waves_split": f64["shape"]},
         "fp32_over_fp64": {"kick": f64["kick_ms"] / f32["kick_ms"], "step": f64["ms_per_step"] / f32["ms_per_step"]},
         "energy": {"fp32": {k: v for k, v in f32.items() if "dE" in k or "dL" in k or k in ("records", "cadence")},
                    "fp64": {k: v for k, v in f64.items() if "dE" in k or "dL" in k or k in ("records", "cadence")}},

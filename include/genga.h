@@ -140,13 +140,17 @@ int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, 
 /* Launch the captured graph `repeats` times on `stream`. */
 int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream);
 
-/* Time the kick kernel's launch shapes on the current layout and keep the fastest for
- * `prec` (synchronises the device; the bodies are read, velocities are restored). */
+/* Time the kick's launch shapes (waves per workgroup x source split) on the current layout
+ * and keep the fastest for `prec` (synchronises `stream`; computes accelerations only, the
+ * velocities are not changed). */
 int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream);
 
-/* Waves per workgroup of the kick for `prec` (4, 8 or 16); 0 resets to the default. */
-int genga_set_kick_waves(genga_ctx *ctx, int prec, int waves);
-int genga_get_kick_waves(genga_ctx *ctx, int prec);
+/* Launch shape of the kick for `prec`: `waves` per workgroup (4, 8 or 16; 0 = default) and
+ * `split`, the number of workgroups that share one block of 64 targets' sources (1..4;
+ * 0 = chosen from the layout; > 1 adds a small finishing kernel that sums the shares in a
+ * fixed order). */
+int genga_set_kick_shape(genga_ctx *ctx, int prec, int waves, int split);
+int genga_get_kick_shape(genga_ctx *ctx, int prec, int *waves, int *split);
 
 /* Synchronise the device, then return and clear the deferred device status:
  * GENGA_ERR_CAPACITY, GENGA_ERR_NONFINITE, GENGA_ERR_NOCONVERGE or GENGA_OK. */

@@ -34,8 +34,8 @@ GENGA_KICK_FP32 = 1
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_rcrit", "genga_accel",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
-    "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_waves",
-    "genga_get_kick_waves", "genga_poll_status", "genga_last_error",
+    "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
+    "genga_get_kick_shape", "genga_poll_status", "genga_last_error",
 )
 
 
@@ -77,8 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_graph_capture": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, vp],
         "genga_graph_launch": [vp, ctypes.c_int, vp],
         "genga_autotune": [vp, bp, ctypes.c_int, vp],
-        "genga_set_kick_waves": [vp, ctypes.c_int, ctypes.c_int],
-        "genga_get_kick_waves": [vp, ctypes.c_int],
+        "genga_set_kick_shape": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+        "genga_get_kick_shape": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
         "genga_poll_status": [vp],
     }
     for name, args in sig.items():
@@ -222,12 +222,15 @@ def genga_autotune(ctx: int, b: Bodies, prec: int, stream=None) -> None:
     _check(load_library().genga_autotune(ctx, ctypes.byref(cb), int(prec), _stream(stream)))
 
 
-def genga_set_kick_waves(ctx: int, prec: int, waves: int) -> None:
-    _check(load_library().genga_set_kick_waves(ctx, int(prec), int(waves)))
+def genga_set_kick_shape(ctx: int, prec: int, waves: int, split: int = 0) -> None:
+    _check(load_library().genga_set_kick_shape(ctx, int(prec), int(waves), int(split)))
 
 
-def genga_get_kick_waves(ctx: int, prec: int) -> int:
-    return _check(load_library().genga_get_kick_waves(ctx, int(prec)))
+def genga_get_kick_shape(ctx: int, prec: int):
+    """(waves per workgroup, source split) of the kick for `prec`."""
+    w, s = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().genga_get_kick_shape(ctx, int(prec), ctypes.byref(w), ctypes.byref(s)))
+    return w.value, s.value
 
 
 def genga_poll_status(ctx: int) -> int:

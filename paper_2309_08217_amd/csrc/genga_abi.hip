@@ -1,6 +1,7 @@
 // C ABI of the kick library: argument checks, the context (layout, scratch, launch plan,
 // deferred device status), the step sequence and HIP graph capture.  Host code.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -61,8 +62,10 @@ struct genga_ctx {
     int32_t n_items = 0;
     WorkItem *eitems = nullptr; // energy items, in system order
     int32_t *item_first = nullptr;
-    int waves[2] = {8, 8};      // [prec] waves per workgroup of the kick
-    int grid[2] = {0, 0};       // 0: one workgroup per item
+    int waves[2] = {8, 16};     // [prec] waves per workgroup of the kick
+    int grid[2] = {0, 0};       // 0: one workgroup per task
+    int split[2] = {1, 1};      // [prec] workgroups sharing an item's sources
+    double *kpart = nullptr;    // [KICK_MAX_SPLIT][3][n_total]
     // scratch
     uint8_t *jrec = nullptr;    // 32 B per body
     double *rc2_part = nullptr;   // [n_chunks]
@@ -107,6 +110,7 @@ struct genga_ctx {
         dfree(member_slot);
         dfree(bs_out);
         dfree(epartial);
+        dfree(kpart);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         graph_exec = nullptr;
@@ -134,6 +138,24 @@ int check_bodies(const genga_ctx *ctx, const genga_bodies *b, bool need_v, bool 
     if (need_v && (!b->vx || !b->vy || !b->vz)) return fail(GENGA_ERR_ARG, "null velocity array");
     if (need_rc && !b->rcrit) return fail(GENGA_ERR_ARG, "null rcrit array");
     return GENGA_OK;
+}
+
+// Source split that best fills the chip: the kick's workgroups run about one per CU at a
+// time, so pick the split whose number of workgroups wastes the least of the last round.
+int default_split(const genga_ctx *ctx)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int sp = 1; sp <= KICK_MAX_SPLIT; ++sp) {
+        const double tasks = (double)ctx->n_items * sp;
+        const double rounds = std::ceil(tasks / ctx->n_cu);
+        const double eff = tasks / (rounds * ctx->n_cu);
+        if (eff > best_eff + 0.02) {
+            best_eff = eff;
+            best = sp;
+        }
+    }
+    return best;
 }
 
 int check_prec(int prec)
@@ -173,6 +195,9 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     a.pair_count = ctx->pair_count;
     a.pair_cap = ctx->pair_cap;
     a.flags = ctx->flags;
+    a.split = ctx->split[fp32];
+    a.n_total = L.n_total;
+    a.part = ctx->kpart;
     HIP_TRY(launch_kick(a, fp32, ctx->waves[fp32], ctx->grid[fp32], s));
     return GENGA_OK;
 }
@@ -330,6 +355,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->member_slot, nt));
     HIP_TRY(dalloc(ctx->bs_out, 6 * (size_t)CE_MAX_MEMBERS));
     HIP_TRY(dalloc(ctx->epartial, 9 * it.size()));
+    HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
 
     HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nt) HIP_TRY(hipMemcpy(ctx->L.sys_of, sys_of.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -353,6 +379,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     ctx->L.n_sys = n_sys;
     ctx->L.n_total = n_total;
     ctx->L.n_chunks = (int32_t)chunks.size();
+    ctx->split[0] = ctx->split[1] = default_split(ctx);
     return GENGA_OK;
 }
 
@@ -463,23 +490,28 @@ int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream)
     return GENGA_OK;
 }
 
-int genga_set_kick_waves(genga_ctx *ctx, int prec, int waves)
+int genga_set_kick_shape(genga_ctx *ctx, int prec, int waves, int split)
 {
     if (!ctx) return fail(GENGA_ERR_ARG, "null context");
     int rc = check_prec(prec);
     if (rc) return rc;
-    if (waves == 0) waves = 8;
+    if (waves == 0) waves = prec == GENGA_KICK_FP32 ? 16 : 8;
     if (waves != 4 && waves != 8 && waves != 16) return fail(GENGA_ERR_ARG, "waves must be 4, 8 or 16");
+    if (split == 0) split = default_split(ctx);
+    if (split < 1 || split > KICK_MAX_SPLIT) return fail(GENGA_ERR_ARG, "split must be 1..%d", KICK_MAX_SPLIT);
     ctx->waves[prec == GENGA_KICK_FP32] = waves;
+    ctx->split[prec == GENGA_KICK_FP32] = split;
     return GENGA_OK;
 }
 
-int genga_get_kick_waves(genga_ctx *ctx, int prec)
+int genga_get_kick_shape(genga_ctx *ctx, int prec, int *waves, int *split)
 {
-    if (!ctx) return fail(GENGA_ERR_ARG, "null context");
+    if (!ctx || !waves || !split) return fail(GENGA_ERR_ARG, "null argument");
     int rc = check_prec(prec);
     if (rc) return rc;
-    return ctx->waves[prec == GENGA_KICK_FP32];
+    *waves = ctx->waves[prec == GENGA_KICK_FP32];
+    *split = ctx->split[prec == GENGA_KICK_FP32];
+    return GENGA_OK;
 }
 
 int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
@@ -494,27 +526,31 @@ int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cand[3] = {4, 8, 16};
     float best = 1e30f;
-    int best_w = ctx->waves[fp32];
-    for (int w : cand) {
-        ctx->waves[fp32] = w;
-        // accelerations only (velocities untouched); one warm-up then five timed launches
-        rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
-        if (rc) break;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < 5 && !rc; ++r)
+    int best_w = ctx->waves[fp32], best_s = ctx->split[fp32];
+    for (int w : {4, 8, 16}) {
+        for (int sp = 1; sp <= KICK_MAX_SPLIT && !rc; ++sp) {
+            ctx->waves[fp32] = w;
+            ctx->split[fp32] = sp;
+            // accelerations only (velocities untouched); one warm-up then three timed launches
             rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
-            best_w = w;
+            if (rc) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && !rc; ++r)
+                rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_w = w;
+                best_s = sp;
+            }
         }
     }
     ctx->waves[fp32] = best_w;
+    ctx->split[fp32] = best_s;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;

@@ -73,7 +73,12 @@ struct KickArgs {
     int32_t *pair_count;
     int32_t pair_cap;
     int32_t *flags;
+    int32_t split;                // workgroups sharing one item's sources (>= 1)
+    int32_t n_total;
+    double *part;                 // [split][3][n_total] shares when split > 1
 };
+
+constexpr int KICK_MAX_SPLIT = 4;
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,

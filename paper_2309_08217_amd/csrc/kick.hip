@@ -147,10 +147,23 @@ __device__ __forceinline__ void far64(double mj, double dx, double dy, double dz
     sz = fma(s, dz, sz);
 }
 
+// Sources of system s visited by part `part` of an item when the source range is split
+// over a.split workgroups.
+__device__ __forceinline__ void source_range(const KickArgs &a, int s, int part, int &j0, int &j1)
+{
+    const int b = a.sys_off[s], e = a.sys_off[s + 1];
+    const int per = (e - b + a.split - 1) / a.split;
+    j0 = min(b + part * per, e);
+    j1 = min(j0 + per, e);
+}
+
+// Sum the W waves' partial accelerations in a fixed order; then either finish the body
+// (a_i out, v += tau a_i) or, when the sources are split over workgroups, store this
+// workgroup's share for kick_finish_kernel.
 template <int W>
 __device__ __forceinline__ void finish(const KickArgs &a, double (*red)[W][64], int wave,
-                                       int lane, bool valid, int i, double sx, double sy,
-                                       double sz)
+                                       int lane, bool valid, int i, int part, double sx,
+                                       double sy, double sz)
 {
     red[0][wave][lane] = sx;
     red[1][wave][lane] = sy;
@@ -165,18 +178,50 @@ __device__ __forceinline__ void finish(const KickArgs &a, double (*red)[W][64], 
             tz += red[2][w][lane];
         }
         if (valid) {
-            a.ax[i] = tx;
-            a.ay[i] = ty;
-            a.az[i] = tz;
-            if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) atomicOr(a.flags, FLAG_NONFINITE);
-            if (a.update_v) {
-                a.vx[i] += a.tau * tx;
-                a.vy[i] += a.tau * ty;
-                a.vz[i] += a.tau * tz;
+            if (a.split > 1) {
+                const size_t n = (size_t)a.n_total;
+                double *p = a.part + (size_t)part * 3 * n;
+                p[i] = tx;
+                p[n + i] = ty;
+                p[2 * n + i] = tz;
+            } else {
+                a.ax[i] = tx;
+                a.ay[i] = ty;
+                a.az[i] = tz;
+                if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) atomicOr(a.flags, FLAG_NONFINITE);
+                if (a.update_v) {
+                    a.vx[i] += a.tau * tx;
+                    a.vy[i] += a.tau * ty;
+                    a.vz[i] += a.tau * tz;
+                }
             }
         }
     }
     __syncthreads();
+}
+
+// Adds the split shares of every body in part order, then as finish() above.
+__global__ __launch_bounds__(256) void kick_finish_kernel(KickArgs a)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n_total) return;
+    const size_t n = (size_t)a.n_total;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+    for (int p = 0; p < a.split; ++p) {
+        const double *q = a.part + (size_t)p * 3 * n;
+        tx += q[i];
+        ty += q[n + i];
+        tz += q[2 * n + i];
+    }
+    a.ax[i] = tx;
+    a.ay[i] = ty;
+    a.az[i] = tz;
+    if (!(isfinite(tx) && isfinite(ty) && isfinite(tz))) atomicOr(a.flags, FLAG_NONFINITE);
+    if (a.update_v) {
+        a.vx[i] += a.tau * tx;
+        a.vy[i] += a.tau * ty;
+        a.vz[i] += a.tau * tz;
+    }
 }
 
 template <int W>
@@ -186,9 +231,12 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     CJ32 *J = (CJ32 *)a.jrec;
-    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-        const WorkItem w = a.items[it];
-        const int j0 = a.sys_off[w.sys], j1 = a.sys_off[w.sys + 1];
+    const int n_tasks = a.n_items * a.split;
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        const int part = task % a.split;
+        const WorkItem w = a.items[task / a.split];
+        int j0, j1;
+        source_range(a, w.sys, part, j0, j1);
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
@@ -212,7 +260,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
                 float q1 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
                 float q2 = fmaf(dx2, dx2, fmaf(dy2, dy2, dz2 * dz2));
                 float q3 = fmaf(dx3, dx3, fmaf(dy3, dy3, dz3 * dz3));
-                const bool near = (q0 < T) | (q1 < T) | (q2 < T) | (q3 < T);
+                const bool near = fminf(fminf(q0, q1), fminf(q2, q3)) < T;
                 if (__builtin_expect(near, 0)) {
                     if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
                         far32(r0.m, dx0, dy0, dz0, q0, c);
@@ -242,7 +290,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
             sz += (double)c.fz;
             c.fx = c.fy = c.fz = 0.f;
         }
-        finish<W>(a, red, wave, lane, valid, i, sx, sy, sz);
+        finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
 
@@ -253,9 +301,12 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     CJ64 *J = (CJ64 *)a.jrec;
-    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-        const WorkItem w = a.items[it];
-        const int j0 = a.sys_off[w.sys], j1 = a.sys_off[w.sys + 1];
+    const int n_tasks = a.n_items * a.split;
+    for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
+        const int part = task % a.split;
+        const WorkItem w = a.items[task / a.split];
+        int j0, j1;
+        source_range(a, w.sys, part, j0, j1);
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
@@ -274,7 +325,7 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
             double q2 = fma(dx2, dx2, fma(dy2, dy2, dz2 * dz2));
             double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
-            const bool near = (q0 < T) | (q1 < T) | (q2 < T) | (q3 < T);
+            const bool near = fmin(fmin(q0, q1), fmin(q2, q3)) < T;
             if (__builtin_expect(near, 0)) {
                 if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
                     far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
@@ -298,7 +349,7 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
                 far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
         }
-        finish<W>(a, red, wave, lane, valid, i, sx, sy, sz);
+        finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
 
@@ -379,7 +430,8 @@ hipError_t launch_prep(const Layout &L, const double *x, const double *y, const 
 hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream)
 {
     if (a.n_items == 0) return hipSuccess;
-    if (grid <= 0 || grid > a.n_items) grid = a.n_items;
+    const int n_tasks = a.n_items * a.split;
+    if (grid <= 0 || grid > n_tasks) grid = n_tasks;
 #define GENGA_KICK_CASE(Wv)                                                                   \
     case Wv:                                                                                  \
         if (fp32)                                                                             \
@@ -395,6 +447,7 @@ hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStre
         return hipErrorInvalidValue;
     }
 #undef GENGA_KICK_CASE
+    if (a.split > 1) kick_finish_kernel<<<(a.n_total + 255) / 256, 256, 0, stream>>>(a);
     return hipGetLastError();
 }
 

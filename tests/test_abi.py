@@ -37,7 +37,7 @@ def test_host_side_argument_errors_without_gpu():
     assert lib.genga_kick(None, None, 0.1, 1, None) == genga.GENGA_ERR_ARG
     assert b"null context" in lib.genga_last_error()
     assert lib.genga_set_systems(None, 1, None, None, 0) == genga.GENGA_ERR_ARG
-    assert lib.genga_set_kick_waves(None, 1, 8) == genga.GENGA_ERR_ARG
+    assert lib.genga_set_kick_shape(None, 1, 8, 1) == genga.GENGA_ERR_ARG
     assert lib.genga_create(None, 0) == genga.GENGA_ERR_ARG
 
 

@@ -38,17 +38,21 @@ def test_accel_ragged_sizes_fp64_and_fp32(n):
     s.close()
 
 
-def test_accel_c1_disc_and_waves():
+@pytest.mark.parametrize("split", [1, 2, 3, 4])
+def test_accel_c1_disc_and_launch_shapes(split):
     d = discs.disc_c1()
     s = System([d])
     ref = oracle_accel_systems(s)
     for w in (4, 8, 16):
         for prec, bar in ((FP64, 1e-12), (FP32, 1e-5)):
-            genga.genga_set_kick_waves(s.ctx.handle, prec, w)
-            rms, mx = force_errors(s.accel(prec), ref)
-            print(f"[accel c1] waves={w} prec={prec} rms={rms:.3e} max={mx:.3e}", flush=True)
+            genga.genga_set_kick_shape(s.ctx.handle, prec, w, split)
+            a = s.accel(prec)
+            rms, mx = force_errors(a, ref)
+            print(f"[accel c1] waves={w} split={split} prec={prec} rms={rms:.3e} max={mx:.3e}", flush=True)
             assert rms <= bar
             assert mx <= (1e-10 if prec == FP64 else 1e-3)
+            got, cnt = s.encounter_list()
+            np.testing.assert_array_equal(got, oracle.encounters(d.state(), s.rc))
     s.close()
 
 
@@ -320,7 +324,7 @@ def test_c3_full_size_sampled_rows():
         genga.genga_autotune(s.ctx.handle, s.b, prec)
         a = s.accel(prec)[rows]
         rms, mx = force_errors(a, ref)
-        print(f"[c3 sampled] prec={prec} waves={genga.genga_get_kick_waves(s.ctx.handle, prec)} "
+        print(f"[c3 sampled] prec={prec} shape={genga.genga_get_kick_shape(s.ctx.handle, prec)} "
               f"rms={rms:.3e} max={mx:.3e}", flush=True)
         assert rms <= bar
     got, cnt = s.encounter_list()
