@@ -369,8 +369,10 @@ static void modified_midpoint(int nb, const double *Y0, double H, int nsub, doub
     for (int q = 0; q < dim; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
-/* Integrate one group's state Y (6*nb) over dt.  Returns 0 on success, 1 if the step
- * had to be halved more than 60 times. */
+/* Integrate one group's state Y (6*nb) over dt.  Step control: after a step accepted at
+ * extrapolation column k the next step is doubled (k <= 4), kept (k = 5, 6) or halved
+ * (k = 7); a rejected step is halved.  Returns 1 (failure) if the step falls below
+ * dt * 2^-40 or more than 20000 steps are attempted, else 0. */
 static int bs_group(int nb, double *Y, const double *gm, const double *grc, double mstar,
                     double dt, double tol)
 {
@@ -380,9 +382,11 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
     double *zm = T + (size_t)dim * BS_KMAX * BS_KMAX, *zc = zm + dim, *dd = zc + dim;
 #define TAB(k, l) (T + (size_t)dim * ((k) * BS_KMAX + (l)))
     double t = 0.0, H = dt;
-    int halvings = 0;
+    int attempts = 0;
     while (t < dt) {
-        if (H > dt - t) H = dt - t;
+        int last = H >= (dt - t) * (1.0 - 0x1p-30); /* ends the interval (exactly) */
+        if (last) H = dt - t;
+        if (H < dt * 0x1p-40 || ++attempts > 20000) { free(T); return 1; }
         double sr = 0.0, sv = 0.0;
         for (int a = 0; a < nb; ++a) {
             const double *ya = Y + 6 * a;
@@ -411,11 +415,11 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
         }
         if (done >= 0) {
             memcpy(Y, TAB(done, done), sizeof(double) * (size_t)dim);
-            t += H;
-            H = 2.0 * H;
+            t = last ? dt : t + H;
+            if (done <= 4) H = 2.0 * H;
+            else if (done == BS_KMAX - 1) H = 0.5 * H;
         } else {
             H = 0.5 * H;
-            if (++halvings > 60) { free(T); return 1; }
         }
     }
 #undef TAB

@@ -434,3 +434,19 @@ def test_kepler_strongly_hyperbolic_converges():
             return np.concatenate([y[3:], -MU * y[:3] / r**3])
         ref = solve_ivp(rhs, (0, dt), np.concatenate([x0, v0]), rtol=1e-13, atol=1e-15, method="DOP853").y[:, -1]
         assert np.max(np.abs(got - ref) / np.maximum(1, np.abs(ref))) < 1e-11
+
+
+def test_step_through_dense_embryo_encounters():
+    """Cold annulus with embryos: many strongly focused encounters over 160 steps.  Every
+    Bulirsch-Stoer group step must reach the end of its interval (the last sub-step lands
+    exactly on dt, and step control does not exhaust a budget of halvings), energy stays
+    bounded and L is kept to round-off."""
+    d = discs.make_disc(3000, 2.0, seed=5, sigma_e=0.001, sigma_i=0.001, n_embryo=40,
+                        embryo_mass_earth=0.05, a_in=0.7, a_out=1.0)
+    st = d.state()
+    rc = oracle.rcrit(st, 1.0, 3.0, 0.0, discs.DT_6_DAYS)
+    assert len(oracle.encounters(st, rc)) > 30
+    s, e = oracle.step(st, rc, 1.0, discs.DT_6_DAYS, 160, cadence=20)
+    assert np.max(np.abs(e[:, 0] / e[0, 0] - 1)) < 1e-7
+    L = np.linalg.norm(e[:, 1:], axis=1)
+    assert np.max(np.abs(L / L[0] - 1)) < 1e-13
