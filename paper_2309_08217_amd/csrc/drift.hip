@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void kepler_kernel(int n_total, const int32_t 
     }
     double px = x[i], py = y[i], pz = z[i], ux = vx[i], uy = vy[i], uz = vz[i];
     const bool ok = kepler_universal(px, py, pz, ux, uy, uz, mstar[sys_of[i]], dt);
-    if (!ok) atomicOr(flags, FLAG_NOCONVERGE);
+    if (!ok) atomicOr(flags, FLAG_KEPLER);
     x[i] = px;
     y[i] = py;
     z[i] = pz;
@@ -458,18 +458,21 @@ __device__ void lane_midpoint(const LaneGroup &g, const double y0[6], double H, 
     for (int q = 0; q < 6; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
-// Integrate this lane's member over dt; returns false (uniformly) if the step had to be
-// halved more than 60 times.
+// Integrate this lane's member over dt.  After a step accepted at column k the next step is
+// doubled (k <= 4), kept (k = 5, 6) or halved (k = 7); a rejected step is halved.  Returns
+// false (uniformly) if the step falls below dt * 2^-40 or more than 20000 steps are tried.
 __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
 {
     double t = 0.0, H = dt;
-    int halvings = 0;
+    int attempts = 0;
     while (t < dt) {
-        if (H > dt - t) H = dt - t;
+        const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
+        if (last) H = dt - t;
+        if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
         const double sr = wave_max(g.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
         const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
         double T[BS_KMAX][6];
-        bool accepted = false;
+        int accepted = -1;
 #pragma unroll
         for (int k = 0; k < BS_KMAX; ++k) {
             double est[6];
@@ -497,17 +500,17 @@ __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
                 if (err <= tol) {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) Y[q] = T[k][q];
-                    accepted = true;
+                    accepted = k;
                     break;
                 }
             }
         }
-        if (accepted) {
-            t += H;
-            H = 2.0 * H;
+        if (accepted >= 0) {
+            t = last ? dt : t + H;
+            if (accepted <= 4) H = 2.0 * H;
+            else if (accepted == BS_KMAX - 1) H = 0.5 * H;
         } else {
             H = 0.5 * H;
-            if (++halvings > 60) return false;
         }
     }
     return true;
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
         for (int k = a; k < nb; k += BS_LANES) {
             const int b = members[k0 + k];
             double px = x[b], py = y[b], pz = z[b], ux = vx[b], uy = vy[b], uz = vz[b];
-            if (!kepler_universal(px, py, pz, ux, uy, uz, ms, dt)) atomicOr(flags, FLAG_NOCONVERGE);
+            if (!kepler_universal(px, py, pz, ux, uy, uz, ms, dt)) atomicOr(flags, FLAG_KEPLER);
             double *o = bs_out + 6 * (size_t)(k0 + k);
             o[0] = px;
             o[1] = py;

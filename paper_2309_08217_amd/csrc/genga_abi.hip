@@ -566,7 +566,8 @@ int genga_poll_status(genga_ctx *ctx)
     HIP_TRY(hipMemset(ctx->flags, 0, sizeof(int32_t)));
     HIP_TRY(hipDeviceSynchronize());
     if (f & FLAG_NONFINITE) return fail(GENGA_ERR_NONFINITE, "non-finite acceleration");
-    if (f & FLAG_NOCONVERGE) return fail(GENGA_ERR_NOCONVERGE, "Kepler or Bulirsch-Stoer solve did not converge");
+    if (f & FLAG_NOCONVERGE) return fail(GENGA_ERR_NOCONVERGE, "Bulirsch-Stoer step did not converge");
+    if (f & FLAG_KEPLER) return fail(GENGA_ERR_NOCONVERGE, "Kepler solve did not converge");
     if (f & FLAG_CAPACITY) return fail(GENGA_ERR_CAPACITY, "encounter capacity exceeded");
     return GENGA_OK;
 }

@@ -30,7 +30,8 @@ struct JRec64 {
 enum DeviceFlag : int32_t {
     FLAG_CAPACITY = 1,
     FLAG_NONFINITE = 2,
-    FLAG_NOCONVERGE = 4,
+    FLAG_NOCONVERGE = 4,   // Bulirsch-Stoer step
+    FLAG_KEPLER = 8,       // Kepler solve
 };
 
 // Maximum sizes of the close-encounter step (one workgroup builds the groups in LDS).
