@@ -371,7 +371,8 @@ static void modified_midpoint(int nb, const double *Y0, double H, int nsub, doub
 
 /* Integrate one group's state Y (6*nb) over dt.  Step control: after a step accepted at
  * extrapolation column k the next step is doubled (k <= 4), kept (k = 5, 6) or halved
- * (k = 7); a rejected step is halved.  Returns 1 (failure) if the step falls below
+ * (k = 7); a rejected step is multiplied by 0.9 (tol/err)^(1/15), err being the last
+ * column's error estimate, kept within [1/50, 1/2].  Returns 1 (failure) if the step falls below
  * dt * 2^-40 or more than 20000 steps are attempted, else 0. */
 static int bs_group(int nb, double *Y, const double *gm, const double *grc, double mstar,
                     double dt, double tol)
@@ -396,6 +397,7 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
             if (vv > sv) sv = vv;
         }
         int done = -1;
+        double err = 0.0;
         for (int k = 0; k < BS_KMAX && done < 0; ++k) {
             modified_midpoint(nb, Y, H, 2 * (k + 1), TAB(k, 0), zm, zc, dd, gm, grc, mstar);
             for (int l = 1; l <= k; ++l) {
@@ -405,7 +407,7 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
                     TAB(k, l)[q] = TAB(k, l - 1)[q] + (TAB(k, l - 1)[q] - TAB(k - 1, l - 1)[q]) / den;
             }
             if (k == 0) continue;
-            double err = 0.0;
+            err = 0.0;
             for (int q = 0; q < dim; ++q) {
                 double sc = ((q % 6) < 3) ? sr : sv;
                 double e = fabs(TAB(k, k)[q] - TAB(k, k - 1)[q]) / sc;
@@ -419,7 +421,9 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
             if (done <= 4) H = 2.0 * H;
             else if (done == BS_KMAX - 1) H = 0.5 * H;
         } else {
-            H = 0.5 * H;
+            /* rejected: shrink by the last column's error, between 1/50 and 1/2 */
+            double f = 0.9 * pow(tol / err, 1.0 / (2 * BS_KMAX - 1));
+            H = H * fmax(0.02, fmin(0.5, f));
         }
     }
 #undef TAB
