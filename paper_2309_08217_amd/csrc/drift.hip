@@ -458,9 +458,18 @@ __device__ void lane_midpoint(const LaneGroup &g, const double y0[6], double H, 
     for (int q = 0; q < 6; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
-// Integrate this lane's member over dt.  After a step accepted at column k the next step is
-// doubled (k <= 4), kept (k = 5, 6) or halved (k = 7); a rejected step is halved.  Returns
-// false (uniformly) if the step falls below dt * 2^-40 or more than 20000 steps are tried.
+// Step reduction after a rejected step: 0.9 (tol/err)^(1/15) from the last column's error,
+// kept within [1/50, 1/2].
+__device__ __forceinline__ double shrink_factor(double err, double tol)
+{
+    const double f = 0.9 * pow(tol / err, 1.0 / (2 * BS_KMAX - 1));
+    return fmax(0.02, fmin(0.5, f));
+}
+
+// Integrate this lane's member over dt (one lane per member, columns in sequence).  After a
+// step accepted at column k the next step is doubled (k <= 4), kept (k = 5, 6) or halved
+// (k = 7); a rejected step shrinks by shrink_factor.  Returns false (uniformly) if the step
+// falls below dt * 2^-40 or more than 20000 steps are tried.
 __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
 {
     double t = 0.0, H = dt;
@@ -473,6 +482,7 @@ __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
         const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
         double T[BS_KMAX][6];
         int accepted = -1;
+        double err_last = 0.0;
 #pragma unroll
         for (int k = 0; k < BS_KMAX; ++k) {
             double est[6];
@@ -497,6 +507,7 @@ __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
             }
             if (k > 0) {
                 err = wave_max(g.act ? err : 0.0);
+                err_last = err;
                 if (err <= tol) {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) Y[q] = T[k][q];
@@ -510,7 +521,127 @@ __device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
             if (accepted <= 4) H = 2.0 * H;
             else if (accepted == BS_KMAX - 1) H = 0.5 * H;
         } else {
-            H = 0.5 * H;
+            H = H * shrink_factor(err_last, tol);
+        }
+    }
+    return true;
+}
+
+// ---- groups of up to 8 members: the 8 extrapolation columns run side by side -------------
+// Lane = 8 k + a: column k (n_k = 2(k+1) midpoint sub-steps) of member a.  Members of one
+// column exchange positions by shuffles within their 8 lanes; the tableau is built across
+// columns by shuffles from the column below.  The accepted column is the first whose error
+// estimate meets the tolerance, so the result equals the sequential scheme's.
+constexpr int CP_MEM = 8;
+static_assert(CP_MEM * BS_KMAX == BS_LANES, "one lane per (column, member)");
+
+struct ColGroup {
+    int k, a, base, nb;
+    bool act;
+    double rc, mstar;
+    const double *sm, *src; // [8] member masses and critical radii (LDS)
+};
+
+__device__ void col_deriv(const ColGroup &g, const double y[6], double d[6])
+{
+    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const double r = sqrt(r2);
+    const double s = -g.mstar / (r2 * r);
+    double ax = s * y[0], ay = s * y[1], az = s * y[2];
+    for (int b = 0; b < g.nb; ++b) {
+        const double xb = __shfl(y[0], g.base + b, 64);
+        const double yb = __shfl(y[1], g.base + b, 64);
+        const double zb = __shfl(y[2], g.base + b, 64);
+        if (b == g.a) continue;
+        const double dx = xb - y[0], dy = yb - y[1], dz = zb - y[2];
+        const double q = sep2_rn(dx, dy, dz);
+        const double rcij = fmax(g.rc, g.src[b]);
+        if (!(q < sq_rn(rcij))) continue;
+        const double rr = sqrt(q);
+        const double w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
+        if (w == 0.0) continue;
+        const double t = g.sm[b] * w / (q * rr);
+        ax += t * dx;
+        ay += t * dy;
+        az += t * dz;
+    }
+    if (g.act) {
+        d[0] = y[3];
+        d[1] = y[4];
+        d[2] = y[5];
+        d[3] = ax;
+        d[4] = ay;
+        d[5] = az;
+    } else {
+        for (int q = 0; q < 6; ++q) d[q] = 0.0;
+    }
+}
+
+__device__ bool col_bs(const ColGroup &g, double Y[6], double dt, double tol)
+{
+    const int lane = g.base + g.a;
+    const int nsub = 2 * (g.k + 1);
+    double t = 0.0, H = dt;
+    int attempts = 0;
+    while (t < dt) {
+        const bool last = H >= (dt - t) * (1.0 - 0x1p-30);
+        if (last) H = dt - t;
+        if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
+        const double sr = wave_max(g.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
+        const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        // this lane's column: modified midpoint with nsub sub-steps
+        const double h = H / nsub;
+        double zm[6], zc[6], dd[6], cur[6], sub[6];
+        col_deriv(g, Y, dd);
+        for (int q = 0; q < 6; ++q) {
+            zm[q] = Y[q];
+            zc[q] = Y[q] + h * dd[q];
+        }
+        for (int i = 1; i < nsub; ++i) {
+            col_deriv(g, zc, dd);
+            for (int q = 0; q < 6; ++q) {
+                const double tq = zm[q] + 2.0 * h * dd[q];
+                zm[q] = zc[q];
+                zc[q] = tq;
+            }
+        }
+        col_deriv(g, zc, dd);
+        for (int q = 0; q < 6; ++q) {
+            cur[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]); // T(k, 0)
+            sub[q] = cur[q];
+        }
+        // Neville across columns: round l turns T(k, l-1) into T(k, l) for k >= l
+        const int below = g.k > 0 ? lane - CP_MEM : lane;
+#pragma unroll
+        for (int l = 1; l < BS_KMAX; ++l) {
+            const double ratio = (double)(g.k + 1) / (double)(g.k + 1 - l);
+            const double den = ratio * ratio - 1.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const double tb = __shfl(cur[q], below, 64); // T(k-1, l-1)
+                if (g.k >= l) {
+                    const double nxt = cur[q] + (cur[q] - tb) / den;
+                    sub[q] = cur[q];
+                    cur[q] = nxt;
+                }
+            }
+        }
+        // error of every column (over its members), then the first column that converged
+        double err = 0.0;
+        if (g.act && g.k > 0)
+            for (int q = 0; q < 6; ++q) err = fmax(err, fabs(cur[q] - sub[q]) / (q < 3 ? sr : sv));
+        for (int o = 1; o < CP_MEM; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
+        const bool conv = g.k > 0 && err <= tol && g.a == 0;
+        const unsigned long long mask = __ballot(conv);
+        if (mask) {
+            const int kstar = (__ffsll((long long)mask) - 1) / CP_MEM;
+            for (int q = 0; q < 6; ++q) Y[q] = __shfl(cur[q], kstar * CP_MEM + g.a, 64);
+            t = last ? dt : t + H;
+            if (kstar <= 4) H = 2.0 * H;
+            else if (kstar == BS_KMAX - 1) H = 0.5 * H;
+        } else {
+            const double err_last = __shfl(err, (BS_KMAX - 1) * CP_MEM, 64);
+            H = H * shrink_factor(err_last, tol);
         }
     }
     return true;
@@ -548,6 +679,26 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
             o[4] = uy;
             o[5] = uz;
         }
+        return;
+    }
+    if (nb <= CP_MEM) {
+        // column-parallel path
+        const int k = a / CP_MEM, am = a % CP_MEM;
+        const bool act = am < nb;
+        const int b = members[k0 + (act ? am : 0)];
+        if (k == 0) {
+            sm[am] = act ? m[b] : 0.0;
+            src[am] = act ? rc[b] : 0.0;
+        }
+        __syncthreads();
+        ColGroup cg{k, am, k * CP_MEM, nb, act, rc[b], ms, sm, src};
+        double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
+        const bool ok = col_bs(cg, Y, dt, 1e-12);
+        if (act && k == 0) {
+            double *o = bs_out + 6 * (size_t)(k0 + am);
+            for (int q = 0; q < 6; ++q) o[q] = Y[q];
+        }
+        if (!ok && a == 0) atomicOr(flags, FLAG_NOCONVERGE);
         return;
     }
     const bool act = a < nb;
