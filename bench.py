@@ -91,6 +91,20 @@ def time_steps(ctx, b, prec, steps, warmup, n_sys, torch, stream):
     return t1 - t0, e_rec.cpu().numpy().reshape(-1, n_sys, 4)[:nrec], e_init.cpu().numpy().reshape(n_sys, 4), status
 
 
+def time_graph(ctx, b, prec, steps, torch, stream, per_graph=10):
+    """Steps replayed from a captured HIP graph of `per_graph` steps (no diagnostics)."""
+    with torch.cuda.stream(stream):
+        genga.genga_graph_capture(ctx.handle, b, DT, per_graph, prec, stream=stream)
+        genga.genga_graph_launch(ctx.handle, 1, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(1, steps // per_graph)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        genga.genga_graph_launch(ctx.handle, reps, stream=stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / (reps * per_graph)
+
+
 def drift_stats(e_init, e_rec):
     E0 = e_init[:, 0]
     L0 = np.linalg.norm(e_init[:, 1:], axis=1)
@@ -184,6 +198,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-kick", type=int, default=0,
                     help="profiling aid: run this many FP32 kicks of the N=40000 disc and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="profiling aid: run only the 64-disc batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling aid: copy a 256 MiB buffer 4 times (a plain copy of known size, "
                          "to scale HBM byte counters) and exit")
@@ -206,6 +222,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 4}))
         return
+    if args.batched_only:
+        print(json.dumps(batched(torch, stream)))
+        return
     d = discs.disc_c3()
     if args.only_kick > 0:
         ctx, b, st, _ = setup([d], torch)
@@ -225,7 +244,9 @@ def main():
         genga.genga_autotune(ctx.handle, b, prec)
         kick_ms = time_kicks(ctx, b, prec, args.kick_reps, torch, stream)
         t, e_rec, e_init, status = time_steps(ctx, b, prec, args.steps, args.warmup, 1, torch, stream)
+        t_graph = time_graph(ctx, b, prec, args.steps, torch, stream)
         result[name] = {"step_seconds": t, "ms_per_step": 1e3 * t / args.steps,
+                        "graph_ms_per_step_no_diagnostics": 1e3 * t_graph,
                         "value": pairs * args.steps / t / 1e9,
                         "kick_ms": kick_ms, "kick_G_pairs_per_s": pairs / (kick_ms * 1e-3) / 1e9,
                         "kick_tflops": FLOP_PER_PAIR * pairs / (kick_ms * 1e-3) / 1e12,
@@ -258,6 +279,9 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs,
                      "launch_ms": f32["kick_ms"], "traffic": kick_traffic(pairs)},
         "fp32_kick": {"G_pair_interactions_per_s": f32["kick_G_pairs_per_s"], "kick_ms": f32["kick_ms"]},
+        "graph": {"fp32_ms_per_step": f32["graph_ms_per_step_no_diagnostics"],
+                  "fp64_ms_per_step": f64["graph_ms_per_step_no_diagnostics"],
+                  "note": "10-step HIP graphs replayed, energy diagnostics not included"},
         "fp64": {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                  "G_pair_interactions_per_s_kick": f64["kick_G_pairs_per_s"], "kick_ms": f64["kick_ms"],
                  "roofline": {"bound": "alu", "achieved": f64["kick_tflops"], "peak": PEAK_FP64_TFLOPS,

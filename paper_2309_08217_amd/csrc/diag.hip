@@ -37,7 +37,7 @@ __global__ __launch_bounds__(64 * EW) void energy_kernel(
     const WorkItem *items, int n_items, const int32_t *sys_off, const double *mstar, const double *x,
     const double *y, const double *z, const double *vx, const double *vy, const double *vz,
     const double *m, const double *ax, const double *ay, const double *az, double vshift,
-    double *partial)
+    double *partial, int split)
 {
     __shared__ double red[EW][64];
     const int lane = threadIdx.x & 63;
@@ -46,15 +46,20 @@ __global__ __launch_bounds__(64 * EW) void energy_kernel(
     CJ64 *Y = (CJ64 *)y;
     CJ64 *Z = (CJ64 *)z;
     CJ64 *M = (CJ64 *)m;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const WorkItem w = items[it];
-        const int j1 = sys_off[w.sys + 1];
+    const int n_tasks = n_items * split;
+    for (int it = blockIdx.x; it < n_tasks; it += gridDim.x) {
+        const WorkItem w = items[it / split];
+        const int part = it % split;
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = x[i], yi = y[i], zi = z[i];
-        // sources j in [i0, j1), split over the waves; only j > i counts
-        const int chunk = (j1 - w.i0 + EW - 1) / EW;
-        const int jb = min(w.i0 + wave * chunk, j1), je = min(jb + chunk, j1);
+        // sources j in [i0, end of system), split into `split` parts over workgroups and each
+        // part over the waves; only j > i counts
+        const int per = (sys_off[w.sys + 1] - w.i0 + split - 1) / split;
+        const int p0 = min(w.i0 + part * per, sys_off[w.sys + 1]);
+        const int p1 = min(p0 + per, sys_off[w.sys + 1]);
+        const int chunk = (p1 - p0 + EW - 1) / EW;
+        const int jb = min(p0 + wave * chunk, p1), je = min(jb + chunk, p1);
         double s = 0.0;
         const int jmask = min(je, w.i0 + 64);
         int j = jb;
@@ -87,7 +92,10 @@ __global__ __launch_bounds__(64 * EW) void energy_kernel(
 #pragma unroll
             for (int k = 0; k < EW; ++k) tot += red[k][lane];
             double v[NPART];
-            if (valid) {
+            if (valid && part > 0) {
+                v[0] = m[i] * tot;
+                for (int k = 1; k < NPART; ++k) v[k] = 0.0;
+            } else if (valid) {
                 const double mi = m[i];
                 const double ux = vx[i] - vshift * ax[i];
                 const double uy = vy[i] - vshift * ay[i];
@@ -121,13 +129,14 @@ constexpr int EF_THREADS = 256;
 
 __global__ __launch_bounds__(EF_THREADS) void energy_finish_kernel(const int32_t *item_first,
                                                                    const double *mstar,
-                                                                   const double *partial, double *out)
+                                                                   const double *partial, double *out,
+                                                                   int split)
 {
     __shared__ double red[NPART][EF_THREADS];
     const int s = blockIdx.x;
     double t[NPART];
     for (int k = 0; k < NPART; ++k) t[k] = 0.0;
-    for (int it = item_first[s] + threadIdx.x; it < item_first[s + 1]; it += EF_THREADS)
+    for (int it = item_first[s] * split + threadIdx.x; it < item_first[s + 1] * split; it += EF_THREADS)
         for (int k = 0; k < NPART; ++k) t[k] += partial[(size_t)it * NPART + k];
     for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] = t[k];
     __syncthreads();
@@ -214,9 +223,10 @@ hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items
                          const int32_t *item_first, double *out, hipStream_t stream)
 {
     if (n_items > 0)
-        energy_kernel<<<n_items, 64 * EW, 0, stream>>>(items, n_items, L.sys_off, L.mstar, x, y, z, vx,
-                                                       vy, vz, m, ax, ay, az, vshift, partial);
-    energy_finish_kernel<<<L.n_sys, EF_THREADS, 0, stream>>>(item_first, L.mstar, partial, out);
+        energy_kernel<<<n_items * ENERGY_SPLIT, 64 * EW, 0, stream>>>(items, n_items, L.sys_off, L.mstar, x, y,
+                                                                      z, vx, vy, vz, m, ax, ay, az, vshift,
+                                                                      partial, ENERGY_SPLIT);
+    energy_finish_kernel<<<L.n_sys, EF_THREADS, 0, stream>>>(item_first, L.mstar, partial, out, ENERGY_SPLIT);
     return hipGetLastError();
 }
 

@@ -80,12 +80,31 @@ __global__ __launch_bounds__(SUN_THREADS) void sun_shift_kernel(const Chunk *chu
                                                                 const double *mom_part, double tau,
                                                                 double *x, double *y, double *z)
 {
+    __shared__ double red[3][SUN_THREADS / 64];
     const Chunk c = chunks[blockIdx.x];
+    // the system's momentum: strided sums of the chunk partials, then a fixed tree
     double Px = 0.0, Py = 0.0, Pz = 0.0;
-    for (int k = chunk_first[c.sys]; k < chunk_first[c.sys + 1]; ++k) {
+    for (int k = chunk_first[c.sys] + threadIdx.x; k < chunk_first[c.sys + 1]; k += SUN_THREADS) {
         Px += mom_part[3 * (size_t)k];
         Py += mom_part[3 * (size_t)k + 1];
         Pz += mom_part[3 * (size_t)k + 2];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        Px += __shfl_xor(Px, o, 64);
+        Py += __shfl_xor(Py, o, 64);
+        Pz += __shfl_xor(Pz, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = Px;
+        red[1][threadIdx.x >> 6] = Py;
+        red[2][threadIdx.x >> 6] = Pz;
+    }
+    __syncthreads();
+    Px = Py = Pz = 0.0;
+    for (int w = 0; w < SUN_THREADS / 64; ++w) {
+        Px += red[0][w];
+        Py += red[1][w];
+        Pz += red[2][w];
     }
     const double f = tau / mstar[c.sys];
     const double sx = f * Px, sy = f * Py, sz = f * Pz;
@@ -205,7 +224,7 @@ __device__ bool kepler_universal(double &x, double &y, double &z, double &vx, do
     return ok;
 }
 
-__global__ __launch_bounds__(256) void kepler_kernel(int n_total, const int32_t *sys_of,
+__global__ __launch_bounds__(64) void kepler_kernel(int n_total, const int32_t *sys_of,
                                                      const double *mstar, double *x, double *y,
                                                      double *z, double *vx, double *vy,
                                                      double *vz, double dt, int32_t *member_slot,
@@ -245,12 +264,19 @@ __global__ __launch_bounds__(256) void kepler_kernel(int n_total, const int32_t 
 // ------------------------------------------------------------------------------------------
 constexpr int CE_THREADS = 1024;
 
-__device__ __forceinline__ int find_root(const int32_t *lab, int a)
+// lab[] is read with device-coherent atomic loads, so the hooks made by other waves through
+// atomicMin (performed in L2) are seen without cache maintenance.
+__device__ __forceinline__ int lab_load(int32_t *lab, int a)
 {
-    int r = lab[a];
+    return __hip_atomic_load(&lab[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int find_root(int32_t *lab, int a)
+{
+    int r = lab_load(lab, a);
     while (r != a) {
         a = r;
-        r = lab[a];
+        r = lab_load(lab, a);
     }
     return r;
 }
@@ -281,7 +307,7 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
             if (atomicCAS(&mark[b], 0, 1) == 0) {
                 const int k = atomicAdd(&s_nmem, 1);
                 if (k < CE_MAX_MEMBERS) keys[k] = (uint64_t)(uint32_t)b;
-                lab[b] = b;
+                __hip_atomic_store(&lab[b], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -291,7 +317,6 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
     if (nmem_all > CE_MAX_MEMBERS) {
         if (tid == 0) atomicOr(flags, FLAG_CAPACITY);
     }
-    __threadfence_block();
     // union by hooking the larger root under the smaller until no pair spans two roots
     for (int round = 0; round < 4096; ++round) {
         if (tid == 0) s_changed = 0;
@@ -305,7 +330,6 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
                 s_changed = 1;
             }
         }
-        __threadfence();
         __syncthreads();
         if (!s_changed) break;
         __syncthreads();
@@ -337,7 +361,7 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
         }
     }
     // write members and slots; number the groups with a chunked scan of the start flags
-    __shared__ int32_t s_cnt[CE_THREADS];
+    __shared__ int32_t s_cnt[CE_THREADS / 64];
     const int per = (nmem + CE_THREADS - 1) / CE_THREADS;
     const int kb = min(tid * per, nmem), ke = min(kb + per, nmem);
     int nstart = 0;
@@ -347,19 +371,26 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
         member_slot[b] = k;
         if (k == 0 || (keys[k - 1] >> 32) != (keys[k] >> 32)) ++nstart;
     }
-    s_cnt[tid] = nstart;
+    // exclusive scan of the per-thread start counts: in-wave shuffles, then the wave totals
+    const int lane = tid & 63, wave = tid >> 6;
+    int incl = nstart;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) s_cnt[wave] = incl;
     __syncthreads();
     if (tid == 0) {
         int acc = 0;
-        for (int t = 0; t < CE_THREADS; ++t) {
-            const int c = s_cnt[t];
-            s_cnt[t] = acc;
+        for (int w = 0; w < CE_THREADS / 64; ++w) {
+            const int c = s_cnt[w];
+            s_cnt[w] = acc;
             acc += c;
         }
         s_ng = acc;
     }
     __syncthreads();
-    int g = s_cnt[tid];
+    int g = s_cnt[wave] + incl - nstart;
     for (int k = kb; k < ke; ++k)
         if (k == 0 || (keys[k - 1] >> 32) != (keys[k] >> 32)) group_start[g++] = k;
     if (tid == 0) {
@@ -538,29 +569,41 @@ static_assert(CP_MEM * BS_KMAX == BS_LANES, "one lane per (column, member)");
 struct ColGroup {
     int k, a, base, nb;
     bool act;
-    double rc, mstar;
-    const double *sm, *src; // [8] member masses and critical radii (LDS)
+    double mstar;
+    // per partner b (constant over the step): r_crit,ab^2, 0.1 r_crit,ab, 1/(0.9 r_crit,ab), m_b
+    double rc2[CP_MEM], r01[CP_MEM], inv09[CP_MEM], mb[CP_MEM];
 };
+
+// 1/sqrt(q) in FP64: v_rsq_f64 (about 2^-24) and one third-order correction
+__device__ __forceinline__ double inv_sqrt64(double q)
+{
+    const double y0 = __builtin_amdgcn_rsq(q);
+    const double t = q * y0;
+    const double e = fma(-t, y0, 1.0);
+    const double p = fma(0.375, e, 0.5);
+    return fma(y0 * e, p, y0);
+}
 
 __device__ void col_deriv(const ColGroup &g, const double y[6], double d[6])
 {
     const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-    const double r = sqrt(r2);
-    const double s = -g.mstar / (r2 * r);
+    const double ri = inv_sqrt64(r2);
+    const double s = -g.mstar * (ri * ri) * ri;
     double ax = s * y[0], ay = s * y[1], az = s * y[2];
-    for (int b = 0; b < g.nb; ++b) {
+#pragma unroll
+    for (int b = 0; b < CP_MEM; ++b) {
+        if (b >= g.nb) break;
         const double xb = __shfl(y[0], g.base + b, 64);
         const double yb = __shfl(y[1], g.base + b, 64);
         const double zb = __shfl(y[2], g.base + b, 64);
         if (b == g.a) continue;
         const double dx = xb - y[0], dy = yb - y[1], dz = zb - y[2];
         const double q = sep2_rn(dx, dy, dz);
-        const double rcij = fmax(g.rc, g.src[b]);
-        if (!(q < sq_rn(rcij))) continue;
-        const double rr = sqrt(q);
-        const double w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
+        if (!(q < g.rc2[b])) continue;
+        const double rq = inv_sqrt64(q);
+        const double w = 1.0 - changeover_k((q * rq - g.r01[b]) * g.inv09[b]);
         if (w == 0.0) continue;
-        const double t = g.sm[b] * w / (q * rr);
+        const double t = g.mb[b] * w * (rq * rq) * rq;
         ax += t * dx;
         ay += t * dy;
         az += t * dz;
@@ -615,12 +658,12 @@ __device__ bool col_bs(const ColGroup &g, double Y[6], double dt, double tol)
 #pragma unroll
         for (int l = 1; l < BS_KMAX; ++l) {
             const double ratio = (double)(g.k + 1) / (double)(g.k + 1 - l);
-            const double den = ratio * ratio - 1.0;
+            const double rden = 1.0 / (ratio * ratio - 1.0);
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const double tb = __shfl(cur[q], below, 64); // T(k-1, l-1)
                 if (g.k >= l) {
-                    const double nxt = cur[q] + (cur[q] - tb) / den;
+                    const double nxt = cur[q] + (cur[q] - tb) * rden;
                     sub[q] = cur[q];
                     cur[q] = nxt;
                 }
@@ -691,7 +734,22 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
             src[am] = act ? rc[b] : 0.0;
         }
         __syncthreads();
-        ColGroup cg{k, am, k * CP_MEM, nb, act, rc[b], ms, sm, src};
+        ColGroup cg;
+        cg.k = k;
+        cg.a = am;
+        cg.base = k * CP_MEM;
+        cg.nb = nb;
+        cg.act = act;
+        cg.mstar = ms;
+        const double rca = rc[b];
+#pragma unroll
+        for (int p = 0; p < CP_MEM; ++p) {
+            const double rcij = fmax(rca, src[p]);
+            cg.rc2[p] = sq_rn(rcij);
+            cg.r01[p] = 0.1 * rcij;
+            cg.inv09[p] = 1.0 / (0.9 * rcij);
+            cg.mb[p] = sm[p];
+        }
         double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
         const bool ok = col_bs(cg, Y, dt, 1e-12);
         if (act && k == 0) {
@@ -758,7 +816,8 @@ hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, doubl
                          int32_t *flags, hipStream_t stream)
 {
     if (L.n_total == 0) return hipSuccess;
-    kepler_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, L.sys_of, L.mstar, x, y, z,
+    // one wave per workgroup spreads the latency-bound solves over all CUs
+    kepler_kernel<<<(L.n_total + 63) / 64, 64, 0, stream>>>(L.n_total, L.sys_of, L.mstar, x, y, z,
                                                                vx, vy, vz, dt, member_slot, bs_out,
                                                                flags);
     return hipGetLastError();

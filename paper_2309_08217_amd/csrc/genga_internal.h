@@ -80,6 +80,7 @@ struct KickArgs {
 };
 
 constexpr int KICK_MAX_SPLIT = 4;
+constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in the energy sum
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
