@@ -336,3 +336,82 @@ def test_c3_full_size_sampled_rows():
     p = (d.m[:, None] * a).sum(axis=0)
     assert np.max(np.abs(p)) <= 1e-6 * np.sum(d.m[:, None] * np.abs(a))
     s.close()
+
+
+def _chain_disc(n_chain, n_field=300, spacing=0.45, rc0=2e-3, seed=61):
+    """A field disc plus a chain of n_chain bodies spaced `spacing` r_crit apart, so that the
+    chain forms one encounter group."""
+    base = discs.make_disc(n_field, 2.5, seed=seed, a_in=0.7, a_out=1.0)
+    st = base.state()
+    rng = np.random.default_rng(seed)
+    p0 = np.array([0.95, 0.1, 0.0])
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    vk = np.array([-p0[1], p0[0], 0.0]) / np.linalg.norm(p0) ** 1.5
+    pts = p0 + np.outer(np.arange(n_chain) * spacing * rc0, u)
+    vel = vk + rng.normal(scale=1e-3, size=(n_chain, 3))
+    for q, k in enumerate(("x", "y", "z")):
+        st[k] = np.concatenate([st[k], pts[:, q]])
+        st["v" + k] = np.concatenate([st["v" + k], vel[:, q]])
+    st["m"] = np.concatenate([st["m"], np.full(n_chain, 1e-9)])
+    rc = np.concatenate([oracle.rcrit(base.state(), 1.0, 3.0, 0.0, DT), np.full(n_chain, rc0)])
+    return discs.Disc(**st), rc
+
+
+@pytest.mark.parametrize("n_chain", [5, 8, 9, 12, 40])
+def test_drift_large_groups(n_chain):
+    """Groups of up to 8 bodies take the column-parallel path, 9..64 the lane-per-member path;
+    both must agree with the oracle's Bulirsch-Stoer to its tolerance."""
+    d, rc = _chain_disc(n_chain)
+    s = System([d], rcrit=rc)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    big = np.bincount(gid[gid >= 0]).max()
+    assert big >= n_chain
+    exp = oracle.drift(d.state(), rc, 1.0, DT, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    inside = gid >= 0
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        e_bs = np.max(np.abs(got[k][inside] - exp[k][inside]))
+        print(f"[large group n={n_chain} (largest {big})] {k} BS err {e_bs:.2e}", flush=True)
+        assert e_bs <= 1e-10
+    s.close()
+
+
+def test_group_over_capacity_is_flagged():
+    d, rc = _chain_disc(70)
+    s = System([d], rcrit=rc)
+    s.accel(FP64)
+    genga.genga_drift(s.ctx.handle, s.b, DT)
+    s.torch.cuda.synchronize()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_ERR_CAPACITY
+    st = s.numpy_state()
+    assert all(np.all(np.isfinite(st[k])) for k in st)
+    s.close()
+
+
+@pytest.mark.parametrize("layout", ["random", "mixed_blocks"])
+def test_accel_unequal_masses(layout):
+    """Masses differ within the aligned 64-source blocks (general path) or only in some blocks
+    (one-mass blocks take the folded path); both against the oracle."""
+    d = _sizes_disc(1500, seed=71, a_in=0.7, a_out=1.0)
+    st = d.state()
+    rng = np.random.default_rng(71)
+    if layout == "random":
+        st["m"] = 10 ** rng.uniform(-10, -7, d.n)
+    else:
+        st["m"][:200] = 10 ** rng.uniform(-10, -7, 200)     # blocks 0..3 mixed, rest one mass
+        st["m"][1000:1064] = 3e-8                          # a one-mass block of another mass
+    dd = discs.Disc(**st)
+    s = System([dd])
+    ref = oracle_accel_systems(s)
+    for prec, bar in ((FP64, 1e-12), (FP32, 1e-5)):
+        for split in (1, 3):
+            genga.genga_set_kick_shape(s.ctx.handle, prec, 8, split)
+            rms, mx = force_errors(s.accel(prec), ref)
+            print(f"[unequal masses {layout}] prec={prec} split={split} rms={rms:.3e} max={mx:.3e}", flush=True)
+            assert rms <= bar
+    s.close()
