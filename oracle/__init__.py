@@ -56,26 +56,26 @@ def lib() -> ctypes.CDLL:
         L.oracle_changeover.restype = ctypes.c_double
         L.oracle_changeover.argtypes = [ctypes.c_double]
         L.oracle_rcrit.argtypes = [i64] + [d] * 7 + [ctypes.c_double] * 4 + [d]
-        L.oracle_accel.argtypes = [i64] + [d] * 5 + [d] * 3
-        L.oracle_accel_rows.argtypes = [i64] + [d] * 5 + [i64, ctypes.POINTER(ctypes.c_int64)] + [d] * 3
+        L.oracle_accel.argtypes = [i64, i64] + [d] * 5 + [d] * 3
+        L.oracle_accel_rows.argtypes = [i64, i64] + [d] * 5 + [i64, ctypes.POINTER(ctypes.c_int64)] + [d] * 3
         L.oracle_encounters.restype = i64
-        L.oracle_encounters.argtypes = [i64, d, d, d, d, i64, ctypes.POINTER(ctypes.c_int32)]
-        L.oracle_energy.argtypes = [i64] + [d] * 7 + [ctypes.c_double, d]
+        L.oracle_encounters.argtypes = [i64, i64, d, d, d, d, i64, ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_energy.argtypes = [i64, i64] + [d] * 7 + [ctypes.c_double, d]
         L.oracle_sun_drift.argtypes = [i64] + [d] * 7 + [ctypes.c_double, ctypes.c_double]
         L.oracle_kepler_drift.restype = ctypes.c_int
         L.oracle_kepler_drift.argtypes = [i64] + [d] * 6 + [ctypes.c_double, ctypes.c_double,
                                                             ctypes.POINTER(ctypes.c_uint8)]
         L.oracle_bs_group.restype = ctypes.c_int
-        L.oracle_bs_group.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)] + [d] * 8 + \
+        L.oracle_bs_group.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int32), i64] + [d] * 8 + \
             [ctypes.c_double] * 3
         L.oracle_groups.restype = i64
         L.oracle_groups.argtypes = [i64, i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
         L.oracle_drift.restype = ctypes.c_int
-        L.oracle_drift.argtypes = [i64] + [d] * 8 + [ctypes.c_double, ctypes.c_double, i64,
-                                                     ctypes.POINTER(ctypes.c_int32), ctypes.c_double]
+        L.oracle_drift.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_double, ctypes.c_double, i64,
+                                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_double]
         L.oracle_step.restype = ctypes.c_int
-        L.oracle_step.argtypes = [i64] + [d] * 8 + [ctypes.c_double, ctypes.c_double, i64,
-                                                    ctypes.c_double, i64, d]
+        L.oracle_step.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_double, ctypes.c_double, i64,
+                                                         ctypes.c_double, i64, d]
         _lib = L
     return _lib
 
@@ -112,45 +112,53 @@ def rcrit(st: Dict[str, np.ndarray], mstar: float, n1: float, n2: float, dt: flo
     return rc
 
 
-def accel(st: Dict[str, np.ndarray], rc: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Changeover-weighted long-range accelerations a_i (the kick force, Sect. 1)."""
+def _nm(n: int, n_massive: Optional[int]) -> int:
+    return n if n_massive is None else int(n_massive)
+
+
+def accel(st: Dict[str, np.ndarray], rc: np.ndarray, n_massive: Optional[int] = None
+          ) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Changeover-weighted long-range accelerations a_i (the kick force, Sect. 1).  With
+    n_massive < n, bodies n_massive.. are TP2 test bodies (Sect. 3.3)."""
     n = len(st["x"])
     ax, ay, az = np.zeros(n), np.zeros(n), np.zeros(n)
     a = [_f64(st[k]) for k in ("x", "y", "z", "m")] + [_f64(rc)]
-    lib().oracle_accel(n, *[_p(v) for v in a], _p(ax), _p(ay), _p(az))
+    lib().oracle_accel(n, _nm(n, n_massive), *[_p(v) for v in a], _p(ax), _p(ay), _p(az))
     return ax, ay, az
 
 
-def accel_rows(st: Dict[str, np.ndarray], rc: np.ndarray, rows: np.ndarray):
+def accel_rows(st: Dict[str, np.ndarray], rc: np.ndarray, rows: np.ndarray, n_massive: Optional[int] = None):
     """a_i for the listed rows only (for sampled checks at large n)."""
     n = len(st["x"])
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     k = len(rows)
     ax, ay, az = np.zeros(k), np.zeros(k), np.zeros(k)
     a = [_f64(st[k_]) for k_ in ("x", "y", "z", "m")] + [_f64(rc)]
-    lib().oracle_accel_rows(n, *[_p(v) for v in a], k, _p(rows, ctypes.c_int64), _p(ax), _p(ay), _p(az))
+    lib().oracle_accel_rows(n, _nm(n, n_massive), *[_p(v) for v in a], k, _p(rows, ctypes.c_int64),
+                            _p(ax), _p(ay), _p(az))
     return ax, ay, az
 
 
-def encounters(st: Dict[str, np.ndarray], rc: np.ndarray, cap: Optional[int] = None) -> np.ndarray:
+def encounters(st: Dict[str, np.ndarray], rc: np.ndarray, cap: Optional[int] = None,
+               n_massive: Optional[int] = None) -> np.ndarray:
     """Encounter pairs (i < j, r_ij < r_crit,ij), lexicographic, as an int32 array [P, 2]."""
     n = len(st["x"])
     if cap is None:
         cap = 16 * n + 16
     pairs = np.zeros((cap, 2), dtype=np.int32)
     a = [_f64(st[k]) for k in ("x", "y", "z")] + [_f64(rc)]
-    cnt = lib().oracle_encounters(n, *[_p(v) for v in a], cap, _p(pairs, ctypes.c_int32))
+    cnt = lib().oracle_encounters(n, _nm(n, n_massive), *[_p(v) for v in a], cap, _p(pairs, ctypes.c_int32))
     if cnt > cap:
-        return encounters(st, rc, cap=int(cnt))
+        return encounters(st, rc, cap=int(cnt), n_massive=n_massive)
     return pairs[:cnt].copy()
 
 
-def energy(st: Dict[str, np.ndarray], mstar: float) -> np.ndarray:
+def energy(st: Dict[str, np.ndarray], mstar: float, n_massive: Optional[int] = None) -> np.ndarray:
     """(E, Lx, Ly, Lz) of the system (Sect. 3.1 diagnostics)."""
     n = len(st["x"])
     out = np.zeros(4)
     a = [_f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")]
-    lib().oracle_energy(n, *[_p(v) for v in a], float(mstar), _p(out))
+    lib().oracle_energy(n, _nm(n, n_massive), *[_p(v) for v in a], float(mstar), _p(out))
     return out
 
 
@@ -181,11 +189,12 @@ def kepler_drift(st: Dict[str, np.ndarray], mu: float, dt: float, skip: Optional
     return s
 
 
-def bs_group(st: Dict[str, np.ndarray], rc: np.ndarray, members, mstar: float, dt: float, tol: float = BS_TOL):
+def bs_group(st: Dict[str, np.ndarray], rc: np.ndarray, members, mstar: float, dt: float, tol: float = BS_TOL,
+             n_massive: Optional[int] = None):
     """One encounter group integrated over dt with Bulirsch-Stoer (FP64, Sect. 1)."""
     s = _mut(st)
     idx = np.ascontiguousarray(members, dtype=np.int32)
-    bad = lib().oracle_bs_group(len(idx), _p(idx, ctypes.c_int32),
+    bad = lib().oracle_bs_group(len(idx), _p(idx, ctypes.c_int32), _nm(len(s["x"]), n_massive),
                                 *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
                                 _p(_f64(rc)), float(mstar), float(dt), float(tol))
     if bad:
@@ -201,19 +210,21 @@ def groups(n: int, pairs: np.ndarray) -> np.ndarray:
     return gid
 
 
-def drift(st, rc, mstar: float, dt: float, pairs: np.ndarray, tol: float = BS_TOL):
+def drift(st, rc, mstar: float, dt: float, pairs: np.ndarray, tol: float = BS_TOL,
+          n_massive: Optional[int] = None):
     """Sun drift(dt/2), Kepler drift or BS per group (dt), Sun drift(dt/2)."""
     s = _mut(st)
     n = len(s["x"])
     p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
-    bad = lib().oracle_drift(n, *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], _p(_f64(rc)),
+    bad = lib().oracle_drift(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], _p(_f64(rc)),
                              float(mstar), float(dt), len(p), _p(p, ctypes.c_int32), float(tol))
     if bad:
         raise RuntimeError("oracle drift failed")
     return s
 
 
-def step(st, rc, mstar: float, dt: float, nsteps: int, cadence: int = 0, tol: float = BS_TOL):
+def step(st, rc, mstar: float, dt: float, nsteps: int, cadence: int = 0, tol: float = BS_TOL,
+         n_massive: Optional[int] = None):
     """nsteps full steps; returns (new state, energy rows [k, 4] at the cadence or None)."""
     s = _mut(st)
     n = len(s["x"])
@@ -222,7 +233,7 @@ def step(st, rc, mstar: float, dt: float, nsteps: int, cadence: int = 0, tol: fl
     if cadence > 0:
         e = np.zeros((nsteps // cadence + 1, 4))
         ep = _p(e)
-    bad = lib().oracle_step(n, *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], _p(_f64(rc)),
+    bad = lib().oracle_step(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], _p(_f64(rc)),
                             float(mstar), float(dt), int(nsteps), float(tol), int(cadence), ep)
     if bad:
         raise RuntimeError("oracle step failed")

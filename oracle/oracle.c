@@ -27,6 +27,9 @@
  *  - Sect. 3.1: Delta E/E = E(t)/E_0 - 1 and Delta L/L = L(t)/L_0 - 1.
  *  - Step order (democratic heliocentric split): Kick(dt/2), Sun drift(dt/2),
  *    [Kepler drift | Bulirsch-Stoer for encounter groups](dt), Sun drift(dt/2), Kick(dt/2).
+ *  - TP2 mode (Sect. 3.3): with nm < n, bodies nm..n-1 are test bodies that feel and exert
+ *    forces on bodies 0..nm-1 but do not interact with each other; nm = n is the plain
+ *    fully self-gravitating system.
  *  - A pair is an encounter pair iff r_ij^2 < r_crit,ij^2, with
  *    r_ij^2 = (dx*dx + dy*dy) + dz*dz evaluated left to right in FP64, at the positions
  *    the kick used.
@@ -90,12 +93,14 @@ void oracle_rcrit(int64_t n, const double *x, const double *y, const double *z,
  * Long-range (changeover-weighted) accelerations: the kick's force, Sect. 1.
  *   a_i = sum_{j != i} m_j K(r_ij) (r_j - r_i) / r_ij^3
  * ---------------------------------------------------------------------------------- */
-static void accel_row(int64_t n, int64_t i, const double *x, const double *y, const double *z,
-                      const double *m, const double *rc, double *ax, double *ay, double *az)
+static void accel_row(int64_t n, int64_t nm, int64_t i, const double *x, const double *y,
+                      const double *z, const double *m, const double *rc, double *ax, double *ay,
+                      double *az)
 {
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int64_t j = 0; j < n; ++j) {
         if (j == i) continue;
+        if (i >= nm && j >= nm) continue; /* two test bodies */
         double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
         double r2 = sep2(dx, dy, dz);
         double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
@@ -112,22 +117,22 @@ static void accel_row(int64_t n, int64_t i, const double *x, const double *y, co
     *az = sz;
 }
 
-void oracle_accel(int64_t n, const double *x, const double *y, const double *z, const double *m,
-                  const double *rc, double *ax, double *ay, double *az)
+void oracle_accel(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
+                  const double *m, const double *rc, double *ax, double *ay, double *az)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i)
-        accel_row(n, i, x, y, z, m, rc, &ax[i], &ay[i], &az[i]);
+        accel_row(n, nm, i, x, y, z, m, rc, &ax[i], &ay[i], &az[i]);
 }
 
 /* Same sum for a chosen subset of rows (used for sampled checks at large n). */
-void oracle_accel_rows(int64_t n, const double *x, const double *y, const double *z, const double *m,
-                       const double *rc, int64_t nrows, const int64_t *rows,
+void oracle_accel_rows(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
+                       const double *m, const double *rc, int64_t nrows, const int64_t *rows,
                        double *ax, double *ay, double *az)
 {
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < nrows; ++k)
-        accel_row(n, rows[k], x, y, z, m, rc, &ax[k], &ay[k], &az[k]);
+        accel_row(n, nm, rows[k], x, y, z, m, rc, &ax[k], &ay[k], &az[k]);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -135,12 +140,13 @@ void oracle_accel_rows(int64_t n, const double *x, const double *y, const double
  * lexicographic order.  Returns the number of pairs (which may exceed cap; only the
  * first cap are written).
  * ---------------------------------------------------------------------------------- */
-int64_t oracle_encounters(int64_t n, const double *x, const double *y, const double *z,
+int64_t oracle_encounters(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
                           const double *rc, int64_t cap, int32_t *pairs)
 {
     int64_t cnt = 0;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = i + 1; j < n; ++j) {
+            if (i >= nm && j >= nm) continue; /* test bodies do not meet each other */
             double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
             double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
             if (sep2(dx, dy, dz) < rcij * rcij) {
@@ -161,7 +167,7 @@ int64_t oracle_encounters(int64_t n, const double *x, const double *y, const dou
  *   L = sum m r x v
  * out[0] = E, out[1..3] = L.
  * ---------------------------------------------------------------------------------- */
-void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
+void oracle_energy(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
                    const double *vx, const double *vy, const double *vz, const double *m,
                    double mstar, double *out)
 {
@@ -182,6 +188,7 @@ void oracle_energy(int64_t n, const double *x, const double *y, const double *z,
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t j = i + 1; j < n; ++j) {
+            if (i >= nm && j >= nm) continue;
             double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
             s += m[j] / sqrt(sep2(dx, dy, dz));
         }
@@ -312,7 +319,7 @@ int oracle_kepler_drift(int64_t n, double *x, double *y, double *z, double *vx, 
 #define BS_KMAX 8
 
 static void group_rhs(int nb, const double *Y, double *D, const double *gm, const double *grc,
-                      double mstar)
+                      const uint8_t *gtest, double mstar)
 {
     /* Y = [x y z vx vy vz] per body, 6 doubles each */
     for (int a = 0; a < nb; ++a) {
@@ -330,6 +337,7 @@ static void group_rhs(int nb, const double *Y, double *D, const double *gm, cons
     for (int a = 0; a < nb; ++a) {
         for (int b = 0; b < nb; ++b) {
             if (b == a) continue;
+            if (gtest[a] && gtest[b]) continue;
             const double *ya = Y + 6 * a, *yb = Y + 6 * b;
             double dx = yb[0] - ya[0], dy = yb[1] - ya[1], dz = yb[2] - ya[2];
             double r2 = sep2(dx, dy, dz);
@@ -348,24 +356,24 @@ static void group_rhs(int nb, const double *Y, double *D, const double *gm, cons
 /* modified midpoint over H with nsub sub-steps: Y0 -> out */
 static void modified_midpoint(int nb, const double *Y0, double H, int nsub, double *out,
                               double *zm, double *zc, double *dd, const double *gm,
-                              const double *grc, double mstar)
+                              const double *grc, const uint8_t *gtest, double mstar)
 {
     int dim = 6 * nb;
     double h = H / nsub;
-    group_rhs(nb, Y0, dd, gm, grc, mstar);
+    group_rhs(nb, Y0, dd, gm, grc, gtest, mstar);
     for (int q = 0; q < dim; ++q) {
         zm[q] = Y0[q];
         zc[q] = Y0[q] + h * dd[q];
     }
     for (int k = 1; k < nsub; ++k) {
-        group_rhs(nb, zc, dd, gm, grc, mstar);
+        group_rhs(nb, zc, dd, gm, grc, gtest, mstar);
         for (int q = 0; q < dim; ++q) {
             double t = zm[q] + 2.0 * h * dd[q];
             zm[q] = zc[q];
             zc[q] = t;
         }
     }
-    group_rhs(nb, zc, dd, gm, grc, mstar);
+    group_rhs(nb, zc, dd, gm, grc, gtest, mstar);
     for (int q = 0; q < dim; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
@@ -374,8 +382,8 @@ static void modified_midpoint(int nb, const double *Y0, double H, int nsub, doub
  * (k = 7); a rejected step is multiplied by 0.9 (tol/err)^(1/15), err being the last
  * column's error estimate, kept within [1/50, 1/2].  Returns 1 (failure) if the step falls below
  * dt * 2^-40 or more than 20000 steps are attempted, else 0. */
-static int bs_group(int nb, double *Y, const double *gm, const double *grc, double mstar,
-                    double dt, double tol)
+static int bs_group(int nb, double *Y, const double *gm, const double *grc, const uint8_t *gtest,
+                    double mstar, double dt, double tol)
 {
     int dim = 6 * nb;
     /* tableau T[k][l] (l <= k), each a state vector */
@@ -399,7 +407,7 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
         int done = -1;
         double err = 0.0;
         for (int k = 0; k < BS_KMAX && done < 0; ++k) {
-            modified_midpoint(nb, Y, H, 2 * (k + 1), TAB(k, 0), zm, zc, dd, gm, grc, mstar);
+            modified_midpoint(nb, Y, H, 2 * (k + 1), TAB(k, 0), zm, zc, dd, gm, grc, gtest, mstar);
             for (int l = 1; l <= k; ++l) {
                 double ratio = (double)(k + 1) / (double)(k + 1 - l); /* n_k / n_{k-l} */
                 double den = ratio * ratio - 1.0;
@@ -432,25 +440,28 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, doub
 }
 
 /* Public wrapper: integrate bodies idx[0..nb-1] (a group) of the full arrays in place. */
-int oracle_bs_group(int nb, const int32_t *idx, double *x, double *y, double *z, double *vx,
-                    double *vy, double *vz, const double *m, const double *rc, double mstar,
-                    double dt, double tol)
+int oracle_bs_group(int nb, const int32_t *idx, int64_t nm, double *x, double *y, double *z,
+                    double *vx, double *vy, double *vz, const double *m, const double *rc,
+                    double mstar, double dt, double tol)
 {
     double *Y = (double *)malloc(sizeof(double) * (size_t)(8 * nb));
     double *gm = Y + 6 * nb, *grc = gm + nb;
+    uint8_t *gtest = (uint8_t *)malloc((size_t)nb);
     for (int a = 0; a < nb; ++a) {
         int32_t i = idx[a];
         Y[6 * a + 0] = x[i]; Y[6 * a + 1] = y[i]; Y[6 * a + 2] = z[i];
         Y[6 * a + 3] = vx[i]; Y[6 * a + 4] = vy[i]; Y[6 * a + 5] = vz[i];
         gm[a] = m[i];
         grc[a] = rc[i];
+        gtest[a] = i >= nm;
     }
-    int st = bs_group(nb, Y, gm, grc, mstar, dt, tol);
+    int st = bs_group(nb, Y, gm, grc, gtest, mstar, dt, tol);
     for (int a = 0; a < nb; ++a) {
         int32_t i = idx[a];
         x[i] = Y[6 * a + 0]; y[i] = Y[6 * a + 1]; z[i] = Y[6 * a + 2];
         vx[i] = Y[6 * a + 3]; vy[i] = Y[6 * a + 4]; vz[i] = Y[6 * a + 5];
     }
+    free(gtest);
     free(Y);
     return st;
 }
@@ -500,9 +511,9 @@ int64_t oracle_groups(int64_t n, int64_t npairs, const int32_t *pairs, int64_t *
  * outside encounter groups and Bulirsch-Stoer for each group, then Sun drift(dt/2).
  * Returns 0 on success, 1 if a Kepler solve or a BS step failed.
  * ---------------------------------------------------------------------------------- */
-int oracle_drift(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
-                 const double *m, const double *rc, double mstar, double dt, int64_t npairs,
-                 const int32_t *pairs, double tol)
+int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                 double *vz, const double *m, const double *rc, double mstar, double dt,
+                 int64_t npairs, const int32_t *pairs, double tol)
 {
     int bad = 0;
     oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, 0.5 * dt);
@@ -516,7 +527,7 @@ int oracle_drift(int64_t n, double *x, double *y, double *z, double *vx, double 
         int nb = 0;
         for (int64_t i = 0; i < n; ++i)
             if (gid[i] == g) members[nb++] = (int32_t)i;
-        bad |= oracle_bs_group(nb, members, x, y, z, vx, vy, vz, m, rc, mstar, dt, tol);
+        bad |= oracle_bs_group(nb, members, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, tol);
     }
     free(members);
     free(skip);
@@ -526,11 +537,11 @@ int oracle_drift(int64_t n, double *x, double *y, double *z, double *vx, double 
 }
 
 /* v += tau * a_K */
-static void kick(int64_t n, const double *x, const double *y, const double *z, double *vx,
-                 double *vy, double *vz, const double *m, const double *rc, double tau,
+static void kick(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
+                 double *vx, double *vy, double *vz, const double *m, const double *rc, double tau,
                  double *ax, double *ay, double *az)
 {
-    oracle_accel(n, x, y, z, m, rc, ax, ay, az);
+    oracle_accel(n, nm, x, y, z, m, rc, ax, ay, az);
     for (int64_t i = 0; i < n; ++i) {
         vx[i] += tau * ax[i];
         vy[i] += tau * ay[i];
@@ -545,9 +556,9 @@ static void kick(int64_t n, const double *x, const double *y, const double *z, d
  * when k is a multiple of cadence (k = 0 is the initial state); the caller sizes it.
  * Returns 0 on success.
  * ---------------------------------------------------------------------------------- */
-int oracle_step(int64_t n, double *x, double *y, double *z, double *vx, double *vy, double *vz,
-                const double *m, const double *rc, double mstar, double dt, int64_t nsteps,
-                double tol, int64_t cadence, double *energy)
+int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                double *vz, const double *m, const double *rc, double mstar, double dt,
+                int64_t nsteps, double tol, int64_t cadence, double *energy)
 {
     double *ax = (double *)malloc(sizeof(double) * (size_t)(3 * (n > 0 ? n : 1)));
     double *ay = ax + n, *az = ay + n;
@@ -555,20 +566,20 @@ int oracle_step(int64_t n, double *x, double *y, double *z, double *vx, double *
     int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
     int bad = 0;
     int64_t e_idx = 0;
-    if (energy && cadence > 0) oracle_energy(n, x, y, z, vx, vy, vz, m, mstar, energy + 4 * e_idx++);
+    if (energy && cadence > 0) oracle_energy(n, nm, x, y, z, vx, vy, vz, m, mstar, energy + 4 * e_idx++);
     for (int64_t s = 1; s <= nsteps; ++s) {
-        kick(n, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
-        int64_t np = oracle_encounters(n, x, y, z, rc, cap, pairs);
+        kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
+        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
         if (np > cap) {
             free(pairs);
             cap = np;
             pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
-            np = oracle_encounters(n, x, y, z, rc, cap, pairs);
+            np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
         }
-        bad |= oracle_drift(n, x, y, z, vx, vy, vz, m, rc, mstar, dt, np, pairs, tol);
-        kick(n, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
+        bad |= oracle_drift(n, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, np, pairs, tol);
+        kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
         if (energy && cadence > 0 && s % cadence == 0)
-            oracle_energy(n, x, y, z, vx, vy, vz, m, mstar, energy + 4 * e_idx++);
+            oracle_energy(n, nm, x, y, z, vx, vy, vz, m, mstar, energy + 4 * e_idx++);
     }
     free(pairs);
     free(ax);

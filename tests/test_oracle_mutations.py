@@ -45,6 +45,10 @@ MUTATIONS = [
     ("first half-kick length", "kick(n, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);\n        int64_t np",
      "kick(n, x, y, z, vx, vy, vz, m, rc, dt, ax, ay, az);\n        int64_t np"),
     ("Hill radius factor 3", "double rh = a * cbrt(m[i] / (3.0 * mstar));", "double rh = a * cbrt(m[i] / mstar);"),
+    ("TP2 test bodies interact", "        if (i >= nm && j >= nm) continue; /* two test bodies */\n", ""),
+    ("TP2 energy keeps test pairs", "            if (i >= nm && j >= nm) continue;\n            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]",
+     "            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]"),
+    ("TP2 BS keeps test pairs", "            if (gtest[a] && gtest[b]) continue;\n", ""),
     ("encounter self pairs", "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i + 1;",
      "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i;"),
 ]

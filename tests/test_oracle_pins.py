@@ -450,3 +450,99 @@ def test_step_through_dense_embryo_encounters():
     assert np.max(np.abs(e[:, 0] / e[0, 0] - 1)) < 1e-7
     L = np.linalg.norm(e[:, 1:], axis=1)
     assert np.max(np.abs(L / L[0] - 1)) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# TP2 mode (Sect. 3.3): test bodies feel and exert forces on the massive bodies only
+# ------------------------------------------------------------------------------------------
+
+def test_tp2_three_body_closed_form():
+    pts = np.array([[1.0, 0.0, 0.0], [1.3, 0.4, 0.0], [0.6, -0.3, 0.1]])
+    m = np.array([1e-3, 2e-6, 5e-6])
+    st = state(pts, m=m)
+    a = np.stack(oracle.accel(st, np.zeros(3), n_massive=1), axis=1)
+
+    def term(i, j):
+        d = pts[j] - pts[i]
+        return m[j] * d / np.linalg.norm(d) ** 3
+    np.testing.assert_allclose(a[0], term(0, 1) + term(0, 2), rtol=1e-14)
+    np.testing.assert_allclose(a[1], term(1, 0), rtol=1e-14)        # no pull from body 2
+    np.testing.assert_allclose(a[2], term(2, 0), rtol=1e-14)
+    # all bodies massive: the full sum; none massive: nothing
+    full = np.stack(oracle.accel(st, np.zeros(3)), axis=1)
+    np.testing.assert_allclose(full[1], term(1, 0) + term(1, 2), rtol=1e-14)
+    assert np.all(np.stack(oracle.accel(st, np.zeros(3), n_massive=0)) == 0.0)
+
+
+def test_tp2_force_is_minus_gradient_of_energy():
+    rng = np.random.default_rng(8)
+    n, nm = 7, 3
+    pts = rng.normal(size=(n, 3)) * 0.3 + np.array([1.0, 0.5, 0.0])
+    m = rng.uniform(1e-6, 1e-4, n)
+    st = state(pts, m=m)
+    a = np.stack(oracle.accel(st, np.zeros(n), n_massive=nm), axis=1)
+    h = 1e-6
+    for i in range(n):
+        for q, key in enumerate("xyz"):
+            sp, sm = {k: v.copy() for k, v in st.items()}, {k: v.copy() for k, v in st.items()}
+            sp[key][i] += h
+            sm[key][i] -= h
+            g = (oracle.energy(sp, 1.0, n_massive=nm)[0] - oracle.energy(sm, 1.0, n_massive=nm)[0]) / (2 * h)
+            r = np.linalg.norm(pts[i])
+            # central differences of an O(1e-4) energy with h = 1e-6: ~1e-14 of round-off
+            assert -g == pytest.approx(-m[i] * pts[i, q] / r**3 + m[i] * a[i, q], rel=1e-6, abs=1e-13)
+    assert np.max(np.abs((m[:, None] * a).sum(axis=0))) < 1e-14 * np.sum(m[:, None] * np.abs(a))
+
+
+def test_tp2_encounters_exclude_test_pairs():
+    d = discs.make_disc(600, 2.5, seed=13, a_in=0.9, a_out=1.0, sigma_e=0.001, sigma_i=0.001,
+                        n_embryo=10, embryo_mass_earth=0.05)
+    st = d.state()
+    rc = oracle.rcrit(st, 1.0, 3.0, 0.0, discs.DT_6_DAYS)
+    full = oracle.encounters(st, rc)
+    tp2 = oracle.encounters(st, rc, n_massive=10)
+    keep = full[full[:, 0] < 10]
+    np.testing.assert_array_equal(tp2, keep)
+    assert len(full) > len(tp2) > 0
+
+
+def test_tp2_bs_group_against_numerical_integration():
+    from scipy.integrate import solve_ivp
+    rc = np.array([0.02, 0.02, 0.02])
+    m = np.array([3e-6, 1e-9, 1e-9])
+    p0 = np.array([1.0, 0.0, 0.0])
+    pts = np.array([p0, p0 + [0.0, 0.004, 0.0], p0 + [0.004, 0.0, 0.001]])
+    vel = np.array([[0, 1.0, 0], [-0.02, 1.0, 0.0], [0.0, 1.02, 0.0]])
+    st = state(pts, vel, m)
+    dt = 0.02
+    got = oracle.bs_group(st, rc, [0, 1, 2], 1.0, dt, n_massive=1)
+
+    def rhs(t, y):
+        Y = y.reshape(3, 6)
+        out = np.zeros_like(Y)
+        out[:, :3] = Y[:, 3:]
+        for a_ in range(3):
+            out[a_, 3:] = -Y[a_, :3] / np.linalg.norm(Y[a_, :3]) ** 3
+            for b in range(3):
+                if a_ == b or (a_ >= 1 and b >= 1):
+                    continue
+                dv = Y[b, :3] - Y[a_, :3]
+                rr = np.linalg.norm(dv)
+                R = max(rc[a_], rc[b])
+                w = 1.0 - (oracle.changeover((rr - 0.1 * R) / (0.9 * R)) if rr < R else 1.0)
+                out[a_, 3:] += m[b] * w * dv / rr**3
+        return out.ravel()
+    y0 = np.concatenate([pts, vel], axis=1).ravel()
+    ref = solve_ivp(rhs, (0, dt), y0, rtol=1e-13, atol=1e-16, method="DOP853").y[:, -1].reshape(3, 6)
+    g = np.concatenate([vec(got), vec(got, ("vx", "vy", "vz"))], axis=1)
+    assert np.max(np.abs(g - ref)) < 1e-10
+
+
+def test_tp2_step_conserves_its_energy():
+    d = discs.make_disc(400, 2.0, seed=14, a_in=0.7, a_out=1.0, n_embryo=5, embryo_mass_earth=0.5)
+    st = d.state()
+    rc = oracle.rcrit(st, 1.0, 3.0, 0.0, discs.DT_6_DAYS)
+    _, e = oracle.step(st, rc, 1.0, discs.DT_6_DAYS, 60, cadence=10, n_massive=5)
+    assert np.max(np.abs(e[:, 0] / e[0, 0] - 1)) < 1e-7
+    L = np.linalg.norm(e[:, 1:], axis=1)
+    assert np.max(np.abs(L / L[0] - 1)) < 1e-13
