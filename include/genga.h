@@ -82,6 +82,13 @@ int genga_destroy(genga_ctx *ctx);
 int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host,
                       const double *mstar_host, int32_t pair_capacity);
 
+/* TP2 mode (Sect. 3.3): in system s the first n_massive_host[s] bodies are massive and the
+ * rest are test bodies, which feel and exert forces on the massive bodies but do not
+ * interact with each other (no mutual force, no encounter pair, no pair energy).  NULL makes
+ * every body massive (the default after genga_set_systems).  Rebuilds the launch plan,
+ * synchronises the device and drops any captured graph. */
+int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host);
+
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
  * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).

@@ -55,9 +55,11 @@ __global__ __launch_bounds__(64 * EW) void energy_kernel(
         const double xi = x[i], yi = y[i], zi = z[i];
         // sources j in [i0, end of system), split into `split` parts over workgroups and each
         // part over the waves; only j > i counts
-        const int per = (sys_off[w.sys + 1] - w.i0 + split - 1) / split;
-        const int p0 = min(w.i0 + part * per, sys_off[w.sys + 1]);
-        const int p1 = min(p0 + per, sys_off[w.sys + 1]);
+        // test-body items have nsrc <= i0 - off: no pair terms (test pairs do not count)
+        const int jend = max(sys_off[w.sys] + w.nsrc, w.i0);
+        const int per = (jend - w.i0 + split - 1) / split;
+        const int p0 = min(w.i0 + part * per, jend);
+        const int p1 = min(p0 + per, jend);
         const int chunk = (p1 - p0 + EW - 1) / EW;
         const int jb = min(p0 + wave * chunk, p1), je = min(jb + chunk, p1);
         double s = 0.0;

@@ -427,6 +427,8 @@ struct LaneGroup {
     double m, rc, mstar;
     double (*sp)[BS_LANES]; // [3][64] positions of the members
     const double *sm, *src; // [64] masses and critical radii of the members
+    bool test;              // this member is a test body (TP2)
+    const int32_t *stest;   // [64] members that are test bodies
 };
 
 // dY/dt for this lane's member: Kepler term about the Sun plus the (1 - K) share of the
@@ -443,6 +445,7 @@ __device__ void lane_deriv(const LaneGroup &g, const double y[6], double d[6])
     double ax = s * y[0], ay = s * y[1], az = s * y[2];
     for (int b = 0; b < g.nb; ++b) {
         if (b == g.a) continue;
+        if (g.test && g.stest[b]) continue; // two test bodies do not interact
         const double dx = g.sp[0][b] - y[0], dy = g.sp[1][b] - y[1], dz = g.sp[2][b] - y[2];
         const double q = sep2_rn(dx, dy, dz);
         const double rcij = fmax(g.rc, g.src[b]);
@@ -572,6 +575,7 @@ struct ColGroup {
     double mstar;
     // per partner b (constant over the step): r_crit,ab^2, 0.1 r_crit,ab, 1/(0.9 r_crit,ab), m_b
     double rc2[CP_MEM], r01[CP_MEM], inv09[CP_MEM], mb[CP_MEM];
+    bool skip[CP_MEM]; // both this member and partner b are test bodies (TP2)
 };
 
 // 1/sqrt(q) in FP64: v_rsq_f64 (about 2^-24) and one third-order correction
@@ -596,7 +600,7 @@ __device__ void col_deriv(const ColGroup &g, const double y[6], double d[6])
         const double xb = __shfl(y[0], g.base + b, 64);
         const double yb = __shfl(y[1], g.base + b, 64);
         const double zb = __shfl(y[2], g.base + b, 64);
-        if (b == g.a) continue;
+        if (b == g.a || g.skip[b]) continue;
         const double dx = xb - y[0], dy = yb - y[1], dz = zb - y[2];
         const double q = sep2_rn(dx, dy, dz);
         if (!(q < g.rc2[b])) continue;
@@ -690,7 +694,8 @@ __device__ bool col_bs(const ColGroup &g, double Y[6], double dt, double tol)
     return true;
 }
 
-__global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, const double *mstar,
+__global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, const int32_t *sys_off,
+                                                         const int32_t *n_massive, const double *mstar,
                                                          const double *x, const double *y,
                                                          const double *z, const double *vx,
                                                          const double *vy, const double *vz,
@@ -702,6 +707,7 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
 {
     __shared__ double sp[3][BS_LANES];
     __shared__ double sm[BS_LANES], src[BS_LANES];
+    __shared__ int32_t stest[BS_LANES];
     const int g = blockIdx.x;
     if (g >= *n_groups) return;
     const int k0 = group_start[g], nb = group_start[g + 1] - k0;
@@ -729,9 +735,12 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
         const int k = a / CP_MEM, am = a % CP_MEM;
         const bool act = am < nb;
         const int b = members[k0 + (act ? am : 0)];
+        const int sb = sys_of[b];
+        const bool is_test = b - sys_off[sb] >= n_massive[sb];
         if (k == 0) {
             sm[am] = act ? m[b] : 0.0;
             src[am] = act ? rc[b] : 0.0;
+            stest[am] = act && is_test;
         }
         __syncthreads();
         ColGroup cg;
@@ -749,6 +758,7 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
             cg.r01[p] = 0.1 * rcij;
             cg.inv09[p] = 1.0 / (0.9 * rcij);
             cg.mb[p] = sm[p];
+            cg.skip[p] = is_test && stest[p];
         }
         double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
         const bool ok = col_bs(cg, Y, dt, 1e-12);
@@ -761,10 +771,13 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
     }
     const bool act = a < nb;
     const int b = members[k0 + (act ? a : 0)];
+    const int sb = sys_of[b];
+    const bool is_test = b - sys_off[sb] >= n_massive[sb];
     sm[a] = act ? m[b] : 0.0;
     src[a] = act ? rc[b] : 0.0;
+    stest[a] = act && is_test;
     __syncthreads();
-    LaneGroup lg{a, nb, act, m[b], rc[b], ms, sp, sm, src};
+    LaneGroup lg{a, nb, act, m[b], rc[b], ms, sp, sm, src, is_test, stest};
     double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
     const bool ok = lane_bs(lg, Y, dt, 1e-12);
     if (act) {
@@ -805,7 +818,8 @@ hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const
                         int32_t *flags, hipStream_t stream)
 {
     // one wave per group; at most CE_MAX_MEMBERS / 2 groups (every group has >= 2 members)
-    ce_bs_kernel<<<CE_MAX_MEMBERS / 2, BS_LANES, 0, stream>>>(L.sys_of, L.mstar, x, y, z, vx, vy, vz, m, rc,
+    ce_bs_kernel<<<CE_MAX_MEMBERS / 2, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar,
+                                                              x, y, z, vx, vy, vz, m, rc,
                                                               dt, members, group_start, n_groups, bs_out,
                                                               flags);
     return hipGetLastError();

@@ -57,6 +57,8 @@ struct genga_ctx {
     int n_cu = 256;
     Layout L;
     std::vector<int32_t> sys_off_h;
+    std::vector<int32_t> n_massive_h; // per system; bodies beyond are TP2 test bodies
+    size_t max_items = 0;
     // launch plan
     WorkItem *items = nullptr;  // kick items, largest systems first
     int32_t n_items = 0;
@@ -99,6 +101,7 @@ struct genga_ctx {
         dfree(mom_part);
         dfree(L.chunks);
         dfree(L.chunk_first);
+        dfree(L.n_massive);
         dfree(acc);
         dfree(pairs);
         dfree(pair_count);
@@ -252,6 +255,36 @@ int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int pre
     return GENGA_OK;
 }
 
+// Work items: 64 consecutive bodies of one system, never mixing massive and test bodies;
+// massive targets visit every body of their system, test targets only the massive ones.
+// Kick items are ordered by work (largest first), energy items by system.
+int upload_plan(genga_ctx *ctx)
+{
+    const int n_sys = ctx->L.n_sys;
+    std::vector<WorkItem> it;
+    std::vector<int32_t> first(n_sys + 1, 0);
+    for (int s = 0; s < n_sys; ++s) {
+        first[s] = (int32_t)it.size();
+        const int b = ctx->sys_off_h[s], e = ctx->sys_off_h[s + 1];
+        const int nm = ctx->n_massive_h[s];
+        for (int i0 = b; i0 < b + nm; i0 += 64) it.push_back(WorkItem{s, i0, std::min(64, b + nm - i0), e - b});
+        for (int i0 = b + nm; i0 < e; i0 += 64) it.push_back(WorkItem{s, i0, std::min(64, e - i0), nm});
+    }
+    first[n_sys] = (int32_t)it.size();
+    if (it.size() > ctx->max_items) return fail(GENGA_ERR_STATE, "work plan larger than its allocation");
+    std::vector<WorkItem> kit = it;
+    std::stable_sort(kit.begin(), kit.end(), [](const WorkItem &a, const WorkItem &b) { return a.nsrc > b.nsrc; });
+    ctx->n_items = (int32_t)it.size();
+    if (!it.empty()) {
+        HIP_TRY(hipMemcpy(ctx->items, kit.data(), kit.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->eitems, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(ctx->item_first, first.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->L.n_massive, ctx->n_massive_h.data(), n_sys * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
+    return GENGA_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -304,14 +337,6 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     ctx->sys_off_h.assign(sys_off_host, sys_off_host + n_sys + 1);
 
     // work items: 64 consecutive bodies of one system
-    std::vector<WorkItem> it;
-    std::vector<int32_t> first(n_sys + 1, 0);
-    for (int s = 0; s < n_sys; ++s) {
-        first[s] = (int32_t)it.size();
-        const int b = sys_off_host[s], e = sys_off_host[s + 1];
-        for (int i0 = b; i0 < e; i0 += 64) it.push_back(WorkItem{s, i0, std::min(64, e - i0), e - b});
-    }
-    first[n_sys] = (int32_t)it.size();
     std::vector<Chunk> chunks;
     std::vector<int32_t> cfirst(n_sys + 1, 0);
     for (int s = 0; s < n_sys; ++s) {
@@ -320,9 +345,6 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
             chunks.push_back(Chunk{s, b, std::min(b + CHUNK, sys_off_host[s + 1]), 0});
     }
     cfirst[n_sys] = (int32_t)chunks.size();
-    std::vector<WorkItem> kit = it;
-    std::stable_sort(kit.begin(), kit.end(), [](const WorkItem &a, const WorkItem &b) { return a.cost > b.cost; });
-    ctx->n_items = (int32_t)it.size();
 
     std::vector<int32_t> sys_of(n_total);
     for (int s = 0; s < n_sys; ++s)
@@ -337,9 +359,14 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->L.sys_off, n_sys + 1));
     HIP_TRY(dalloc(ctx->L.sys_of, nt));
     HIP_TRY(dalloc(ctx->L.mstar, n_sys));
-    HIP_TRY(dalloc(ctx->items, it.size()));
-    HIP_TRY(dalloc(ctx->eitems, it.size()));
+    // at most one more item per system when the massive / test boundary splits a block
+    size_t max_items = 0;
+    for (int s = 0; s < n_sys; ++s) max_items += (size_t)(sys_off_host[s + 1] - sys_off_host[s] + 63) / 64 + 1;
+    ctx->max_items = max_items;
+    HIP_TRY(dalloc(ctx->items, max_items));
+    HIP_TRY(dalloc(ctx->eitems, max_items));
     HIP_TRY(dalloc(ctx->item_first, n_sys + 1));
+    HIP_TRY(dalloc(ctx->L.n_massive, n_sys));
     HIP_TRY(dalloc(ctx->jrec, nt * 32));
     HIP_TRY(dalloc(ctx->L.chunks, chunks.size()));
     HIP_TRY(dalloc(ctx->L.chunk_first, n_sys + 1));
@@ -358,17 +385,13 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->n_groups, 1));
     HIP_TRY(dalloc(ctx->member_slot, nt));
     HIP_TRY(dalloc(ctx->bs_out, 6 * (size_t)CE_MAX_MEMBERS));
-    HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * it.size()));
+    HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * max_items));
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
 
     HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nt) HIP_TRY(hipMemcpy(ctx->L.sys_of, sys_of.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->L.mstar, mstar_host, n_sys * sizeof(double), hipMemcpyHostToDevice));
-    if (!it.empty()) {
-        HIP_TRY(hipMemcpy(ctx->items, kit.data(), kit.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(ctx->eitems, it.data(), it.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-    }
-    HIP_TRY(hipMemcpy(ctx->item_first, first.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+
     if (!chunks.empty())
         HIP_TRY(hipMemcpy(ctx->L.chunks, chunks.data(), chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->L.chunk_first, cfirst.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -383,8 +406,32 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     ctx->L.n_sys = n_sys;
     ctx->L.n_total = n_total;
     ctx->L.n_chunks = (int32_t)chunks.size();
+    ctx->n_massive_h.assign(sys_off_host, sys_off_host + n_sys);
+    for (int s = 0; s < n_sys; ++s) ctx->n_massive_h[s] = sys_off_host[s + 1] - sys_off_host[s];
+    rc = upload_plan(ctx);
+    if (rc) return rc;
     ctx->split[0] = ctx->split[1] = default_split(ctx);
     return GENGA_OK;
+}
+
+int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    const int n_sys = ctx->L.n_sys;
+    for (int s = 0; s < n_sys; ++s) {
+        const int ns = ctx->sys_off_h[s + 1] - ctx->sys_off_h[s];
+        const int nm = n_massive_host ? n_massive_host[s] : ns;
+        if (nm < 0 || nm > ns) return fail(GENGA_ERR_ARG, "n_massive[%d] = %d outside [0, %d]", s, nm, ns);
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    for (int s = 0; s < n_sys; ++s)
+        ctx->n_massive_h[s] = n_massive_host ? n_massive_host[s] : ctx->sys_off_h[s + 1] - ctx->sys_off_h[s];
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    return upload_plan(ctx);
 }
 
 int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, double dt, double *rc_out,

@@ -8,12 +8,14 @@
 
 namespace genga {
 
-// One unit of kick / energy work: up to 64 consecutive bodies (one per lane) of one system.
+// One unit of kick / energy work: up to 64 consecutive bodies (one per lane) of one system,
+// all massive or all test bodies.
 struct WorkItem {
     int32_t sys;
     int32_t i0;   // first body (global index)
     int32_t ni;   // number of bodies, 1..64
-    int32_t cost; // sources to visit (system size), used for ordering
+    int32_t nsrc; // sources: the first nsrc bodies of the system (all, or the massive ones
+                  // for test-body targets)
 };
 
 // Source ("j") records, rebuilt from the SoA state before each kick; 32 bytes so that one
@@ -55,6 +57,7 @@ struct Layout {
     double *mstar = nullptr;        // device [n_sys]
     Chunk *chunks = nullptr;        // device [n_chunks], systems in order
     int32_t *chunk_first = nullptr; // device [n_sys + 1]
+    int32_t *n_massive = nullptr;   // device [n_sys]: bodies [off, off + n_massive) are massive
 };
 
 struct KickArgs {

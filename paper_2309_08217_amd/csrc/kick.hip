@@ -151,11 +151,12 @@ __device__ __forceinline__ void far64(double mj, double dx, double dy, double dz
     sz = fma(s, dz, sz);
 }
 
-// Sources of system s visited by part `part` of an item when the source range is split
-// over a.split workgroups.
-__device__ __forceinline__ void source_range(const KickArgs &a, int s, int part, int &j0, int &j1)
+// Sources visited by part `part` of an item when its source range (the first w.nsrc bodies
+// of the system) is split over a.split workgroups.
+__device__ __forceinline__ void source_range(const KickArgs &a, const WorkItem &w, int part, int &j0,
+                                             int &j1)
 {
-    const int b = a.sys_off[s], e = a.sys_off[s + 1];
+    const int b = a.sys_off[w.sys], e = b + w.nsrc;
     const int per = (e - b + a.split - 1) / a.split;
     j0 = min(b + part * per, e);
     j1 = min(j0 + per, e);
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
         const int part = task % a.split;
         const WorkItem w = a.items[task / a.split];
         int j0, j1;
-        source_range(a, w.sys, part, j0, j1);
+        source_range(a, w, part, j0, j1);
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
         const int part = task % a.split;
         const WorkItem w = a.items[task / a.split];
         int j0, j1;
-        source_range(a, w.sys, part, j0, j1);
+        source_range(a, w, part, j0, j1);
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
