@@ -160,6 +160,7 @@ def batched(torch, stream, steps=10, warmup=2):
     ctx, b, st, off = setup(ds, torch)
     genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
     t, e_rec, e_init, status = time_steps(ctx, b, genga.GENGA_KICK_FP32, steps, warmup, len(ds), torch, stream)
+    t_graph = time_graph(ctx, b, genga.GENGA_KICK_FP32, steps, torch, stream)
     pairs = float(sum(d.n * (d.n - 1) for d in ds))
     # the same discs stepped one context after another (64 launches per kernel per step)
     singles = []
@@ -183,6 +184,7 @@ def batched(torch, stream, steps=10, warmup=2):
     ctx.close()
     return {"workload": "64 discs, N uniform in [2000, 8000] (seeds 1000+s), 2.5 Earth masses each",
             "n_total": int(off[-1]), "steps": steps, "steps_per_s": steps / t,
+            "graph_steps_per_s": 1.0 / t_graph,
             "pair_interactions_per_s_G": pairs * steps / t / 1e9,
             "loop_of_single_disc_launches_steps_per_s": steps / t_loop,
             "speedup_vs_loop": t_loop / t, "status": status, **drift_stats(e_init, e_rec)}
