@@ -71,7 +71,6 @@ struct genga_ctx {
     // scratch
     uint8_t *jrec = nullptr;    // 32 B per body
     double *rc2_part = nullptr;   // [n_chunks]
-    double *umass = nullptr;      // [ceil(n_total / 64)]
     double *mom_part = nullptr;   // [n_chunks][3]
     double *acc = nullptr;      // a_i of the last kick: [3][n_total]
     int32_t *pairs = nullptr;
@@ -97,7 +96,6 @@ struct genga_ctx {
         dfree(item_first);
         dfree(jrec);
         dfree(rc2_part);
-        dfree(umass);
         dfree(mom_part);
         dfree(L.chunks);
         dfree(L.chunk_first);
@@ -175,7 +173,7 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
     const int fp32 = prec == GENGA_KICK_FP32;
-    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->umass, ctx->pair_count, s));
+    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->pair_count, s));
     KickArgs a;
     a.items = ctx->items;
     a.n_items = ctx->n_items;
@@ -191,7 +189,6 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     a.jrec = ctx->jrec;
     a.rc2_part = ctx->rc2_part;
     a.chunk_first = L.chunk_first;
-    a.umass = ctx->umass;
     a.ax = ax;
     a.ay = ay;
     a.az = az;
@@ -371,7 +368,6 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->L.chunks, chunks.size()));
     HIP_TRY(dalloc(ctx->L.chunk_first, n_sys + 1));
     HIP_TRY(dalloc(ctx->rc2_part, chunks.size()));
-    HIP_TRY(dalloc(ctx->umass, (nt + 63) / 64));
     HIP_TRY(dalloc(ctx->mom_part, 3 * chunks.size()));
     HIP_TRY(dalloc(ctx->acc, 3 * nt));
     HIP_TRY(dalloc(ctx->pairs, 2 * (size_t)cap));

@@ -70,7 +70,6 @@ struct KickArgs {
     const void *jrec;             // JRec32[] or JRec64[]
     const double *rc2_part;       // [n_chunks] max r_crit^2 per chunk
     const int32_t *chunk_first;   // [n_sys + 1]
-    const double *umass;          // [ceil(n_total/64)] mass of each aligned 64-source block, or -1
     double *ax, *ay, *az;         // a_i out (FP64), always written
     double tau;
     int32_t update_v;
@@ -89,7 +88,7 @@ constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in th
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
                        const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
-                       double *umass, int32_t *pair_count, hipStream_t stream);
+                       int32_t *pair_count, hipStream_t stream);
 hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream);
 hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz, const double *m,

@@ -123,19 +123,15 @@ struct Acc32 {
     float fx, fy, fz;
 };
 
-// Far pair in FP32.  With UM (a block of sources of one mass) the mass is applied when the
-// block's partial sum is folded, so the pair term is r^-3 d only.
-template <bool UM>
 __device__ __forceinline__ void far32(float mj, float dx, float dy, float dz, float q, Acc32 &c)
 {
     float ri = __builtin_amdgcn_rsqf(q);
-    float s = UM ? (ri * ri) * ri : mj * (ri * ri) * ri;
+    float s = mj * (ri * ri) * ri;
     c.fx = fmaf(s, dx, c.fx);
     c.fy = fmaf(s, dy, c.fy);
     c.fz = fmaf(s, dz, c.fz);
 }
 
-template <bool UM>
 __device__ __forceinline__ void far64(double mj, double dx, double dy, double dz, double q,
                                       double &sx, double &sy, double &sz)
 {
@@ -145,7 +141,7 @@ __device__ __forceinline__ void far64(double mj, double dx, double dy, double dz
     double e = fma(-t, y0, 1.0);
     double p = fma(0.375, e, 0.5);
     double y = fma(y0 * e, p, y0);
-    double s = UM ? (y * y) * y : mj * (y * y) * y;
+    double s = mj * (y * y) * y;
     sx = fma(s, dx, sx);
     sy = fma(s, dy, sy);
     sz = fma(s, dz, sz);
@@ -229,123 +225,6 @@ __global__ __launch_bounds__(256) void kick_finish_kernel(KickArgs a)
     }
 }
 
-// Sources [j, jend) for one lane's target in FP32: four at a time, one candidate test per
-// four, exact FP64 handling of candidates (close_pair), partial sums into c.
-__device__ __forceinline__ void group32(const KickArgs &a, CJ32 *J, int j, float T, int i, bool valid,
-                                        double xi, double yi, double zi, double rci, bool um, Acc32 &c,
-                                        double &sx, double &sy, double &sz)
-{
-    const JRec32 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
-    float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
-    float dx1 = (float)(r1.x - xi), dy1 = (float)(r1.y - yi), dz1 = (float)(r1.z - zi);
-    float dx2 = (float)(r2.x - xi), dy2 = (float)(r2.y - yi), dz2 = (float)(r2.z - zi);
-    float dx3 = (float)(r3.x - xi), dy3 = (float)(r3.y - yi), dz3 = (float)(r3.z - zi);
-    float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
-    float q1 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
-    float q2 = fmaf(dx2, dx2, fmaf(dy2, dy2, dz2 * dz2));
-    float q3 = fmaf(dx3, dx3, fmaf(dy3, dy3, dz3 * dz3));
-    const bool near = fminf(fminf(q0, q1), fminf(q2, q3)) < T;
-    if (__builtin_expect(near, 0)) {
-        if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far32<true>(r0.m, dx0, dy0, dz0, q0, c) : far32<false>(r0.m, dx0, dy0, dz0, q0, c);
-        if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far32<true>(r1.m, dx1, dy1, dz1, q1, c) : far32<false>(r1.m, dx1, dy1, dz1, q1, c);
-        if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far32<true>(r2.m, dx2, dy2, dz2, q2, c) : far32<false>(r2.m, dx2, dy2, dz2, q2, c);
-        if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far32<true>(r3.m, dx3, dy3, dz3, q3, c) : far32<false>(r3.m, dx3, dy3, dz3, q3, c);
-    } else if (um) {
-        far32<true>(r0.m, dx0, dy0, dz0, q0, c);
-        far32<true>(r1.m, dx1, dy1, dz1, q1, c);
-        far32<true>(r2.m, dx2, dy2, dz2, q2, c);
-        far32<true>(r3.m, dx3, dy3, dz3, q3, c);
-    } else {
-        far32<false>(r0.m, dx0, dy0, dz0, q0, c);
-        far32<false>(r1.m, dx1, dy1, dz1, q1, c);
-        far32<false>(r2.m, dx2, dy2, dz2, q2, c);
-        far32<false>(r3.m, dx3, dy3, dz3, q3, c);
-    }
-}
-
-// Sources [j, jend) for one lane's target in FP32: four at a time, one candidate test per
-// four, exact FP64 handling of candidates (close_pair), partial sums into c.  With um (all
-// sources of the block have one mass) the mass is left out of the pair term and applied by
-// the caller when it folds c.
-__device__ __forceinline__ void block32(const KickArgs &a, CJ32 *J, int j, int jend, float T, int i,
-                                        bool valid, double xi, double yi, double zi, double rci,
-                                        bool um, Acc32 &c, double &sx, double &sy, double &sz)
-{
-#pragma unroll 1
-    for (; j + 4 <= jend; j += 4) group32(a, J, j, T, i, valid, xi, yi, zi, rci, um, c, sx, sy, sz);
-#pragma unroll 1
-    for (; j < jend; ++j) {
-        const JRec32 r0 = ldj(J, j);
-        float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
-        float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
-        if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz))) {
-            if (um) far32<true>(r0.m, dx0, dy0, dz0, q0, c);
-            else far32<false>(r0.m, dx0, dy0, dz0, q0, c);
-        }
-    }
-}
-
-// Same for the FP64 path; far terms go to (bx, by, bz), candidates straight to (sx, sy, sz).
-__device__ __forceinline__ void group64(const KickArgs &a, CJ64 *J, int j, double T, int i, bool valid,
-                                        double xi, double yi, double zi, double rci, bool um,
-                                        double &bx, double &by, double &bz, double &sx, double &sy,
-                                        double &sz)
-{
-    const JRec64 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
-    double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
-    double dx1 = r1.x - xi, dy1 = r1.y - yi, dz1 = r1.z - zi;
-    double dx2 = r2.x - xi, dy2 = r2.y - yi, dz2 = r2.z - zi;
-    double dx3 = r3.x - xi, dy3 = r3.y - yi, dz3 = r3.z - zi;
-    double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
-    double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
-    double q2 = fma(dx2, dx2, fma(dy2, dy2, dz2 * dz2));
-    double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
-    const bool near = fmin(fmin(q0, q1), fmin(q2, q3)) < T;
-    if (__builtin_expect(near, 0)) {
-        if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far64<true>(r0.m, dx0, dy0, dz0, q0, bx, by, bz) : far64<false>(r0.m, dx0, dy0, dz0, q0, bx, by, bz);
-        if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far64<true>(r1.m, dx1, dy1, dz1, q1, bx, by, bz) : far64<false>(r1.m, dx1, dy1, dz1, q1, bx, by, bz);
-        if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far64<true>(r2.m, dx2, dy2, dz2, q2, bx, by, bz) : far64<false>(r2.m, dx2, dy2, dz2, q2, bx, by, bz);
-        if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
-            um ? far64<true>(r3.m, dx3, dy3, dz3, q3, bx, by, bz) : far64<false>(r3.m, dx3, dy3, dz3, q3, bx, by, bz);
-    } else if (um) {
-        far64<true>(r0.m, dx0, dy0, dz0, q0, bx, by, bz);
-        far64<true>(r1.m, dx1, dy1, dz1, q1, bx, by, bz);
-        far64<true>(r2.m, dx2, dy2, dz2, q2, bx, by, bz);
-        far64<true>(r3.m, dx3, dy3, dz3, q3, bx, by, bz);
-    } else {
-        far64<false>(r0.m, dx0, dy0, dz0, q0, bx, by, bz);
-        far64<false>(r1.m, dx1, dy1, dz1, q1, bx, by, bz);
-        far64<false>(r2.m, dx2, dy2, dz2, q2, bx, by, bz);
-        far64<false>(r3.m, dx3, dy3, dz3, q3, bx, by, bz);
-    }
-}
-
-__device__ __forceinline__ void block64(const KickArgs &a, CJ64 *J, int j, int jend, double T, int i,
-                                        bool valid, double xi, double yi, double zi, double rci,
-                                        bool um, double &bx, double &by, double &bz, double &sx,
-                                        double &sy, double &sz)
-{
-#pragma unroll 1
-    for (; j + 4 <= jend; j += 4) group64(a, J, j, T, i, valid, xi, yi, zi, rci, um, bx, by, bz, sx, sy, sz);
-#pragma unroll 1
-    for (; j < jend; ++j) {
-        const JRec64 r0 = ldj(J, j);
-        double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
-        double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
-        if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz))) {
-            if (um) far64<true>(r0.m, dx0, dy0, dz0, q0, bx, by, bz);
-            else far64<false>(r0.m, dx0, dy0, dz0, q0, bx, by, bz);
-        }
-    }
-}
-
 template <int W>
 __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
 {
@@ -371,16 +250,46 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
         Acc32 c{0.f, 0.f, 0.f};
         int j = jb;
         while (j < je) {
-            // blocks end at multiples of 64 sources; a block of one mass folds it in at the end
-            const int jend = min((j & ~63) + 64, je);
-            const double mu = a.umass[j >> 6];
-            block32(a, J, j, jend, T, i, valid, xi, yi, zi, rci, mu >= 0.0, c, sx, sy, sz);
-            const double f = mu >= 0.0 ? mu : 1.0;
-            sx = fma(f, (double)c.fx, sx);
-            sy = fma(f, (double)c.fy, sy);
-            sz = fma(f, (double)c.fz, sz);
+            const int jend = min(j + 64, je);
+            for (; j + 4 <= jend; j += 4) {
+                const JRec32 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
+                float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
+                float dx1 = (float)(r1.x - xi), dy1 = (float)(r1.y - yi), dz1 = (float)(r1.z - zi);
+                float dx2 = (float)(r2.x - xi), dy2 = (float)(r2.y - yi), dz2 = (float)(r2.z - zi);
+                float dx3 = (float)(r3.x - xi), dy3 = (float)(r3.y - yi), dz3 = (float)(r3.z - zi);
+                float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
+                float q1 = fmaf(dx1, dx1, fmaf(dy1, dy1, dz1 * dz1));
+                float q2 = fmaf(dx2, dx2, fmaf(dy2, dy2, dz2 * dz2));
+                float q3 = fmaf(dx3, dx3, fmaf(dy3, dy3, dz3 * dz3));
+                const bool near = fminf(fminf(q0, q1), fminf(q2, q3)) < T;
+                if (__builtin_expect(near, 0)) {
+                    if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r0.m, dx0, dy0, dz0, q0, c);
+                    if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r1.m, dx1, dy1, dz1, q1, c);
+                    if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r2.m, dx2, dy2, dz2, q2, c);
+                    if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                        far32(r3.m, dx3, dy3, dz3, q3, c);
+                } else {
+                    far32(r0.m, dx0, dy0, dz0, q0, c);
+                    far32(r1.m, dx1, dy1, dz1, q1, c);
+                    far32(r2.m, dx2, dy2, dz2, q2, c);
+                    far32(r3.m, dx3, dy3, dz3, q3, c);
+                }
+            }
+            for (; j < jend; ++j) {
+                const JRec32 r0 = ldj(J, j);
+                float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
+                float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far32(r0.m, dx0, dy0, dz0, q0, c);
+            }
+            // fold the block's FP32 partial sums into the FP64 accumulators
+            sx += (double)c.fx;
+            sy += (double)c.fy;
+            sz += (double)c.fz;
             c.fx = c.fy = c.fz = 0.f;
-            j = jend;
         }
         finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
@@ -407,16 +316,39 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
         const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
         double sx = 0.0, sy = 0.0, sz = 0.0;
         int j = jb;
-        while (j < je) {
-            const int jend = min((j & ~63) + 64, je);
-            const double mu = a.umass[j >> 6];
-            double bx = 0.0, by = 0.0, bz = 0.0;
-            block64(a, J, j, jend, T, i, valid, xi, yi, zi, rci, mu >= 0.0, bx, by, bz, sx, sy, sz);
-            const double f = mu >= 0.0 ? mu : 1.0;
-            sx = fma(f, bx, sx);
-            sy = fma(f, by, sy);
-            sz = fma(f, bz, sz);
-            j = jend;
+        for (; j + 4 <= je; j += 4) {
+            const JRec64 r0 = ldj(J, j), r1 = ldj(J, j + 1), r2 = ldj(J, j + 2), r3 = ldj(J, j + 3);
+            double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
+            double dx1 = r1.x - xi, dy1 = r1.y - yi, dz1 = r1.z - zi;
+            double dx2 = r2.x - xi, dy2 = r2.y - yi, dz2 = r2.z - zi;
+            double dx3 = r3.x - xi, dy3 = r3.y - yi, dz3 = r3.z - zi;
+            double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
+            double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
+            double q2 = fma(dx2, dx2, fma(dy2, dy2, dz2 * dz2));
+            double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
+            const bool near = fmin(fmin(q0, q1), fmin(q2, q3)) < T;
+            if (__builtin_expect(near, 0)) {
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
+                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
+                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
+                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
+            } else {
+                far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
+                far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
+                far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
+                far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
+            }
+        }
+        for (; j < je; ++j) {
+            const JRec64 r0 = ldj(J, j);
+            double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
+            double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
+            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
         }
         finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
@@ -424,24 +356,11 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
 
 // Source records, the largest r_crit^2 of every chunk, and a cleared pair counter.
 template <bool F32>
-__global__ __launch_bounds__(256) void prep_kernel(const Chunk *chunks, int n_chunks, int n_total,
-                                                   const double *x, const double *y,
-                                                   const double *z, const double *m,
-                                                   const double *rc, void *jrec, double *rc2_part,
-                                                   double *umass, int32_t *pair_count)
+__global__ __launch_bounds__(256) void prep_kernel(const Chunk *chunks, const double *x,
+                                                   const double *y, const double *z,
+                                                   const double *m, const double *rc, void *jrec,
+                                                   double *rc2_part, int32_t *pair_count)
 {
-    if ((int)blockIdx.x >= n_chunks) {
-        // mass of every aligned block of 64 sources if it is one mass, else -1
-        const int blk = (blockIdx.x - n_chunks) * 256 + threadIdx.x;
-        const int b = blk * 64;
-        if (b >= n_total) return;
-        const int e = min(b + 64, n_total);
-        const double m0 = m[b];
-        bool same = m0 >= 0.0;
-        for (int k = b + 1; k < e; ++k) same = same && (m[k] == m0);
-        umass[blk] = same ? (F32 ? (double)(float)m0 : m0) : -1.0;
-        return;
-    }
     const Chunk c = chunks[blockIdx.x];
     double mx = 0.0;
     for (int i = c.b + threadIdx.x; i < c.e; i += 256) {
@@ -497,17 +416,15 @@ __global__ __launch_bounds__(256) void rcrit_kernel(int n_total, const int32_t *
 
 hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
                        const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
-                       double *umass, int32_t *pair_count, hipStream_t stream)
+                       int32_t *pair_count, hipStream_t stream)
 {
     if (L.n_chunks == 0) return hipSuccess;
-    const int n_blk = (L.n_total + 63) / 64;
-    const int grid = L.n_chunks + (n_blk + 255) / 256;
     if (fp32)
-        prep_kernel<true><<<grid, 256, 0, stream>>>(L.chunks, L.n_chunks, L.n_total, x, y, z, m, rc, jrec,
-                                                    rc2_part, umass, pair_count);
+        prep_kernel<true><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
+                                                          pair_count);
     else
-        prep_kernel<false><<<grid, 256, 0, stream>>>(L.chunks, L.n_chunks, L.n_total, x, y, z, m, rc, jrec,
-                                                     rc2_part, umass, pair_count);
+        prep_kernel<false><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
+                                                           pair_count);
     return hipGetLastError();
 }
 

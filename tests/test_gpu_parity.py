@@ -395,8 +395,8 @@ def test_group_over_capacity_is_flagged():
 
 @pytest.mark.parametrize("layout", ["random", "mixed_blocks"])
 def test_accel_unequal_masses(layout):
-    """Masses differ within the aligned 64-source blocks (general path) or only in some blocks
-    (one-mass blocks take the folded path); both against the oracle."""
+    """Masses that differ from body to body, or only in some 64-source blocks, against the
+    oracle (the discs elsewhere have equal planetesimal masses)."""
     d = _sizes_disc(1500, seed=71, a_in=0.7, a_out=1.0)
     st = d.state()
     rng = np.random.default_rng(71)
