@@ -16,8 +16,7 @@
 //    slow path, which decides "inside r_crit,ij" in FP64 exactly as the definition states,
 //    evaluates K and the pair term in FP64 and appends (i, j) to the encounter list.
 //  * FP32 path: FP32 partial sums over blocks of 64 sources, folded into FP64 accumulators.
-//    FP64 path: v_rsq_f32 of the FP64 r^2 as the seed, refined in FP64 by one third-order
-//    correction (v_rsq_f32 runs at twice the rate of v_rsq_f64 and is as precise).
+//    FP64 path: v_rsq_f64 (about 2^-24) refined by one third-order correction.
 #include "genga_internal.h"
 
 namespace genga {
@@ -136,9 +135,8 @@ __device__ __forceinline__ void far32(float mj, float dx, float dy, float dz, fl
 __device__ __forceinline__ void far64(double mj, double dx, double dy, double dz, double q,
                                       double &sx, double &sy, double &sz)
 {
-    // seed from the FP32 reciprocal square root (about 2^-23), then one third-order step:
-    // rsqrt(q) = y0 (1 - e)^(-1/2), e = 1 - q y0^2, which leaves a relative error ~2^-69
-    double y0 = (double)__builtin_amdgcn_rsqf((float)q);
+    double y0 = __builtin_amdgcn_rsq(q);
+    // one third-order step: rsqrt(q) = y0 (1 - e)^(-1/2), e = 1 - q y0^2
     double t = q * y0;
     double e = fma(-t, y0, 1.0);
     double p = fma(0.375, e, 0.5);
