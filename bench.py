@@ -200,7 +200,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-kick", type=int, default=0,
-                    help="profiling aid: run this many FP32 kicks of the N=40000 disc and exit")
+                    help="profiling aid: run this many kicks of the N=40000 disc and exit")
+    ap.add_argument("--kick-prec", choices=("fp32", "fp64"), default="fp32",
+                    help="precision of the --only-kick kicks")
     ap.add_argument("--batched-only", action="store_true",
                     help="profiling aid: run only the 64-disc batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -230,13 +232,15 @@ def main():
         return
     d = discs.disc_c3()
     if args.only_kick > 0:
+        prec = genga.GENGA_KICK_FP32 if args.kick_prec == "fp32" else genga.GENGA_KICK_FP64
         ctx, b, st, _ = setup([d], torch)
-        genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
+        genga.genga_autotune(ctx.handle, b, prec)
         with torch.cuda.stream(stream):
             for _ in range(args.only_kick):
-                genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32, stream=stream)
+                genga.genga_kick(ctx.handle, b, 0.0, prec, stream=stream)
         torch.cuda.synchronize()
-        print(json.dumps({"kicks": args.only_kick, "shape": genga.genga_get_kick_shape(ctx.handle, genga.GENGA_KICK_FP32)}))
+        print(json.dumps({"kicks": args.only_kick, "prec": args.kick_prec,
+                          "shape": genga.genga_get_kick_shape(ctx.handle, prec)}))
         ctx.close()
         return
     n = d.n

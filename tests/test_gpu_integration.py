@@ -137,3 +137,19 @@ def test_checkpoint_resume_is_bit_identical():
         np.testing.assert_array_equal(end_a[k], end_b[k])
     a.close()
     b.close()
+
+
+def test_c2_force_error_at_checkpoints():
+    """Force error of both kicks against the oracle at steps 0, 100 and 200 of the N = 6600
+    disc, feeding the GPU's own state to the oracle at each checkpoint."""
+    d = discs.disc_c2()
+    s = System([d])
+    for k in range(3):
+        st = s.numpy_state()
+        ref = np.stack(oracle.accel(st, s.rc), axis=1)
+        for prec, bar in ((FP64, 1e-12), (FP32, 1e-5)):
+            rms, mx = force_errors(s.accel(prec), ref)
+            print(f"[c2 checkpoint step {100 * k}] prec={prec} rms={rms:.3e} max={mx:.3e}", flush=True)
+            assert rms <= bar
+        genga.genga_step(s.ctx.handle, s.b, DT, 100, FP32)
+    s.close()
