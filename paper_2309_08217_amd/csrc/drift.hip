@@ -405,178 +405,27 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
 }
 
 // ------------------------------------------------------------------------------------------
-// Bulirsch-Stoer over dt: one wavefront per group, one member per lane.  Each lane keeps its
-// member's state, midpoint sub-step values and extrapolation tableau in registers; the
-// members' positions are exchanged through LDS for the pair forces; step decisions use
-// wave-wide maxima, so the control flow is uniform.  Same method as the oracle: modified
-// midpoint with n_k = 2k sub-steps (k = 1..8), polynomial extrapolation in h^2, accept when
-// the last two diagonal entries agree to tol on the group's position / velocity scales,
-// otherwise halve the step; after an accepted step the next one is twice as long.
+// Bulirsch-Stoer over dt for the close-encounter groups (FP64): one wavefront per group.
+// Same method as the oracle: modified midpoint with n_k = 2(k+1) sub-steps (k = 0..7),
+// polynomial extrapolation in h^2 by Neville's scheme, and the step accepted at the first
+// column k >= 1 whose last two entries agree to tol on the group's position and velocity
+// scales.  After a step accepted at column k the next one is doubled (k <= 4), kept
+// (k = 5, 6) or halved (k = 7); a rejected step shrinks by shrink_factor.  Step decisions use
+// wave-wide values, so control flow stays uniform.
+//
+// Everything per lane lives in registers except what other lanes read: the positions
+// published for the pair forces and the tableau rows, both in LDS.  Force evaluations are
+// plain loops over the members, so the code stays small and nothing spills.
 // ------------------------------------------------------------------------------------------
 constexpr int BS_LANES = 64;
+constexpr int CP_MEM = 8; // largest group whose extrapolation columns run side by side
+static_assert(CP_MEM * BS_KMAX == BS_LANES, "one lane per (column, member)");
 
 __device__ __forceinline__ double wave_max(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-
-struct LaneGroup {
-    int a, nb;
-    bool act;
-    double m, rc, mstar;
-    double (*sp)[BS_LANES]; // [3][64] positions of the members
-    const double *sm, *src; // [64] masses and critical radii of the members
-    bool test;              // this member is a test body (TP2)
-    const int32_t *stest;   // [64] members that are test bodies
-};
-
-// dY/dt for this lane's member: Kepler term about the Sun plus the (1 - K) share of the
-// Newtonian forces from the other members.  Every lane of the wave must call it.
-__device__ void lane_deriv(const LaneGroup &g, const double y[6], double d[6])
-{
-    g.sp[0][g.a] = y[0];
-    g.sp[1][g.a] = y[1];
-    g.sp[2][g.a] = y[2];
-    __syncthreads();
-    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-    const double r = sqrt(r2);
-    const double s = -g.mstar / (r2 * r);
-    double ax = s * y[0], ay = s * y[1], az = s * y[2];
-    for (int b = 0; b < g.nb; ++b) {
-        if (b == g.a) continue;
-        if (g.test && g.stest[b]) continue; // two test bodies do not interact
-        const double dx = g.sp[0][b] - y[0], dy = g.sp[1][b] - y[1], dz = g.sp[2][b] - y[2];
-        const double q = sep2_rn(dx, dy, dz);
-        const double rcij = fmax(g.rc, g.src[b]);
-        if (!(q < sq_rn(rcij))) continue;
-        const double rr = sqrt(q);
-        const double w = 1.0 - changeover_k((rr - 0.1 * rcij) / (0.9 * rcij));
-        if (w == 0.0) continue;
-        const double t = g.sm[b] * w / (q * rr);
-        ax += t * dx;
-        ay += t * dy;
-        az += t * dz;
-    }
-    __syncthreads();
-    if (g.act) {
-        d[0] = y[3];
-        d[1] = y[4];
-        d[2] = y[5];
-        d[3] = ax;
-        d[4] = ay;
-        d[5] = az;
-    } else {
-        for (int q = 0; q < 6; ++q) d[q] = 0.0;
-    }
-}
-
-__device__ void lane_midpoint(const LaneGroup &g, const double y0[6], double H, int nsub, double out[6])
-{
-    const double h = H / nsub;
-    double zm[6], zc[6], dd[6];
-    lane_deriv(g, y0, dd);
-    for (int q = 0; q < 6; ++q) {
-        zm[q] = y0[q];
-        zc[q] = y0[q] + h * dd[q];
-    }
-    for (int k = 1; k < nsub; ++k) {
-        lane_deriv(g, zc, dd);
-        for (int q = 0; q < 6; ++q) {
-            const double t = zm[q] + 2.0 * h * dd[q];
-            zm[q] = zc[q];
-            zc[q] = t;
-        }
-    }
-    lane_deriv(g, zc, dd);
-    for (int q = 0; q < 6; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
-}
-
-// Step reduction after a rejected step: 0.9 (tol/err)^(1/15) from the last column's error,
-// kept within [1/50, 1/2].
-__device__ __forceinline__ double shrink_factor(double err, double tol)
-{
-    const double f = 0.9 * pow(tol / err, 1.0 / (2 * BS_KMAX - 1));
-    return fmax(0.02, fmin(0.5, f));
-}
-
-// Integrate this lane's member over dt (one lane per member, columns in sequence).  After a
-// step accepted at column k the next step is doubled (k <= 4), kept (k = 5, 6) or halved
-// (k = 7); a rejected step shrinks by shrink_factor.  Returns false (uniformly) if the step
-// falls below dt * 2^-40 or more than 20000 steps are tried.
-__device__ bool lane_bs(const LaneGroup &g, double Y[6], double dt, double tol)
-{
-    double t = 0.0, H = dt;
-    int attempts = 0;
-    while (t < dt) {
-        const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
-        if (last) H = dt - t;
-        if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
-        const double sr = wave_max(g.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
-        const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
-        double T[BS_KMAX][6];
-        int accepted = -1;
-        double err_last = 0.0;
-#pragma unroll
-        for (int k = 0; k < BS_KMAX; ++k) {
-            double est[6];
-            lane_midpoint(g, Y, H, 2 * (k + 1), est);
-            double err = 0.0;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                double prev = T[0][q]; // T(k-1, 0)
-                double cur = est[q];   // T(k, 0)
-                T[0][q] = cur;
-                double last = cur;
-#pragma unroll
-                for (int l = 1; l <= k; ++l) {
-                    const double ratio = (double)(k + 1) / (double)(k + 1 - l);
-                    const double nxt = cur + (cur - prev) / (ratio * ratio - 1.0);
-                    prev = T[l][q];
-                    last = cur;
-                    cur = nxt;
-                    T[l][q] = cur;
-                }
-                if (k > 0) err = fmax(err, fabs(cur - last) / (q < 3 ? sr : sv));
-            }
-            if (k > 0) {
-                err = wave_max(g.act ? err : 0.0);
-                err_last = err;
-                if (err <= tol) {
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) Y[q] = T[k][q];
-                    accepted = k;
-                    break;
-                }
-            }
-        }
-        if (accepted >= 0) {
-            t = last ? dt : t + H;
-            if (accepted <= 4) H = 2.0 * H;
-            else if (accepted == BS_KMAX - 1) H = 0.5 * H;
-        } else {
-            H = H * shrink_factor(err_last, tol);
-        }
-    }
-    return true;
-}
-
-// ---- groups of up to 8 members: the 8 extrapolation columns run side by side -------------
-// Lane = 8 k + a: column k (n_k = 2(k+1) midpoint sub-steps) of member a.  Members of one
-// column exchange positions by shuffles within their 8 lanes; the tableau is built across
-// columns by shuffles from the column below.  The accepted column is the first whose error
-// estimate meets the tolerance, so the result equals the sequential scheme's.
-constexpr int CP_MEM = 8;
-static_assert(CP_MEM * BS_KMAX == BS_LANES, "one lane per (column, member)");
-
-struct ColGroup {
-    int k, a, base, nb;
-    bool act;
-    double mstar;
-    // per partner b (constant over the step): r_crit,ab^2, 0.1 r_crit,ab, 1/(0.9 r_crit,ab), m_b
-    double rc2[CP_MEM], r01[CP_MEM], inv09[CP_MEM], mb[CP_MEM];
-    bool skip[CP_MEM]; // both this member and partner b are test bodies (TP2)
-};
 
 // 1/sqrt(q) in FP64: v_rsq_f64 (about 2^-24) and one third-order correction
 __device__ __forceinline__ double inv_sqrt64(double q)
@@ -588,110 +437,456 @@ __device__ __forceinline__ double inv_sqrt64(double q)
     return fma(y0 * e, p, y0);
 }
 
-__device__ void col_deriv(const ColGroup &g, const double y[6], double d[6])
+// Step reduction after a rejected step: 0.9 (tol/err)^(1/15) from the last column's error,
+// kept within [1/50, 1/2].
+__device__ __forceinline__ double shrink_factor(double err, double tol)
 {
-    const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
-    const double ri = inv_sqrt64(r2);
-    const double s = -g.mstar * (ri * ri) * ri;
-    double ax = s * y[0], ay = s * y[1], az = s * y[2];
-#pragma unroll
-    for (int b = 0; b < CP_MEM; ++b) {
-        if (b >= g.nb) break;
-        const double xb = __shfl(y[0], g.base + b, 64);
-        const double yb = __shfl(y[1], g.base + b, 64);
-        const double zb = __shfl(y[2], g.base + b, 64);
-        if (b == g.a || g.skip[b]) continue;
-        const double dx = xb - y[0], dy = yb - y[1], dz = zb - y[2];
-        const double q = sep2_rn(dx, dy, dz);
-        if (!(q < g.rc2[b])) continue;
-        const double rq = inv_sqrt64(q);
-        const double w = 1.0 - changeover_k((q * rq - g.r01[b]) * g.inv09[b]);
-        if (w == 0.0) continue;
-        const double t = g.mb[b] * w * (rq * rq) * rq;
-        ax += t * dx;
-        ay += t * dy;
-        az += t * dz;
-    }
-    if (g.act) {
-        d[0] = y[3];
-        d[1] = y[4];
-        d[2] = y[5];
-        d[3] = ax;
-        d[4] = ay;
-        d[5] = az;
-    } else {
-        for (int q = 0; q < 6; ++q) d[q] = 0.0;
-    }
+    const double f = 0.9 * pow(tol / err, 1.0 / (2 * BS_KMAX - 1));
+    return fmax(0.02, fmin(0.5, f));
 }
 
-__device__ bool col_bs(const ColGroup &g, double Y[6], double dt, double tol)
+// Neville factor 1 / ((n_k / n_(k-l))^2 - 1) for n_k = 2(k+1), written as p^2 / (q^2 - p^2)
+// with q = k + 1, p = k + 1 - l: exact small integers and one rounding.
+__device__ __forceinline__ double neville_c(int k, int l)
 {
-    const int lane = g.base + g.a;
-    const int nsub = 2 * (g.k + 1);
+    const double q = (double)(k + 1), p = (double)(k + 1 - l);
+    return (p * p) / (q * q - p * p);
+}
+
+// Members' data shared by the lanes of the group's wave.
+struct BsShared {
+    double pos[BS_LANES][4];                   // positions published for the pair forces
+    double m[BS_LANES];                        // member masses
+    double rc[BS_LANES], r01[BS_LANES], i09[BS_LANES]; // r_crit, 0.1 r_crit, 1 / (0.9 r_crit)
+    int32_t test[BS_LANES];                    // member is a test body (TP2)
+};
+
+// This lane's member: its constants and which lanes hold its partners' positions.
+struct BsMember {
+    int a, nb, base; // member index, group size, lane of member 0 in pos[]
+    bool act, test;
+    double mstar, rc, r01, i09;
+};
+
+// dY/dt: Kepler term about the Sun plus the (1 - K) share of the Newtonian forces from the
+// other members (K of Chambers 1999 over [0.1, 1] r_crit,ab; two test bodies do not
+// interact).  Every lane of the wave calls it.
+__device__ void bs_forces(const BsMember &me, BsShared &S, int slot, const double z[6], double d[6])
+{
+    S.pos[slot][0] = z[0];
+    S.pos[slot][1] = z[1];
+    S.pos[slot][2] = z[2];
+    __syncthreads();
+    const double ri = inv_sqrt64(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+    const double s = -me.mstar * (ri * ri) * ri;
+    double ax = s * z[0], ay = s * z[1], az = s * z[2];
+#pragma unroll 1
+    for (int b = 0; b < me.nb; ++b) {
+        if (b == me.a || (me.test && S.test[b])) continue;
+        const double dx = S.pos[me.base + b][0] - z[0];
+        const double dy = S.pos[me.base + b][1] - z[1];
+        const double dz = S.pos[me.base + b][2] - z[2];
+        const double q = sep2_rn(dx, dy, dz);
+        // r_crit,ab = max(r_crit,a, r_crit,b), with that member's derived constants
+        const bool own = me.rc >= S.rc[b];
+        const double rcab = own ? me.rc : S.rc[b];
+        if (!(q < sq_rn(rcab))) continue;
+        const double rq = inv_sqrt64(q);
+        const double w = 1.0 - changeover_k((q * rq - (own ? me.r01 : S.r01[b])) * (own ? me.i09 : S.i09[b]));
+        const double t = S.m[b] * w * (rq * rq) * rq;
+        ax = fma(t, dx, ax);
+        ay = fma(t, dy, ay);
+        az = fma(t, dz, az);
+    }
+    __syncthreads(); // the next call overwrites pos
+    d[0] = me.act ? z[3] : 0.0;
+    d[1] = me.act ? z[4] : 0.0;
+    d[2] = me.act ? z[5] : 0.0;
+    d[3] = me.act ? ax : 0.0;
+    d[4] = me.act ? ay : 0.0;
+    d[5] = me.act ? az : 0.0;
+}
+
+// Groups of up to CP_MEM members.  Lane 8k + a runs extrapolation column k for member a, so
+// the columns advance side by side, one force evaluation per pass.  Column k's sub-steps end
+// after n_k + 1 passes; its lanes then extend the tableau by row k (reading row k-1 from LDS)
+// and the wave ends the attempt as soon as a column has converged.  The accepted column is
+// the first converged one, as in the sequential scheme.
+__device__ bool bs_columns(const BsMember &me, int k, BsShared &S, double (*row)[BS_KMAX][CP_MEM][6],
+                           double Y[6], double dt, double tol)
+{
+    const int slot = me.base + me.a;
+    const int nsub = 2 * (k + 1);
+    double t = 0.0, H = dt;
+    int attempts = 0;
+    while (t < dt) {
+        const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
+        if (last) H = dt - t;
+        if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
+        const double sr = wave_max(me.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
+        const double sv = wave_max(me.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        const double h = H / nsub;
+        double zm[6], zc[6], T[6];
+        for (int q = 0; q < 6; ++q) zc[q] = zm[q] = T[q] = Y[q];
+        int kstar = -1;
+        double err_last = 0.0;
+#pragma unroll 1
+        for (int i = 0; i <= 2 * BS_KMAX; ++i) {
+            double dd[6];
+            bs_forces(me, S, slot, zc, dd);
+            if (i == 0) {
+                for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
+            } else if (i < nsub) {
+                for (int q = 0; q < 6; ++q) {
+                    const double tq = zm[q] + 2.0 * h * dd[q];
+                    zm[q] = zc[q];
+                    zc[q] = tq;
+                }
+            } else if (i == nsub) {
+                for (int q = 0; q < 6; ++q) T[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]); // T(k, 0)
+            }
+            if (i < 2 || (i & 1)) continue;
+            const int kk = i / 2 - 1; // the column whose sub-steps have just ended
+            double err = 0.0;
+            if (k == kk) {
+                double(*mine)[CP_MEM][6] = row[kk & 1];
+                const double(*below)[CP_MEM][6] = row[(kk + 1) & 1]; // row kk - 1
+                for (int q = 0; q < 6; ++q) mine[0][me.a][q] = T[q];
+                double dp = 0.0, dv = 0.0; // |T(kk, l) - T(kk, l-1)| of the last pass, l = kk
+#pragma unroll 1
+                for (int l = 1; l <= kk; ++l) {
+                    const double c = neville_c(kk, l);
+                    dp = dv = 0.0;
+                    double bl[6];
+                    for (int q = 0; q < 6; ++q) bl[q] = below[l - 1][me.a][q];
+                    for (int q = 0; q < 6; ++q) {
+                        const double nx = T[q] + (T[q] - bl[q]) * c;
+                        if (q < 3) dp = fmax(dp, fabs(nx - T[q]));
+                        else dv = fmax(dv, fabs(nx - T[q]));
+                        T[q] = nx;
+                    }
+                    for (int q = 0; q < 6; ++q) mine[l][me.a][q] = T[q];
+                }
+                // max over elements of |diff| / scale (the scale is common, so divide once)
+                err = me.act ? fmax(dp / sr, dv / sv) : 0.0;
+            }
+            if (kk == 0) continue;
+            for (int o = 1; o < CP_MEM; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
+            if (__ballot(k == kk && me.a == 0 && err <= tol)) {
+                kstar = kk;
+                break;
+            }
+            if (kk == BS_KMAX - 1) err_last = __shfl(err, kk * CP_MEM, 64);
+        }
+        if (kstar >= 0) {
+            __syncthreads(); // row kstar, written by its column's lanes, is read by all
+            for (int q = 0; q < 6; ++q) Y[q] = row[kstar & 1][kstar][me.a][q];
+            __syncthreads();
+            t = last ? dt : t + H;
+            if (kstar <= 4) H = 2.0 * H;
+            else if (kstar == BS_KMAX - 1) H = 0.5 * H;
+        } else {
+            H = H * shrink_factor(err_last, tol);
+        }
+    }
+    return true;
+}
+
+// Groups of CP_MEM + 1 .. BS_LANES members: one lane per member, columns in sequence, each
+// lane's tableau in its own LDS column tab[l][q][lane].
+__device__ bool bs_lanes(const BsMember &me, BsShared &S, double (*tab)[6][BS_LANES], double Y[6],
+                         double dt, double tol)
+{
     double t = 0.0, H = dt;
     int attempts = 0;
     while (t < dt) {
         const bool last = H >= (dt - t) * (1.0 - 0x1p-30);
         if (last) H = dt - t;
         if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
-        const double sr = wave_max(g.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
-        const double sv = wave_max(g.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
-        // this lane's column: modified midpoint with nsub sub-steps
-        const double h = H / nsub;
-        double zm[6], zc[6], dd[6], cur[6], sub[6];
-        col_deriv(g, Y, dd);
-        for (int q = 0; q < 6; ++q) {
-            zm[q] = Y[q];
-            zc[q] = Y[q] + h * dd[q];
-        }
-        for (int i = 1; i < nsub; ++i) {
-            col_deriv(g, zc, dd);
-            for (int q = 0; q < 6; ++q) {
-                const double tq = zm[q] + 2.0 * h * dd[q];
-                zm[q] = zc[q];
-                zc[q] = tq;
+        const double sr = wave_max(me.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
+        const double sv = wave_max(me.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        int kstar = -1;
+        double err_last = 0.0;
+        double T[6];
+#pragma unroll 1
+        for (int k = 0; k < BS_KMAX; ++k) {
+            const int nsub = 2 * (k + 1);
+            const double h = H / nsub;
+            double zm[6], zc[6];
+            for (int q = 0; q < 6; ++q) zc[q] = zm[q] = Y[q];
+#pragma unroll 1
+            for (int i = 0; i <= nsub; ++i) {
+                double dd[6];
+                bs_forces(me, S, me.a, zc, dd);
+                if (i == 0) {
+                    for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
+                } else if (i < nsub) {
+                    for (int q = 0; q < 6; ++q) {
+                        const double tq = zm[q] + 2.0 * h * dd[q];
+                        zm[q] = zc[q];
+                        zc[q] = tq;
+                    }
+                } else {
+                    for (int q = 0; q < 6; ++q) T[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
+                }
             }
-        }
-        col_deriv(g, zc, dd);
-        for (int q = 0; q < 6; ++q) {
-            cur[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]); // T(k, 0)
-            sub[q] = cur[q];
-        }
-        // Neville across columns: round l turns T(k, l-1) into T(k, l) for k >= l
-        const int below = g.k > 0 ? lane - CP_MEM : lane;
-#pragma unroll
-        for (int l = 1; l < BS_KMAX; ++l) {
-            const double ratio = (double)(g.k + 1) / (double)(g.k + 1 - l);
-            const double rden = 1.0 / (ratio * ratio - 1.0);
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const double tb = __shfl(cur[q], below, 64); // T(k-1, l-1)
-                if (g.k >= l) {
-                    const double nxt = cur[q] + (cur[q] - tb) * rden;
-                    sub[q] = cur[q];
-                    cur[q] = nxt;
+            // Neville: tab holds row k-1; replace it by row k in place (T(k, l-1) goes into
+            // slot l-1 once T(k-1, l-1) has been read from it)
+            double err = 0.0, dp = 0.0, dv = 0.0;
+#pragma unroll 1
+            for (int l = 1; l <= k; ++l) {
+                const double c = neville_c(k, l);
+                double old[6];
+                for (int q = 0; q < 6; ++q) old[q] = tab[l - 1][q][me.a];
+                for (int q = 0; q < 6; ++q) tab[l - 1][q][me.a] = T[q];
+                for (int q = 0; q < 6; ++q) {
+                    const double nx = T[q] + (T[q] - old[q]) * c;
+                    if (l == k) {
+                        if (q < 3) dp = fmax(dp, fabs(nx - T[q]));
+                        else dv = fmax(dv, fabs(nx - T[q]));
+                    }
+                    T[q] = nx;
+                }
+            }
+            for (int q = 0; q < 6; ++q) tab[k][q][me.a] = T[q];
+            if (k > 0) err = fmax(dp / sr, dv / sv);
+            if (k > 0) {
+                err = wave_max(me.act ? err : 0.0);
+                err_last = err;
+                if (err <= tol) {
+                    kstar = k;
+                    break;
                 }
             }
         }
-        // error of every column (over its members), then the first column that converged
-        double err = 0.0;
-        if (g.act && g.k > 0)
-            for (int q = 0; q < 6; ++q) err = fmax(err, fabs(cur[q] - sub[q]) / (q < 3 ? sr : sv));
-        for (int o = 1; o < CP_MEM; o <<= 1) err = fmax(err, __shfl_xor(err, o, 64));
-        const bool conv = g.k > 0 && err <= tol && g.a == 0;
-        const unsigned long long mask = __ballot(conv);
-        if (mask) {
-            const int kstar = (__ffsll((long long)mask) - 1) / CP_MEM;
-            for (int q = 0; q < 6; ++q) Y[q] = __shfl(cur[q], kstar * CP_MEM + g.a, 64);
+        if (kstar >= 0) {
+            for (int q = 0; q < 6; ++q) Y[q] = T[q];
             t = last ? dt : t + H;
             if (kstar <= 4) H = 2.0 * H;
             else if (kstar == BS_KMAX - 1) H = 0.5 * H;
         } else {
-            const double err_last = __shfl(err, (BS_KMAX - 1) * CP_MEM, 64);
             H = H * shrink_factor(err_last, tol);
         }
     }
     return true;
+}
+
+// Groups of 2 or 3 members (almost all groups when r_crit is a few Hill radii): lane k runs
+// extrapolation column k for the whole group, so a force evaluation is lane-local (the pair
+// force is formed once and applied to both members) and needs no exchange between lanes.
+// When column k completes, T(k, 0) goes to LDS and the wave forms T(k, k) - T(k, k-1) with
+// one lane per state element, from the Lagrange form of the extrapolation below.
+//
+// Polynomial extrapolation in h^2 to h = 0 over the nodes n_0..n_k (n_j = 2(j+1)) has the
+// Lagrange weights w_j = prod_{m != j} n_j^2 / (n_j^2 - n_m^2); it is the value Neville's
+// scheme computes, T(k, k), and the same over the nodes 1..k gives T(k, k-1).  Both sets of
+// weights sum to one, so the sums are formed relative to T(0, 0), which keeps their rounding
+// at the size of the differences.
+struct LagrangeTable {
+    double w[BS_KMAX][BS_KMAX]; // w[k][j]: weight of T(j, 0) in T(k, k)
+    double d[BS_KMAX][BS_KMAX]; // d[k][j]: weight of T(j, 0) in T(k, k) - T(k, k-1)
+    constexpr LagrangeTable() : w(), d()
+    {
+        for (int k = 0; k < BS_KMAX; ++k)
+            for (int j = 0; j <= k; ++j) {
+                const double nj2 = 4.0 * (j + 1) * (j + 1);
+                double a = 1.0, b = 1.0;
+                for (int m = 0; m <= k; ++m) {
+                    if (m == j) continue;
+                    const double nm2 = 4.0 * (m + 1) * (m + 1);
+                    a *= nj2 / (nj2 - nm2);
+                    if (m >= 1) b *= nj2 / (nj2 - nm2);
+                }
+                w[k][j] = a;
+                d[k][j] = j >= 1 ? a - b : a;
+            }
+    }
+};
+__constant__ constexpr LagrangeTable LAGRANGE{};
+
+template <int NB>
+struct SmallGroup {
+    double mstar;
+    double m[NB];
+    double rc2[NB][NB], r01[NB][NB], i09[NB][NB]; // per pair a < b, from r_crit,ab
+    bool skip[NB][NB];                            // both are test bodies (TP2)
+};
+
+template <int NB>
+__device__ __forceinline__ void small_forces(const SmallGroup<NB> &g, const double (&z)[NB][6],
+                                             double (&d)[NB][6])
+{
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        const double ri = inv_sqrt64(z[a][0] * z[a][0] + z[a][1] * z[a][1] + z[a][2] * z[a][2]);
+        const double s = -g.mstar * (ri * ri) * ri;
+        d[a][0] = z[a][3];
+        d[a][1] = z[a][4];
+        d[a][2] = z[a][5];
+        d[a][3] = s * z[a][0];
+        d[a][4] = s * z[a][1];
+        d[a][5] = s * z[a][2];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = a + 1; b < NB; ++b) {
+            if (g.skip[a][b]) continue;
+            const double dx = z[b][0] - z[a][0], dy = z[b][1] - z[a][1], dz = z[b][2] - z[a][2];
+            const double q = sep2_rn(dx, dy, dz);
+            if (!(q < g.rc2[a][b])) continue;
+            const double rq = inv_sqrt64(q);
+            const double w = 1.0 - changeover_k((q * rq - g.r01[a][b]) * g.i09[a][b]);
+            const double u = w * (rq * rq) * rq;
+            const double ua = g.m[b] * u, ub = g.m[a] * u;
+            d[a][3] = fma(ua, dx, d[a][3]);
+            d[a][4] = fma(ua, dy, d[a][4]);
+            d[a][5] = fma(ua, dz, d[a][5]);
+            d[b][3] = fma(-ub, dx, d[b][3]);
+            d[b][4] = fma(-ub, dy, d[b][4]);
+            d[b][5] = fma(-ub, dz, d[b][5]);
+        }
+}
+
+// Sum over the completed columns 1..k of c[j] (T(j, 0) - T(0, 0)) for this lane's element,
+// tcol[j * E + e] holding T(j, 0); every load is issued before the first use.
+template <int E>
+__device__ __forceinline__ double lagrange_sum(const double *tcol, const double *c, int k, int e)
+{
+    const double t0 = tcol[e];
+    double v[BS_KMAX], cj[BS_KMAX];
+#pragma unroll
+    for (int j = 1; j < BS_KMAX; ++j) {
+        v[j] = tcol[j * E + e];
+        cj[j] = c[j];
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int j = 1; j < BS_KMAX; ++j) {
+        const double f = fma(cj[j], v[j] - t0, s);
+        s = j <= k ? f : s; // rows above k are stale
+    }
+    return s;
+}
+
+// ybuf: the group state [NB][6] in LDS (read at entry, holds the result on return);
+// tcol: LDS [BS_KMAX][NB * 6] for T(k, 0); lag: LAGRANGE copied to LDS (w, then d).
+template <int NB>
+__device__ bool bs_small(const SmallGroup<NB> &g, int lane, double *ybuf, double *tcol, const double *lag,
+                         double dt, double tol)
+{
+    constexpr int E = NB * 6;
+    const double *lw = lag, *ld = lag + BS_KMAX * BS_KMAX;
+    const int k = lane & (BS_KMAX - 1);
+    const bool writer = lane < BS_KMAX;
+    const int nsub = 2 * (k + 1);
+    const int e = lane < E ? lane : 0; // state element of this lane in the extrapolation
+    double t = 0.0, H = dt;
+    int attempts = 0;
+    while (t < dt) {
+        const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
+        if (last) H = dt - t;
+        if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
+        const double h = H / nsub;
+        double zm[NB][6], zc[NB][6];
+        double sr = 0.0, sv = 0.0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) zc[a][q] = zm[a][q] = ybuf[6 * a + q];
+            sr = fmax(sr, sqrt(zm[a][0] * zm[a][0] + zm[a][1] * zm[a][1] + zm[a][2] * zm[a][2]));
+            sv = fmax(sv, sqrt(zm[a][3] * zm[a][3] + zm[a][4] * zm[a][4] + zm[a][5] * zm[a][5]));
+        }
+        const double scale = e % 6 < 3 ? sr : sv;
+        int kstar = -1;
+        double err_last = 0.0;
+#pragma unroll 1
+        for (int i = 0; i <= 2 * BS_KMAX; ++i) {
+            double dd[NB][6];
+            small_forces<NB>(g, zc, dd);
+            if (i == 0) {
+#pragma unroll
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) zc[a][q] = zm[a][q] + h * dd[a][q];
+            } else if (i < nsub) {
+#pragma unroll
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        const double tq = zm[a][q] + 2.0 * h * dd[a][q];
+                        zm[a][q] = zc[a][q];
+                        zc[a][q] = tq;
+                    }
+            } else if (i == nsub && writer) {
+#pragma unroll
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) tcol[k * E + 6 * a + q] = 0.5 * (zm[a][q] + zc[a][q] + h * dd[a][q]);
+            }
+            if (i < 2 || (i & 1)) continue;
+            const int kk = i / 2 - 1; // the column that has just completed
+            __syncthreads();          // its T(kk, 0) is read by every lane
+            if (kk == 0) continue;
+            const double err = fabs(lagrange_sum<E>(tcol, ld + kk * BS_KMAX, kk, e)) / scale;
+            if (!__ballot(lane < E && !(err <= tol))) {
+                kstar = kk;
+                break;
+            }
+            if (kk == BS_KMAX - 1) err_last = wave_max(lane < E ? err : 0.0);
+        }
+        if (kstar >= 0) {
+            const double y = tcol[e] + lagrange_sum<E>(tcol, lw + kstar * BS_KMAX, kstar, e);
+            __syncthreads(); // every lane has read ybuf and tcol
+            if (lane < E) ybuf[e] = y;
+            __syncthreads();
+            t = last ? dt : t + H;
+            if (kstar <= 4) H = 2.0 * H;
+            else if (kstar == BS_KMAX - 1) H = 0.5 * H;
+        } else {
+            H = H * shrink_factor(err_last, tol);
+        }
+    }
+    return true;
+}
+
+template <int NB>
+__device__ bool run_small(const BsShared &S, int lane, double ms, const double *x, const double *y,
+                          const double *z, const double *vx, const double *vy, const double *vz,
+                          const int32_t *mem, double *ybuf, double *tcol, double *lag, double dt,
+                          double *out)
+{
+    SmallGroup<NB> g;
+    g.mstar = ms;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+        g.m[a] = S.m[a];
+#pragma unroll
+        for (int b = a + 1; b < NB; ++b) {
+            const bool own = S.rc[a] >= S.rc[b];
+            const double rcab = own ? S.rc[a] : S.rc[b];
+            g.rc2[a][b] = sq_rn(rcab);
+            g.r01[a][b] = own ? S.r01[a] : S.r01[b];
+            g.i09[a][b] = own ? S.i09[a] : S.i09[b];
+            g.skip[a][b] = S.test[a] && S.test[b];
+        }
+    }
+    if (lane < NB) {
+        const int b = mem[lane];
+        ybuf[6 * lane + 0] = x[b];
+        ybuf[6 * lane + 1] = y[b];
+        ybuf[6 * lane + 2] = z[b];
+        ybuf[6 * lane + 3] = vx[b];
+        ybuf[6 * lane + 4] = vy[b];
+        ybuf[6 * lane + 5] = vz[b];
+    }
+    lag[lane] = (&LAGRANGE.w[0][0])[lane];
+    lag[BS_LANES + lane] = (&LAGRANGE.d[0][0])[lane];
+    __syncthreads();
+    const bool ok = bs_small<NB>(g, lane, ybuf, tcol, lag, dt, 1e-12);
+    __syncthreads();
+    if (lane < NB * 6) out[lane] = ybuf[lane];
+    return ok;
 }
 
 __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, const int32_t *sys_off,
@@ -705,18 +900,17 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
                                                          const int32_t *n_groups, double *bs_out,
                                                          int32_t *flags)
 {
-    __shared__ double sp[3][BS_LANES];
-    __shared__ double sm[BS_LANES], src[BS_LANES];
-    __shared__ int32_t stest[BS_LANES];
+    __shared__ BsShared S;
+    __shared__ double tab[BS_KMAX * 6 * BS_LANES];
     const int g = blockIdx.x;
     if (g >= *n_groups) return;
     const int k0 = group_start[g], nb = group_start[g + 1] - k0;
-    const int a = threadIdx.x;
+    const int lane = threadIdx.x;
     const double ms = mstar[sys_of[members[k0]]];
     if (nb > BS_LANES) {
         // larger than one wave: Kepler-drift the members instead and flag it
-        if (a == 0) atomicOr(flags, FLAG_CAPACITY);
-        for (int k = a; k < nb; k += BS_LANES) {
+        if (lane == 0) atomicOr(flags, FLAG_CAPACITY);
+        for (int k = lane; k < nb; k += BS_LANES) {
             const int b = members[k0 + k];
             double px = x[b], py = y[b], pz = z[b], ux = vx[b], uy = vy[b], uz = vz[b];
             if (!kepler_universal(px, py, pz, ux, uy, uz, ms, dt)) atomicOr(flags, FLAG_KEPLER);
@@ -730,61 +924,46 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
         }
         return;
     }
-    if (nb <= CP_MEM) {
-        // column-parallel path
-        const int k = a / CP_MEM, am = a % CP_MEM;
-        const bool act = am < nb;
-        const int b = members[k0 + (act ? am : 0)];
+    if (lane < nb) {
+        const int b = members[k0 + lane];
         const int sb = sys_of[b];
-        const bool is_test = b - sys_off[sb] >= n_massive[sb];
-        if (k == 0) {
-            sm[am] = act ? m[b] : 0.0;
-            src[am] = act ? rc[b] : 0.0;
-            stest[am] = act && is_test;
-        }
-        __syncthreads();
-        ColGroup cg;
-        cg.k = k;
-        cg.a = am;
-        cg.base = k * CP_MEM;
-        cg.nb = nb;
-        cg.act = act;
-        cg.mstar = ms;
-        const double rca = rc[b];
-#pragma unroll
-        for (int p = 0; p < CP_MEM; ++p) {
-            const double rcij = fmax(rca, src[p]);
-            cg.rc2[p] = sq_rn(rcij);
-            cg.r01[p] = 0.1 * rcij;
-            cg.inv09[p] = 1.0 / (0.9 * rcij);
-            cg.mb[p] = sm[p];
-            cg.skip[p] = is_test && stest[p];
-        }
-        double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
-        const bool ok = col_bs(cg, Y, dt, 1e-12);
-        if (act && k == 0) {
-            double *o = bs_out + 6 * (size_t)(k0 + am);
-            for (int q = 0; q < 6; ++q) o[q] = Y[q];
-        }
-        if (!ok && a == 0) atomicOr(flags, FLAG_NOCONVERGE);
+        S.m[lane] = m[b];
+        S.rc[lane] = rc[b];
+        S.r01[lane] = 0.1 * rc[b];
+        S.i09[lane] = 1.0 / (0.9 * rc[b]);
+        S.test[lane] = b - sys_off[sb] >= n_massive[sb];
+    }
+    __syncthreads();
+    if (nb <= 3) {
+        __shared__ double ybuf[3 * 6];
+        double *out = bs_out + 6 * (size_t)k0, *lag = tab + BS_KMAX * 3 * 6;
+        const bool ok = nb == 2 ? run_small<2>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt, out)
+                                : run_small<3>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt, out);
+        if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
         return;
     }
-    const bool act = a < nb;
-    const int b = members[k0 + (act ? a : 0)];
-    const int sb = sys_of[b];
-    const bool is_test = b - sys_off[sb] >= n_massive[sb];
-    sm[a] = act ? m[b] : 0.0;
-    src[a] = act ? rc[b] : 0.0;
-    stest[a] = act && is_test;
-    __syncthreads();
-    LaneGroup lg{a, nb, act, m[b], rc[b], ms, sp, sm, src, is_test, stest};
+    const bool cols = nb <= CP_MEM;
+    const int k = cols ? lane / CP_MEM : 0;
+    BsMember me;
+    me.a = cols ? lane % CP_MEM : lane;
+    me.nb = nb;
+    me.base = cols ? k * CP_MEM : 0;
+    me.act = me.a < nb;
+    const int ai = me.act ? me.a : 0;
+    me.test = S.test[ai] != 0;
+    me.mstar = ms;
+    me.rc = S.rc[ai];
+    me.r01 = S.r01[ai];
+    me.i09 = S.i09[ai];
+    const int b = members[k0 + ai];
     double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
-    const bool ok = lane_bs(lg, Y, dt, 1e-12);
-    if (act) {
-        double *o = bs_out + 6 * (size_t)(k0 + a);
+    const bool ok = cols ? bs_columns(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12)
+                         : bs_lanes(me, S, (double(*)[6][BS_LANES])tab, Y, dt, 1e-12);
+    if (me.act && k == 0) {
+        double *o = bs_out + 6 * (size_t)(k0 + me.a);
         for (int q = 0; q < 6; ++q) o[q] = Y[q];
-        if (!ok && a == 0) atomicOr(flags, FLAG_NOCONVERGE);
     }
+    if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
 } // namespace
