@@ -40,7 +40,7 @@ __device__ __forceinline__ double changeover_k(double y)
 // block reduction), then every chunk adds its system's partials in chunk order and shifts
 // its positions.  Deterministic.
 // ------------------------------------------------------------------------------------------
-constexpr int SUN_THREADS = 256;
+constexpr int SUN_THREADS = SYS_P_THREADS;
 
 __global__ __launch_bounds__(SUN_THREADS) void momentum_kernel(const Chunk *chunks, const double *m,
                                                                const double *vx, const double *vy,
@@ -80,34 +80,12 @@ __global__ __launch_bounds__(SUN_THREADS) void sun_shift_kernel(const Chunk *chu
                                                                 const double *mom_part, double tau,
                                                                 double *x, double *y, double *z)
 {
-    __shared__ double red[3][SUN_THREADS / 64];
+    __shared__ double red[3][SYS_P_THREADS / 64];
     const Chunk c = chunks[blockIdx.x];
-    // the system's momentum: strided sums of the chunk partials, then a fixed tree
-    double Px = 0.0, Py = 0.0, Pz = 0.0;
-    for (int k = chunk_first[c.sys] + threadIdx.x; k < chunk_first[c.sys + 1]; k += SUN_THREADS) {
-        Px += mom_part[3 * (size_t)k];
-        Py += mom_part[3 * (size_t)k + 1];
-        Pz += mom_part[3 * (size_t)k + 2];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        Px += __shfl_xor(Px, o, 64);
-        Py += __shfl_xor(Py, o, 64);
-        Pz += __shfl_xor(Pz, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = Px;
-        red[1][threadIdx.x >> 6] = Py;
-        red[2][threadIdx.x >> 6] = Pz;
-    }
-    __syncthreads();
-    Px = Py = Pz = 0.0;
-    for (int w = 0; w < SUN_THREADS / 64; ++w) {
-        Px += red[0][w];
-        Py += red[1][w];
-        Pz += red[2][w];
-    }
+    double P[3];
+    system_momentum(chunk_first, mom_part, c.sys, red, P);
     const double f = tau / mstar[c.sys];
-    const double sx = f * Px, sy = f * Py, sz = f * Pz;
+    const double sx = f * P[0], sy = f * P[1], sz = f * P[2];
     for (int i = c.b + threadIdx.x; i < c.e; i += SUN_THREADS) {
         x[i] += sx;
         y[i] += sy;
@@ -224,36 +202,15 @@ __device__ bool kepler_universal(double &x, double &y, double &z, double &vx, do
     return ok;
 }
 
-__global__ __launch_bounds__(64) void kepler_kernel(int n_total, const int32_t *sys_of,
-                                                     const double *mstar, double *x, double *y,
-                                                     double *z, double *vx, double *vy,
-                                                     double *vz, double dt, int32_t *member_slot,
-                                                     const double *bs_out, int32_t *flags)
+__device__ __forceinline__ void store_state(double *x, double *y, double *z, double *vx, double *vy,
+                                            double *vz, int b, const double *Y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_total) return;
-    const int slot = member_slot[i];
-    if (slot >= 0) {
-        // body integrated by the encounter step: take its result, clear the slot
-        const double *o = bs_out + 6 * (size_t)slot;
-        x[i] = o[0];
-        y[i] = o[1];
-        z[i] = o[2];
-        vx[i] = o[3];
-        vy[i] = o[4];
-        vz[i] = o[5];
-        member_slot[i] = -1;
-        return;
-    }
-    double px = x[i], py = y[i], pz = z[i], ux = vx[i], uy = vy[i], uz = vz[i];
-    const bool ok = kepler_universal(px, py, pz, ux, uy, uz, mstar[sys_of[i]], dt);
-    if (!ok) atomicOr(flags, FLAG_KEPLER);
-    x[i] = px;
-    y[i] = py;
-    z[i] = pz;
-    vx[i] = ux;
-    vy[i] = uy;
-    vz[i] = uz;
+    x[b] = Y[0];
+    y[b] = Y[1];
+    z[b] = Y[2];
+    vx[b] = Y[3];
+    vy[b] = Y[4];
+    vz[b] = Y[5];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -851,10 +808,9 @@ __device__ bool bs_small(const SmallGroup<NB> &g, int lane, double *ybuf, double
 }
 
 template <int NB>
-__device__ bool run_small(const BsShared &S, int lane, double ms, const double *x, const double *y,
-                          const double *z, const double *vx, const double *vy, const double *vz,
-                          const int32_t *mem, double *ybuf, double *tcol, double *lag, double dt,
-                          double *out)
+__device__ bool run_small(const BsShared &S, int lane, double ms, double *x, double *y, double *z,
+                          double *vx, double *vy, double *vz, const int32_t *mem, double *ybuf,
+                          double *tcol, double *lag, double dt)
 {
     SmallGroup<NB> g;
     g.mstar = ms;
@@ -885,42 +841,52 @@ __device__ bool run_small(const BsShared &S, int lane, double ms, const double *
     __syncthreads();
     const bool ok = bs_small<NB>(g, lane, ybuf, tcol, lag, dt, 1e-12);
     __syncthreads();
-    if (lane < NB * 6) out[lane] = ybuf[lane];
+    if (lane < NB) store_state(x, y, z, vx, vy, vz, mem[lane], ybuf + 6 * lane);
     return ok;
 }
 
-__global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, const int32_t *sys_off,
+// The drift over dt: blocks [0, CE_MAX_MEMBERS / 2) integrate one encounter group each with
+// Bulirsch-Stoer, the blocks after them Kepler-drift 64 bodies each and skip the group
+// members.  Each body is read and written by one block only.
+constexpr int BS_BLOCKS = CE_MAX_MEMBERS / 2; // every group has >= 2 members
+
+__global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, const int32_t *sys_off,
                                                          const int32_t *n_massive, const double *mstar,
-                                                         const double *x, const double *y,
-                                                         const double *z, const double *vx,
-                                                         const double *vy, const double *vz,
+                                                         int n_total, double *x, double *y, double *z,
+                                                         double *vx, double *vy, double *vz,
                                                          const double *m, const double *rc, double dt,
                                                          const int32_t *members,
                                                          const int32_t *group_start,
-                                                         const int32_t *n_groups, double *bs_out,
+                                                         const int32_t *n_groups, int32_t *member_slot,
                                                          int32_t *flags)
 {
     __shared__ BsShared S;
     __shared__ double tab[BS_KMAX * 6 * BS_LANES];
+    const int lane = threadIdx.x;
+    if (blockIdx.x >= BS_BLOCKS) {
+        const int i = (blockIdx.x - BS_BLOCKS) * BS_LANES + lane;
+        if (i >= n_total) return;
+        if (member_slot[i] >= 0) {
+            member_slot[i] = -1; // integrated by its group's block; leave the slot clear
+            return;
+        }
+        double Y[6] = {x[i], y[i], z[i], vx[i], vy[i], vz[i]};
+        if (!kepler_universal(Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], mstar[sys_of[i]], dt)) atomicOr(flags, FLAG_KEPLER);
+        store_state(x, y, z, vx, vy, vz, i, Y);
+        return;
+    }
     const int g = blockIdx.x;
     if (g >= *n_groups) return;
     const int k0 = group_start[g], nb = group_start[g + 1] - k0;
-    const int lane = threadIdx.x;
     const double ms = mstar[sys_of[members[k0]]];
     if (nb > BS_LANES) {
         // larger than one wave: Kepler-drift the members instead and flag it
         if (lane == 0) atomicOr(flags, FLAG_CAPACITY);
         for (int k = lane; k < nb; k += BS_LANES) {
             const int b = members[k0 + k];
-            double px = x[b], py = y[b], pz = z[b], ux = vx[b], uy = vy[b], uz = vz[b];
-            if (!kepler_universal(px, py, pz, ux, uy, uz, ms, dt)) atomicOr(flags, FLAG_KEPLER);
-            double *o = bs_out + 6 * (size_t)(k0 + k);
-            o[0] = px;
-            o[1] = py;
-            o[2] = pz;
-            o[3] = ux;
-            o[4] = uy;
-            o[5] = uz;
+            double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
+            if (!kepler_universal(Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], ms, dt)) atomicOr(flags, FLAG_KEPLER);
+            store_state(x, y, z, vx, vy, vz, b, Y);
         }
         return;
     }
@@ -936,9 +902,9 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
     __syncthreads();
     if (nb <= 3) {
         __shared__ double ybuf[3 * 6];
-        double *out = bs_out + 6 * (size_t)k0, *lag = tab + BS_KMAX * 3 * 6;
-        const bool ok = nb == 2 ? run_small<2>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt, out)
-                                : run_small<3>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt, out);
+        double *lag = tab + BS_KMAX * 3 * 6;
+        const bool ok = nb == 2 ? run_small<2>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt)
+                                : run_small<3>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt);
         if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
         return;
     }
@@ -959,10 +925,8 @@ __global__ __launch_bounds__(BS_LANES) void ce_bs_kernel(const int32_t *sys_of, 
     double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
     const bool ok = cols ? bs_columns(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12)
                          : bs_lanes(me, S, (double(*)[6][BS_LANES])tab, Y, dt, 1e-12);
-    if (me.act && k == 0) {
-        double *o = bs_out + 6 * (size_t)(k0 + me.a);
-        for (int q = 0; q < 6; ++q) o[q] = Y[q];
-    }
+    // every lane has read its member's state before the first force evaluation's barrier
+    if (me.act && k == 0) store_state(x, y, z, vx, vy, vz, b, Y);
     if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
@@ -979,6 +943,14 @@ hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, co
     return hipGetLastError();
 }
 
+hipError_t launch_momentum(const Layout &L, const double *vx, const double *vy, const double *vz,
+                           const double *m, double *mom_part, hipStream_t stream)
+{
+    if (L.n_chunks == 0) return hipSuccess;
+    momentum_kernel<<<L.n_chunks, SUN_THREADS, 0, stream>>>(L.chunks, m, vx, vy, vz, mom_part);
+    return hipGetLastError();
+}
+
 hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
                             int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
@@ -990,29 +962,16 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const double *z,
-                        const double *vx, const double *vy, const double *vz, const double *m,
-                        const double *rc, double dt, const int32_t *members,
-                        const int32_t *group_start, const int32_t *n_groups, double *bs_out,
+hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, const double *m, const double *rc, double dt, const int32_t *members,
+                        const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
                         int32_t *flags, hipStream_t stream)
 {
-    // one wave per group; at most CE_MAX_MEMBERS / 2 groups (every group has >= 2 members)
-    ce_bs_kernel<<<CE_MAX_MEMBERS / 2, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar,
-                                                              x, y, z, vx, vy, vz, m, rc,
-                                                              dt, members, group_start, n_groups, bs_out,
-                                                              flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
-                         double *vz, double dt, int32_t *member_slot, const double *bs_out,
-                         int32_t *flags, hipStream_t stream)
-{
     if (L.n_total == 0) return hipSuccess;
-    // one wave per workgroup spreads the latency-bound solves over all CUs
-    kepler_kernel<<<(L.n_total + 63) / 64, 64, 0, stream>>>(L.n_total, L.sys_of, L.mstar, x, y, z,
-                                                               vx, vy, vz, dt, member_slot, bs_out,
-                                                               flags);
+    const int grid = BS_BLOCKS + (L.n_total + BS_LANES - 1) / BS_LANES;
+    drift_kernel<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z,
+                                                vx, vy, vz, m, rc, dt, members, group_start, n_groups,
+                                                member_slot, flags);
     return hipGetLastError();
 }
 

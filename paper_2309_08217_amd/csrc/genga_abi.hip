@@ -80,7 +80,6 @@ struct genga_ctx {
     int32_t *flags = nullptr;
     int32_t *lab = nullptr, *mark = nullptr, *members = nullptr, *group_start = nullptr;
     int32_t *n_groups = nullptr, *member_slot = nullptr;
-    double *bs_out = nullptr;
     double *epartial = nullptr;
     // graph
     hipGraph_t graph = nullptr;
@@ -111,7 +110,6 @@ struct genga_ctx {
         dfree(group_start);
         dfree(n_groups);
         dfree(member_slot);
-        dfree(bs_out);
         dfree(epartial);
         dfree(kpart);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -167,13 +165,16 @@ int check_prec(int prec)
     return GENGA_OK;
 }
 
+// shift_tau != 0: the source-record pass first applies the pending second half of a Sun drift
+// (see enqueue_drift with defer_shift)
 int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v, int prec, double *ax,
-                 double *ay, double *az, hipStream_t s)
+                 double *ay, double *az, hipStream_t s, double shift_tau = 0.0)
 {
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
     const int fp32 = prec == GENGA_KICK_FP32;
-    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->pair_count, s));
+    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->pair_count,
+                        ctx->mom_part, shift_tau, s));
     KickArgs a;
     a.items = ctx->items;
     a.n_items = ctx->n_items;
@@ -205,18 +206,22 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     return GENGA_OK;
 }
 
-int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+// Sun drift (dt/2), Kepler / Bulirsch-Stoer (dt), Sun drift (dt/2).  With defer_shift the
+// last position shift is left to the next kick's source-record pass (only the momentum
+// partials are formed here); that kick must be given shift_tau = dt/2.
+int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, bool defer_shift = false)
 {
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
     HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
                              ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
-    HIP_TRY(launch_ce_bs(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
-                         ctx->group_start, ctx->n_groups, ctx->bs_out, ctx->flags, s));
-    HIP_TRY(launch_kepler(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, dt, ctx->member_slot, ctx->bs_out,
-                          ctx->flags, s));
-    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
+    HIP_TRY(launch_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
+                         ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
+    if (defer_shift)
+        HIP_TRY(launch_momentum(L, b->vx, b->vy, b->vz, b->m, ctx->mom_part, s));
+    else
+        HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     return GENGA_OK;
 }
 
@@ -238,10 +243,10 @@ int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int pre
     if (rc) return rc;
     int rec = 0;
     for (int k = 1; k <= nsteps; ++k) {
-        rc = enqueue_drift(ctx, b, dt, s);
+        rc = enqueue_drift(ctx, b, dt, s, true);
         if (rc) return rc;
         const bool last = k == nsteps;
-        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s);
+        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s, 0.5 * dt);
         if (rc) return rc;
         if (cadence > 0 && d_energy && k % cadence == 0) {
             rc = enqueue_energy(ctx, b, last ? 0.0 : 0.5 * dt, d_energy + (size_t)rec * 4 * ctx->L.n_sys, s);
@@ -380,7 +385,6 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->group_start, CE_MAX_MEMBERS + 1));
     HIP_TRY(dalloc(ctx->n_groups, 1));
     HIP_TRY(dalloc(ctx->member_slot, nt));
-    HIP_TRY(dalloc(ctx->bs_out, 6 * (size_t)CE_MAX_MEMBERS));
     HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * max_items));
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
 

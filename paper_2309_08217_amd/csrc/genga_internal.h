@@ -86,9 +86,12 @@ constexpr int KICK_MAX_SPLIT = 4;
 constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in the energy sum
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
-hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
-                       const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
-                       int32_t *pair_count, hipStream_t stream);
+// Source records and r_crit^2 maxima for the kick.  With shift_tau != 0 the launch first
+// finishes a Sun drift: x += shift_tau P / Mstar per system, P summed from mom_part (the
+// per-chunk partials of a preceding launch_momentum).
+hipError_t launch_prep(const Layout &L, double *x, double *y, double *z, const double *m,
+                       const double *rc, void *jrec, int fp32, double *rc2_part, int32_t *pair_count,
+                       const double *mom_part, double shift_tau, hipStream_t stream);
 hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream);
 hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz, const double *m,
@@ -96,18 +99,48 @@ hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const
 hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
                             const double *vy, const double *vz, const double *m, double tau,
                             double *mom_part, hipStream_t stream);
+// Per-chunk partials of sum m v (the first half of launch_sun_drift).
+hipError_t launch_momentum(const Layout &L, const double *vx, const double *vy, const double *vz,
+                           const double *m, double *mom_part, hipStream_t stream);
+
+// Momentum of system s for a block of SYS_P_THREADS threads: the chunk partials summed with a
+// stride, then a fixed tree, so every block of the system gets the same value.
+constexpr int SYS_P_THREADS = 256;
+__device__ inline void system_momentum(const int32_t *chunk_first, const double *mom_part, int s,
+                                       double (*red)[SYS_P_THREADS / 64], double P[3])
+{
+    double Px = 0.0, Py = 0.0, Pz = 0.0;
+    for (int k = chunk_first[s] + threadIdx.x; k < chunk_first[s + 1]; k += SYS_P_THREADS) {
+        Px += mom_part[3 * (size_t)k];
+        Py += mom_part[3 * (size_t)k + 1];
+        Pz += mom_part[3 * (size_t)k + 2];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        Px += __shfl_xor(Px, o, 64);
+        Py += __shfl_xor(Py, o, 64);
+        Pz += __shfl_xor(Pz, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = Px;
+        red[1][threadIdx.x >> 6] = Py;
+        red[2][threadIdx.x >> 6] = Pz;
+    }
+    __syncthreads();
+    P[0] = P[1] = P[2] = 0.0;
+    for (int w = 0; w < SYS_P_THREADS / 64; ++w)
+        for (int q = 0; q < 3; ++q) P[q] += red[q][w];
+    __syncthreads();
+}
 hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
                             int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
                             int32_t *flags, hipStream_t stream);
-hipError_t launch_ce_bs(const Layout &L, const double *x, const double *y, const double *z,
-                        const double *vx, const double *vy, const double *vz, const double *m,
-                        const double *rc, double dt, const int32_t *members,
-                        const int32_t *group_start, const int32_t *n_groups, double *bs_out,
+// Kepler drift of the bodies outside encounter groups and Bulirsch-Stoer of each group, in
+// one launch; clears member_slot for the next step.
+hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, const double *m, const double *rc, double dt, const int32_t *members,
+                        const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
                         int32_t *flags, hipStream_t stream);
-hipError_t launch_kepler(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
-                         double *vz, double dt, int32_t *member_slot, const double *bs_out,
-                         int32_t *flags, hipStream_t stream);
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,
                          const double *vz, const double *m, const double *ax, const double *ay,

@@ -356,14 +356,32 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
 
 // Source records, the largest r_crit^2 of every chunk, and a cleared pair counter.
 template <bool F32>
-__global__ __launch_bounds__(256) void prep_kernel(const Chunk *chunks, const double *x,
-                                                   const double *y, const double *z,
-                                                   const double *m, const double *rc, void *jrec,
-                                                   double *rc2_part, int32_t *pair_count)
+__global__ __launch_bounds__(SYS_P_THREADS) void prep_kernel(const Chunk *chunks, const int32_t *chunk_first,
+                                                             const double *mstar, const double *mom_part,
+                                                             double shift_tau, double *x, double *y,
+                                                             double *z, const double *m,
+                                                             const double *rc, void *jrec,
+                                                             double *rc2_part, int32_t *pair_count)
 {
     const Chunk c = chunks[blockIdx.x];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (shift_tau != 0.0) {
+        // the pending half of a Sun drift: x += tau P / Mstar (same arithmetic as sun_shift)
+        __shared__ double pred[3][SYS_P_THREADS / 64];
+        double P[3];
+        system_momentum(chunk_first, mom_part, c.sys, pred, P);
+        const double f = shift_tau / mstar[c.sys];
+        sx = f * P[0];
+        sy = f * P[1];
+        sz = f * P[2];
+    }
     double mx = 0.0;
-    for (int i = c.b + threadIdx.x; i < c.e; i += 256) {
+    for (int i = c.b + threadIdx.x; i < c.e; i += SYS_P_THREADS) {
+        if (shift_tau != 0.0) {
+            x[i] += sx;
+            y[i] += sy;
+            z[i] += sz;
+        }
         if (F32) {
             JRec32 r;
             r.x = x[i];
@@ -414,17 +432,19 @@ __global__ __launch_bounds__(256) void rcrit_kernel(int n_total, const int32_t *
 
 } // namespace
 
-hipError_t launch_prep(const Layout &L, const double *x, const double *y, const double *z,
-                       const double *m, const double *rc, void *jrec, int fp32, double *rc2_part,
-                       int32_t *pair_count, hipStream_t stream)
+hipError_t launch_prep(const Layout &L, double *x, double *y, double *z, const double *m,
+                       const double *rc, void *jrec, int fp32, double *rc2_part, int32_t *pair_count,
+                       const double *mom_part, double shift_tau, hipStream_t stream)
 {
     if (L.n_chunks == 0) return hipSuccess;
     if (fp32)
-        prep_kernel<true><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
-                                                          pair_count);
+        prep_kernel<true><<<L.n_chunks, SYS_P_THREADS, 0, stream>>>(L.chunks, L.chunk_first, L.mstar, mom_part,
+                                                                    shift_tau, x, y, z, m, rc, jrec,
+                                                                    rc2_part, pair_count);
     else
-        prep_kernel<false><<<L.n_chunks, 256, 0, stream>>>(L.chunks, x, y, z, m, rc, jrec, rc2_part,
-                                                           pair_count);
+        prep_kernel<false><<<L.n_chunks, SYS_P_THREADS, 0, stream>>>(L.chunks, L.chunk_first, L.mstar, mom_part,
+                                                                     shift_tau, x, y, z, m, rc, jrec,
+                                                                     rc2_part, pair_count);
     return hipGetLastError();
 }
 
