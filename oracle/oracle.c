@@ -334,6 +334,8 @@ static void group_rhs(int nb, const double *Y, double *D, const double *gm, cons
         D[6 * a + 4] = s * ya[1];
         D[6 * a + 5] = s * ya[2];
     }
+    /* rows are independent (each a sums over b in index order): threads split the rows only */
+#pragma omp parallel for schedule(static) if (nb >= 256)
     for (int a = 0; a < nb; ++a) {
         for (int b = 0; b < nb; ++b) {
             if (b == a) continue;
