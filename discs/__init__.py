@@ -187,6 +187,29 @@ def disc_c5() -> Disc:
                      n_embryo=40, embryo_mass_earth=0.05, name="c5_mixed")
 
 
+# ---------------------------------------------------------------------------------------------
+# The encounter-dominated regime: the paper's dense annulus (6600 planetesimals between 0.7
+# and 1 au, 2 Earth masses, 5-day step) with r_crit from the full eq. (1), n1 = 3, n2 = 0.4.
+# There r_crit (about 0.037 au) exceeds the mean spacing and the encounter groups percolate.
+# ---------------------------------------------------------------------------------------------
+DT_5_DAYS = days_to_code(5.0)
+DENSE_N1, DENSE_N2 = 3.0, 0.4
+
+
+def disc_dense(n: int = 6600, seed: int = 11, a_in: float = 0.7, a_out: float = 1.0) -> Disc:
+    """n planetesimals in [a_in, a_out] au carrying 2 Earth masses per 6600 bodies (the
+    paper's surface density), cold: e~R(0.002), i~R(0.001).  The default is the paper's
+    first experiment: one encounter group of all 6600 bodies at n2 = 0.4."""
+    return make_disc(n, 2.0 * n / 6600.0, seed, a_in=a_in, a_out=a_out, sigma_e=0.002, sigma_i=0.001,
+                     name=f"dense_n{n}")
+
+
+def ring_dense(n: int = 1000, seed: int = 12) -> Disc:
+    """A narrower dense ring (0.8-0.9 au) of n bodies at the same surface density scale: a few
+    groups of some hundred bodies each at n2 = 0.4 (1000 bodies: 4 groups, the largest 511)."""
+    return disc_dense(n, seed, a_in=0.8, a_out=0.9)
+
+
 def concat(discs: List[Disc]):
     """Flatten several systems into CSR form: (state dict, sys_off int32[n_sys+1], mstar[n_sys])."""
     off = np.zeros(len(discs) + 1, dtype=np.int32)

@@ -89,6 +89,17 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
  * synchronises the device and drops any captured graph. */
 int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host);
 
+/* Encounter groups of more than 64 bodies (the encounter-dominated phase of Sect. 4, where
+ * with the full eq. (1) the groups can span most of a disc).  enable = 0 (the default): such a
+ * group raises GENGA_ERR_CAPACITY and its bodies are only Kepler-drifted.  enable = 1: they
+ * are integrated by the same FP64 Bulirsch-Stoer method as the small groups, with the group's
+ * state spread over the device; genga_drift and genga_step then synchronise the host with
+ * `stream` once per step (to read the group sizes) and once per Bulirsch-Stoer attempt, so
+ * graph capture is refused (GENGA_ERR_STATE) while enabled.  Capacity: 8192 bodies in
+ * encounters per step, at most 126 groups above 64 bodies.  Allocates about 80 MB of
+ * device memory; kept across genga_set_systems.  Synchronises the device. */
+int genga_set_large_groups(genga_ctx *ctx, int32_t enable);
+
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
  * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).

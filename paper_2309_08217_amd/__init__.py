@@ -32,7 +32,8 @@ GENGA_KICK_FP32 = 1
 
 # every entry point of include/genga.h
 ENTRY_POINTS = (
-    "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_rcrit", "genga_accel",
+    "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
+    "genga_rcrit", "genga_accel",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
     "genga_get_kick_shape", "genga_poll_status", "genga_last_error",
@@ -68,6 +69,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_destroy": [vp],
         "genga_set_systems": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32],
         "genga_set_test_bodies": [vp, ctypes.POINTER(i32)],
+        "genga_set_large_groups": [vp, i32],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
         "genga_accel": [vp, bp, ctypes.c_int, vp, vp, vp, vp],
         "genga_kick": [vp, bp, dbl, ctypes.c_int, vp],
@@ -177,6 +179,11 @@ def genga_set_test_bodies(ctx: int, n_massive: Optional[Sequence[int]]) -> None:
         return
     nm = np.ascontiguousarray(n_massive, dtype=np.int32)
     _check(load_library().genga_set_test_bodies(ctx, nm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+
+
+def genga_set_large_groups(ctx: int, enable: bool) -> None:
+    """Encounter groups above 64 bodies: integrate them (True) or flag them (False, default)."""
+    _check(load_library().genga_set_large_groups(ctx, int(enable)))
 
 
 def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:

@@ -8,6 +8,7 @@
 // sources j > i); per-item partial sums are reduced in a fixed order, so the result is
 // deterministic.  Velocities may be given half a kick ahead: v_sync = v - vshift * a.
 #include "genga_internal.h"
+#include "pair_math.h"
 
 namespace genga {
 
@@ -17,15 +18,6 @@ constexpr int EW = 8;      // waves per workgroup in the pair sum
 constexpr int NPART = 9;   // pairpot, kin, sunpot, px, py, pz, lx, ly, lz
 
 using CJ64 = const __attribute__((address_space(4))) double;
-
-__device__ __forceinline__ double inv_sqrt64(double q)
-{
-    double y0 = __builtin_amdgcn_rsq(q);
-    double t = q * y0;
-    double e = fma(-t, y0, 1.0);
-    double p = fma(0.375, e, 0.5);
-    return fma(y0 * e, p, y0);
-}
 
 __device__ __forceinline__ double wave_sum(double v)
 {

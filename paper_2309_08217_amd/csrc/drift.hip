@@ -7,33 +7,11 @@
 //    integrated over dt by Gragg-Bulirsch-Stoer under the Sun's force plus the (1 - K) share
 //    of the members' mutual forces; the Kepler kernel then writes the group results back.
 #include "genga_internal.h"
+#include "pair_math.h"
 
 namespace genga {
 
 namespace {
-
-__device__ __forceinline__ double sep2_rn(double dx, double dy, double dz)
-{
-#pragma clang fp contract(off)
-    double a = dx * dx;
-    double b = dy * dy;
-    double c = dz * dz;
-    return (a + b) + c;
-}
-
-__device__ __forceinline__ double sq_rn(double a)
-{
-#pragma clang fp contract(off)
-    return a * a;
-}
-
-__device__ __forceinline__ double changeover_k(double y)
-{
-    if (y <= 0.0) return 0.0;
-    if (y >= 1.0) return 1.0;
-    double y2 = y * y;
-    return y2 / (2.0 * y2 - 2.0 * y + 1.0);
-}
 
 // ------------------------------------------------------------------------------------------
 // Sun drift in two launches over chunks of one system: partial momenta per chunk (fixed-order
@@ -384,24 +362,6 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// 1/sqrt(q) in FP64: v_rsq_f64 (about 2^-24) and one third-order correction
-__device__ __forceinline__ double inv_sqrt64(double q)
-{
-    const double y0 = __builtin_amdgcn_rsq(q);
-    const double t = q * y0;
-    const double e = fma(-t, y0, 1.0);
-    const double p = fma(0.375, e, 0.5);
-    return fma(y0 * e, p, y0);
-}
-
-// Step reduction after a rejected step: 0.9 (tol/err)^(1/15) from the last column's error,
-// kept within [1/50, 1/2].
-__device__ __forceinline__ double shrink_factor(double err, double tol)
-{
-    const double f = 0.9 * pow(tol / err, 1.0 / (2 * BS_KMAX - 1));
-    return fmax(0.02, fmin(0.5, f));
-}
-
 // Neville factor 1 / ((n_k / n_(k-l))^2 - 1) for n_k = 2(k+1), written as p^2 / (q^2 - p^2)
 // with q = k + 1, p = k + 1 - l: exact small integers and one rounding.
 __device__ __forceinline__ double neville_c(int k, int l)
@@ -632,35 +592,7 @@ __device__ bool bs_lanes(const BsMember &me, BsShared &S, double (*tab)[6][BS_LA
 // extrapolation column k for the whole group, so a force evaluation is lane-local (the pair
 // force is formed once and applied to both members) and needs no exchange between lanes.
 // When column k completes, T(k, 0) goes to LDS and the wave forms T(k, k) - T(k, k-1) with
-// one lane per state element, from the Lagrange form of the extrapolation below.
-//
-// Polynomial extrapolation in h^2 to h = 0 over the nodes n_0..n_k (n_j = 2(j+1)) has the
-// Lagrange weights w_j = prod_{m != j} n_j^2 / (n_j^2 - n_m^2); it is the value Neville's
-// scheme computes, T(k, k), and the same over the nodes 1..k gives T(k, k-1).  Both sets of
-// weights sum to one, so the sums are formed relative to T(0, 0), which keeps their rounding
-// at the size of the differences.
-struct LagrangeTable {
-    double w[BS_KMAX][BS_KMAX]; // w[k][j]: weight of T(j, 0) in T(k, k)
-    double d[BS_KMAX][BS_KMAX]; // d[k][j]: weight of T(j, 0) in T(k, k) - T(k, k-1)
-    constexpr LagrangeTable() : w(), d()
-    {
-        for (int k = 0; k < BS_KMAX; ++k)
-            for (int j = 0; j <= k; ++j) {
-                const double nj2 = 4.0 * (j + 1) * (j + 1);
-                double a = 1.0, b = 1.0;
-                for (int m = 0; m <= k; ++m) {
-                    if (m == j) continue;
-                    const double nm2 = 4.0 * (m + 1) * (m + 1);
-                    a *= nj2 / (nj2 - nm2);
-                    if (m >= 1) b *= nj2 / (nj2 - nm2);
-                }
-                w[k][j] = a;
-                d[k][j] = j >= 1 ? a - b : a;
-            }
-    }
-};
-__constant__ constexpr LagrangeTable LAGRANGE{};
-
+// one lane per state element, from the Lagrange form of the extrapolation (LAGRANGE).
 template <int NB>
 struct SmallGroup {
     double mstar;
@@ -858,7 +790,7 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
                                                          const int32_t *members,
                                                          const int32_t *group_start,
                                                          const int32_t *n_groups, int32_t *member_slot,
-                                                         int32_t *flags)
+                                                         int32_t *flags, int big_groups)
 {
     __shared__ BsShared S;
     __shared__ double tab[BS_KMAX * 6 * BS_LANES];
@@ -880,6 +812,7 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
     const int k0 = group_start[g], nb = group_start[g + 1] - k0;
     const double ms = mstar[sys_of[members[k0]]];
     if (nb > BS_LANES) {
+        if (big_groups) return; // integrated by the grid-wide path
         // larger than one wave: Kepler-drift the members instead and flag it
         if (lane == 0) atomicOr(flags, FLAG_CAPACITY);
         for (int k = lane; k < nb; k += BS_LANES) {
@@ -965,13 +898,13 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, hipStream_t stream)
+                        int32_t *flags, int big_groups, hipStream_t stream)
 {
     if (L.n_total == 0) return hipSuccess;
     const int grid = BS_BLOCKS + (L.n_total + BS_LANES - 1) / BS_LANES;
     drift_kernel<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z,
                                                 vx, vy, vz, m, rc, dt, members, group_start, n_groups,
-                                                member_slot, flags);
+                                                member_slot, flags, big_groups);
     return hipGetLastError();
 }
 

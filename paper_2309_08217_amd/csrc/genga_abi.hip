@@ -81,9 +81,44 @@ struct genga_ctx {
     int32_t *lab = nullptr, *mark = nullptr, *members = nullptr, *group_start = nullptr;
     int32_t *n_groups = nullptr, *member_slot = nullptr;
     double *epartial = nullptr;
+    // grid-wide Bulirsch-Stoer for groups of more than CE_MAX_GROUP members (opt-in)
+    int32_t large_groups = 0;
+    BigBs big;
+    int32_t *pin = nullptr;            // pinned host words for the per-attempt status reads
+    std::vector<int32_t> gs_h;         // group_start copied to the host
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+
+    void release_big()
+    {
+        dfree(big.k0);
+        dfree(big.off);
+        dfree(big.tiles);
+        dfree(big.body);
+        dfree(big.grp);
+        dfree(big.test);
+        dfree(big.rc);
+        dfree(big.mass);
+        dfree(big.Y);
+        dfree(big.tcol);
+        dfree(big.mstar);
+        dfree(big.t);
+        dfree(big.H);
+        dfree(big.rcmax2);
+        dfree(big.last);
+        dfree(big.attempts);
+        dfree(big.acc);
+        dfree(big.done);
+        dfree(big.sr);
+        dfree(big.sv);
+        dfree(big.err);
+        dfree(big.n_active);
+        if (pin) (void)hipHostFree(pin);
+        pin = nullptr;
+        big.G = big.M = big.n_tiles = 0;
+        large_groups = 0;
+    }
 
     void release()
     {
@@ -112,6 +147,7 @@ struct genga_ctx {
         dfree(member_slot);
         dfree(epartial);
         dfree(kpart);
+        release_big();
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         graph_exec = nullptr;
@@ -206,6 +242,8 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     return GENGA_OK;
 }
 
+int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
+
 // Sun drift (dt/2), Kepler / Bulirsch-Stoer (dt), Sun drift (dt/2).  With defer_shift the
 // last position shift is left to the next kick's source-record pass (only the momentum
 // partials are formed here); that kick must be given shift_tau = dt/2.
@@ -217,11 +255,93 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
     HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
                              ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
     HIP_TRY(launch_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
-                         ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
+                         ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, ctx->large_groups, s));
+    if (ctx->large_groups) {
+        const int rc = run_big_groups(ctx, b, dt, s);
+        if (rc) return rc;
+    }
     if (defer_shift)
         HIP_TRY(launch_momentum(L, b->vx, b->vy, b->vz, b->m, ctx->mom_part, s));
     else
         HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
+    return GENGA_OK;
+}
+
+int alloc_big(genga_ctx *ctx)
+{
+    BigBs &b = ctx->big;
+    const size_t M = CE_MAX_MEMBERS, G = BIG_MAX_GROUPS;
+    HIP_TRY(dalloc(b.k0, G));
+    HIP_TRY(dalloc(b.off, G + 1));
+    HIP_TRY(dalloc(b.tiles, (size_t)BIG_MAX_TILES));
+    HIP_TRY(dalloc(b.body, M));
+    HIP_TRY(dalloc(b.grp, M));
+    HIP_TRY(dalloc(b.test, M));
+    HIP_TRY(dalloc(b.rc, M));
+    HIP_TRY(dalloc(b.mass, M));
+    HIP_TRY(dalloc(b.Y, 3 * 6 * M));
+    HIP_TRY(dalloc(b.tcol, (size_t)BS_KMAX * 6 * M));
+    HIP_TRY(dalloc(b.mstar, G));
+    HIP_TRY(dalloc(b.t, G));
+    HIP_TRY(dalloc(b.H, G));
+    HIP_TRY(dalloc(b.rcmax2, G));
+    HIP_TRY(dalloc(b.last, G));
+    HIP_TRY(dalloc(b.attempts, G));
+    HIP_TRY(dalloc(b.acc, G));
+    HIP_TRY(dalloc(b.done, G));
+    HIP_TRY(dalloc(b.sr, G));
+    HIP_TRY(dalloc(b.sv, G));
+    HIP_TRY(dalloc(b.err, G * BS_KMAX));
+    HIP_TRY(dalloc(b.n_active, 1));
+    if (!ctx->pin) HIP_TRY(hipHostMalloc((void **)&ctx->pin, 4 * sizeof(int32_t), hipHostMallocDefault));
+    return GENGA_OK;
+}
+
+// Groups of more than CE_MAX_GROUP members: read the group sizes (the one host round trip of
+// a step in this mode), lay the large groups out for the grid-wide path, and run attempts
+// until every group has reached dt.
+int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+{
+    BigBs &bg = ctx->big;
+    bg.G = bg.M = bg.n_tiles = 0;
+    HIP_TRY(hipMemcpyAsync(ctx->pin, ctx->n_groups, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int ng = ctx->pin[0];
+    if (ng <= 0) return GENGA_OK;
+    ctx->gs_h.resize((size_t)ng + 1);
+    HIP_TRY(hipMemcpyAsync(ctx->gs_h.data(), ctx->group_start, ((size_t)ng + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> k0, off(1, 0);
+    std::vector<int4> tiles;
+    for (int g = 0; g < ng; ++g) {
+        const int nb = ctx->gs_h[g + 1] - ctx->gs_h[g];
+        if (nb <= CE_MAX_GROUP) continue;
+        const int gi = (int)k0.size(), o = off.back();
+        k0.push_back(ctx->gs_h[g]);
+        off.push_back(o + nb);
+        for (int f = 0; f < nb; f += 64) tiles.push_back(make_int4(gi, o + f, std::min(64, nb - f), 0));
+    }
+    if (k0.empty()) return GENGA_OK;
+    if ((int)k0.size() > BIG_MAX_GROUPS || off.back() > CE_MAX_MEMBERS || (int)tiles.size() > BIG_MAX_TILES)
+        return fail(GENGA_ERR_STATE, "large-group layout exceeds its allocation");
+    bg.G = (int32_t)k0.size();
+    bg.M = off.back();
+    bg.n_tiles = (int32_t)tiles.size();
+    HIP_TRY(hipMemcpy(bg.k0, k0.data(), k0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+    const Layout &L = ctx->L;
+    HIP_TRY(launch_big_setup(L, bg, ctx->members, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, s));
+    // every attempt ends with the count of groups still short of dt; the device gives up on a
+    // group after 20000 attempts, so the loop ends
+    for (int attempt = 0; attempt <= 20001; ++attempt) {
+        HIP_TRY(launch_big_attempt(bg, dt, 1e-12, ctx->flags, s));
+        HIP_TRY(hipMemcpyAsync(ctx->pin + 1, bg.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ctx->pin[1] == 0) break;
+    }
+    HIP_TRY(launch_big_finish(bg, b->x, b->y, b->z, b->vx, b->vy, b->vz, s));
     return GENGA_OK;
 }
 
@@ -335,6 +455,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     if (n_total64 > (int64_t)1 << 30) return fail(GENGA_ERR_ARG, "too many bodies");
     const int32_t n_total = (int32_t)n_total64;
     HIP_TRY(hipDeviceSynchronize());
+    const int32_t keep_large = ctx->large_groups;
     ctx->release();
     ctx->sys_off_h.assign(sys_off_host, sys_off_host + n_sys + 1);
 
@@ -411,6 +532,29 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     rc = upload_plan(ctx);
     if (rc) return rc;
     ctx->split[0] = ctx->split[1] = default_split(ctx);
+    if (keep_large) {
+        if ((rc = alloc_big(ctx))) return rc;
+        ctx->large_groups = 1;
+    }
+    return GENGA_OK;
+}
+
+int genga_set_large_groups(genga_ctx *ctx, int32_t enable)
+{
+    int rc = check_ctx(ctx, false);
+    if (rc) return rc;
+    if (enable != 0 && enable != 1) return fail(GENGA_ERR_ARG, "enable must be 0 or 1");
+    HIP_TRY(hipDeviceSynchronize());
+    if (!enable) {
+        ctx->release_big();
+        return GENGA_OK;
+    }
+    if (ctx->graph_exec) return fail(GENGA_ERR_STATE, "a captured graph exists: large groups need host round trips");
+    if (!ctx->large_groups && (rc = alloc_big(ctx))) {
+        ctx->release_big();
+        return rc;
+    }
+    ctx->large_groups = 1;
     return GENGA_OK;
 }
 
@@ -512,6 +656,8 @@ int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, 
     if (nsteps < 1) return fail(GENGA_ERR_ARG, "nsteps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     if (!s) return fail(GENGA_ERR_ARG, "graph capture needs a non-default stream");
+    if (ctx->large_groups)
+        return fail(GENGA_ERR_STATE, "graph capture is not available while large groups are enabled (host round trips)");
     HIP_TRY(hipStreamSynchronize(s));
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);

@@ -135,12 +135,45 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
                             int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
                             int32_t *flags, hipStream_t stream);
-// Kepler drift of the bodies outside encounter groups and Bulirsch-Stoer of each group, in
-// one launch; clears member_slot for the next step.
+// Kepler drift of the bodies outside encounter groups and Bulirsch-Stoer of each group of up
+// to CE_MAX_GROUP members, in one launch; clears member_slot for the next step.  Larger groups
+// are flagged (GENGA_ERR_CAPACITY) and Kepler-drifted, or, with big_groups != 0, left alone
+// for the grid-wide path below.
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, hipStream_t stream);
+                        int32_t *flags, int big_groups, hipStream_t stream);
+
+// Grid-wide Bulirsch-Stoer for the groups of more than CE_MAX_GROUP members.  Members of the G
+// large groups are numbered f = 0..M-1, group g holding [off[g], off[g+1]); state arrays are
+// SoA with stride M.  Capacities: members CE_MAX_MEMBERS, groups CE_MAX_MEMBERS / 65, tiles
+// CE_MAX_MEMBERS / 64 + groups.
+struct BigBs {
+    int32_t G = 0, M = 0, n_tiles = 0;
+    int32_t *k0 = nullptr;         // [G] first entry of the group in members[]
+    int32_t *off = nullptr;        // [G + 1]
+    int4 *tiles = nullptr;         // [n_tiles] (group, first member, count, 0): 64 targets
+    int32_t *body = nullptr, *grp = nullptr, *test = nullptr; // [M]
+    double *rc = nullptr, *mass = nullptr;                    // [M]
+    double *Y = nullptr;           // [3][6][M]: the state, then two sub-step buffers
+    double *tcol = nullptr;        // [BS_KMAX][6][M]: T(k, 0)
+    double *mstar = nullptr, *t = nullptr, *H = nullptr, *rcmax2 = nullptr; // [G]
+    int32_t *last = nullptr, *attempts = nullptr, *acc = nullptr, *done = nullptr; // [G]
+    unsigned long long *sr = nullptr, *sv = nullptr; // [G] bit patterns of max |r|, max |v|
+    unsigned long long *err = nullptr;               // [G][BS_KMAX] bit patterns of the estimates
+    int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
+};
+constexpr int BIG_MAX_GROUPS = CE_MAX_MEMBERS / (CE_MAX_GROUP + 1);
+constexpr int BIG_MAX_TILES = CE_MAX_MEMBERS / 64 + BIG_MAX_GROUPS;
+
+hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
+                            const double *y, const double *z, const double *vx, const double *vy,
+                            const double *vz, const double *m, const double *rc, double dt,
+                            hipStream_t stream);
+// One attempt of every active group (a fixed sequence of launches).
+hipError_t launch_big_attempt(const BigBs &b, double dt, double tol, int32_t *flags, hipStream_t stream);
+hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz, hipStream_t stream);
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,
                          const double *vz, const double *m, const double *ax, const double *ay,

@@ -18,6 +18,7 @@
 //  * FP32 path: FP32 partial sums over blocks of 64 sources, folded into FP64 accumulators.
 //    FP64 path: v_rsq_f64 (about 2^-24) refined by one third-order correction.
 #include "genga_internal.h"
+#include "pair_math.h"
 
 namespace genga {
 
@@ -47,33 +48,6 @@ __device__ __forceinline__ JRec64 ldj(CJ64 *J, int j)
     r.z = J[j].z;
     r.m = J[j].m;
     return r;
-}
-
-// separation^2 and squares without contraction: the encounter decision uses exactly the
-// rounding of the definition ((dx*dx + dy*dy) + dz*dz, then compare with rc*rc)
-__device__ __forceinline__ double sep2_rn(double dx, double dy, double dz)
-{
-#pragma clang fp contract(off)
-    double a = dx * dx;
-    double b = dy * dy;
-    double c = dz * dz;
-    return (a + b) + c;
-}
-
-__device__ __forceinline__ double sq_rn(double a)
-{
-#pragma clang fp contract(off)
-    return a * a;
-}
-
-// Changeover weight of Chambers (1999), cited in Sect. 1: K(y) = y^2 / (2y^2 - 2y + 1) on
-// [0, 1], 0 below, 1 above.
-__device__ __forceinline__ double changeover_k(double y)
-{
-    if (y <= 0.0) return 0.0;
-    if (y >= 1.0) return 1.0;
-    double y2 = y * y;
-    return y2 / (2.0 * y2 - 2.0 * y + 1.0);
 }
 
 __device__ __forceinline__ void emit_pair(const KickArgs &a, int i, int j)

@@ -1,0 +1,96 @@
+"""Encounter-dominated regime (Sect. 4): with the full eq. (1) (n1 = 3, n2 = 0.4) on the
+paper's dense annulus the encounter groups grow past one wavefront, up to the whole disc.
+The grid-wide Bulirsch-Stoer path (genga_set_large_groups) against the oracle's drift and
+steps, on the GPU's own input state."""
+import numpy as np
+import pytest
+
+import discs
+import oracle
+import paper_2309_08217_amd as genga
+from gpu_helpers import System
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = genga.GENGA_KICK_FP64, genga.GENGA_KICK_FP32
+DT5 = discs.DT_5_DAYS
+
+
+def dense_system(d, large=True):
+    rc = oracle.rcrit(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5)
+    s = System([d], rcrit=rc)
+    if large:
+        genga.genga_set_large_groups(s.ctx.handle, True)
+    return s
+
+
+def compare_drift(d, label):
+    s = dense_system(d)
+    s.accel(FP64)                       # the encounter list of this state
+    pairs, cnt = s.encounter_list()
+    b0 = s.numpy_state()
+    gid = oracle.groups(d.n, pairs)
+    sizes = np.bincount(gid[gid >= 0])
+    print(f"[{label}] pairs={cnt} groups={len(sizes)} largest={sizes.max()} above 64={(sizes > 64).sum()}", flush=True)
+    assert sizes.max() > 64
+    exp = oracle.drift(b0, s.rc, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    inside = gid >= 0
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        e_bs = np.max(np.abs(got[k][inside] - exp[k][inside]))
+        e_kep = np.max(np.abs(got[k][~inside] - exp[k][~inside])) if (~inside).any() else 0.0
+        print(f"[{label}] {k} BS err {e_bs:.2e} Kepler err {e_kep:.2e}", flush=True)
+        assert e_bs <= 1e-10
+        assert e_kep <= 1e-13
+    s.close()
+
+
+def test_ring_groups_of_hundreds():
+    """1000 bodies, 0.8-0.9 au: 4 groups, three above 64 bodies (the largest 511)."""
+    compare_drift(discs.ring_dense(1000), "ring 1000")
+
+
+def test_annulus_mixed_group_sizes():
+    """2000 bodies, 0.7-1 au: large groups and groups of 2-64 in the same drift."""
+    compare_drift(discs.disc_dense(2000, seed=14), "annulus 2000")
+
+
+def test_whole_disc_is_one_group():
+    """The paper's first experiment at n2 = 0.4: all 6600 bodies form one encounter group."""
+    compare_drift(discs.disc_dense(), "dense 6600")
+
+
+def test_ring_steps_against_oracle():
+    """Five full steps (kick, list, drift with large groups, kick) in FP64 and FP32."""
+    d = discs.ring_dense(1000)
+    for prec, bar in ((FP64, 1e-10), (FP32, 1e-8)):
+        s = dense_system(d)
+        genga.genga_step(s.ctx.handle, s.b, DT5, 5, prec)
+        got = s.numpy_state()
+        assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+        exp, _ = oracle.step(d.state(), s.rc, 1.0, DT5, 5)
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            err = np.max(np.abs(got[k] - exp[k]))
+            print(f"[ring steps prec={prec}] {k} max err {err:.2e}", flush=True)
+            assert err <= bar
+        s.close()
+
+
+def test_large_groups_off_flags_capacity_and_graph_refused():
+    """Without the switch a group above 64 bodies is flagged; with it, graph capture is refused."""
+    d = discs.ring_dense(1000)
+    s = dense_system(d, large=False)
+    s.accel(FP64)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    s.torch.cuda.synchronize()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_ERR_CAPACITY
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    stream = s.torch.cuda.Stream()
+    with pytest.raises(genga.GengaError) as e:
+        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream)
+    assert e.value.status == genga.GENGA_ERR_STATE
+    with pytest.raises(genga.GengaError):
+        genga.genga_set_large_groups(s.ctx.handle, 2)
+    s.close()
