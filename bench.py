@@ -9,8 +9,10 @@ times steps per second, for state already resident in HBM.
 
 Also reported: the FP64 kick path, kick-only rates and their ratio, the roofline of the
 kick kernel (HIP events on the launch stream), a batched run of 64 uneven discs in one
-launch per kernel vs a loop of single-disc launches, Delta E/E and Delta L/L over the
-timed steps, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+launch per kernel vs a loop of single-disc launches, the encounter-dominated regime (the
+dense 6600-body annulus with the full eq. (1), one encounter group of the whole disc, on the
+grid-wide Bulirsch-Stoer path), Delta E/E and Delta L/L over the timed steps, and the FP64
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -191,6 +193,63 @@ def batched(torch, stream, steps=10, warmup=2):
             "speedup_vs_loop": t_loop / t, "status": status, **drift_stats(e_init, e_rec)}
 
 
+def dense(torch, stream, steps=10, warmup=2):
+    """Encounter-dominated regime: the dense annulus (6600 bodies, 0.7-1 au, 2 Earth masses,
+    5-day step) with r_crit from the full eq. (1), n2 = 0.4, where all bodies form one
+    encounter group; the grid-wide Bulirsch-Stoer path integrates it (host round trips per
+    attempt, so eager steps only)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    d = discs.disc_dense()
+    st, off, mstar = discs.concat([d])
+    ctx = genga.Context(0)
+    genga.genga_set_systems(ctx.handle, off, mstar)
+    genga.genga_set_large_groups(ctx.handle, True)
+    b = genga.Bodies.from_numpy(st, device="cuda:0")
+    rc = torch.zeros_like(b.x)
+    genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS, rc)
+    b.rcrit = rc
+    genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
+    # group sizes of the initial state, from the GPU's encounter list
+    genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32)
+    cap = 16 * d.n
+    pairs = torch.zeros(2 * cap, dtype=torch.int32, device="cuda:0")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    genga.genga_encounter_list(ctx.handle, pairs, cap, cnt)
+    torch.cuda.synchronize()
+    npair = int(cnt.item())
+    p = pairs[: 2 * npair].cpu().numpy().reshape(-1, 2)
+    adj = coo_matrix((np.ones(npair), (p[:, 0], p[:, 1])), shape=(d.n, d.n))
+    _, lab = connected_components(adj, directed=False)
+    sizes = np.bincount(lab)
+    e0 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    genga.genga_energy(ctx.handle, b, e0)
+    with torch.cuda.stream(stream):
+        genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, warmup, genga.GENGA_KICK_FP32, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, steps, genga.GENGA_KICK_FP32, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    e1 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    genga.genga_energy(ctx.handle, b, e1)
+    torch.cuda.synchronize()
+    status = genga.genga_poll_status(ctx.handle)
+    kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
+    E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
+    ctx.close()
+    return {"workload": "dense annulus N=6600, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
+                        "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11",
+            "encounter_pairs_at_start": npair, "largest_group_at_start": int(sizes.max()),
+            "groups_above_64_at_start": int((sizes > 64).sum()),
+            "steps": steps, "warmup": warmup, "steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps,
+            "kick_ms": kick_ms, "non_kick_ms_per_step": 1e3 * t / steps - kick_ms,
+            "dE_over_E": float(E1[0] / E0[0] - 1.0),
+            "dL_over_L": float(np.linalg.norm(E1[1:]) / np.linalg.norm(E0[1:]) - 1.0),
+            "status": status}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,6 +264,10 @@ def main():
                     help="precision of the --only-kick kicks")
     ap.add_argument("--batched-only", action="store_true",
                     help="profiling aid: run only the 64-disc batched measurement")
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the encounter-dominated dense-annulus measurement")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="profiling aid: run only the dense-annulus measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling aid: copy a 256 MiB buffer 4 times (a plain copy of known size, "
                          "to scale HBM byte counters) and exit")
@@ -229,6 +292,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(batched(torch, stream)))
+        return
+    if args.dense_only:
+        print(json.dumps(dense(torch, stream)))
         return
     d = discs.disc_c3()
     if args.only_kick > 0:
@@ -301,6 +367,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched(torch, stream)
+    if not args.no_dense:
+        out["dense"] = dense(torch, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d.state(), n)
     print(json.dumps(out), flush=True)

@@ -12,6 +12,13 @@
 // split the group's members as sources), then per column an error launch and a decision
 // launch.  A group that has accepted a column, or reached dt, skips the rest.  The host
 // repeats attempts until no group is active.
+//
+// The members of a group are ordered by ring and azimuth about the star (by the host, once per
+// step), so a tile of 64 consecutive members is compact in space.  Each state buffer carries the
+// bounding box of every tile, written by the launch that wrote the positions; a wave skips a
+// source tile whose box is farther than the group's largest r_crit from the target tile's
+// box, since no pair across the two can lie inside r_crit,ab.  The order only decides how
+// much is skipped, never the result beyond rounding.
 #include "genga_internal.h"
 #include "pair_math.h"
 
@@ -24,10 +31,55 @@ using CI = const __attribute__((address_space(4))) int32_t;
 
 constexpr int GB_TILE = 64;
 constexpr int GB_WAVES = 8;
+constexpr int GB_SPLIT = BIG_SPLIT; // workgroups sharing one target tile's sources
 constexpr int GB_THREADS = 256;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+__device__ __forceinline__ double wave_minv(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_maxv(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// max into slot[g] for every lane with use = true: the lanes of the wave's first group
+// combine first and one of them updates the slot; lanes of another group update their own.
+// Every lane of the wave must call it.
+__device__ __forceinline__ void wave_atomic_max(unsigned long long *slot, int g, bool use,
+                                                unsigned long long v)
+{
+    const unsigned long long any = __ballot(use);
+    if (!any) return;
+    const int leader = __ffsll((long long)any) - 1;
+    const int g0 = __shfl(g, leader, 64);
+    const bool same = use && g == g0;
+    unsigned long long m = same ? v : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(m, o, 64);
+        m = w > m ? w : m;
+    }
+    if ((int)(threadIdx.x & 63) == leader) atomicMax(&slot[g0], m);
+    if (use && !same) atomicMax(&slot[g], v);
+}
+
+// Bounding box of the positions held by the lanes with v = true, into
+// out[t * 8 + 0..5] = (min x, y, z, max x, y, z).  Every lane of the wave calls it.
+__device__ __forceinline__ void tile_box(bool v, double x, double y, double z, double *out, int t)
+{
+    const int lane = threadIdx.x & 63;
+    const double lo[3] = {wave_minv(v ? x : INFINITY), wave_minv(v ? y : INFINITY), wave_minv(v ? z : INFINITY)};
+    const double hi[3] = {wave_maxv(v ? x : -INFINITY), wave_maxv(v ? y : -INFINITY), wave_maxv(v ? z : -INFINITY)};
+    if (lane < 3) {
+        out[t * 8 + lane] = lo[lane];
+        out[t * 8 + 3 + lane] = hi[lane];
+    }
+}
 
 // Flat member m of large group g: body index, constants, state Y[q * M + m].
 __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const int32_t *sys_of,
@@ -47,10 +99,10 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
     const size_t M = (size_t)b.M;
     double mx = 0.0;
     for (int l = threadIdx.x; l < nb; l += GB_THREADS) {
-        const int body = members[k0 + l], f = o + l, s = sys_of[body];
-        b.body[f] = body;
+        const int f = o + l, body = b.body[f], s = sys_of[body];
         b.grp[f] = g;
         b.rc[f] = rc[body];
+        b.i09[f] = 1.0 / (0.9 * rc[body]);
         b.mass[f] = m[body];
         b.test[f] = body - sys_off[s] >= n_massive[s];
         b.Y[0 * M + f] = x[body];
@@ -103,16 +155,28 @@ __global__ __launch_bounds__(64) void big_begin_kernel(BigBs b, double dt, int32
 // non-negative doubles through their bit patterns, so the order of updates does not matter).
 __global__ __launch_bounds__(GB_THREADS) void big_scale_kernel(BigBs b)
 {
-    const int f = blockIdx.x * GB_THREADS + threadIdx.x;
-    if (f >= b.M) return;
+    const int f0 = blockIdx.x * GB_THREADS + threadIdx.x;
+    const bool in = f0 < b.M;
+    const int f = in ? f0 : 0;
     const int g = b.grp[f];
-    if (b.done[g]) return;
+    const bool use = in && !b.done[g];
     const size_t M = (size_t)b.M;
     const double *Y = b.Y;
     const double rr = sqrt(sep2_rn(Y[f], Y[M + f], Y[2 * M + f]));
     const double vv = sqrt(sep2_rn(Y[3 * M + f], Y[4 * M + f], Y[5 * M + f]));
-    atomicMax(&b.sr[g], dbits(rr));
-    atomicMax(&b.sv[g], dbits(vv));
+    wave_atomic_max(b.sr, g, use, dbits(rr));
+    wave_atomic_max(b.sv, g, use, dbits(vv));
+}
+
+// Tile boxes of the attempt's starting state Y.
+__global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
+{
+    const int4 tile = b.tiles[blockIdx.x];
+    if (b.done[tile.x]) return;
+    const size_t M = (size_t)b.M;
+    const bool v = (int)threadIdx.x < tile.z;
+    const int f = tile.y + (v ? (int)threadIdx.x : 0);
+    tile_box(v, b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.bb, blockIdx.x);
 }
 
 // One sub-step of column k for every target of a tile: f(Z) (Kepler term plus the (1 - K)
@@ -120,98 +184,153 @@ __global__ __launch_bounds__(GB_THREADS) void big_scale_kernel(BigBs b)
 //   mode 0: OUT = Z + h f(Z)            (first sub-step, Z = Y)
 //   mode 1: OUT = ZM + 2 h f(Z)         (OUT may be ZM's buffer: each lane rewrites its own)
 //   mode 2: T(k, 0) = (ZM + Z + h f(Z)) / 2, into tcol[k]
-// Source positions come through scalar loads: Z is not written by this launch.
+// and, in modes 0 and 1, the tile's box in OUT's box array.  Source positions and boxes come
+// through scalar loads: neither is written by this launch.  GB_SPLIT workgroups share a target
+// tile; wave w of part p visits the source tiles p GB_WAVES + w, + GB_WAVES GB_SPLIT, ... of
+// the group and skips those out of reach.  Each part stores its sum; the part that finishes
+// last (a ticket counter per tile) adds them in part order and completes the sub-step.
 __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
-                                                                       const double *Z,
-                                                                       const double *ZM, double *OUT)
+                                                                       const double *Z, const double *ZM,
+                                                                       double *OUT, const double *bbZ,
+                                                                       double *bbOUT)
 {
     __shared__ double red[3][GB_WAVES][GB_TILE];
-    const int4 tile = b.tiles[blockIdx.x]; // (group, first member, count, -)
+    __shared__ int s_last;
+    const int me = blockIdx.x / GB_SPLIT, part = blockIdx.x % GB_SPLIT;
+    const int4 tile = b.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
     if (b.done[g] || b.acc[g] >= 0) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const size_t M = (size_t)b.M;
     const int o = b.off[g], nb = b.off[g + 1] - o;
+    const int tf = b.tfirst[g], nt = b.tfirst[g + 1] - tf;
     const bool valid = lane < tile.z;
     const int fa = tile.y + (valid ? lane : 0);
     const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
     const double rca = b.rc[fa];
     const bool testa = b.test[fa] != 0;
-    // candidate radius: the group's largest r_crit^2, with a margin for the contracted r^2
+    // candidate radius: the group's largest r_crit^2, with a margin for the contracted r^2;
+    // a source tile is skipped when the gap between the boxes exceeds it
     const double T = b.rcmax2[g] * (1.0 + 0x1p-40);
+    const double Tcull = b.rcmax2[g] * (1.0 + 0x1p-30);
     CD *ZX = (CD *)Z;
     CD *ZY = (CD *)(Z + M);
     CD *ZZ = (CD *)(Z + 2 * M);
     CD *RC = (CD *)b.rc;
     CD *MS = (CD *)b.mass;
     CI *TS = (CI *)b.test;
-    const int chunk = (nb + GB_WAVES - 1) / GB_WAVES;
-    const int jb = o + min(wave * chunk, nb), je = o + min(wave * chunk + chunk, nb);
+    CD *BB = (CD *)bbZ;
+    const double tlx = BB[me * 8 + 0], tly = BB[me * 8 + 1], tlz = BB[me * 8 + 2];
+    const double thx = BB[me * 8 + 3], thy = BB[me * 8 + 4], thz = BB[me * 8 + 5];
     double ax = 0.0, ay = 0.0, az = 0.0;
-    auto pair = [&](int j, double dx, double dy, double dz) {
-        if (j == fa) return;
-        if (testa && TS[j]) return;
-        const double q = sep2_rn(dx, dy, dz);
-        const double rcab = fmax(rca, RC[j]);
-        if (!(q < sq_rn(rcab))) return;
-        const double rq = inv_sqrt64(q);
-        const double w = 1.0 - changeover_k((q * rq - 0.1 * rcab) / (0.9 * rcab));
-        const double t = MS[j] * w * (rq * rq) * rq;
-        ax = fma(t, dx, ax);
-        ay = fma(t, dy, ay);
-        az = fma(t, dz, az);
+    const double i09a = b.i09[fa];
+    CD *I9 = (CD *)b.i09;
+    // the (1 - K) Newtonian terms of sources j .. j + cnt - 1 (cnt <= 4), side by side and
+    // without branches: a pair outside r_crit,ab, the target itself and a test-test pair get
+    // weight zero; the terms are added in source order
+    auto pairs4 = [&](int j, int cnt, const double (&dx)[4], const double (&dy)[4], const double (&dz)[4]) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jj = min(j + u, j + cnt - 1);
+            const double rcj = RC[jj], mj = MS[jj], i9j = I9[jj];
+            const bool tj = TS[jj] != 0;
+            const bool own = rca >= rcj;
+            const double rcab = own ? rca : rcj;
+            const double q = sep2_rn(dx[u], dy[u], dz[u]);
+            const bool in = u < cnt && j + u != fa && !(testa && tj) && q < sq_rn(rcab);
+            const double rq = inv_sqrt64(q);
+            const double yv = (q * rq - 0.1 * rcab) * (own ? i09a : i9j);
+            const double y2 = yv * yv;
+            const double kv = yv <= 0.0 ? 0.0 : (yv >= 1.0 ? 1.0 : y2 / (2.0 * y2 - 2.0 * yv + 1.0));
+            t[u] = in ? mj * (1.0 - kv) * (rq * rq) * rq : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ax = fma(t[u], dx[u], ax);
+            ay = fma(t[u], dy[u], ay);
+            az = fma(t[u], dz[u], az);
+        }
     };
-    int j = jb;
-    for (; j + 4 <= je; j += 4) {
-        const double dx0 = ZX[j] - xa, dy0 = ZY[j] - ya, dz0 = ZZ[j] - za;
-        const double dx1 = ZX[j + 1] - xa, dy1 = ZY[j + 1] - ya, dz1 = ZZ[j + 1] - za;
-        const double dx2 = ZX[j + 2] - xa, dy2 = ZY[j + 2] - ya, dz2 = ZZ[j + 2] - za;
-        const double dx3 = ZX[j + 3] - xa, dy3 = ZY[j + 3] - ya, dz3 = ZZ[j + 3] - za;
-        const double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
-        const double q1 = fma(dx1, dx1, fma(dy1, dy1, dz1 * dz1));
-        const double q2 = fma(dx2, dx2, fma(dy2, dy2, dz2 * dz2));
-        const double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
-        if (__builtin_expect(fmin(fmin(q0, q1), fmin(q2, q3)) < T, 0)) {
-            if (q0 < T) pair(j, dx0, dy0, dz0);
-            if (q1 < T) pair(j + 1, dx1, dy1, dz1);
-            if (q2 < T) pair(j + 2, dx2, dy2, dz2);
-            if (q3 < T) pair(j + 3, dx3, dy3, dz3);
+    for (int st = part * GB_WAVES + wave; st < nt; st += GB_WAVES * GB_SPLIT) {
+        const int ts = tf + st;
+        const double gx = fmax(0.0, fmax(BB[ts * 8 + 0] - thx, tlx - BB[ts * 8 + 3]));
+        const double gy = fmax(0.0, fmax(BB[ts * 8 + 1] - thy, tly - BB[ts * 8 + 4]));
+        const double gz = fmax(0.0, fmax(BB[ts * 8 + 2] - thz, tlz - BB[ts * 8 + 5]));
+        if ((gx * gx + gy * gy) + gz * gz > Tcull) continue; // no pair of the two tiles is close
+        const int jb = o + GB_TILE * st, je = min(jb + GB_TILE, o + nb);
+        for (int j = jb; j < je; j += 4) {
+            const int cnt = min(4, je - j);
+            double dx[4], dy[4], dz[4], q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = min(j + u, je - 1);
+                dx[u] = ZX[jj] - xa;
+                dy[u] = ZY[jj] - ya;
+                dz[u] = ZZ[jj] - za;
+                q[u] = u < cnt ? fma(dx[u], dx[u], fma(dy[u], dy[u], dz[u] * dz[u])) : INFINITY;
+            }
+            if (fmin(fmin(q[0], q[1]), fmin(q[2], q[3])) < T) pairs4(j, cnt, dx, dy, dz);
         }
     }
-    for (; j < je; ++j) pair(j, ZX[j] - xa, ZY[j] - ya, ZZ[j] - za);
     red[0][wave][lane] = ax;
     red[1][wave][lane] = ay;
     red[2][wave][lane] = az;
     __syncthreads();
-    if (wave != 0 || !valid) return;
+    if (wave == 0) {
+        double px = 0.0, py = 0.0, pz = 0.0;
+        for (int w = 0; w < GB_WAVES; ++w) {
+            px += red[0][w][lane];
+            py += red[1][w][lane];
+            pz += red[2][w][lane];
+        }
+        if (valid) {
+            double *P = b.part + (size_t)part * 3 * M;
+            P[fa] = px;
+            P[M + fa] = py;
+            P[2 * M + fa] = pz;
+        }
+        __threadfence(); // the sums are visible device-wide before the ticket is drawn
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&b.cnt[me], 1) == GB_SPLIT - 1;
+    __syncthreads();
+    if (!s_last || wave != 0) return;
+    __threadfence(); // see every part's sums
+    if (lane == 0) b.cnt[me] = 0; // ready for the next launch
     const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
     const double s = -b.mstar[g] * (ri * ri) * ri;
     double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa, s * ya, s * za};
-    for (int w = 0; w < GB_WAVES; ++w) {
-        d[3] += red[0][w][lane];
-        d[4] += red[1][w][lane];
-        d[5] += red[2][w][lane];
+    for (int p = 0; p < GB_SPLIT; ++p) {
+        const double *P = b.part + (size_t)p * 3 * M;
+        d[3] += P[fa];
+        d[4] += P[M + fa];
+        d[5] += P[2 * M + fa];
     }
     const double h = b.H[g] / (2 * (k + 1));
-    if (mode == 0) {
-        for (int q = 0; q < 6; ++q) OUT[q * M + fa] = Z[q * M + fa] + h * d[q];
-    } else if (mode == 1) {
-        for (int q = 0; q < 6; ++q) OUT[q * M + fa] = ZM[q * M + fa] + 2.0 * h * d[q];
-    } else {
+    if (mode == 2) {
+        if (!valid) return;
         double *T0 = b.tcol + (size_t)k * 6 * M;
         for (int q = 0; q < 6; ++q) T0[q * M + fa] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
+        return;
     }
+    double nx[6];
+    for (int q = 0; q < 6; ++q) nx[q] = (mode == 0 ? Z[q * M + fa] : ZM[q * M + fa]) + (mode == 0 ? h : 2.0 * h) * d[q];
+    if (valid)
+        for (int q = 0; q < 6; ++q) OUT[q * M + fa] = nx[q];
+    tile_box(valid, nx[0], nx[1], nx[2], bbOUT, me);
 }
 
 // Error estimate of column k: per member max(|T(k,k) - T(k,k-1)| / scale) over its six
 // elements, into the group's maximum.
 __global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
 {
-    const int f = blockIdx.x * GB_THREADS + threadIdx.x;
-    if (f >= b.M) return;
+    const int f0 = blockIdx.x * GB_THREADS + threadIdx.x;
+    const bool in = f0 < b.M;
+    const int f = in ? f0 : 0;
     const int g = b.grp[f];
-    if (b.done[g] || b.acc[g] >= 0) return;
+    const bool use = in && !b.done[g] && b.acc[g] < 0;
     const size_t M = (size_t)b.M;
     double dp = 0.0, dv = 0.0;
     bool bad = false;
@@ -225,7 +344,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
     }
     const double e = fmax(dp / bitsd(b.sr[g]), dv / bitsd(b.sv[g]));
     // a non-finite estimate is kept as the all-ones pattern, above every finite one
-    atomicMax(&b.err[g * BS_KMAX + k], (bad || !(e == e)) ? ~0ull : dbits(e));
+    wave_atomic_max(b.err + k, g * BS_KMAX, use, (bad || !(e == e)) ? ~0ull : dbits(e));
 }
 
 __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double tol)
@@ -322,23 +441,27 @@ hipError_t launch_big_attempt(const BigBs &b, double dt, double tol, int32_t *fl
     if (b.G == 0) return hipSuccess;
     const int gg = (b.G + 63) / 64, gm = (b.M + GB_THREADS - 1) / GB_THREADS;
     const size_t M6 = 6 * (size_t)b.M;
-    double *Y = b.Y, *B1 = b.Y + M6, *B2 = b.Y + 2 * M6;
+    double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
+    double *box[3] = {b.bb, b.bb + 8 * BIG_MAX_TILES, b.bb + 16 * BIG_MAX_TILES};
     big_begin_kernel<<<gg, 64, 0, stream>>>(b, dt, flags);
     big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_box_kernel<<<b.n_tiles, 64, 0, stream>>>(b);
     for (int k = 0; k < BS_KMAX; ++k) {
         const int nsub = 2 * (k + 1);
         // sub-step i reads zc_i and zm_i and writes zc_(i+1): zc_1 = B1 (zm_1 = Y), then the
         // new point goes into zm's buffer, B2 first
-        big_substep_kernel<<<b.n_tiles, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, Y, Y, B1);
-        const double *zc = B1, *zm = Y;
-        double *spare = B2;
+        big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1],
+                                                                                     box[0], box[1]);
+        int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
-            double *out = zm == Y ? spare : const_cast<double *>(zm);
-            big_substep_kernel<<<b.n_tiles, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, zc, zm, out);
+            const int out = zm == 0 ? 2 : zm;
+            big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm],
+                                                                                         buf[out], box[zc], box[out]);
             zm = zc;
             zc = out;
         }
-        big_substep_kernel<<<b.n_tiles, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, zc, zm, nullptr);
+        big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr,
+                                                                                     box[zc], nullptr);
         if (k > 0) {
             big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
             big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);

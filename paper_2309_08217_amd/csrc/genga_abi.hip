@@ -95,11 +95,16 @@ struct genga_ctx {
         dfree(big.k0);
         dfree(big.off);
         dfree(big.tiles);
+        dfree(big.tfirst);
+        dfree(big.bb);
+        dfree(big.part);
+        dfree(big.cnt);
         dfree(big.body);
         dfree(big.grp);
         dfree(big.test);
         dfree(big.rc);
         dfree(big.mass);
+        dfree(big.i09);
         dfree(big.Y);
         dfree(big.tcol);
         dfree(big.mstar);
@@ -274,11 +279,17 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.k0, G));
     HIP_TRY(dalloc(b.off, G + 1));
     HIP_TRY(dalloc(b.tiles, (size_t)BIG_MAX_TILES));
+    HIP_TRY(dalloc(b.tfirst, G + 1));
+    HIP_TRY(dalloc(b.bb, 3 * 8 * (size_t)BIG_MAX_TILES));
+    HIP_TRY(dalloc(b.part, (size_t)BIG_SPLIT * 3 * M));
+    HIP_TRY(dalloc(b.cnt, (size_t)BIG_MAX_TILES));
+    HIP_TRY(hipMemset(b.cnt, 0, (size_t)BIG_MAX_TILES * sizeof(int32_t)));
     HIP_TRY(dalloc(b.body, M));
     HIP_TRY(dalloc(b.grp, M));
     HIP_TRY(dalloc(b.test, M));
     HIP_TRY(dalloc(b.rc, M));
     HIP_TRY(dalloc(b.mass, M));
+    HIP_TRY(dalloc(b.i09, M));
     HIP_TRY(dalloc(b.Y, 3 * 6 * M));
     HIP_TRY(dalloc(b.tcol, (size_t)BS_KMAX * 6 * M));
     HIP_TRY(dalloc(b.mstar, G));
@@ -314,6 +325,7 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<int32_t> k0, off(1, 0);
     std::vector<int4> tiles;
+    std::vector<int32_t> tfirst(1, 0);
     for (int g = 0; g < ng; ++g) {
         const int nb = ctx->gs_h[g + 1] - ctx->gs_h[g];
         if (nb <= CE_MAX_GROUP) continue;
@@ -321,6 +333,7 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
         k0.push_back(ctx->gs_h[g]);
         off.push_back(o + nb);
         for (int f = 0; f < nb; f += 64) tiles.push_back(make_int4(gi, o + f, std::min(64, nb - f), 0));
+        tfirst.push_back((int32_t)tiles.size());
     }
     if (k0.empty()) return GENGA_OK;
     if ((int)k0.size() > BIG_MAX_GROUPS || off.back() > CE_MAX_MEMBERS || (int)tiles.size() > BIG_MAX_TILES)
@@ -331,6 +344,43 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     HIP_TRY(hipMemcpy(bg.k0, k0.data(), k0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bg.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bg.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.tfirst, tfirst.data(), tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // members of each large group ordered by ring (equal-width bands of distance to the star,
+    // as many as make a tile of 64 members about as wide as long) and then by azimuth, so that
+    // 64 consecutive members are close together and the force tiles can skip distant tiles
+    {
+        const size_t nt = (size_t)ctx->L.n_total;
+        std::vector<int32_t> mem(ctx->gs_h[ng]);
+        std::vector<double> hx(nt), hy(nt);
+        HIP_TRY(hipMemcpy(mem.data(), ctx->members, mem.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<int32_t> body((size_t)bg.M);
+        std::vector<std::pair<double, int32_t>> key;
+        for (int gi = 0; gi < bg.G; ++gi) {
+            const int nb = off[gi + 1] - off[gi];
+            double r0 = INFINITY, r1 = 0.0, rs = 0.0;
+            for (int l = 0; l < nb; ++l) {
+                const int32_t bi = mem[k0[gi] + l];
+                const double r = std::hypot(hx[bi], hy[bi]);
+                r0 = std::min(r0, r);
+                r1 = std::max(r1, r);
+                rs += r;
+            }
+            const double rmean = rs / nb, width = std::max(r1 - r0, 1e-300);
+            const int rings = std::max(1, (int)std::lround(std::sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
+            key.resize(nb);
+            for (int l = 0; l < nb; ++l) {
+                const int32_t bi = mem[k0[gi] + l];
+                const double r = std::hypot(hx[bi], hy[bi]);
+                const int ring = std::min(rings - 1, (int)((r - r0) / width * rings));
+                key[l] = {ring * 8.0 + std::atan2(hy[bi], hx[bi]), bi};
+            }
+            std::sort(key.begin(), key.end());
+            for (int l = 0; l < nb; ++l) body[off[gi] + l] = key[l].second;
+        }
+        HIP_TRY(hipMemcpy(bg.body, body.data(), body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     const Layout &L = ctx->L;
     HIP_TRY(launch_big_setup(L, bg, ctx->members, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, s));
     // every attempt ends with the count of groups still short of dt; the device gives up on a

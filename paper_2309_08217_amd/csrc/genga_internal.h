@@ -145,16 +145,20 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
                         int32_t *flags, int big_groups, hipStream_t stream);
 
 // Grid-wide Bulirsch-Stoer for the groups of more than CE_MAX_GROUP members.  Members of the G
-// large groups are numbered f = 0..M-1, group g holding [off[g], off[g+1]); state arrays are
-// SoA with stride M.  Capacities: members CE_MAX_MEMBERS, groups CE_MAX_MEMBERS / 65, tiles
+// large groups are numbered f = 0..M-1, group g holding [off[g], off[g+1]) (in an order the
+// host chooses: body[f]); state arrays are SoA with stride M.  Capacities: members CE_MAX_MEMBERS, groups CE_MAX_MEMBERS / 65, tiles
 // CE_MAX_MEMBERS / 64 + groups.
 struct BigBs {
     int32_t G = 0, M = 0, n_tiles = 0;
     int32_t *k0 = nullptr;         // [G] first entry of the group in members[]
     int32_t *off = nullptr;        // [G + 1]
     int4 *tiles = nullptr;         // [n_tiles] (group, first member, count, 0): 64 targets
+    int32_t *tfirst = nullptr;     // [G + 1] first tile of each group
+    double *bb = nullptr;          // [3][BIG_MAX_TILES][8] tile boxes of Y, B1, B2
+    double *part = nullptr;        // [BIG_SPLIT][3][M] per-part force sums of a sub-step
+    int32_t *cnt = nullptr;        // [BIG_MAX_TILES] parts finished per tile (0 between launches)
     int32_t *body = nullptr, *grp = nullptr, *test = nullptr; // [M]
-    double *rc = nullptr, *mass = nullptr;                    // [M]
+    double *rc = nullptr, *mass = nullptr, *i09 = nullptr;    // [M]; i09 = 1 / (0.9 r_crit)
     double *Y = nullptr;           // [3][6][M]: the state, then two sub-step buffers
     double *tcol = nullptr;        // [BS_KMAX][6][M]: T(k, 0)
     double *mstar = nullptr, *t = nullptr, *H = nullptr, *rcmax2 = nullptr; // [G]
@@ -164,6 +168,7 @@ struct BigBs {
     int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
 };
 constexpr int BIG_MAX_GROUPS = CE_MAX_MEMBERS / (CE_MAX_GROUP + 1);
+constexpr int BIG_SPLIT = 4;
 constexpr int BIG_MAX_TILES = CE_MAX_MEMBERS / 64 + BIG_MAX_GROUPS;
 
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
