@@ -17,9 +17,11 @@
  *  - Body arrays are structure-of-arrays float64, length n_total, systems stored one after
  *    the other in the order given to genga_set_systems (CSR offsets).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and never
- *    synchronises the host, except genga_set_systems, genga_poll_status, genga_autotune and
- *    the graph calls as documented.  Every launch sequence is capturable into a HIP graph
- *    (no memset nodes, no host round trips).
+ *    synchronises the host, except genga_set_systems, genga_set_test_bodies,
+ *    genga_set_large_groups, genga_poll_status, genga_autotune, the graph calls, and
+ *    genga_drift / genga_step while large groups are enabled, as documented.  Every launch
+ *    sequence is otherwise capturable into a HIP graph (no memset nodes, no host round
+ *    trips).
  *  - Return value: GENGA_OK (0) or a negative genga_status.  Errors knowable on the host
  *    (null pointer, bad enum, no layout set) return at once and enqueue nothing.
  *    Conditions found on the device (pair-list overflow, non-finite acceleration,
