@@ -96,7 +96,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
     __shared__ double red[GB_THREADS / 64];
     const int g = blockIdx.x;
     const int o = b.off[g], nb = b.off[g + 1] - o, k0 = b.k0[g];
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     double mx = 0.0;
     for (int l = threadIdx.x; l < nb; l += GB_THREADS) {
         const int f = o + l, body = b.body[f], s = sys_of[body];
@@ -117,6 +117,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (g == 0) b.dtp[0] = dt;
         for (int w = 1; w < GB_THREADS / 64; ++w) mx = fmax(mx, red[w]);
         b.rcmax2[g] = mx;
         b.mstar[g] = mstar[sys_of[members[k0]]];
@@ -128,10 +129,11 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
 }
 
 // Start of an attempt, per group.
-__global__ __launch_bounds__(64) void big_begin_kernel(BigBs b, double dt, int32_t *flags)
+__global__ __launch_bounds__(64) void big_begin_kernel(BigBs b, int32_t *flags)
 {
+    const double dt = b.dtp[0];
     const int g = blockIdx.x * 64 + threadIdx.x;
-    if (g >= b.G || b.done[g]) return;
+    if (g >= b.dims[0] || b.done[g]) return;
     double H = b.H[g];
     const double t = b.t[g];
     const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
@@ -156,11 +158,11 @@ __global__ __launch_bounds__(64) void big_begin_kernel(BigBs b, double dt, int32
 __global__ __launch_bounds__(GB_THREADS) void big_scale_kernel(BigBs b)
 {
     const int f0 = blockIdx.x * GB_THREADS + threadIdx.x;
-    const bool in = f0 < b.M;
+    const bool in = f0 < b.dims[1];
     const int f = in ? f0 : 0;
     const int g = b.grp[f];
     const bool use = in && !b.done[g];
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     const double *Y = b.Y;
     const double rr = sqrt(sep2_rn(Y[f], Y[M + f], Y[2 * M + f]));
     const double vv = sqrt(sep2_rn(Y[3 * M + f], Y[4 * M + f], Y[5 * M + f]));
@@ -171,38 +173,33 @@ __global__ __launch_bounds__(GB_THREADS) void big_scale_kernel(BigBs b)
 // Tile boxes of the attempt's starting state Y.
 __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
 {
+    if ((int)blockIdx.x >= b.dims[2]) return;
     const int4 tile = b.tiles[blockIdx.x];
     if (b.done[tile.x]) return;
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     const bool v = (int)threadIdx.x < tile.z;
     const int f = tile.y + (v ? (int)threadIdx.x : 0);
     tile_box(v, b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.bb, blockIdx.x);
 }
 
-// One sub-step of column k for every target of a tile: f(Z) (Kepler term plus the (1 - K)
-// share of the Newtonian forces from the group's other members), then
-//   mode 0: OUT = Z + h f(Z)            (first sub-step, Z = Y)
-//   mode 1: OUT = ZM + 2 h f(Z)         (OUT may be ZM's buffer: each lane rewrites its own)
-//   mode 2: T(k, 0) = (ZM + Z + h f(Z)) / 2, into tcol[k]
-// and, in modes 0 and 1, the tile's box in OUT's box array.  Source positions and boxes come
-// through scalar loads: neither is written by this launch.  GB_SPLIT workgroups share a target
-// tile; wave w of part p visits the source tiles p GB_WAVES + w, + GB_WAVES GB_SPLIT, ... of
-// the group and skips those out of reach.  Each part stores its sum; the part that finishes
-// last (a ticket counter per tile) adds them in part order and completes the sub-step.
-__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
-                                                                       const double *Z, const double *ZM,
-                                                                       double *OUT, const double *bbZ,
-                                                                       double *bbOUT)
+// A sub-step, first half: the (1 - K) share of the Newtonian forces on every target of a tile
+// from the group's other members at state Z.  The workgroup first lists the source tiles in
+// reach of the target tile (box gap within the largest r_crit); their quarters (16 members)
+// are dealt out to the waves of the GB_SPLIT workgroups that share the target tile, so the
+// few near tiles are spread over many waves.  Each part stores its sum in part[p].  Source
+// positions come through scalar loads: Z is not written by this launch.
+__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_force_kernel(BigBs b, const double *Z,
+                                                                     const double *bbZ)
 {
     __shared__ double red[3][GB_WAVES][GB_TILE];
-    __shared__ int s_last;
-    const int me = blockIdx.x / GB_SPLIT, part = blockIdx.x % GB_SPLIT;
+    const int me = blockIdx.x / GB_SPLIT, pidx = blockIdx.x % GB_SPLIT;
+    if (me >= b.dims[2]) return;
     const int4 tile = b.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
     if (b.done[g] || b.acc[g] >= 0) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     const int o = b.off[g], nb = b.off[g + 1] - o;
     const int tf = b.tfirst[g], nt = b.tfirst[g + 1] - tf;
     const bool valid = lane < tile.z;
@@ -253,13 +250,34 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
             az = fma(t[u], dz[u], az);
         }
     };
-    for (int st = part * GB_WAVES + wave; st < nt; st += GB_WAVES * GB_SPLIT) {
-        const int ts = tf + st;
-        const double gx = fmax(0.0, fmax(BB[ts * 8 + 0] - thx, tlx - BB[ts * 8 + 3]));
-        const double gy = fmax(0.0, fmax(BB[ts * 8 + 1] - thy, tly - BB[ts * 8 + 4]));
-        const double gz = fmax(0.0, fmax(BB[ts * 8 + 2] - thz, tlz - BB[ts * 8 + 5]));
-        if ((gx * gx + gy * gy) + gz * gz > Tcull) continue; // no pair of the two tiles is close
-        const int jb = o + GB_TILE * st, je = min(jb + GB_TILE, o + nb);
+    // the source tiles in reach of this target tile, in tile order: one test per thread, then
+    // an ordered compaction (ballots within a wave, wave offsets through LDS)
+    __shared__ int near_tile[BIG_MAX_TILES];
+    __shared__ int wave_cnt[GB_WAVES];
+    bool near = false;
+    const int tt = threadIdx.x;
+    if (tt < nt) {
+        const double *bs = bbZ + (size_t)(tf + tt) * 8;
+        const double gx = fmax(0.0, fmax(bs[0] - thx, tlx - bs[3]));
+        const double gy = fmax(0.0, fmax(bs[1] - thy, tly - bs[4]));
+        const double gz = fmax(0.0, fmax(bs[2] - thz, tlz - bs[5]));
+        near = (gx * gx + gy * gy) + gz * gz <= Tcull; // else no pair of the two tiles is close
+    }
+    const unsigned long long bal = __ballot(near);
+    if (lane == 0) wave_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int base = 0, n_near = 0;
+    for (int w = 0; w < GB_WAVES; ++w) {
+        if (w < wave) base += wave_cnt[w];
+        n_near += wave_cnt[w];
+    }
+    if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
+    static_assert(BIG_MAX_TILES <= GB_TILE * GB_WAVES, "one thread per source tile");
+    __syncthreads();
+    // units of 16 sources (quarters of the near tiles), spread over the parts' waves
+    for (int u = pidx * GB_WAVES + wave; u < 4 * n_near; u += GB_WAVES * GB_SPLIT) {
+        const int st = near_tile[u >> 2];
+        const int jb = o + GB_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
         for (int j = jb; j < je; j += 4) {
             const int cnt = min(4, je - j);
             double dx[4], dy[4], dz[4], q[4];
@@ -278,27 +296,38 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
     red[1][wave][lane] = ay;
     red[2][wave][lane] = az;
     __syncthreads();
-    if (wave == 0) {
-        double px = 0.0, py = 0.0, pz = 0.0;
-        for (int w = 0; w < GB_WAVES; ++w) {
-            px += red[0][w][lane];
-            py += red[1][w][lane];
-            pz += red[2][w][lane];
-        }
-        if (valid) {
-            double *P = b.part + (size_t)part * 3 * M;
-            P[fa] = px;
-            P[M + fa] = py;
-            P[2 * M + fa] = pz;
-        }
-        __threadfence(); // the sums are visible device-wide before the ticket is drawn
+    if (wave != 0 || !valid) return;
+    double px = 0.0, py = 0.0, pz = 0.0;
+    for (int w = 0; w < GB_WAVES; ++w) {
+        px += red[0][w][lane];
+        py += red[1][w][lane];
+        pz += red[2][w][lane];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(&b.cnt[me], 1) == GB_SPLIT - 1;
-    __syncthreads();
-    if (!s_last || wave != 0) return;
-    __threadfence(); // see every part's sums
-    if (lane == 0) b.cnt[me] = 0; // ready for the next launch
+    double *P = b.part + (size_t)pidx * 3 * M;
+    P[fa] = px;
+    P[M + fa] = py;
+    P[2 * M + fa] = pz;
+}
+
+// A sub-step, second half (one wave per tile): f(Z) = (velocity, Kepler term + the parts'
+// sums in part order), then
+//   mode 0: OUT = Z + h f(Z)            (first sub-step, Z = Y)
+//   mode 1: OUT = ZM + 2 h f(Z)         (OUT may be ZM's buffer: each lane rewrites its own)
+//   mode 2: T(k, 0) = (ZM + Z + h f(Z)) / 2, into tcol[k]
+// and, in modes 0 and 1, the tile's box in OUT's box array.
+__global__ __launch_bounds__(GB_TILE) void big_update_kernel(BigBs b, int k, int mode, const double *Z,
+                                                             const double *ZM, double *OUT, double *bbOUT)
+{
+    const int me = blockIdx.x;
+    if (me >= b.dims[2]) return;
+    const int4 tile = b.tiles[me];
+    const int g = tile.x;
+    if (b.done[g] || b.acc[g] >= 0) return;
+    const int lane = threadIdx.x;
+    const size_t M = (size_t)b.dims[1];
+    const bool valid = lane < tile.z;
+    const int fa = tile.y + (valid ? lane : 0);
+    const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
     const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
     const double s = -b.mstar[g] * (ri * ri) * ri;
     double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa, s * ya, s * za};
@@ -327,11 +356,11 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
 __global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
 {
     const int f0 = blockIdx.x * GB_THREADS + threadIdx.x;
-    const bool in = f0 < b.M;
+    const bool in = f0 < b.dims[1];
     const int f = in ? f0 : 0;
     const int g = b.grp[f];
     const bool use = in && !b.done[g] && b.acc[g] < 0;
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     double dp = 0.0, dv = 0.0;
     bool bad = false;
     for (int q = 0; q < 6; ++q) {
@@ -350,7 +379,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
 __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double tol)
 {
     const int g = blockIdx.x * 64 + threadIdx.x;
-    if (g >= b.G || b.done[g] || b.acc[g] >= 0) return;
+    if (g >= b.dims[0] || b.done[g] || b.acc[g] >= 0) return;
     const unsigned long long e = b.err[g * BS_KMAX + k];
     if (e != ~0ull && bitsd(e) <= tol) b.acc[g] = k;
 }
@@ -359,11 +388,11 @@ __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double t
 __global__ __launch_bounds__(GB_THREADS) void big_accept_kernel(BigBs b)
 {
     const int f = blockIdx.x * GB_THREADS + threadIdx.x;
-    if (f >= b.M) return;
+    if (f >= b.dims[1]) return;
     const int g = b.grp[f];
     const int ks = b.acc[g];
     if (b.done[g] || ks < 0) return;
-    const size_t M = (size_t)b.M;
+    const size_t M = (size_t)b.dims[1];
     for (int q = 0; q < 6; ++q) {
         const double t0 = b.tcol[q * M + f];
         double s = 0.0;
@@ -373,12 +402,13 @@ __global__ __launch_bounds__(GB_THREADS) void big_accept_kernel(BigBs b)
 }
 
 // Step control per group, and the number of groups still short of dt.
-__global__ __launch_bounds__(GB_THREADS) void big_control_kernel(BigBs b, double dt, double tol,
+__global__ __launch_bounds__(GB_THREADS) void big_control_kernel(BigBs b, double tol,
                                                                  int32_t *flags)
 {
     __shared__ int cnt[GB_THREADS / 64];
+    const double dt = b.dtp[0];
     int active = 0;
-    for (int g = threadIdx.x; g < b.G; g += GB_THREADS) {
+    for (int g = threadIdx.x; g < b.dims[0]; g += GB_THREADS) {
         if (b.done[g]) continue;
         const int ks = b.acc[g];
         if (ks >= 0) {
@@ -412,8 +442,8 @@ __global__ __launch_bounds__(GB_THREADS) void big_finish_kernel(BigBs b, double 
                                                                 double *vx, double *vy, double *vz)
 {
     const int f = blockIdx.x * GB_THREADS + threadIdx.x;
-    if (f >= b.M) return;
-    const size_t M = (size_t)b.M;
+    if (f >= b.dims[1]) return;
+    const size_t M = (size_t)b.dims[1];
     const int body = b.body[f];
     x[body] = b.Y[f];
     y[body] = b.Y[M + f];
@@ -436,39 +466,41 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
     return hipGetLastError();
 }
 
-hipError_t launch_big_attempt(const BigBs &b, double dt, double tol, int32_t *flags, hipStream_t stream)
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStream_t stream)
 {
-    if (b.G == 0) return hipSuccess;
-    const int gg = (b.G + 63) / 64, gm = (b.M + GB_THREADS - 1) / GB_THREADS;
-    const size_t M6 = 6 * (size_t)b.M;
+    // grids for the largest layout: launches past the current one (sizes in b.dims) return at
+    // once, so one captured sequence serves every step
+    const int gg = (BIG_MAX_GROUPS + 63) / 64, gm = (CE_MAX_MEMBERS + GB_THREADS - 1) / GB_THREADS;
+    const int nt = BIG_MAX_TILES;
+    const size_t M6 = 6 * (size_t)CE_MAX_MEMBERS;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
     double *box[3] = {b.bb, b.bb + 8 * BIG_MAX_TILES, b.bb + 16 * BIG_MAX_TILES};
-    big_begin_kernel<<<gg, 64, 0, stream>>>(b, dt, flags);
+    big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
     big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
-    big_box_kernel<<<b.n_tiles, 64, 0, stream>>>(b);
+    big_box_kernel<<<nt, 64, 0, stream>>>(b);
     for (int k = 0; k < BS_KMAX; ++k) {
         const int nsub = 2 * (k + 1);
         // sub-step i reads zc_i and zm_i and writes zc_(i+1): zc_1 = B1 (zm_1 = Y), then the
         // new point goes into zm's buffer, B2 first
-        big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1],
-                                                                                     box[0], box[1]);
+        big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[0], box[0]);
+        big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
-            big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm],
-                                                                                         buf[out], box[zc], box[out]);
+            big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[zc], box[zc]);
+            big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[out]);
             zm = zc;
             zc = out;
         }
-        big_substep_kernel<<<b.n_tiles * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr,
-                                                                                     box[zc], nullptr);
+        big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[zc], box[zc]);
+        big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, nullptr);
         if (k > 0) {
             big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
             big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);
         }
     }
     big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
-    big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, dt, tol, flags);
+    big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);
     return hipGetLastError();
 }
 

@@ -85,6 +85,8 @@ struct genga_ctx {
     int32_t large_groups = 0;
     BigBs big;
     int32_t *pin = nullptr;            // pinned host words for the per-attempt status reads
+    hipStream_t big_stream = nullptr;  // private stream to capture one attempt
+    hipGraphExec_t big_exec = nullptr; // the captured attempt, replayed on the caller's stream
     std::vector<int32_t> gs_h;         // group_start copied to the host
     // graph
     hipGraph_t graph = nullptr;
@@ -98,7 +100,6 @@ struct genga_ctx {
         dfree(big.tfirst);
         dfree(big.bb);
         dfree(big.part);
-        dfree(big.cnt);
         dfree(big.body);
         dfree(big.grp);
         dfree(big.test);
@@ -120,6 +121,12 @@ struct genga_ctx {
         dfree(big.err);
         dfree(big.n_active);
         if (pin) (void)hipHostFree(pin);
+        if (big_exec) (void)hipGraphExecDestroy(big_exec);
+        if (big_stream) (void)hipStreamDestroy(big_stream);
+        big_exec = nullptr;
+        big_stream = nullptr;
+        dfree(big.dims);
+        dfree(big.dtp);
         pin = nullptr;
         big.G = big.M = big.n_tiles = 0;
         large_groups = 0;
@@ -282,8 +289,6 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.tfirst, G + 1));
     HIP_TRY(dalloc(b.bb, 3 * 8 * (size_t)BIG_MAX_TILES));
     HIP_TRY(dalloc(b.part, (size_t)BIG_SPLIT * 3 * M));
-    HIP_TRY(dalloc(b.cnt, (size_t)BIG_MAX_TILES));
-    HIP_TRY(hipMemset(b.cnt, 0, (size_t)BIG_MAX_TILES * sizeof(int32_t)));
     HIP_TRY(dalloc(b.body, M));
     HIP_TRY(dalloc(b.grp, M));
     HIP_TRY(dalloc(b.test, M));
@@ -304,6 +309,8 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.sv, G));
     HIP_TRY(dalloc(b.err, G * BS_KMAX));
     HIP_TRY(dalloc(b.n_active, 1));
+    HIP_TRY(dalloc(b.dims, 4));
+    HIP_TRY(dalloc(b.dtp, 1));
     if (!ctx->pin) HIP_TRY(hipHostMalloc((void **)&ctx->pin, 4 * sizeof(int32_t), hipHostMallocDefault));
     return GENGA_OK;
 }
@@ -345,6 +352,8 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     HIP_TRY(hipMemcpy(bg.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bg.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bg.tfirst, tfirst.data(), tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    const int32_t dims[4] = {bg.G, bg.M, bg.n_tiles, 0};
+    HIP_TRY(hipMemcpy(bg.dims, dims, sizeof(dims), hipMemcpyHostToDevice));
     // members of each large group ordered by ring (equal-width bands of distance to the star,
     // as many as make a tile of 64 members about as wide as long) and then by azimuth, so that
     // 64 consecutive members are close together and the force tiles can skip distant tiles
@@ -385,8 +394,28 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     HIP_TRY(launch_big_setup(L, bg, ctx->members, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, s));
     // every attempt ends with the count of groups still short of dt; the device gives up on a
     // group after 20000 attempts, so the loop ends
+    if (!ctx->big_exec) {
+        // one attempt's launch sequence, captured once per context (sizes and dt live in
+        // device memory, every buffer address is fixed)
+        if (!ctx->big_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->big_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(ctx->big_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = launch_big_attempt(bg, 1e-12, ctx->flags, ctx->big_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(ctx->big_stream, &g);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(GENGA_ERR_HIP, "capturing the large-group attempt failed: %s",
+                        hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&ctx->big_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            ctx->big_exec = nullptr;
+            return fail(GENGA_ERR_HIP, "hipGraphInstantiate (large-group attempt) failed: %s", hipGetErrorString(ie));
+        }
+    }
     for (int attempt = 0; attempt <= 20001; ++attempt) {
-        HIP_TRY(launch_big_attempt(bg, dt, 1e-12, ctx->flags, s));
+        HIP_TRY(hipGraphLaunch(ctx->big_exec, s));
         HIP_TRY(hipMemcpyAsync(ctx->pin + 1, bg.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[1] == 0) break;

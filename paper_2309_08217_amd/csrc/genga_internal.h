@@ -149,14 +149,15 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
 // host chooses: body[f]); state arrays are SoA with stride M.  Capacities: members CE_MAX_MEMBERS, groups CE_MAX_MEMBERS / 65, tiles
 // CE_MAX_MEMBERS / 64 + groups.
 struct BigBs {
-    int32_t G = 0, M = 0, n_tiles = 0;
+    int32_t G = 0, M = 0, n_tiles = 0; // host copies of dims[0..2]
+    int32_t *dims = nullptr;       // device [4]: G, M, n_tiles (read by the attempt kernels)
+    double *dtp = nullptr;         // device [1]: dt of the step
     int32_t *k0 = nullptr;         // [G] first entry of the group in members[]
     int32_t *off = nullptr;        // [G + 1]
     int4 *tiles = nullptr;         // [n_tiles] (group, first member, count, 0): 64 targets
     int32_t *tfirst = nullptr;     // [G + 1] first tile of each group
     double *bb = nullptr;          // [3][BIG_MAX_TILES][8] tile boxes of Y, B1, B2
     double *part = nullptr;        // [BIG_SPLIT][3][M] per-part force sums of a sub-step
-    int32_t *cnt = nullptr;        // [BIG_MAX_TILES] parts finished per tile (0 between launches)
     int32_t *body = nullptr, *grp = nullptr, *test = nullptr; // [M]
     double *rc = nullptr, *mass = nullptr, *i09 = nullptr;    // [M]; i09 = 1 / (0.9 r_crit)
     double *Y = nullptr;           // [3][6][M]: the state, then two sub-step buffers
@@ -168,15 +169,16 @@ struct BigBs {
     int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
 };
 constexpr int BIG_MAX_GROUPS = CE_MAX_MEMBERS / (CE_MAX_GROUP + 1);
-constexpr int BIG_SPLIT = 4;
+constexpr int BIG_SPLIT = 4;   // workgroups sharing one target tile's sources
 constexpr int BIG_MAX_TILES = CE_MAX_MEMBERS / 64 + BIG_MAX_GROUPS;
 
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
                             const double *y, const double *z, const double *vx, const double *vy,
                             const double *vz, const double *m, const double *rc, double dt,
                             hipStream_t stream);
-// One attempt of every active group (a fixed sequence of launches).
-hipError_t launch_big_attempt(const BigBs &b, double dt, double tol, int32_t *flags, hipStream_t stream);
+// One attempt of every active group: a fixed sequence of launches that takes its sizes and dt
+// from device memory, so it can be captured once and replayed.
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStream_t stream);
 hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, hipStream_t stream);
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
