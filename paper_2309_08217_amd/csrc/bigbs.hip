@@ -30,8 +30,7 @@ using CD = const __attribute__((address_space(4))) double;
 using CI = const __attribute__((address_space(4))) int32_t;
 
 constexpr int GB_TILE = 64;
-constexpr int GB_WAVES = 8;
-constexpr int GB_SPLIT = BIG_SPLIT; // workgroups sharing one target tile's sources
+constexpr int GB_WAVES = 16;
 constexpr int GB_THREADS = 256;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -182,17 +181,23 @@ __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
     tile_box(v, b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.bb, blockIdx.x);
 }
 
-// A sub-step, first half: the (1 - K) share of the Newtonian forces on every target of a tile
-// from the group's other members at state Z.  The workgroup first lists the source tiles in
-// reach of the target tile (box gap within the largest r_crit); their quarters (16 members)
-// are dealt out to the waves of the GB_SPLIT workgroups that share the target tile, so the
-// few near tiles are spread over many waves.  Each part stores its sum in part[p].  Source
-// positions come through scalar loads: Z is not written by this launch.
-__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_force_kernel(BigBs b, const double *Z,
-                                                                     const double *bbZ)
+// One sub-step of column k for the targets of a tile (one workgroup per tile): the (1 - K)
+// share of the Newtonian forces from the group's other members at state Z, then
+//   mode 0: OUT = Z + h f(Z)            (first sub-step, Z = Y)
+//   mode 1: OUT = ZM + 2 h f(Z)         (OUT may be ZM's buffer: each lane rewrites its own)
+//   mode 2: T(k, 0) = (ZM + Z + h f(Z)) / 2, into tcol[k]
+// and, in modes 0 and 1, the tile's box in OUT's box array.  The workgroup first lists the
+// source tiles in reach of the target tile (box gap within the largest r_crit); their
+// quarters (16 members) are dealt out to the waves, so the few near tiles are spread over
+// many waves.  Source positions and boxes come through scalar loads: neither is written by
+// this launch.
+__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
+                                                                       const double *Z, const double *ZM,
+                                                                       double *OUT, const double *bbZ,
+                                                                       double *bbOUT)
 {
     __shared__ double red[3][GB_WAVES][GB_TILE];
-    const int me = blockIdx.x / GB_SPLIT, pidx = blockIdx.x % GB_SPLIT;
+    const int me = blockIdx.x;
     if (me >= b.dims[2]) return;
     const int4 tile = b.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
@@ -274,8 +279,8 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_force_kernel(BigBs b, c
     if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
     static_assert(BIG_MAX_TILES <= GB_TILE * GB_WAVES, "one thread per source tile");
     __syncthreads();
-    // units of 16 sources (quarters of the near tiles), spread over the parts' waves
-    for (int u = pidx * GB_WAVES + wave; u < 4 * n_near; u += GB_WAVES * GB_SPLIT) {
+    // units of 16 sources (quarters of the near tiles), dealt out to the waves
+    for (int u = wave; u < 4 * n_near; u += GB_WAVES) {
         const int st = near_tile[u >> 2];
         const int jb = o + GB_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
         for (int j = jb; j < je; j += 4) {
@@ -296,46 +301,14 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_force_kernel(BigBs b, c
     red[1][wave][lane] = ay;
     red[2][wave][lane] = az;
     __syncthreads();
-    if (wave != 0 || !valid) return;
-    double px = 0.0, py = 0.0, pz = 0.0;
-    for (int w = 0; w < GB_WAVES; ++w) {
-        px += red[0][w][lane];
-        py += red[1][w][lane];
-        pz += red[2][w][lane];
-    }
-    double *P = b.part + (size_t)pidx * 3 * M;
-    P[fa] = px;
-    P[M + fa] = py;
-    P[2 * M + fa] = pz;
-}
-
-// A sub-step, second half (one wave per tile): f(Z) = (velocity, Kepler term + the parts'
-// sums in part order), then
-//   mode 0: OUT = Z + h f(Z)            (first sub-step, Z = Y)
-//   mode 1: OUT = ZM + 2 h f(Z)         (OUT may be ZM's buffer: each lane rewrites its own)
-//   mode 2: T(k, 0) = (ZM + Z + h f(Z)) / 2, into tcol[k]
-// and, in modes 0 and 1, the tile's box in OUT's box array.
-__global__ __launch_bounds__(GB_TILE) void big_update_kernel(BigBs b, int k, int mode, const double *Z,
-                                                             const double *ZM, double *OUT, double *bbOUT)
-{
-    const int me = blockIdx.x;
-    if (me >= b.dims[2]) return;
-    const int4 tile = b.tiles[me];
-    const int g = tile.x;
-    if (b.done[g] || b.acc[g] >= 0) return;
-    const int lane = threadIdx.x;
-    const size_t M = (size_t)b.dims[1];
-    const bool valid = lane < tile.z;
-    const int fa = tile.y + (valid ? lane : 0);
-    const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
+    if (wave != 0) return;
     const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
     const double s = -b.mstar[g] * (ri * ri) * ri;
     double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa, s * ya, s * za};
-    for (int p = 0; p < GB_SPLIT; ++p) {
-        const double *P = b.part + (size_t)p * 3 * M;
-        d[3] += P[fa];
-        d[4] += P[M + fa];
-        d[5] += P[2 * M + fa];
+    for (int w = 0; w < GB_WAVES; ++w) {
+        d[3] += red[0][w][lane];
+        d[4] += red[1][w][lane];
+        d[5] += red[2][w][lane];
     }
     const double h = b.H[g] / (2 * (k + 1));
     if (mode == 2) {
@@ -482,18 +455,16 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStr
         const int nsub = 2 * (k + 1);
         // sub-step i reads zc_i and zm_i and writes zc_(i+1): zc_1 = B1 (zm_1 = Y), then the
         // new point goes into zm's buffer, B2 first
-        big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[0], box[0]);
-        big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[1]);
+        big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[0], box[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
-            big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[zc], box[zc]);
-            big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[out]);
+            big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[zc],
+                                                                       box[out]);
             zm = zc;
             zc = out;
         }
-        big_force_kernel<<<nt * GB_SPLIT, GB_TILE * GB_WAVES, 0, stream>>>(b, buf[zc], box[zc]);
-        big_update_kernel<<<nt, GB_TILE, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, nullptr);
+        big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
         if (k > 0) {
             big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
             big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);

@@ -99,7 +99,6 @@ struct genga_ctx {
         dfree(big.tiles);
         dfree(big.tfirst);
         dfree(big.bb);
-        dfree(big.part);
         dfree(big.body);
         dfree(big.grp);
         dfree(big.test);
@@ -288,7 +287,6 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.tiles, (size_t)BIG_MAX_TILES));
     HIP_TRY(dalloc(b.tfirst, G + 1));
     HIP_TRY(dalloc(b.bb, 3 * 8 * (size_t)BIG_MAX_TILES));
-    HIP_TRY(dalloc(b.part, (size_t)BIG_SPLIT * 3 * M));
     HIP_TRY(dalloc(b.body, M));
     HIP_TRY(dalloc(b.grp, M));
     HIP_TRY(dalloc(b.test, M));

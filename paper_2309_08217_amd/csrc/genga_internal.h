@@ -157,7 +157,6 @@ struct BigBs {
     int4 *tiles = nullptr;         // [n_tiles] (group, first member, count, 0): 64 targets
     int32_t *tfirst = nullptr;     // [G + 1] first tile of each group
     double *bb = nullptr;          // [3][BIG_MAX_TILES][8] tile boxes of Y, B1, B2
-    double *part = nullptr;        // [BIG_SPLIT][3][M] per-part force sums of a sub-step
     int32_t *body = nullptr, *grp = nullptr, *test = nullptr; // [M]
     double *rc = nullptr, *mass = nullptr, *i09 = nullptr;    // [M]; i09 = 1 / (0.9 r_crit)
     double *Y = nullptr;           // [3][6][M]: the state, then two sub-step buffers
@@ -169,7 +168,6 @@ struct BigBs {
     int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
 };
 constexpr int BIG_MAX_GROUPS = CE_MAX_MEMBERS / (CE_MAX_GROUP + 1);
-constexpr int BIG_SPLIT = 4;   // workgroups sharing one target tile's sources
 constexpr int BIG_MAX_TILES = CE_MAX_MEMBERS / 64 + BIG_MAX_GROUPS;
 
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
