@@ -257,7 +257,7 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
     };
     // the source tiles in reach of this target tile, in tile order: one test per thread, then
     // an ordered compaction (ballots within a wave, wave offsets through LDS)
-    __shared__ int near_tile[BIG_MAX_TILES];
+    __shared__ int near_tile[BIG_TILES_PER_GROUP];
     __shared__ int wave_cnt[GB_WAVES];
     bool near = false;
     const int tt = threadIdx.x;
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
         n_near += wave_cnt[w];
     }
     if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
-    static_assert(BIG_MAX_TILES <= GB_TILE * GB_WAVES, "one thread per source tile");
+    static_assert(BIG_TILES_PER_GROUP <= GB_TILE * GB_WAVES, "one thread per source tile");
     __syncthreads();
     // units of 16 sources (quarters of the near tiles), dealt out to the waves
     for (int u = wave; u < 4 * n_near; u += GB_WAVES) {
@@ -443,11 +443,11 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStr
 {
     // grids for the largest layout: launches past the current one (sizes in b.dims) return at
     // once, so one captured sequence serves every step
-    const int gg = (BIG_MAX_GROUPS + 63) / 64, gm = (CE_MAX_MEMBERS + GB_THREADS - 1) / GB_THREADS;
-    const int nt = BIG_MAX_TILES;
-    const size_t M6 = 6 * (size_t)CE_MAX_MEMBERS;
+    const int gg = (b.cap_G + 63) / 64, gm = (b.cap_M + GB_THREADS - 1) / GB_THREADS;
+    const int nt = b.cap_T;
+    const size_t M6 = 6 * (size_t)b.cap_M;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
-    double *box[3] = {b.bb, b.bb + 8 * BIG_MAX_TILES, b.bb + 16 * BIG_MAX_TILES};
+    double *box[3] = {b.bb, b.bb + 8 * (size_t)b.cap_T, b.bb + 16 * (size_t)b.cap_T};
     big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
     big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
     big_box_kernel<<<nt, 64, 0, stream>>>(b);

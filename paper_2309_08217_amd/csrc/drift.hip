@@ -216,6 +216,55 @@ __device__ __forceinline__ int find_root(int32_t *lab, int a)
     return r;
 }
 
+// Grid-wide union-find over the encounter pairs, for the large-group mode, where the host
+// reads the labels back: every body of a pair becomes its own root, rounds of hooking (the
+// larger root under the smaller) run until a round changes nothing, then every member's label
+// is compressed to its root.  Non-members keep lab = -1.
+__global__ __launch_bounds__(256) void uf_init_kernel(const int32_t *pairs, const int32_t *pair_count,
+                                                      int32_t pair_cap, int32_t *lab)
+{
+    const int np = min(*pair_count, pair_cap);
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < np; p += gridDim.x * 256) {
+        const int a = pairs[2 * p], b = pairs[2 * p + 1];
+        __hip_atomic_store(&lab[a], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&lab[b], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ __launch_bounds__(256) void uf_hook_kernel(const int32_t *pairs, const int32_t *pair_count,
+                                                      int32_t pair_cap, int32_t *lab, int32_t *changed)
+{
+    const int np = min(*pair_count, pair_cap);
+    int ch = 0;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < np; p += gridDim.x * 256) {
+        const int a = find_root(lab, pairs[2 * p]);
+        const int b = find_root(lab, pairs[2 * p + 1]);
+        if (a != b) {
+            atomicMin(&lab[max(a, b)], min(a, b));
+            ch = 1;
+        }
+    }
+    if (__ballot(ch) && (threadIdx.x & 63) == 0) atomicOr(changed, 1);
+}
+
+__global__ __launch_bounds__(256) void uf_compress_kernel(int n_total, int32_t *lab)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_total || lab_load(lab, i) < 0) return;
+    __hip_atomic_store(&lab[i], find_root(lab, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// members[k] -> member_slot, and lab back to -1 (clean for the next step)
+__global__ __launch_bounds__(256) void uf_slots_kernel(const int32_t *members, const int32_t *n_members,
+                                                       int32_t *member_slot, int32_t *lab)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= *n_members) return;
+    const int b = members[k];
+    member_slot[b] = k;
+    lab[b] = -1;
+}
+
 __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
     const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab, int32_t *mark,
     int32_t *members, int32_t *group_start, int32_t *n_groups, int32_t *member_slot, int32_t *flags)
@@ -777,10 +826,9 @@ __device__ bool run_small(const BsShared &S, int lane, double ms, double *x, dou
     return ok;
 }
 
-// The drift over dt: blocks [0, CE_MAX_MEMBERS / 2) integrate one encounter group each with
+// The drift over dt: blocks [0, bs_blocks) integrate one encounter group each with
 // Bulirsch-Stoer, the blocks after them Kepler-drift 64 bodies each and skip the group
 // members.  Each body is read and written by one block only.
-constexpr int BS_BLOCKS = CE_MAX_MEMBERS / 2; // every group has >= 2 members
 
 __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, const int32_t *sys_off,
                                                          const int32_t *n_massive, const double *mstar,
@@ -790,13 +838,13 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
                                                          const int32_t *members,
                                                          const int32_t *group_start,
                                                          const int32_t *n_groups, int32_t *member_slot,
-                                                         int32_t *flags, int big_groups)
+                                                         int32_t *flags, int big_groups, int bs_blocks)
 {
     __shared__ BsShared S;
     __shared__ double tab[BS_KMAX * 6 * BS_LANES];
     const int lane = threadIdx.x;
-    if (blockIdx.x >= BS_BLOCKS) {
-        const int i = (blockIdx.x - BS_BLOCKS) * BS_LANES + lane;
+    if ((int)blockIdx.x >= bs_blocks) {
+        const int i = (blockIdx.x - bs_blocks) * BS_LANES + lane;
         if (i >= n_total) return;
         if (member_slot[i] >= 0) {
             member_slot[i] = -1; // integrated by its group's block; leave the slot clear
@@ -884,6 +932,35 @@ hipError_t launch_momentum(const Layout &L, const double *vx, const double *vy, 
     return hipGetLastError();
 }
 
+hipError_t launch_uf_init(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
+                          hipStream_t stream)
+{
+    uf_init_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab);
+    return hipGetLastError();
+}
+
+hipError_t launch_uf_hook(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
+                          int32_t *changed, hipStream_t stream)
+{
+    uf_hook_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab, changed);
+    return hipGetLastError();
+}
+
+hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream)
+{
+    if (L.n_total == 0) return hipSuccess;
+    uf_compress_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, lab);
+    return hipGetLastError();
+}
+
+hipError_t launch_uf_slots(int n_members_max, const int32_t *members, const int32_t *n_members,
+                           int32_t *member_slot, int32_t *lab, hipStream_t stream)
+{
+    if (n_members_max <= 0) return hipSuccess;
+    uf_slots_kernel<<<(n_members_max + 255) / 256, 256, 0, stream>>>(members, n_members, member_slot, lab);
+    return hipGetLastError();
+}
+
 hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t *pair_count,
                             int32_t pair_cap, int32_t *lab, int32_t *mark, int32_t *members,
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
@@ -898,13 +975,15 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, hipStream_t stream)
+                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream)
 {
     if (L.n_total == 0) return hipSuccess;
-    const int grid = BS_BLOCKS + (L.n_total + BS_LANES - 1) / BS_LANES;
+    // one block per possible group: every group has >= 2 members
+    if (bs_blocks <= 0) bs_blocks = CE_MAX_MEMBERS / 2;
+    const int grid = bs_blocks + (L.n_total + BS_LANES - 1) / BS_LANES;
     drift_kernel<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z,
                                                 vx, vy, vz, m, rc, dt, members, group_start, n_groups,
-                                                member_slot, flags, big_groups);
+                                                member_slot, flags, big_groups, bs_blocks);
     return hipGetLastError();
 }
 

@@ -87,6 +87,8 @@ struct genga_ctx {
     int32_t *pin = nullptr;            // pinned host words for the per-attempt status reads
     hipStream_t big_stream = nullptr;  // private stream to capture one attempt
     hipGraphExec_t big_exec = nullptr; // the captured attempt, replayed on the caller's stream
+    int32_t *big_changed = nullptr;    // device word of the union-find rounds
+    int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
     // graph
     hipGraph_t graph = nullptr;
@@ -126,6 +128,7 @@ struct genga_ctx {
         big_stream = nullptr;
         dfree(big.dims);
         dfree(big.dtp);
+        dfree(big_changed);
         pin = nullptr;
         big.G = big.M = big.n_tiles = 0;
         large_groups = 0;
@@ -254,6 +257,7 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
 }
 
 int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
+int build_groups_large(genga_ctx *ctx, hipStream_t s);
 
 // Sun drift (dt/2), Kepler / Bulirsch-Stoer (dt), Sun drift (dt/2).  With defer_shift the
 // last position shift is left to the next kick's source-record pass (only the momentum
@@ -263,10 +267,18 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
     HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
-    HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
-                             ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
+    int bs_blocks = 0; // default: the one-workgroup group builder's maximum
+    if (ctx->large_groups) {
+        const int rc = build_groups_large(ctx, s);
+        if (rc) return rc;
+        bs_blocks = std::max(1, (int)ctx->gs_h.size() - 1);
+    } else {
+        HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
+                                 ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
+    }
     HIP_TRY(launch_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
-                         ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, ctx->large_groups, s));
+                         ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, ctx->large_groups,
+                         bs_blocks, s));
     if (ctx->large_groups) {
         const int rc = run_big_groups(ctx, b, dt, s);
         if (rc) return rc;
@@ -281,12 +293,16 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
 int alloc_big(genga_ctx *ctx)
 {
     BigBs &b = ctx->big;
-    const size_t M = CE_MAX_MEMBERS, G = BIG_MAX_GROUPS;
+    // every body may be in one large group; groups above CE_MAX_GROUP members
+    b.cap_M = std::max(ctx->L.n_total, 2);
+    b.cap_G = b.cap_M / (CE_MAX_GROUP + 1) + 1;
+    b.cap_T = b.cap_M / 64 + b.cap_G + 1;
+    const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
     HIP_TRY(dalloc(b.off, G + 1));
-    HIP_TRY(dalloc(b.tiles, (size_t)BIG_MAX_TILES));
+    HIP_TRY(dalloc(b.tiles, (size_t)b.cap_T));
     HIP_TRY(dalloc(b.tfirst, G + 1));
-    HIP_TRY(dalloc(b.bb, 3 * 8 * (size_t)BIG_MAX_TILES));
+    HIP_TRY(dalloc(b.bb, 3 * 8 * (size_t)b.cap_T));
     HIP_TRY(dalloc(b.body, M));
     HIP_TRY(dalloc(b.grp, M));
     HIP_TRY(dalloc(b.test, M));
@@ -309,6 +325,7 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.n_active, 1));
     HIP_TRY(dalloc(b.dims, 4));
     HIP_TRY(dalloc(b.dtp, 1));
+    HIP_TRY(dalloc(ctx->big_changed, 1));
     if (!ctx->pin) HIP_TRY(hipHostMalloc((void **)&ctx->pin, 4 * sizeof(int32_t), hipHostMallocDefault));
     return GENGA_OK;
 }
@@ -316,18 +333,70 @@ int alloc_big(genga_ctx *ctx)
 // Groups of more than CE_MAX_GROUP members: read the group sizes (the one host round trip of
 // a step in this mode), lay the large groups out for the grid-wide path, and run attempts
 // until every group has reached dt.
+// Encounter groups in the large-group mode, without the one-workgroup limit: union-find of the
+// pairs on the device (hooking rounds until one changes nothing), labels read back, members
+// bucketed by root on the host (groups in order of their smallest member, members ascending,
+// as the one-workgroup kernel orders them) and sent back with group_start and n_groups.
+int build_groups_large(genga_ctx *ctx, hipStream_t s)
+{
+    const Layout &L = ctx->L;
+    HIP_TRY(hipMemcpyAsync(ctx->pin, ctx->pair_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int np = std::min(ctx->pin[0], ctx->pair_cap);
+    ctx->gs_h.assign(1, 0);
+    if (np <= 0) {
+        ctx->pin[0] = 0;
+        HIP_TRY(hipMemcpyAsync(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return GENGA_OK;
+    }
+    HIP_TRY(launch_uf_init(ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, s));
+    for (int round = 0;; ++round) {
+        if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
+        ctx->pin[2] = 0;
+        HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_uf_hook(ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->big_changed, s));
+        HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ctx->pin[2] == 0) break;
+    }
+    HIP_TRY(launch_uf_compress(L, ctx->lab, s));
+    const size_t nt = (size_t)L.n_total;
+    std::vector<int32_t> lab(nt), cnt(nt, 0);
+    HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < nt; ++i)
+        if (lab[i] >= 0) ++cnt[lab[i]];
+    std::vector<int32_t> first(nt, -1), mem;
+    mem.reserve(2 * (size_t)np);
+    for (size_t r = 0; r < nt; ++r)
+        if (cnt[r] > 0) {
+            first[r] = (int32_t)mem.size();
+            ctx->gs_h.back() = first[r];
+            ctx->gs_h.push_back(first[r] + cnt[r]);
+            mem.resize(mem.size() + cnt[r]);
+            cnt[r] = 0;
+        }
+    for (size_t i = 0; i < nt; ++i)
+        if (lab[i] >= 0) mem[first[lab[i]] + cnt[lab[i]]++] = (int32_t)i;
+    const int ng = (int)ctx->gs_h.size() - 1, nmem = (int)mem.size();
+    if (nmem > ctx->ce_cap) return fail(GENGA_ERR_STATE, "encounter members exceed their allocation");
+    ctx->pin[0] = ng;
+    ctx->pin[1] = nmem;
+    HIP_TRY(hipMemcpy(ctx->members, mem.data(), mem.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(ctx->big_changed, ctx->pin + 1, sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
+    return GENGA_OK;
+}
+
 int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
 {
     BigBs &bg = ctx->big;
     bg.G = bg.M = bg.n_tiles = 0;
-    HIP_TRY(hipMemcpyAsync(ctx->pin, ctx->n_groups, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    const int ng = ctx->pin[0];
+    const int ng = (int)ctx->gs_h.size() - 1;
     if (ng <= 0) return GENGA_OK;
-    ctx->gs_h.resize((size_t)ng + 1);
-    HIP_TRY(hipMemcpyAsync(ctx->gs_h.data(), ctx->group_start, ((size_t)ng + 1) * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     std::vector<int32_t> k0, off(1, 0);
     std::vector<int4> tiles;
     std::vector<int32_t> tfirst(1, 0);
@@ -341,8 +410,11 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
         tfirst.push_back((int32_t)tiles.size());
     }
     if (k0.empty()) return GENGA_OK;
-    if ((int)k0.size() > BIG_MAX_GROUPS || off.back() > CE_MAX_MEMBERS || (int)tiles.size() > BIG_MAX_TILES)
+    if ((int)k0.size() > bg.cap_G || off.back() > bg.cap_M || (int)tiles.size() > bg.cap_T)
         return fail(GENGA_ERR_STATE, "large-group layout exceeds its allocation");
+    for (size_t gi = 0; gi + 1 < tfirst.size(); ++gi)
+        if (tfirst[gi + 1] - tfirst[gi] > BIG_TILES_PER_GROUP)
+            return fail(GENGA_ERR_CAPACITY, "an encounter group of more than %d bodies", 64 * BIG_TILES_PER_GROUP);
     bg.G = (int32_t)k0.size();
     bg.M = off.back();
     bg.n_tiles = (int32_t)tiles.size();
@@ -579,8 +651,9 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->flags, 1));
     HIP_TRY(dalloc(ctx->lab, nt));
     HIP_TRY(dalloc(ctx->mark, nt));
-    HIP_TRY(dalloc(ctx->members, CE_MAX_MEMBERS));
-    HIP_TRY(dalloc(ctx->group_start, CE_MAX_MEMBERS + 1));
+    ctx->ce_cap = std::max(CE_MAX_MEMBERS, n_total);
+    HIP_TRY(dalloc(ctx->members, (size_t)ctx->ce_cap));
+    HIP_TRY(dalloc(ctx->group_start, (size_t)ctx->ce_cap + 1));
     HIP_TRY(dalloc(ctx->n_groups, 1));
     HIP_TRY(dalloc(ctx->member_slot, nt));
     HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * max_items));

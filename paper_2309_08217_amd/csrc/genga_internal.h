@@ -142,24 +142,35 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, hipStream_t stream);
+                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream);
+// Grid-wide union-find of the encounter pairs (large-group mode; the host reads lab back):
+// init (lab = body for the bodies of a pair), hook rounds (changed |= 1 while a round hooks),
+// compress (every member's lab = its root), slots (member_slot for members[0..n), lab = -1).
+hipError_t launch_uf_init(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
+                          hipStream_t stream);
+hipError_t launch_uf_hook(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
+                          int32_t *changed, hipStream_t stream);
+hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream);
+hipError_t launch_uf_slots(int n_members_max, const int32_t *members, const int32_t *n_members,
+                           int32_t *member_slot, int32_t *lab, hipStream_t stream);
 
 // Grid-wide Bulirsch-Stoer for the groups of more than CE_MAX_GROUP members.  Members of the G
 // large groups are numbered f = 0..M-1, group g holding [off[g], off[g+1]) (in an order the
-// host chooses: body[f]); state arrays are SoA with stride M.  Capacities: members CE_MAX_MEMBERS, groups CE_MAX_MEMBERS / 65, tiles
-// CE_MAX_MEMBERS / 64 + groups.
+// host chooses: body[f]); state arrays are SoA with stride M.  Capacities (cap_*) follow the
+// layout: every body in one group at most; a group spans at most BIG_TILES_PER_GROUP tiles.
 struct BigBs {
     int32_t G = 0, M = 0, n_tiles = 0; // host copies of dims[0..2]
+    int32_t cap_M = 0, cap_G = 0, cap_T = 0; // allocated members, groups, tiles
     int32_t *dims = nullptr;       // device [4]: G, M, n_tiles (read by the attempt kernels)
     double *dtp = nullptr;         // device [1]: dt of the step
     int32_t *k0 = nullptr;         // [G] first entry of the group in members[]
     int32_t *off = nullptr;        // [G + 1]
     int4 *tiles = nullptr;         // [n_tiles] (group, first member, count, 0): 64 targets
     int32_t *tfirst = nullptr;     // [G + 1] first tile of each group
-    double *bb = nullptr;          // [3][BIG_MAX_TILES][8] tile boxes of Y, B1, B2
+    double *bb = nullptr;          // [3][cap_T][8] tile boxes of Y, B1, B2
     int32_t *body = nullptr, *grp = nullptr, *test = nullptr; // [M]
     double *rc = nullptr, *mass = nullptr, *i09 = nullptr;    // [M]; i09 = 1 / (0.9 r_crit)
-    double *Y = nullptr;           // [3][6][M]: the state, then two sub-step buffers
+    double *Y = nullptr;           // [3][6][cap_M]: the state, then two sub-step buffers (stride M)
     double *tcol = nullptr;        // [BS_KMAX][6][M]: T(k, 0)
     double *mstar = nullptr, *t = nullptr, *H = nullptr, *rcmax2 = nullptr; // [G]
     int32_t *last = nullptr, *attempts = nullptr, *acc = nullptr, *done = nullptr; // [G]
@@ -167,8 +178,7 @@ struct BigBs {
     unsigned long long *err = nullptr;               // [G][BS_KMAX] bit patterns of the estimates
     int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
 };
-constexpr int BIG_MAX_GROUPS = CE_MAX_MEMBERS / (CE_MAX_GROUP + 1);
-constexpr int BIG_MAX_TILES = CE_MAX_MEMBERS / 64 + BIG_MAX_GROUPS;
+constexpr int BIG_TILES_PER_GROUP = 1024; // a workgroup of 1024 threads tests one source tile each
 
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
                             const double *y, const double *z, const double *vx, const double *vy,

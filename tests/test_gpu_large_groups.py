@@ -62,6 +62,12 @@ def test_whole_disc_is_one_group():
     compare_drift(discs.disc_dense(), "dense 6600")
 
 
+def test_more_members_than_one_workgroup_builds():
+    """20000 bodies in 1-3 au: 15280 bodies in 2794 groups (more than the one-workgroup group
+    builder holds), six of them above 64 bodies, the largest 2891."""
+    compare_drift(discs.disc_dense(20000, seed=23, a_in=1.0, a_out=3.0), "wide 20000")
+
+
 def test_ring_steps_against_oracle():
     """Five full steps (kick, list, drift with large groups, kick) in FP64 and FP32."""
     d = discs.ring_dense(1000)
