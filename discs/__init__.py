@@ -196,12 +196,18 @@ DT_5_DAYS = days_to_code(5.0)
 DENSE_N1, DENSE_N2 = 3.0, 0.4
 
 
-def disc_dense(n: int = 6600, seed: int = 11, a_in: float = 0.7, a_out: float = 1.0) -> Disc:
-    """n planetesimals in [a_in, a_out] au carrying 2 Earth masses per 6600 bodies (the
-    paper's surface density), cold: e~R(0.002), i~R(0.001).  The default is the paper's
-    first experiment: one encounter group of all 6600 bodies at n2 = 0.4."""
-    return make_disc(n, 2.0 * n / 6600.0, seed, a_in=a_in, a_out=a_out, sigma_e=0.002, sigma_i=0.001,
-                     name=f"dense_n{n}")
+def disc_dense(n: int = 6600, seed: int = 11, a_in: float = 0.7, a_out: float = 1.0,
+               mass_earth: float = 0.0) -> Disc:
+    """n planetesimals in [a_in, a_out] au, cold: e~R(0.002), i~R(0.001), carrying mass_earth
+    Earth masses (default: 2 per 6600 bodies, the paper's surface density).  The default is
+    the paper's first experiment: one encounter group of all 6600 bodies at n2 = 0.4."""
+    m = mass_earth if mass_earth > 0.0 else 2.0 * n / 6600.0
+    return make_disc(n, m, seed, a_in=a_in, a_out=a_out, sigma_e=0.002, sigma_i=0.001, name=f"dense_n{n}")
+
+
+def disc_dense_40k(seed: int = 13) -> Disc:
+    """The paper's high-resolution run: 40322 planetesimals (2 Earth masses) in 0.7-1 au."""
+    return disc_dense(40322, seed, mass_earth=2.0)
 
 
 def ring_dense(n: int = 1000, seed: int = 12) -> Disc:

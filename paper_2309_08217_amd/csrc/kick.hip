@@ -50,15 +50,77 @@ __device__ __forceinline__ JRec64 ldj(CJ64 *J, int j)
     return r;
 }
 
-__device__ __forceinline__ void emit_pair(const KickArgs &a, int i, int j)
+// Encounter pairs found by a wave collect in its own LDS buffer and reach the global list in
+// blocks, one counter update per block, so that a dense list does not serialise on the
+// counter.  The calls come from divergent code: only the wave's active lanes take part, and
+// the fill count lives in LDS so that it stays one value for the whole wave.
+constexpr int PAIR_BUF = 128;
+
+struct PairBuf {
+    int2 *buf;  // the wave's PAIR_BUF slots
+    int *n;     // the wave's fill count
+};
+
+// orders the LDS accesses of the lanes of one wave
+__device__ __forceinline__ void wave_lds_sync()
 {
-    int idx = atomicAdd(a.pair_count, 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void store_pair(const KickArgs &a, int idx, int2 p)
+{
     if (idx < a.pair_cap) {
-        a.pairs[2 * idx] = i;
-        a.pairs[2 * idx + 1] = j;
+        a.pairs[2 * idx] = p.x;
+        a.pairs[2 * idx + 1] = p.y;
     } else {
         atomicOr(a.flags, FLAG_CAPACITY);
     }
+}
+
+// Move the buffer's n pairs, followed by the pairs (i, j) of the active lanes with em set
+// (m = their mask), to the global list; the active lanes share the copying.
+__device__ __forceinline__ void spill_pairs(const KickArgs &a, PairBuf pb, int n,
+                                            unsigned long long m, bool em, int i, int j)
+{
+    const unsigned long long act = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1;
+    const int leader = __ffsll((long long)act) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(a.pair_count, n + __popcll(m));
+    base = __shfl(base, leader, 64);
+    const int rank = __popcll(act & below), n_act = __popcll(act);
+    for (int k = rank; k < n; k += n_act) store_pair(a, base + k, pb.buf[k]);
+    if (em) store_pair(a, base + n + __popcll(m & below), make_int2(i, j));
+    wave_lds_sync();
+    *pb.n = 0;
+    wave_lds_sync();
+}
+
+// Record (i, j) for the active lanes with em set.
+__device__ __forceinline__ void emit_pair(const KickArgs &a, PairBuf pb, bool em, int i, int j)
+{
+    const unsigned long long m = __ballot(em);
+    if (!m) return;
+    const int n = *pb.n, c = __popcll(m);
+    if (n + c > PAIR_BUF) {
+        spill_pairs(a, pb, n, m, em, i, j);
+        return;
+    }
+    if (em) pb.buf[n + __popcll(m & ((1ull << (threadIdx.x & 63)) - 1))] = make_int2(i, j);
+    wave_lds_sync();
+    *pb.n = n + c;
+    wave_lds_sync();
+}
+
+// Empty the buffer (every lane of the wave calls this).
+__device__ __forceinline__ void flush_pairs(const KickArgs &a, PairBuf pb)
+{
+    wave_lds_sync();
+    const int n = *pb.n;
+    if (n > 0) spill_pairs(a, pb, n, 0ull, false, 0, 0);
 }
 
 // Pair inside the candidate radius: exact FP64 decision; inside r_crit,ij the weighted
@@ -66,7 +128,7 @@ __device__ __forceinline__ void emit_pair(const KickArgs &a, int i, int j)
 __device__ __forceinline__ bool close_pair(const KickArgs &a, double xj, double yj, double zj,
                                            int j, int i, bool valid, double xi, double yi,
                                            double zi, double rci, double &sx, double &sy,
-                                           double &sz)
+                                           double &sz, PairBuf pb)
 {
     if (j == i) return true;
     double dx = xj - xi, dy = yj - yi, dz = zj - zi;
@@ -81,7 +143,7 @@ __device__ __forceinline__ bool close_pair(const KickArgs &a, double xj, double 
         sy += s * dy;
         sz += s * dz;
     }
-    if (valid && i < j) emit_pair(a, i, j);
+    emit_pair(a, pb, valid && i < j, i, j);
     return true;
 }
 
@@ -205,6 +267,11 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
     __shared__ double red[3][W][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ int2 pair_slots[W][PAIR_BUF];
+    __shared__ int pair_fill[W];
+    const PairBuf pb{pair_slots[wave], &pair_fill[wave]};
+    pair_fill[wave] = 0;
+    wave_lds_sync();
     CJ32 *J = (CJ32 *)a.jrec;
     const int n_tasks = a.n_items * a.split;
     for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
@@ -237,13 +304,13 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
                 float q3 = fmaf(dx3, dx3, fmaf(dy3, dy3, dz3 * dz3));
                 const bool near = fminf(fminf(q0, q1), fminf(q2, q3)) < T;
                 if (__builtin_expect(near, 0)) {
-                    if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                         far32(r0.m, dx0, dy0, dz0, q0, c);
-                    if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                         far32(r1.m, dx1, dy1, dz1, q1, c);
-                    if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                         far32(r2.m, dx2, dy2, dz2, q2, c);
-                    if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                    if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                         far32(r3.m, dx3, dy3, dz3, q3, c);
                 } else {
                     far32(r0.m, dx0, dy0, dz0, q0, c);
@@ -256,7 +323,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
                 const JRec32 r0 = ldj(J, j);
                 float dx0 = (float)(r0.x - xi), dy0 = (float)(r0.y - yi), dz0 = (float)(r0.z - zi);
                 float q0 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
-                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far32(r0.m, dx0, dy0, dz0, q0, c);
             }
             // fold the block's FP32 partial sums into the FP64 accumulators
@@ -265,6 +332,7 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
             sz += (double)c.fz;
             c.fx = c.fy = c.fz = 0.f;
         }
+        flush_pairs(a, pb);
         finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
@@ -275,6 +343,11 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
     __shared__ double red[3][W][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ int2 pair_slots[W][PAIR_BUF];
+    __shared__ int pair_fill[W];
+    const PairBuf pb{pair_slots[wave], &pair_fill[wave]};
+    pair_fill[wave] = 0;
+    wave_lds_sync();
     CJ64 *J = (CJ64 *)a.jrec;
     const int n_tasks = a.n_items * a.split;
     for (int task = blockIdx.x; task < n_tasks; task += gridDim.x) {
@@ -302,13 +375,13 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
             const bool near = fmin(fmin(q0, q1), fmin(q2, q3)) < T;
             if (__builtin_expect(near, 0)) {
-                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
-                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
-                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
-                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
             } else {
                 far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
@@ -321,9 +394,10 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             const JRec64 r0 = ldj(J, j);
             double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
             double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
-            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz)))
+            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                 far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
         }
+        flush_pairs(a, pb);
         finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
