@@ -9,10 +9,10 @@ times steps per second, for state already resident in HBM.
 
 Also reported: the FP64 kick path, kick-only rates and their ratio, the roofline of the
 kick kernel (HIP events on the launch stream), a batched run of 64 uneven discs in one
-launch per kernel vs a loop of single-disc launches, the encounter-dominated regime (the
-dense 6600-body annulus with the full eq. (1), one encounter group of the whole disc, on the
-grid-wide Bulirsch-Stoer path), Delta E/E and Delta L/L over the timed steps, and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+launch per kernel vs a loop of single-disc launches, the encounter-dominated regime (dense
+0.7-1 au annuli of 6600 and 40322 bodies with the full eq. (1), whose encounter groups span
+most of the disc, on the grid-wide Bulirsch-Stoer path), Delta E/E and Delta L/L over the
+timed steps, and the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -193,17 +193,28 @@ def batched(torch, stream, steps=10, warmup=2):
             "speedup_vs_loop": t_loop / t, "status": status, **drift_stats(e_init, e_rec)}
 
 
-def dense(torch, stream, steps=10, warmup=2):
-    """Encounter-dominated regime: the dense annulus (6600 bodies, 0.7-1 au, 2 Earth masses,
-    5-day step) with r_crit from the full eq. (1), n2 = 0.4, where all bodies form one
-    encounter group; the grid-wide Bulirsch-Stoer path integrates it (host round trips per
-    attempt, so eager steps only)."""
+DENSE_WORKLOADS = {
+    "dense": ("dense annulus N=6600, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
+              "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11", discs.disc_dense),
+    "dense_40k": ("dense annulus N=40322, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
+                  "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 13", discs.disc_dense_40k),
+}
+
+
+def dense(torch, stream, which="dense", steps=10, warmup=2):
+    """Encounter-dominated regime: a dense annulus (0.7-1 au, 2 Earth masses, 5-day step) with
+    r_crit from the full eq. (1), n2 = 0.4, where the encounter groups span most of the disc;
+    the grid-wide Bulirsch-Stoer path integrates them (host round trips per attempt, so eager
+    steps only).  "dense": the 6600-body disc (one group of all bodies); "dense_40k": the
+    40322-body disc of the paper's high-resolution run."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
-    d = discs.disc_dense()
+    label, make = DENSE_WORKLOADS[which]
+    d = make()
     st, off, mstar = discs.concat([d])
+    cap = 64 * d.n
     ctx = genga.Context(0)
-    genga.genga_set_systems(ctx.handle, off, mstar)
+    genga.genga_set_systems(ctx.handle, off, mstar, cap)
     genga.genga_set_large_groups(ctx.handle, True)
     b = genga.Bodies.from_numpy(st, device="cuda:0")
     rc = torch.zeros_like(b.x)
@@ -212,12 +223,12 @@ def dense(torch, stream, steps=10, warmup=2):
     genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
     # group sizes of the initial state, from the GPU's encounter list
     genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32)
-    cap = 16 * d.n
     pairs = torch.zeros(2 * cap, dtype=torch.int32, device="cuda:0")
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda:0")
     genga.genga_encounter_list(ctx.handle, pairs, cap, cnt)
     torch.cuda.synchronize()
     npair = int(cnt.item())
+    assert npair <= cap, "encounter list above its capacity"
     p = pairs[: 2 * npair].cpu().numpy().reshape(-1, 2)
     adj = coo_matrix((np.ones(npair), (p[:, 0], p[:, 1])), shape=(d.n, d.n))
     _, lab = connected_components(adj, directed=False)
@@ -239,8 +250,7 @@ def dense(torch, stream, steps=10, warmup=2):
     kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
     E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
     ctx.close()
-    return {"workload": "dense annulus N=6600, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
-                        "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11",
+    return {"workload": label, "n": d.n,
             "encounter_pairs_at_start": npair, "largest_group_at_start": int(sizes.max()),
             "groups_above_64_at_start": int((sizes > 64).sum()),
             "steps": steps, "warmup": warmup, "steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps,
@@ -294,7 +304,7 @@ def main():
         print(json.dumps(batched(torch, stream)))
         return
     if args.dense_only:
-        print(json.dumps(dense(torch, stream)))
+        print(json.dumps({w: dense(torch, stream, w) for w in DENSE_WORKLOADS}))
         return
     d = discs.disc_c3()
     if args.only_kick > 0:
@@ -368,7 +378,8 @@ def main():
     if not args.no_batched:
         out["batched"] = batched(torch, stream)
     if not args.no_dense:
-        out["dense"] = dense(torch, stream)
+        for w in DENSE_WORKLOADS:
+            out[w] = dense(torch, stream, w)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d.state(), n)
     print(json.dumps(out), flush=True)

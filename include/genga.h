@@ -97,9 +97,13 @@ int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host);
  * are integrated by the same FP64 Bulirsch-Stoer method as the small groups, with the group's
  * state spread over the device; genga_drift and genga_step then synchronise the host with
  * `stream` once per step (to read the group sizes) and once per Bulirsch-Stoer attempt, so
- * graph capture is refused (GENGA_ERR_STATE) while enabled.  Capacity: 8192 bodies in
- * encounters per step, at most 126 groups above 64 bodies.  Allocates about 80 MB of
- * device memory; kept across genga_set_systems.  Synchronises the device. */
+ * graph capture is refused (GENGA_ERR_STATE) while enabled.  Capacity: every body of the
+ * layout may be in an encounter group; one group holds at most 65536 bodies.  A larger group
+ * makes genga_drift return GENGA_ERR_CAPACITY before it enqueues anything (genga_step: with
+ * the bodies left after its last kick).
+ * Allocates about 0.6 KB of device memory per body of the layout, resized by
+ * genga_set_systems; the switch itself is kept across genga_set_systems.  Synchronises the
+ * device. */
 int genga_set_large_groups(genga_ctx *ctx, int32_t enable);
 
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
@@ -133,8 +137,9 @@ int genga_encounter_list(genga_ctx *ctx, int32_t *pairs, int32_t cap, int32_t *d
  * FP64 Kepler drift about Mstar for bodies outside encounter groups and an FP64
  * Bulirsch-Stoer integration over dt of each group (connected component of the context's
  * encounter list) under the Sun's force plus the (1 - K) share of the members' mutual
- * forces, then Sun drift dt/2.  Groups larger than 64 bodies or more than 8192 bodies in
- * encounters raise GENGA_ERR_CAPACITY (those bodies are then only Kepler-drifted). */
+ * forces, then Sun drift dt/2.  Unless genga_set_large_groups is on, groups larger than 64
+ * bodies or more than 8192 bodies in encounters raise GENGA_ERR_CAPACITY (those bodies are
+ * then only Kepler-drifted). */
 int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream);
 
 /* Energy and angular momentum per system (Sect. 3.1 diagnostics), FP64:

@@ -266,13 +266,16 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
 {
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
-    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     int bs_blocks = 0; // default: the one-workgroup group builder's maximum
     if (ctx->large_groups) {
+        // the groups depend on the pair list only; built first, so that a group too large
+        // for the grid-wide path is refused before any part of the drift is enqueued
         const int rc = build_groups_large(ctx, s);
         if (rc) return rc;
         bs_blocks = std::max(1, (int)ctx->gs_h.size() - 1);
-    } else {
+    }
+    HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
+    if (!ctx->large_groups) {
         HIP_TRY(launch_ce_groups(L, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->mark, ctx->members,
                                  ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, s));
     }
@@ -380,6 +383,16 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     for (size_t i = 0; i < nt; ++i)
         if (lab[i] >= 0) mem[first[lab[i]] + cnt[lab[i]]++] = (int32_t)i;
     const int ng = (int)ctx->gs_h.size() - 1, nmem = (int)mem.size();
+    for (int g = 0; g < ng; ++g) {
+        const int nb = ctx->gs_h[g + 1] - ctx->gs_h[g];
+        if (nb > 64 * BIG_TILES_PER_GROUP) {
+            // leave the labels clean for the next call (member slots are still untouched)
+            HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
+            ctx->gs_h.assign(1, 0);
+            return fail(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", nb,
+                        64 * BIG_TILES_PER_GROUP);
+        }
+    }
     if (nmem > ctx->ce_cap) return fail(GENGA_ERR_STATE, "encounter members exceed their allocation");
     ctx->pin[0] = ng;
     ctx->pin[1] = nmem;

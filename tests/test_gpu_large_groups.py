@@ -84,6 +84,55 @@ def test_ring_steps_against_oracle():
         s.close()
 
 
+def ring_chain(n):
+    """n bodies of 1e-12 solar masses equally spaced on a circular orbit at 1 au."""
+    th = 2.0 * np.pi * np.arange(n) / n
+    c, s = np.cos(th), np.sin(th)
+    z = np.zeros(n)
+    return discs.Disc(c, s, z.copy(), -s, c.copy(), z.copy(), np.full(n, 1e-12), name=f"chain_n{n}")
+
+
+def test_group_above_limit_refused_before_drift():
+    """66000 bodies in a chain (each within r_crit of its two neighbours on either side) form
+    one group above the 65536-body limit: the drift is refused with GENGA_ERR_CAPACITY and the
+    bodies are untouched.  On the same context a drift whose list holds one group of 104
+    bodies then matches the oracle."""
+    n = 66000
+    d = ring_chain(n)
+    spacing = 2.0 * np.pi / n
+    s = System([d], rcrit=np.full(n, 2.5 * spacing))
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    assert cnt == 2 * n
+    b0 = s.numpy_state()
+    with pytest.raises(genga.GengaError) as e:
+        genga.genga_drift(s.ctx.handle, s.b, DT5)
+    assert e.value.status == genga.GENGA_ERR_CAPACITY
+    got = s.numpy_state()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(got[k], b0[k])
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK
+
+    rc2 = np.full(n, 0.4 * spacing)
+    rc2[:100] = 2.5 * spacing
+    s.b = genga.Bodies.from_numpy(d.state(), rc2)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(n, pairs)
+    assert np.bincount(gid[gid >= 0]).tolist() == [104]
+    b0 = s.numpy_state()
+    exp = oracle.drift(b0, rc2, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    inside = gid >= 0
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.max(np.abs(got[k][inside] - exp[k][inside])) <= 1e-10
+        assert np.max(np.abs(got[k][~inside] - exp[k][~inside])) <= 1e-13
+    s.close()
+
+
 def test_large_groups_off_flags_capacity_and_graph_refused():
     """Without the switch a group above 64 bodies is flagged; with it, graph capture is refused."""
     d = discs.ring_dense(1000)
