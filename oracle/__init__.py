@@ -76,6 +76,15 @@ def lib() -> ctypes.CDLL:
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_double, ctypes.c_double, i64,
                                                          ctypes.c_double, i64, d]
+        L.oracle_level_weight.restype = ctypes.c_double
+        L.oracle_level_weight.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, d]
+        L.oracle_drift_levels.restype = ctypes.c_int
+        L.oracle_drift_levels.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                                 ctypes.c_double, i64, ctypes.POINTER(ctypes.c_int32),
+                                                                 ctypes.c_double]
+        L.oracle_step_levels.restype = ctypes.c_int
+        L.oracle_step_levels.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                                ctypes.c_double, i64, ctypes.c_double, i64, d]
         _lib = L
     return _lib
 
@@ -235,6 +244,60 @@ def step(st, rc, mstar: float, dt: float, nsteps: int, cadence: int = 0, tol: fl
         ep = _p(e)
     bad = lib().oracle_step(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")], _p(_f64(rc)),
                             float(mstar), float(dt), int(nsteps), float(tol), int(cadence), ep)
+    if bad:
+        raise RuntimeError("oracle step failed")
+    return s, e
+
+
+# -------------------------------------------------------------------------------------------
+# Hierarchical levels (Sect. 1: intermediate symplectic levels with reduced steps between the
+# level-0 step and the Bulirsch-Stoer step).  The reading is stated in oracle.c.
+# -------------------------------------------------------------------------------------------
+
+def rcrit_levels(st: Dict[str, np.ndarray], mstar: float, n1: float, n2: float, dt: float,
+                 nlev: int, nsub: int) -> np.ndarray:
+    """Critical radius of every body at levels 0..nlev-1: eq. (1) with the level's step
+    dt / nsub^k.  Shape (nlev, n)."""
+    return np.stack([rcrit(st, mstar, n1, n2, dt / float(nsub) ** k) for k in range(nlev)])
+
+
+def level_weight(r2: float, level: int, nlev: int, rcij) -> float:
+    """Share of the pair force carried by level `level`'s kick (level < nlev) or by the
+    deepest Bulirsch-Stoer integration (level == nlev)."""
+    rc = _f64(rcij)
+    return lib().oracle_level_weight(float(r2), int(level), int(nlev), _p(rc))
+
+
+def drift_levels(st, rcl: np.ndarray, nsub: int, mstar: float, dt: float, pairs: np.ndarray,
+                 tol: float = BS_TOL, n_massive: Optional[int] = None):
+    """The drift with len(rcl) levels and nsub sub-steps per level; rcl[k] is the level-k
+    critical radius of every body (rcl[0] the r_crit of the kick)."""
+    s = _mut(st)
+    n = len(s["x"])
+    rc = _f64(np.asarray(rcl).reshape(-1, n))
+    p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    bad = lib().oracle_drift_levels(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
+                                    _p(rc), rc.shape[0], int(nsub), float(mstar), float(dt), len(p),
+                                    _p(p, ctypes.c_int32), float(tol))
+    if bad:
+        raise RuntimeError("oracle drift failed")
+    return s
+
+
+def step_levels(st, rcl: np.ndarray, nsub: int, mstar: float, dt: float, nsteps: int, cadence: int = 0,
+                tol: float = BS_TOL, n_massive: Optional[int] = None):
+    """nsteps full steps with the drift of drift_levels; returns (state, energy rows or None)."""
+    s = _mut(st)
+    n = len(s["x"])
+    rc = _f64(np.asarray(rcl).reshape(-1, n))
+    e = None
+    ep = None
+    if cadence > 0:
+        e = np.zeros((nsteps // cadence + 1, 4))
+        ep = _p(e)
+    bad = lib().oracle_step_levels(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
+                                   _p(rc), rc.shape[0], int(nsub), float(mstar), float(dt), int(nsteps), float(tol),
+                                   int(cadence), ep)
     if bad:
         raise RuntimeError("oracle step failed")
     return s, e

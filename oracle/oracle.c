@@ -317,9 +317,20 @@ int oracle_kepler_drift(int64_t n, double *x, double *y, double *z, double *vx, 
  * against the group's position and velocity scales; otherwise H is halved.
  * ---------------------------------------------------------------------------------- */
 #define BS_KMAX 8
+#define ORACLE_MAX_LEVELS 8
 
+/* Weight of the deepest integration for a pair: prod_{k<nlev} (1 - K_k), rcij[k] being the
+ * pair's critical radius of level k (one level: 1 - K). */
+static double encounter_weight(double r2, int nlev, const double *rcij)
+{
+    double w = 1.0;
+    for (int k = 0; k < nlev; ++k) w *= 1.0 - pair_weight(r2, rcij[k]);
+    return w;
+}
+
+/* grc[k * nb + a]: level-k critical radius of member a */
 static void group_rhs(int nb, const double *Y, double *D, const double *gm, const double *grc,
-                      const uint8_t *gtest, double mstar)
+                      int nlev, const uint8_t *gtest, double mstar)
 {
     /* Y = [x y z vx vy vz] per body, 6 doubles each */
     for (int a = 0; a < nb; ++a) {
@@ -343,8 +354,10 @@ static void group_rhs(int nb, const double *Y, double *D, const double *gm, cons
             const double *ya = Y + 6 * a, *yb = Y + 6 * b;
             double dx = yb[0] - ya[0], dy = yb[1] - ya[1], dz = yb[2] - ya[2];
             double r2 = sep2(dx, dy, dz);
-            double rcij = grc[a] > grc[b] ? grc[a] : grc[b];
-            double w = 1.0 - pair_weight(r2, rcij);
+            double rcij[ORACLE_MAX_LEVELS];
+            for (int k = 0; k < nlev; ++k)
+                rcij[k] = grc[k * nb + a] > grc[k * nb + b] ? grc[k * nb + a] : grc[k * nb + b];
+            double w = encounter_weight(r2, nlev, rcij);
             if (w == 0.0) continue;
             double r = sqrt(r2);
             double s = gm[b] * w / (r2 * r);
@@ -358,24 +371,24 @@ static void group_rhs(int nb, const double *Y, double *D, const double *gm, cons
 /* modified midpoint over H with nsub sub-steps: Y0 -> out */
 static void modified_midpoint(int nb, const double *Y0, double H, int nsub, double *out,
                               double *zm, double *zc, double *dd, const double *gm,
-                              const double *grc, const uint8_t *gtest, double mstar)
+                              const double *grc, int nlev, const uint8_t *gtest, double mstar)
 {
     int dim = 6 * nb;
     double h = H / nsub;
-    group_rhs(nb, Y0, dd, gm, grc, gtest, mstar);
+    group_rhs(nb, Y0, dd, gm, grc, nlev, gtest, mstar);
     for (int q = 0; q < dim; ++q) {
         zm[q] = Y0[q];
         zc[q] = Y0[q] + h * dd[q];
     }
     for (int k = 1; k < nsub; ++k) {
-        group_rhs(nb, zc, dd, gm, grc, gtest, mstar);
+        group_rhs(nb, zc, dd, gm, grc, nlev, gtest, mstar);
         for (int q = 0; q < dim; ++q) {
             double t = zm[q] + 2.0 * h * dd[q];
             zm[q] = zc[q];
             zc[q] = t;
         }
     }
-    group_rhs(nb, zc, dd, gm, grc, gtest, mstar);
+    group_rhs(nb, zc, dd, gm, grc, nlev, gtest, mstar);
     for (int q = 0; q < dim; ++q) out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
 }
 
@@ -384,8 +397,8 @@ static void modified_midpoint(int nb, const double *Y0, double H, int nsub, doub
  * (k = 7); a rejected step is multiplied by 0.9 (tol/err)^(1/15), err being the last
  * column's error estimate, kept within [1/50, 1/2].  Returns 1 (failure) if the step falls below
  * dt * 2^-40 or more than 20000 steps are attempted, else 0. */
-static int bs_group(int nb, double *Y, const double *gm, const double *grc, const uint8_t *gtest,
-                    double mstar, double dt, double tol)
+static int bs_group(int nb, double *Y, const double *gm, const double *grc, int nlev,
+                    const uint8_t *gtest, double mstar, double dt, double tol)
 {
     int dim = 6 * nb;
     /* tableau T[k][l] (l <= k), each a state vector */
@@ -409,7 +422,7 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, cons
         int done = -1;
         double err = 0.0;
         for (int k = 0; k < BS_KMAX && done < 0; ++k) {
-            modified_midpoint(nb, Y, H, 2 * (k + 1), TAB(k, 0), zm, zc, dd, gm, grc, gtest, mstar);
+            modified_midpoint(nb, Y, H, 2 * (k + 1), TAB(k, 0), zm, zc, dd, gm, grc, nlev, gtest, mstar);
             for (int l = 1; l <= k; ++l) {
                 double ratio = (double)(k + 1) / (double)(k + 1 - l); /* n_k / n_{k-l} */
                 double den = ratio * ratio - 1.0;
@@ -441,12 +454,13 @@ static int bs_group(int nb, double *Y, const double *gm, const double *grc, cons
     return 0;
 }
 
-/* Public wrapper: integrate bodies idx[0..nb-1] (a group) of the full arrays in place. */
-int oracle_bs_group(int nb, const int32_t *idx, int64_t nm, double *x, double *y, double *z,
-                    double *vx, double *vy, double *vz, const double *m, const double *rc,
-                    double mstar, double dt, double tol)
+/* Integrate bodies idx[0..nb-1] (a group) of the full arrays in place under the pair
+ * weight prod_{k<nlev} (1 - K_k); rcl[k * n + i] is body i's level-k critical radius. */
+static int bs_group_levels(int nb, const int32_t *idx, int64_t nm, double *x, double *y, double *z,
+                           double *vx, double *vy, double *vz, const double *m, const double *rcl,
+                           int64_t n, int nlev, double mstar, double dt, double tol)
 {
-    double *Y = (double *)malloc(sizeof(double) * (size_t)(8 * nb));
+    double *Y = (double *)malloc(sizeof(double) * (size_t)((7 + nlev) * nb));
     double *gm = Y + 6 * nb, *grc = gm + nb;
     uint8_t *gtest = (uint8_t *)malloc((size_t)nb);
     for (int a = 0; a < nb; ++a) {
@@ -454,10 +468,10 @@ int oracle_bs_group(int nb, const int32_t *idx, int64_t nm, double *x, double *y
         Y[6 * a + 0] = x[i]; Y[6 * a + 1] = y[i]; Y[6 * a + 2] = z[i];
         Y[6 * a + 3] = vx[i]; Y[6 * a + 4] = vy[i]; Y[6 * a + 5] = vz[i];
         gm[a] = m[i];
-        grc[a] = rc[i];
+        for (int k = 0; k < nlev; ++k) grc[k * nb + a] = rcl[k * n + i];
         gtest[a] = i >= nm;
     }
-    int st = bs_group(nb, Y, gm, grc, gtest, mstar, dt, tol);
+    int st = bs_group(nb, Y, gm, grc, nlev, gtest, mstar, dt, tol);
     for (int a = 0; a < nb; ++a) {
         int32_t i = idx[a];
         x[i] = Y[6 * a + 0]; y[i] = Y[6 * a + 1]; z[i] = Y[6 * a + 2];
@@ -466,6 +480,14 @@ int oracle_bs_group(int nb, const int32_t *idx, int64_t nm, double *x, double *y
     free(gtest);
     free(Y);
     return st;
+}
+
+/* Public wrapper: integrate bodies idx[0..nb-1] (a group) of the full arrays in place. */
+int oracle_bs_group(int nb, const int32_t *idx, int64_t nm, double *x, double *y, double *z,
+                    double *vx, double *vy, double *vz, const double *m, const double *rc,
+                    double mstar, double dt, double tol)
+{
+    return bs_group_levels(nb, idx, nm, x, y, z, vx, vy, vz, m, rc, 0, 1, mstar, dt, tol);
 }
 
 /* ------------------------------------------------------------------------------------
@@ -509,14 +531,136 @@ int64_t oracle_groups(int64_t n, int64_t npairs, const int32_t *pairs, int64_t *
 }
 
 /* ------------------------------------------------------------------------------------
- * Drift part of the step: Sun drift(dt/2), then over dt the Kepler drift for bodies
- * outside encounter groups and Bulirsch-Stoer for each group, then Sun drift(dt/2).
- * Returns 0 on success, 1 if a Kepler solve or a BS step failed.
+ * Hierarchical levels (Sect. 1: intermediate symplectic levels with reduced steps between
+ * the level-0 step and the Bulirsch-Stoer step).  The paper describes them without formulas;
+ * the reading taken here:
+ *  - nlev symplectic levels 0..nlev-1; level k has its own critical radius r_crit,k,i
+ *    (eq. (1) with the level's step, dt / nsub^k; supplied by the caller, non-increasing in
+ *    k) and K_k = K(y; r_crit,k,ij) with r_crit,k,ij = max over the pair.
+ *  - The pair force splits as
+ *        F = K_0 F + W_1 K_1 F + ... + W_{nlev-1} K_{nlev-1} F + W_nlev F,
+ *    W_l = prod_{k<l} (1 - K_k), so that level l's kick carries W_l K_l F and the deepest
+ *    integration (Bulirsch-Stoer) carries W_nlev F.  The weights add up to 1 for every r.
+ *  - Level 0 is the plain step.  Level l >= 1 integrates each group of level l-1 over its
+ *    parent's interval tau in nsub Strang sub-steps of h = tau / nsub: kick(h/2) with
+ *    W_l K_l F over every pair of the group; the level-l pairs are the pairs of the group with
+ *    r^2 < r_crit,l,ij^2 at that moment; Kepler drift(h) for members in no level-l pair and
+ *    level l+1 (Bulirsch-Stoer after the last level) over h for each connected group of
+ *    level-l pairs; kick(h/2) with the new positions.
+ *  - Test bodies (TP2 mode) never interact with each other at any level.
  * ---------------------------------------------------------------------------------- */
-int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
-                 double *vz, const double *m, const double *rc, double mstar, double dt,
-                 int64_t npairs, const int32_t *pairs, double tol)
+
+/* Weight of level l's kick (l < nlev): W_l K_l; of the deepest integration (l == nlev):
+ * W_nlev.  rcij[k] is the pair's level-k critical radius. */
+double oracle_level_weight(double r2, int l, int nlev, const double *rcij)
 {
+    double w = 1.0;
+    for (int k = 0; k < l; ++k) w *= 1.0 - pair_weight(r2, rcij[k]);
+    if (l < nlev) w *= pair_weight(r2, rcij[l]);
+    return w;
+}
+
+static void pair_rc_levels(const double *rcl, int64_t n, int nlev, int64_t i, int64_t j, double *rcij)
+{
+    for (int k = 0; k < nlev; ++k) rcij[k] = rcl[k * n + i] > rcl[k * n + j] ? rcl[k * n + i] : rcl[k * n + j];
+}
+
+/* v += tau * (level-l pair accelerations among the members idx[0..nb-1]) */
+static void level_kick(int l, int nlev, int nb, const int32_t *idx, int64_t nm, const double *x,
+                       const double *y, const double *z, double *vx, double *vy, double *vz,
+                       const double *m, const double *rcl, int64_t n, double tau)
+{
+    double *acc = (double *)malloc(sizeof(double) * (size_t)(3 * (nb > 0 ? nb : 1)));
+    for (int a = 0; a < nb; ++a) {
+        int32_t i = idx[a];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            int32_t j = idx[b];
+            if (j == i || (i >= nm && j >= nm)) continue;
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double r2 = sep2(dx, dy, dz);
+            double rcij[ORACLE_MAX_LEVELS];
+            pair_rc_levels(rcl, n, nlev, i, j, rcij);
+            double w = oracle_level_weight(r2, l, nlev, rcij);
+            if (w == 0.0) continue;
+            double r = sqrt(r2);
+            double s = m[j] * w / (r2 * r);
+            sx += s * dx;
+            sy += s * dy;
+            sz += s * dz;
+        }
+        acc[3 * a] = sx;
+        acc[3 * a + 1] = sy;
+        acc[3 * a + 2] = sz;
+    }
+    for (int a = 0; a < nb; ++a) {
+        int32_t i = idx[a];
+        vx[i] += tau * acc[3 * a];
+        vy[i] += tau * acc[3 * a + 1];
+        vz[i] += tau * acc[3 * a + 2];
+    }
+    free(acc);
+}
+
+/* Integrate the members idx[0..nb-1] (ascending) of one group of level l-1 over tau. */
+static int level_step(int l, int nlev, int nsub, int nb, const int32_t *idx, int64_t nm, double *x,
+                      double *y, double *z, double *vx, double *vy, double *vz, const double *m,
+                      const double *rcl, int64_t n, double mstar, double tau, double tol)
+{
+    if (l == nlev) return bs_group_levels(nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, nlev, mstar, tau, tol);
+    const double h = tau / nsub;
+    int bad = 0;
+    int64_t cap = 16 * (int64_t)nb + 16;
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
+    int64_t *gid = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int32_t *sub = (int32_t *)malloc(sizeof(int32_t) * (size_t)nb);
+    for (int s = 0; s < nsub; ++s) {
+        level_kick(l, nlev, nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, 0.5 * h);
+        int64_t np = 0;
+        for (int a = 0; a < nb; ++a)
+            for (int b = a + 1; b < nb; ++b) {
+                int32_t i = idx[a], j = idx[b];
+                if (i >= nm && j >= nm) continue;
+                double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+                double rcij[ORACLE_MAX_LEVELS];
+                pair_rc_levels(rcl, n, nlev, i, j, rcij);
+                if (sep2(dx, dy, dz) < rcij[l] * rcij[l]) {
+                    if (np == cap) {
+                        cap *= 2;
+                        pairs = (int32_t *)realloc(pairs, sizeof(int32_t) * (size_t)(2 * cap));
+                    }
+                    pairs[2 * np] = i;
+                    pairs[2 * np + 1] = j;
+                    ++np;
+                }
+            }
+        int64_t ng = oracle_groups(n, np, pairs, gid);
+        for (int a = 0; a < nb; ++a)
+            if (gid[idx[a]] < 0)
+                bad |= kepler_one(&x[idx[a]], &y[idx[a]], &z[idx[a]], &vx[idx[a]], &vy[idx[a]], &vz[idx[a]], mstar, h);
+        for (int64_t g = 0; g < ng; ++g) {
+            int k = 0;
+            for (int a = 0; a < nb; ++a)
+                if (gid[idx[a]] == g) sub[k++] = idx[a];
+            bad |= level_step(l + 1, nlev, nsub, k, sub, nm, x, y, z, vx, vy, vz, m, rcl, n, mstar, h, tol);
+        }
+        level_kick(l, nlev, nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, 0.5 * h);
+    }
+    free(sub);
+    free(gid);
+    free(pairs);
+    return bad;
+}
+
+/* The drift with nlev levels: Sun drift(dt/2); Kepler drift(dt) for bodies in no encounter
+ * pair and level 1 (Bulirsch-Stoer when nlev = 1) for each group of the level-0 pairs;
+ * Sun drift(dt/2).  rcl[k * n + i]: level-k critical radius (rcl[0..n-1] = r_crit of eq. (1)).
+ * nlev = 1 is oracle_drift. */
+int oracle_drift_levels(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, const double *m, const double *rcl, int nlev, int nsub, double mstar,
+                        double dt, int64_t npairs, const int32_t *pairs, double tol)
+{
+    if (nlev < 1 || nlev > ORACLE_MAX_LEVELS || nsub < 1) return 1;
     int bad = 0;
     oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, 0.5 * dt);
     int64_t *gid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -529,13 +673,23 @@ int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double 
         int nb = 0;
         for (int64_t i = 0; i < n; ++i)
             if (gid[i] == g) members[nb++] = (int32_t)i;
-        bad |= oracle_bs_group(nb, members, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, tol);
+        bad |= level_step(1, nlev, nsub, nb, members, nm, x, y, z, vx, vy, vz, m, rcl, n, mstar, dt, tol);
     }
     free(members);
     free(skip);
     free(gid);
     oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, 0.5 * dt);
     return bad;
+}
+
+/* Drift part of the plain step: Sun drift(dt/2), then over dt the Kepler drift for bodies
+ * outside encounter groups and Bulirsch-Stoer for each group, then Sun drift(dt/2).
+ * Returns 0 on success, 1 if a Kepler solve or a BS step failed. */
+int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                 double *vz, const double *m, const double *rc, double mstar, double dt,
+                 int64_t npairs, const int32_t *pairs, double tol)
+{
+    return oracle_drift_levels(n, nm, x, y, z, vx, vy, vz, m, rc, 1, 1, mstar, dt, npairs, pairs, tol);
 }
 
 /* v += tau * a_K */
@@ -552,16 +706,19 @@ static void kick(int64_t n, int64_t nm, const double *x, const double *y, const 
 }
 
 /* ------------------------------------------------------------------------------------
- * Full steps: Kick(dt/2) Sun(dt/2) [Kepler | BS](dt) Sun(dt/2) Kick(dt/2), nsteps times.
+ * Full steps: Kick(dt/2) Sun(dt/2) [Kepler | BS](dt) Sun(dt/2) Kick(dt/2), nsteps times
+ * (with nlev > 1 levels, the drift of oracle_drift_levels; the kick and the encounter list
+ * use the level-0 critical radii).
  * The encounter list used by a step's drift is the one at the positions of its first
  * half-kick.  If energy != NULL, energy[4*k..] receives (E, Lx, Ly, Lz) after step k
  * when k is a multiple of cadence (k = 0 is the initial state); the caller sizes it.
  * Returns 0 on success.
  * ---------------------------------------------------------------------------------- */
-int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
-                double *vz, const double *m, const double *rc, double mstar, double dt,
-                int64_t nsteps, double tol, int64_t cadence, double *energy)
+int oracle_step_levels(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                       double *vz, const double *m, const double *rcl, int nlev, int nsub, double mstar,
+                       double dt, int64_t nsteps, double tol, int64_t cadence, double *energy)
 {
+    const double *rc = rcl; /* level 0: the kick's changeover and the encounter list */
     double *ax = (double *)malloc(sizeof(double) * (size_t)(3 * (n > 0 ? n : 1)));
     double *ay = ax + n, *az = ay + n;
     int64_t cap = 16 * n + 16;
@@ -578,7 +735,7 @@ int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *
             pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
             np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
         }
-        bad |= oracle_drift(n, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, np, pairs, tol);
+        bad |= oracle_drift_levels(n, nm, x, y, z, vx, vy, vz, m, rcl, nlev, nsub, mstar, dt, np, pairs, tol);
         kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
         if (energy && cadence > 0 && s % cadence == 0)
             oracle_energy(n, nm, x, y, z, vx, vy, vz, m, mstar, energy + 4 * e_idx++);
@@ -586,4 +743,11 @@ int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *
     free(pairs);
     free(ax);
     return bad;
+}
+
+int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                double *vz, const double *m, const double *rc, double mstar, double dt,
+                int64_t nsteps, double tol, int64_t cadence, double *energy)
+{
+    return oracle_step_levels(n, nm, x, y, z, vx, vy, vz, m, rc, 1, 1, mstar, dt, nsteps, tol, cadence, energy);
 }

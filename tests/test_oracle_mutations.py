@@ -35,7 +35,8 @@ MUTATIONS = [
      "double F = X - c * sin(X) - s * (1.0 - cos(X)) - target;"),
     ("hyperbolic fdot", "fd = -A * A * nm * shX / (r * r0);", "fd = A * A * nm * shX / (r * r0);"),
     ("sun drift index", "y[i] += tau * py / mstar;", "y[i] += tau * px / mstar;"),
-    ("BS uses K instead of 1-K", "double w = 1.0 - pair_weight(r2, rcij);", "double w = pair_weight(r2, rcij);"),
+    ("BS uses K instead of 1-K", "for (int k = 0; k < nlev; ++k) w *= 1.0 - pair_weight(r2, rcij[k]);",
+     "for (int k = 0; k < nlev; ++k) w *= pair_weight(r2, rcij[k]);"),
     # (a wrong extrapolation coefficient only costs work: the accepted result is still held
     # to the tolerance by the error estimate, so it is not listed here)
     ("BS acceptance tolerance", "if (err <= tol) done = k;", "if (err <= 1e-5) done = k;"),
@@ -49,9 +50,29 @@ MUTATIONS = [
     ("TP2 energy keeps test pairs", "            if (i >= nm && j >= nm) continue;\n            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]",
      "            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]"),
     ("TP2 BS keeps test pairs", "            if (gtest[a] && gtest[b]) continue;\n", ""),
+    ("level weight drops the outer levels", "    for (int k = 0; k < l; ++k) w *= 1.0 - pair_weight(r2, rcij[k]);\n", ""),
+    ("level kick over a whole sub-step",
+     "level_kick(l, nlev, nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, 0.5 * h);\n        int64_t np = 0;",
+     "level_kick(l, nlev, nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, h);\n        int64_t np = 0;"),
+    ("level sub-step length", "const double h = tau / nsub;", "const double h = tau / (nsub + 1);"),
+    ("deepest integration with level 0 only",
+     "if (l == nlev) return bs_group_levels(nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, nlev, mstar, tau, tol);",
+     "if (l == nlev) return bs_group_levels(nb, idx, nm, x, y, z, vx, vy, vz, m, rcl, n, 1, mstar, tau, tol);"),
+    ("level members left undrifted", "if (gid[idx[a]] < 0)\n                bad |= kepler_one",
+     "if (gid[idx[a]] < -1)\n                bad |= kepler_one"),
+    ("level kick target mass", "double s = m[j] * w / (r2 * r);", "double s = m[i] * w / (r2 * r);"),
     ("encounter self pairs", "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i + 1;",
      "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i;"),
 ]
+
+
+PIN_FILES = {"pins": "test_oracle_pins.py", "levels": "test_oracle_levels.py"}
+
+
+def pin_file(name):
+    """Mistakes in the level code are run against the level pins, the others against the
+    main pin suite."""
+    return PIN_FILES["levels" if name.startswith(("level", "deepest")) else "pins"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
@@ -65,6 +86,6 @@ def test_planted_mistake_is_caught(name, old, new, tmp_path):
                            "-o", str(lib), str(mutated), "-lm"])
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", pin_file(name))],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutation '{name}' survived the pins:\n{r.stdout[-2000:]}"
