@@ -18,8 +18,8 @@
  *    the other in the order given to genga_set_systems (CSR offsets).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream) and never
  *    synchronises the host, except genga_set_systems, genga_set_test_bodies,
- *    genga_set_large_groups, genga_poll_status, genga_autotune, the graph calls, and
- *    genga_drift / genga_step while large groups are enabled, as documented.  Every launch
+ *    genga_set_large_groups, genga_set_levels, genga_poll_status, genga_autotune, the graph
+ *    calls, and genga_drift / genga_step while large groups are enabled, as documented.  Every launch
  *    sequence is otherwise capturable into a HIP graph (no memset nodes, no host round
  *    trips).
  *  - Return value: GENGA_OK (0) or a negative genga_status.  Errors knowable on the host
@@ -105,6 +105,22 @@ int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host);
  * genga_set_systems; the switch itself is kept across genga_set_systems.  Synchronises the
  * device. */
 int genga_set_large_groups(genga_ctx *ctx, int32_t enable);
+
+/* Hierarchical levels (Sect. 1: intermediate symplectic levels with reduced steps between the
+ * level-0 step and the Bulirsch-Stoer step).  n_levels symplectic levels (1..4; 1 = the plain
+ * two-level step, the default); level k >= 1 has its own critical radius, host-unowned device
+ * array rcrit_levels[(k - 1) * n_total + i] (float64, copied; e.g. genga_rcrit with the
+ * level's step dt / n_sub^k), positive and not larger than level k-1's (level 0 is the bodies'
+ * rcrit).  The pair force splits as K_0 F + W_1 K_1 F + ... + W_n F with W_l = prod_{k<l}
+ * (1 - K_k), K_k the changeover of level k's radius.  Level l integrates each group of level
+ * l-1 over its parent's interval in n_sub (1..64) Strang sub-steps: a half kick with W_l K_l F
+ * over the group's pairs, the Kepler drift of members in no pair closer than level l's radius
+ * and, for each group of such pairs, level l+1 (Bulirsch-Stoer with W_n F after the last
+ * level), a half kick.  Needs genga_set_large_groups on (else GENGA_ERR_STATE); genga_drift /
+ * genga_step then synchronise the host several times per sub-step.  Reset to 1 by
+ * genga_set_systems and by turning large groups off.  Synchronises the device; rcrit_levels
+ * may be NULL when n_levels = 1. */
+int genga_set_levels(genga_ctx *ctx, int32_t n_levels, int32_t n_sub, const double *rcrit_levels);
 
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's

@@ -33,6 +33,7 @@ GENGA_KICK_FP32 = 1
 # every entry point of include/genga.h
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
+    "genga_set_levels",
     "genga_rcrit", "genga_accel",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
@@ -70,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_set_systems": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), i32],
         "genga_set_test_bodies": [vp, ctypes.POINTER(i32)],
         "genga_set_large_groups": [vp, i32],
+        "genga_set_levels": [vp, i32, i32, vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
         "genga_accel": [vp, bp, ctypes.c_int, vp, vp, vp, vp],
         "genga_kick": [vp, bp, dbl, ctypes.c_int, vp],
@@ -184,6 +186,17 @@ def genga_set_test_bodies(ctx: int, n_massive: Optional[Sequence[int]]) -> None:
 def genga_set_large_groups(ctx: int, enable: bool) -> None:
     """Encounter groups above 64 bodies: integrate them (True) or flag them (False, default)."""
     _check(load_library().genga_set_large_groups(ctx, int(enable)))
+
+
+def genga_set_levels(ctx: int, n_levels: int, n_sub: int, rcrit_levels=None) -> None:
+    """Hierarchical levels: n_levels symplectic levels (1 = the plain step) with n_sub
+    sub-steps per level; rcrit_levels a device float64 tensor [n_levels - 1, n_total] with the
+    critical radii of levels 1..n_levels-1 (copied)."""
+    ptr = None
+    if rcrit_levels is not None:
+        assert rcrit_levels.is_cuda and rcrit_levels.dtype.is_floating_point and rcrit_levels.is_contiguous()
+        ptr = rcrit_levels.data_ptr()
+    _check(load_library().genga_set_levels(ctx, int(n_levels), int(n_sub), ptr))
 
 
 def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
                                                                const double *z, const double *vx,
                                                                const double *vy, const double *vz,
                                                                const double *m, const double *rc,
-                                                               double dt)
+                                                               const double *rc_lv, int n_total, double dt)
 {
     __shared__ double red[GB_THREADS / 64];
     const int g = blockIdx.x;
@@ -110,7 +110,13 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
         b.Y[3 * M + f] = vx[body];
         b.Y[4 * M + f] = vy[body];
         b.Y[5 * M + f] = vz[body];
-        mx = fmax(mx, sq_rn(rc[body]));
+        // candidate radius: the deepest level's r_crit
+        double rd = rc[body];
+        for (int k = 1; k < b.nlev; ++k) {
+            rd = rc_lv[(size_t)(k - 1) * n_total + body];
+            b.rcl[(size_t)(k - 1) * b.cap_M + f] = rd;
+        }
+        mx = fmax(mx, sq_rn(rd));
     }
     for (int s = 32; s > 0; s >>= 1) mx = fmax(mx, __shfl_xor(mx, s, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
@@ -191,6 +197,7 @@ __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
 // quarters (16 members) are dealt out to the waves, so the few near tiles are spread over
 // many waves.  Source positions and boxes come through scalar loads: neither is written by
 // this launch.
+template <bool LV>
 __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
                                                                        const double *Z, const double *ZM,
                                                                        double *OUT, const double *bbZ,
@@ -228,6 +235,11 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
     double ax = 0.0, ay = 0.0, az = 0.0;
     const double i09a = b.i09[fa];
     CD *I9 = (CD *)b.i09;
+    // levels 1..nlev-1: the target's radii, and the source radii through scalar loads
+    double rcal[LEVELS_MAX - 1] = {};
+    CD *RCL = (CD *)b.rcl;
+    if constexpr (LV)
+        for (int l = 1; l < b.nlev; ++l) rcal[l - 1] = b.rcl[(size_t)(l - 1) * b.cap_M + fa];
     // the (1 - K) Newtonian terms of sources j .. j + cnt - 1 (cnt <= 4), side by side and
     // without branches: a pair outside r_crit,ab, the target itself and a test-test pair get
     // weight zero; the terms are added in source order
@@ -241,12 +253,22 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
             const bool own = rca >= rcj;
             const double rcab = own ? rca : rcj;
             const double q = sep2_rn(dx[u], dy[u], dz[u]);
-            const bool in = u < cnt && j + u != fa && !(testa && tj) && q < sq_rn(rcab);
             const double rq = inv_sqrt64(q);
             const double yv = (q * rq - 0.1 * rcab) * (own ? i09a : i9j);
             const double y2 = yv * yv;
             const double kv = yv <= 0.0 ? 0.0 : (yv >= 1.0 ? 1.0 : y2 / (2.0 * y2 - 2.0 * yv + 1.0));
-            t[u] = in ? mj * (1.0 - kv) * (rq * rq) * rq : 0.0;
+            double w = 1.0 - kv, rdeep = rcab;
+            if constexpr (LV) {
+                // prod over the deeper levels of (1 - K_l); inside the deepest radius every
+                // level's radius holds the pair, as the radii do not grow with the level
+                for (int l = 1; l < b.nlev; ++l) {
+                    const double rcl_ab = fmax(rcal[l - 1], RCL[(size_t)(l - 1) * b.cap_M + jj]);
+                    w *= 1.0 - changeover_k((q * rq - 0.1 * rcl_ab) / (0.9 * rcl_ab));
+                    rdeep = rcl_ab;
+                }
+            }
+            const bool in = u < cnt && j + u != fa && !(testa && tj) && q < sq_rn(rdeep);
+            t[u] = in ? mj * w * (rq * rq) * rq : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -430,12 +452,12 @@ __global__ __launch_bounds__(GB_THREADS) void big_finish_kernel(BigBs b, double 
 
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
                             const double *y, const double *z, const double *vx, const double *vy,
-                            const double *vz, const double *m, const double *rc, double dt,
-                            hipStream_t stream)
+                            const double *vz, const double *m, const double *rc, const double *rc_lv,
+                            double dt, hipStream_t stream)
 {
     if (b.G == 0) return hipSuccess;
     big_setup_kernel<<<b.G, GB_THREADS, 0, stream>>>(b, L.sys_of, L.sys_off, L.n_massive, L.mstar, members, x, y,
-                                                     z, vx, vy, vz, m, rc, dt);
+                                                     z, vx, vy, vz, m, rc, rc_lv, L.n_total, dt);
     return hipGetLastError();
 }
 
@@ -448,6 +470,7 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStr
     const size_t M6 = 6 * (size_t)b.cap_M;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
     double *box[3] = {b.bb, b.bb + 8 * (size_t)b.cap_T, b.bb + 16 * (size_t)b.cap_T};
+    auto substep = b.nlev > 1 ? big_substep_kernel<true> : big_substep_kernel<false>;
     big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
     big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
     big_box_kernel<<<nt, 64, 0, stream>>>(b);
@@ -455,16 +478,16 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStr
         const int nsub = 2 * (k + 1);
         // sub-step i reads zc_i and zm_i and writes zc_(i+1): zc_1 = B1 (zm_1 = Y), then the
         // new point goes into zm's buffer, B2 first
-        big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[0], box[1]);
+        substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[0], box[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
-            big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[zc],
+            substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[zc],
                                                                        box[out]);
             zm = zc;
             zc = out;
         }
-        big_substep_kernel<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
+        substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
         if (k > 0) {
             big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
             big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);

@@ -911,7 +911,30 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
     if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
+__global__ __launch_bounds__(256) void kepler_list_kernel(const int32_t *sys_of, const double *mstar,
+                                                          const int32_t *list, int n, double *x, double *y,
+                                                          double *z, double *vx, double *vy, double *vz,
+                                                          double dt, int32_t *flags)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const int i = list[k];
+    double Y[6] = {x[i], y[i], z[i], vx[i], vy[i], vz[i]};
+    if (!kepler_universal(Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], mstar[sys_of[i]], dt)) atomicOr(flags, FLAG_KEPLER);
+    store_state(x, y, z, vx, vy, vz, i, Y);
+}
+
 } // namespace
+
+hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
+                              double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
+                              hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    kepler_list_kernel<<<(n + 255) / 256, 256, 0, stream>>>(L.sys_of, L.mstar, list, n, x, y, z, vx, vy, vz, dt,
+                                                            flags);
+    return hipGetLastError();
+}
 
 hipError_t launch_sun_drift(const Layout &L, double *x, double *y, double *z, const double *vx,
                             const double *vy, const double *vz, const double *m, double tau,
@@ -978,8 +1001,10 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
                         int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream)
 {
     if (L.n_total == 0) return hipSuccess;
-    // one block per possible group: every group has >= 2 members
-    if (bs_blocks <= 0) bs_blocks = CE_MAX_MEMBERS / 2;
+    // one block per possible group: every group has >= 2 members; bs_blocks < 0: no group
+    // blocks (the groups are integrated elsewhere), only the Kepler drift of non-members
+    if (bs_blocks == 0) bs_blocks = CE_MAX_MEMBERS / 2;
+    if (bs_blocks < 0) bs_blocks = 0;
     const int grid = bs_blocks + (L.n_total + BS_LANES - 1) / BS_LANES;
     drift_kernel<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z,
                                                 vx, vy, vz, m, rc, dt, members, group_start, n_groups,

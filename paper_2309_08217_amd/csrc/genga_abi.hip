@@ -90,6 +90,14 @@ struct genga_ctx {
     int32_t *big_changed = nullptr;    // device word of the union-find rounds
     int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
+    std::vector<int32_t> mem_h;        // members copied to the host
+    // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
+    int32_t n_levels = 1, n_sub = 1;
+    double *rc_lv = nullptr;           // [n_levels - 1][n_total]
+    struct LevelGroups {
+        int32_t *mem = nullptr, *mgrp = nullptr, *gs = nullptr; // groups of one level, on the device
+    } lv[LEVELS_MAX];
+    int32_t *lv_pairs = nullptr, *lv_count = nullptr, *lv_list = nullptr; // a level's pairs; Kepler list
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -121,6 +129,18 @@ struct genga_ctx {
         dfree(big.sv);
         dfree(big.err);
         dfree(big.n_active);
+        dfree(big.rcl);
+        big.nlev = 1;
+        dfree(rc_lv);
+        for (auto &g : lv) {
+            dfree(g.mem);
+            dfree(g.mgrp);
+            dfree(g.gs);
+        }
+        dfree(lv_pairs);
+        dfree(lv_count);
+        dfree(lv_list);
+        n_levels = n_sub = 1;
         if (pin) (void)hipHostFree(pin);
         if (big_exec) (void)hipGraphExecDestroy(big_exec);
         if (big_stream) (void)hipStreamDestroy(big_stream);
@@ -256,8 +276,10 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     return GENGA_OK;
 }
 
-int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
+int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, const std::vector<int32_t> &gs,
+                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb);
 int build_groups_large(genga_ctx *ctx, hipStream_t s);
+int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
 
 // Sun drift (dt/2), Kepler / Bulirsch-Stoer (dt), Sun drift (dt/2).  With defer_shift the
 // last position shift is left to the next kick's source-record pass (only the momentum
@@ -272,7 +294,8 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
         // for the grid-wide path is refused before any part of the drift is enqueued
         const int rc = build_groups_large(ctx, s);
         if (rc) return rc;
-        bs_blocks = std::max(1, (int)ctx->gs_h.size() - 1);
+        // with levels every group is integrated by the level steps: Kepler blocks only
+        bs_blocks = ctx->n_levels > 1 ? -1 : std::max(1, (int)ctx->gs_h.size() - 1);
     }
     HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
     if (!ctx->large_groups) {
@@ -282,8 +305,11 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
     HIP_TRY(launch_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
                          ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, ctx->large_groups,
                          bs_blocks, s));
-    if (ctx->large_groups) {
-        const int rc = run_big_groups(ctx, b, dt, s);
+    if (ctx->n_levels > 1) {
+        const int rc = run_levels(ctx, b, dt, s);
+        if (rc) return rc;
+    } else if (ctx->large_groups) {
+        const int rc = run_big_groups(ctx, b, dt, s, ctx->gs_h, ctx->mem_h, ctx->members, CE_MAX_GROUP + 1);
         if (rc) return rc;
     }
     if (defer_shift)
@@ -296,10 +322,26 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
 int alloc_big(genga_ctx *ctx)
 {
     BigBs &b = ctx->big;
-    // every body may be in one large group; groups above CE_MAX_GROUP members
+    // every body may be in one large group; groups above CE_MAX_GROUP members (with levels:
+    // the deepest level's groups of any size, at least 2 members each)
+    const bool lvl = ctx->n_levels > 1;
     b.cap_M = std::max(ctx->L.n_total, 2);
-    b.cap_G = b.cap_M / (CE_MAX_GROUP + 1) + 1;
+    b.cap_G = lvl ? b.cap_M / 2 + 1 : b.cap_M / (CE_MAX_GROUP + 1) + 1;
     b.cap_T = b.cap_M / 64 + b.cap_G + 1;
+    b.nlev = ctx->n_levels;
+    if (lvl) {
+        const size_t nt = (size_t)std::max(ctx->L.n_total, 1);
+        HIP_TRY(dalloc(b.rcl, (size_t)(LEVELS_MAX - 1) * b.cap_M));
+        HIP_TRY(dalloc(ctx->rc_lv, (size_t)(LEVELS_MAX - 1) * nt));
+        for (auto &g : ctx->lv) {
+            HIP_TRY(dalloc(g.mem, nt));
+            HIP_TRY(dalloc(g.mgrp, nt));
+            HIP_TRY(dalloc(g.gs, nt + 1));
+        }
+        HIP_TRY(dalloc(ctx->lv_pairs, 2 * (size_t)ctx->pair_cap));
+        HIP_TRY(dalloc(ctx->lv_count, 1));
+        HIP_TRY(dalloc(ctx->lv_list, nt));
+    }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
     HIP_TRY(dalloc(b.off, G + 1));
@@ -340,25 +382,29 @@ int alloc_big(genga_ctx *ctx)
 // pairs on the device (hooking rounds until one changes nothing), labels read back, members
 // bucketed by root on the host (groups in order of their smallest member, members ascending,
 // as the one-workgroup kernel orders them) and sent back with group_start and n_groups.
-int build_groups_large(genga_ctx *ctx, hipStream_t s)
+// Connected components of a pair list on the device (grid-wide union-find, labels read back,
+// bucketed on the host): gs / mem receive the groups (members ascending by body within each
+// group, groups by smallest member).  Leaves lab all -1.  A group above the grid-wide path's
+// limit is refused.
+int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int32_t cap,
+                std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict)
 {
     const Layout &L = ctx->L;
-    HIP_TRY(hipMemcpyAsync(ctx->pin, ctx->pair_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ctx->pin, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const int np = std::min(ctx->pin[0], ctx->pair_cap);
-    ctx->gs_h.assign(1, 0);
-    if (np <= 0) {
-        ctx->pin[0] = 0;
-        HIP_TRY(hipMemcpyAsync(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return GENGA_OK;
-    }
-    HIP_TRY(launch_uf_init(ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, s));
+    // a list cut at its capacity has been flagged by the launch that filled it; strict: refuse
+    if (strict && ctx->pin[0] > cap)
+        return fail(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
+    const int np = std::min(ctx->pin[0], cap);
+    gs.assign(1, 0);
+    mem.clear();
+    if (np <= 0) return GENGA_OK;
+    HIP_TRY(launch_uf_init(pairs, count, cap, ctx->lab, s));
     for (int round = 0;; ++round) {
         if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
         ctx->pin[2] = 0;
         HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_uf_hook(ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->big_changed, s));
+        HIP_TRY(launch_uf_hook(pairs, count, cap, ctx->lab, ctx->big_changed, s));
         HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[2] == 0) break;
@@ -368,56 +414,165 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     std::vector<int32_t> lab(nt), cnt(nt, 0);
     HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
     for (size_t i = 0; i < nt; ++i)
         if (lab[i] >= 0) ++cnt[lab[i]];
-    std::vector<int32_t> first(nt, -1), mem;
+    std::vector<int32_t> first(nt, -1);
     mem.reserve(2 * (size_t)np);
     for (size_t r = 0; r < nt; ++r)
         if (cnt[r] > 0) {
             first[r] = (int32_t)mem.size();
-            ctx->gs_h.back() = first[r];
-            ctx->gs_h.push_back(first[r] + cnt[r]);
+            if (cnt[r] > 64 * BIG_TILES_PER_GROUP) {
+                const int nb = cnt[r];
+                gs.assign(1, 0);
+                mem.clear();
+                return fail(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", nb,
+                            64 * BIG_TILES_PER_GROUP);
+            }
+            gs.back() = first[r];
+            gs.push_back(first[r] + cnt[r]);
             mem.resize(mem.size() + cnt[r]);
             cnt[r] = 0;
         }
     for (size_t i = 0; i < nt; ++i)
         if (lab[i] >= 0) mem[first[lab[i]] + cnt[lab[i]]++] = (int32_t)i;
-    const int ng = (int)ctx->gs_h.size() - 1, nmem = (int)mem.size();
-    for (int g = 0; g < ng; ++g) {
-        const int nb = ctx->gs_h[g + 1] - ctx->gs_h[g];
-        if (nb > 64 * BIG_TILES_PER_GROUP) {
-            // leave the labels clean for the next call (member slots are still untouched)
-            HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
-            ctx->gs_h.assign(1, 0);
-            return fail(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", nb,
-                        64 * BIG_TILES_PER_GROUP);
-        }
-    }
+    return GENGA_OK;
+}
+
+// The encounter groups of the context's pair list, for the large-group mode: members /
+// group_start / n_groups on the device, member_slot set for the drift launch.
+int build_groups_large(genga_ctx *ctx, hipStream_t s)
+{
+    int rc = group_pairs(ctx, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->gs_h, ctx->mem_h, s, false);
+    if (rc) return rc;
+    const int ng = (int)ctx->gs_h.size() - 1, nmem = (int)ctx->mem_h.size();
     if (nmem > ctx->ce_cap) return fail(GENGA_ERR_STATE, "encounter members exceed their allocation");
     ctx->pin[0] = ng;
     ctx->pin[1] = nmem;
-    HIP_TRY(hipMemcpy(ctx->members, mem.data(), mem.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (nmem > 0) {
+        HIP_TRY(hipMemcpy(ctx->members, ctx->mem_h.data(), nmem * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->big_changed, ctx->pin + 1, sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
+// ------------------------------------------------------------------------------------------
+// Hierarchical levels (Sect. 1): level l integrates each group of level l-1 over tau in n_sub
+// Strang sub-steps of h = tau / n_sub: kick(h/2) with the level-l share of the pair forces
+// (which also lists the level-l pairs), the groups of those pairs, Kepler drift(h) for the
+// parent members outside them, level l+1 (Bulirsch-Stoer after the last level) for each,
+// kick(h/2).  The host drives the recursion; it reads each level's pair count and labels.
+// ------------------------------------------------------------------------------------------
+int upload_i32(int32_t *dst, const std::vector<int32_t> &v, hipStream_t s)
+{
+    if (v.empty()) return GENGA_OK;
+    HIP_TRY(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return GENGA_OK;
+}
 
-int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const genga_ctx::LevelGroups &P, int n_mem,
+               double tau, bool emit, hipStream_t s)
+{
+    LevelKickArgs a;
+    a.n_mem = n_mem;
+    a.mem = P.mem;
+    a.mgrp = P.mgrp;
+    a.gs = P.gs;
+    a.sys_of = ctx->L.sys_of;
+    a.sys_off = ctx->L.sys_off;
+    a.n_massive = ctx->L.n_massive;
+    a.x = b->x;
+    a.y = b->y;
+    a.z = b->z;
+    a.m = b->m;
+    a.vx = b->vx;
+    a.vy = b->vy;
+    a.vz = b->vz;
+    a.rc0 = b->rcrit;
+    a.rcl = ctx->rc_lv;
+    a.n_total = ctx->L.n_total;
+    a.level = level;
+    a.emit = emit ? 1 : 0;
+    a.tau = tau;
+    a.pairs = ctx->lv_pairs;
+    a.pair_count = ctx->lv_count;
+    a.flags = ctx->flags;
+    a.pair_cap = ctx->pair_cap;
+    HIP_TRY(launch_level_kick(a, s));
+    return GENGA_OK;
+}
+
+int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int32_t> &pgs,
+              const std::vector<int32_t> &pmem, double tau, hipStream_t s)
+{
+    const int ng = (int)pgs.size() - 1, n_mem = (int)pmem.size();
+    if (ng <= 0) return GENGA_OK;
+    // the parent groups (level - 1) on the device
+    const genga_ctx::LevelGroups &P = ctx->lv[level - 1];
+    std::vector<int32_t> mgrp(n_mem);
+    for (int g = 0; g < ng; ++g)
+        for (int k = pgs[g]; k < pgs[g + 1]; ++k) mgrp[k] = g;
+    int rc;
+    if ((rc = upload_i32(P.mem, pmem, s)) || (rc = upload_i32(P.mgrp, mgrp, s)) || (rc = upload_i32(P.gs, pgs, s)))
+        return rc;
+    const double h = tau / ctx->n_sub;
+    const bool deepest = level + 1 == ctx->n_levels;
+    std::vector<int32_t> cgs, cmem, kep;
+    std::vector<uint8_t> in_child((size_t)ctx->L.n_total, 0);
+    for (int sub = 0; sub < ctx->n_sub; ++sub) {
+        HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
+        if ((rc = level_kick(ctx, b, level, P, n_mem, 0.5 * h, true, s))) return rc;
+        if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true))) return rc;
+        // parent members in no pair of this level: Kepler drift over h
+        for (int32_t i : cmem) in_child[i] = 1;
+        kep.clear();
+        for (int32_t i : pmem)
+            if (!in_child[i]) kep.push_back(i);
+        for (int32_t i : cmem) in_child[i] = 0;
+        if ((rc = upload_i32(ctx->lv_list, kep, s))) return rc;
+        HIP_TRY(launch_kepler_list(ctx->L, ctx->lv_list, (int32_t)kep.size(), b->x, b->y, b->z, b->vx, b->vy, b->vz,
+                                   h, ctx->flags, s));
+        if (!cmem.empty()) {
+            if (deepest) {
+                const genga_ctx::LevelGroups &C = ctx->lv[level];
+                if ((rc = upload_i32(C.mem, cmem, s))) return rc;
+                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, C.mem, 2))) return rc;
+            } else if ((rc = run_level(ctx, b, level + 1, cgs, cmem, h, s))) {
+                return rc;
+            }
+        }
+        if ((rc = level_kick(ctx, b, level, P, n_mem, 0.5 * h, false, s))) return rc;
+    }
+    return GENGA_OK;
+}
+
+// Level 1 over dt for the groups of the context's encounter list (built by enqueue_drift).
+int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+{
+    return run_level(ctx, b, 1, ctx->gs_h, ctx->mem_h, dt, s);
+}
+
+// Grid-wide Bulirsch-Stoer over dt for the groups gs / mem (host copies; members_dev the
+// device copy of mem) of at least min_nb members.
+int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, const std::vector<int32_t> &gs,
+                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb)
 {
     BigBs &bg = ctx->big;
     bg.G = bg.M = bg.n_tiles = 0;
-    const int ng = (int)ctx->gs_h.size() - 1;
+    const int ng = (int)gs.size() - 1;
     if (ng <= 0) return GENGA_OK;
     std::vector<int32_t> k0, off(1, 0);
     std::vector<int4> tiles;
     std::vector<int32_t> tfirst(1, 0);
     for (int g = 0; g < ng; ++g) {
-        const int nb = ctx->gs_h[g + 1] - ctx->gs_h[g];
-        if (nb <= CE_MAX_GROUP) continue;
+        const int nb = gs[g + 1] - gs[g];
+        if (nb < min_nb) continue;
         const int gi = (int)k0.size(), o = off.back();
-        k0.push_back(ctx->gs_h[g]);
+        k0.push_back(gs[g]);
         off.push_back(o + nb);
         for (int f = 0; f < nb; f += 64) tiles.push_back(make_int4(gi, o + f, std::min(64, nb - f), 0));
         tfirst.push_back((int32_t)tiles.size());
@@ -442,9 +597,9 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     // 64 consecutive members are close together and the force tiles can skip distant tiles
     {
         const size_t nt = (size_t)ctx->L.n_total;
-        std::vector<int32_t> mem(ctx->gs_h[ng]);
+        const std::vector<int32_t> &mem = mem_h;
         std::vector<double> hx(nt), hy(nt);
-        HIP_TRY(hipMemcpy(mem.data(), ctx->members, mem.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
         std::vector<int32_t> body((size_t)bg.M);
@@ -474,7 +629,8 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
         HIP_TRY(hipMemcpy(bg.body, body.data(), body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     const Layout &L = ctx->L;
-    HIP_TRY(launch_big_setup(L, bg, ctx->members, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, s));
+    HIP_TRY(launch_big_setup(L, bg, members_dev, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, ctx->rc_lv,
+                             dt, s));
     // every attempt ends with the count of groups still short of dt; the device gives up on a
     // group after 20000 attempts, so the loop ends
     if (!ctx->big_exec) {
@@ -699,6 +855,43 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
         if ((rc = alloc_big(ctx))) return rc;
         ctx->large_groups = 1;
     }
+    return GENGA_OK;
+}
+
+int genga_set_levels(genga_ctx *ctx, int32_t n_levels, int32_t n_sub, const double *rcrit_levels)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (n_levels < 1 || n_levels > LEVELS_MAX) return fail(GENGA_ERR_ARG, "n_levels must be in 1..%d", LEVELS_MAX);
+    if (n_levels > 1 && (n_sub < 1 || n_sub > 64)) return fail(GENGA_ERR_ARG, "n_sub must be in 1..64");
+    if (n_levels > 1 && !rcrit_levels) return fail(GENGA_ERR_ARG, "null rcrit_levels");
+    if (!ctx->large_groups) return fail(GENGA_ERR_STATE, "levels need the large-group mode (genga_set_large_groups)");
+    const size_t nt = (size_t)ctx->L.n_total;
+    std::vector<double> h;
+    if (n_levels > 1) {
+        // the radii must be finite, positive and not grow with the level
+        h.resize((size_t)(n_levels - 1) * nt);
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(h.data(), rcrit_levels, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < h.size(); ++k) {
+            if (!(h[k] > 0.0) || !std::isfinite(h[k]))
+                return fail(GENGA_ERR_ARG, "rcrit_levels[%zu] is not a positive finite radius", k);
+            if (k >= nt && h[k] > h[k - nt])
+                return fail(GENGA_ERR_ARG, "rcrit_levels[%zu] exceeds the level above", k);
+        }
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    ctx->release_big();
+    ctx->n_levels = n_levels;
+    ctx->n_sub = n_levels > 1 ? n_sub : 1;
+    if ((rc = alloc_big(ctx))) {
+        ctx->release_big();
+        return rc;
+    }
+    ctx->large_groups = 1;
+    if (n_levels > 1 && nt)
+        HIP_TRY(hipMemcpy(ctx->rc_lv, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
     return GENGA_OK;
 }
 

@@ -177,18 +177,49 @@ struct BigBs {
     unsigned long long *sr = nullptr, *sv = nullptr; // [G] bit patterns of max |r|, max |v|
     unsigned long long *err = nullptr;               // [G][BS_KMAX] bit patterns of the estimates
     int32_t *n_active = nullptr;   // groups not yet at dt after the last attempt
+    // hierarchical levels: with nlev > 1 the pair weight is prod_{k<nlev} (1 - K_k), level 0
+    // from rc, level k >= 1 from rcl[(k - 1) * cap_M + f]; the candidate radius is the deepest
+    // level's.  Fixed when the attempt graph is captured.
+    int32_t nlev = 1;
+    double *rcl = nullptr;         // [LEVELS_MAX - 1][cap_M]
 };
 constexpr int BIG_TILES_PER_GROUP = 1024; // a workgroup of 1024 threads tests one source tile each
+constexpr int LEVELS_MAX = 4;             // symplectic levels of the hierarchical step
 
+// rc_lv: with b.nlev > 1, the critical radii of levels 1..nlev-1 ([nlev - 1][n_total]).
 hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *members, const double *x,
                             const double *y, const double *z, const double *vx, const double *vy,
-                            const double *vz, const double *m, const double *rc, double dt,
-                            hipStream_t stream);
+                            const double *vz, const double *m, const double *rc, const double *rc_lv,
+                            double dt, hipStream_t stream);
 // One attempt of every active group: a fixed sequence of launches that takes its sizes and dt
 // from device memory, so it can be captured once and replayed.
 hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStream_t stream);
 hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, hipStream_t stream);
+// Kick of level `level` (1 <= level < nlev) over the members of the parent groups:
+// v += tau * sum over the member's group of m_j W_l K_l (r_j - r_i) / r^3 (FP64), and with
+// emit the pairs of a group closer than the level's radius (i < j) into pairs / pair_count.
+struct LevelKickArgs {
+    int32_t n_mem = 0;             // members of all parent groups
+    const int32_t *mem = nullptr;  // [n_mem] body of each member, groups contiguous, ascending
+    const int32_t *mgrp = nullptr; // [n_mem] group of each member
+    const int32_t *gs = nullptr;   // [n_groups + 1] group g = mem[gs[g] .. gs[g+1])
+    const int32_t *sys_of = nullptr, *sys_off = nullptr, *n_massive = nullptr;
+    const double *x = nullptr, *y = nullptr, *z = nullptr, *m = nullptr;
+    double *vx = nullptr, *vy = nullptr, *vz = nullptr;
+    const double *rc0 = nullptr;   // [n_total] level 0 (the bodies' r_crit)
+    const double *rcl = nullptr;   // [nlev - 1][n_total] levels 1..nlev-1
+    int32_t n_total = 0, level = 1, emit = 0;
+    double tau = 0.0;
+    int32_t *pairs = nullptr, *pair_count = nullptr, *flags = nullptr;
+    int32_t pair_cap = 0;
+};
+hipError_t launch_level_kick(const LevelKickArgs &a, hipStream_t stream);
+// Kepler drift over dt of the bodies list[0..n-1].
+hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
+                              double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
+                              hipStream_t stream);
+
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,
                          const double *vz, const double *m, const double *ax, const double *ay,

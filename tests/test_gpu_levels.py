@@ -1,0 +1,130 @@
+"""Hierarchical levels (Sect. 1: intermediate symplectic levels with reduced steps between
+the level-0 step and the Bulirsch-Stoer step) on the GPU against the oracle's
+drift_levels / step_levels, on the GPU's own encounter list.  Level k's radius is eq. (1)
+with the level's step dt / n_sub^k (n1 = 3, n2 = 0.4), as in the encounter-dominated runs."""
+import numpy as np
+import pytest
+
+import discs
+import oracle
+import paper_2309_08217_amd as genga
+from gpu_helpers import System
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = genga.GENGA_KICK_FP64, genga.GENGA_KICK_FP32
+DT5 = discs.DT_5_DAYS
+
+
+def level_system(d, nlev, nsub):
+    rcl = oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, nlev, nsub)
+    s = System([d], rcrit=rcl[0])
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    if nlev > 1:
+        t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+        genga.genga_set_levels(s.ctx.handle, nlev, nsub, t)
+        s.torch.cuda.synchronize()
+    return s, rcl
+
+
+def compare(label, got, exp, gid, bar_in=1e-10, bar_out=1e-13):
+    inside = gid >= 0
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        e_in = np.max(np.abs(got[k][inside] - exp[k][inside])) if inside.any() else 0.0
+        e_out = np.max(np.abs(got[k][~inside] - exp[k][~inside])) if (~inside).any() else 0.0
+        print(f"[{label}] {k} groups err {e_in:.2e} others err {e_out:.2e}", flush=True)
+        assert e_in <= bar_in
+        assert e_out <= bar_out
+
+
+@pytest.mark.parametrize("nlev,nsub", [(2, 2), (3, 2), (2, 3), (4, 2)])
+def test_ring_drift_with_levels(nlev, nsub):
+    d = discs.ring_dense(1000)
+    s, rcl = level_system(d, nlev, nsub)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    print(f"[ring {nlev}x{nsub}] pairs={cnt} level-0 groups={gid.max() + 1}", flush=True)
+    b0 = s.numpy_state()
+    exp = oracle.drift_levels(b0, rcl, nsub, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    compare(f"ring {nlev}x{nsub}", got, exp, gid)
+    s.close()
+
+
+def test_whole_disc_group_with_three_levels():
+    """The 6600-body annulus, one level-0 group of every body, integrated by 3 levels of 2
+    sub-steps (level-2 groups go to Bulirsch-Stoer)."""
+    d = discs.disc_dense()
+    s, rcl = level_system(d, 3, 2)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    assert np.bincount(gid[gid >= 0]).max() == d.n
+    b0 = s.numpy_state()
+    exp = oracle.drift_levels(b0, rcl, 2, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    compare("dense 6600 3x2", got, exp, gid)
+    s.close()
+
+
+def test_steps_with_levels_against_oracle():
+    """Five full steps (kick, list, drift with 3 levels, kick) in FP64 and FP32."""
+    d = discs.ring_dense(1000)
+    rcl = oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, 3, 2)
+    exp, _ = oracle.step_levels(d.state(), rcl, 2, 1.0, DT5, 5)
+    for prec, bar in ((FP64, 1e-10), (FP32, 1e-8)):
+        s, _ = level_system(d, 3, 2)
+        genga.genga_step(s.ctx.handle, s.b, DT5, 5, prec)
+        got = s.numpy_state()
+        assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            err = np.max(np.abs(got[k] - exp[k]))
+            print(f"[ring steps 3x2 prec={prec}] {k} max err {err:.2e}", flush=True)
+            assert err <= bar
+        s.close()
+
+
+def test_one_level_is_the_plain_large_group_drift():
+    """genga_set_levels(1) gives the large-group drift bit for bit."""
+    d = discs.ring_dense(1000)
+    out = []
+    for use_levels in (False, True):
+        s, rcl = level_system(d, 1, 1)
+        if use_levels:
+            genga.genga_set_levels(s.ctx.handle, 1, 1, None)
+        s.accel(FP64)
+        genga.genga_drift(s.ctx.handle, s.b, DT5)
+        out.append(s.numpy_state())
+        s.close()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(out[0][k], out[1][k])
+
+
+def test_set_levels_argument_and_state_checks():
+    d = discs.ring_dense(1000)
+    rcl = oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, 3, 2)
+    s = System([d], rcrit=rcl[0])
+    t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+    with pytest.raises(genga.GengaError) as e:          # large groups off
+        genga.genga_set_levels(s.ctx.handle, 3, 2, t)
+    assert e.value.status == genga.GENGA_ERR_STATE
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    for bad in ((0, 2), (5, 2), (3, 0), (3, 65)):
+        with pytest.raises(genga.GengaError) as e:
+            genga.genga_set_levels(s.ctx.handle, bad[0], bad[1], t)
+        assert e.value.status == genga.GENGA_ERR_ARG
+    grow = s.torch.tensor(np.ascontiguousarray(rcl[[2, 1]]), dtype=s.torch.float64, device="cuda")
+    with pytest.raises(genga.GengaError) as e:          # radii growing with the level
+        genga.genga_set_levels(s.ctx.handle, 3, 2, grow)
+    assert e.value.status == genga.GENGA_ERR_ARG
+    genga.genga_set_levels(s.ctx.handle, 3, 2, t)
+    stream = s.torch.cuda.Stream()
+    with pytest.raises(genga.GengaError) as e:          # host round trips: no graph capture
+        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream)
+    assert e.value.status == genga.GENGA_ERR_STATE
+    s.close()
