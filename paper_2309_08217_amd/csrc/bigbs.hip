@@ -36,17 +36,6 @@ constexpr int GB_THREADS = 256;
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-__device__ __forceinline__ double wave_minv(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_maxv(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // max into slot[g] for every lane with use = true: the lanes of the wave's first group
 // combine first and one of them updates the slot; lanes of another group update their own.
 // Every lane of the wave must call it.
@@ -65,19 +54,6 @@ __device__ __forceinline__ void wave_atomic_max(unsigned long long *slot, int g,
     }
     if ((int)(threadIdx.x & 63) == leader) atomicMax(&slot[g0], m);
     if (use && !same) atomicMax(&slot[g], v);
-}
-
-// Bounding box of the positions held by the lanes with v = true, into
-// out[t * 8 + 0..5] = (min x, y, z, max x, y, z).  Every lane of the wave calls it.
-__device__ __forceinline__ void tile_box(bool v, double x, double y, double z, double *out, int t)
-{
-    const int lane = threadIdx.x & 63;
-    const double lo[3] = {wave_minv(v ? x : INFINITY), wave_minv(v ? y : INFINITY), wave_minv(v ? z : INFINITY)};
-    const double hi[3] = {wave_maxv(v ? x : -INFINITY), wave_maxv(v ? y : -INFINITY), wave_maxv(v ? z : -INFINITY)};
-    if (lane < 3) {
-        out[t * 8 + lane] = lo[lane];
-        out[t * 8 + 3 + lane] = hi[lane];
-    }
 }
 
 // Flat member m of large group g: body index, constants, state Y[q * M + m].
@@ -178,13 +154,14 @@ __global__ __launch_bounds__(GB_THREADS) void big_scale_kernel(BigBs b)
 // Tile boxes of the attempt's starting state Y.
 __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
 {
-    if ((int)blockIdx.x >= b.dims[2]) return;
-    const int4 tile = b.tiles[blockIdx.x];
-    if (b.done[tile.x]) return;
-    const size_t M = (size_t)b.dims[1];
-    const bool v = (int)threadIdx.x < tile.z;
-    const int f = tile.y + (v ? (int)threadIdx.x : 0);
-    tile_box(v, b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.bb, blockIdx.x);
+    for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
+        const int4 tile = b.tiles[me];
+        if (b.done[tile.x]) continue;
+        const size_t M = (size_t)b.dims[1];
+        const bool v = (int)threadIdx.x < tile.z;
+        const int f = tile.y + (v ? (int)threadIdx.x : 0);
+        tile_box(v, b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.bb, me);
+    }
 }
 
 // One sub-step of column k for the targets of a tile (one workgroup per tile): the (1 - K)
@@ -198,14 +175,10 @@ __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
 // many waves.  Source positions and boxes come through scalar loads: neither is written by
 // this launch.
 template <bool LV>
-__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
-                                                                       const double *Z, const double *ZM,
-                                                                       double *OUT, const double *bbZ,
-                                                                       double *bbOUT)
+__device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int mode, const double *Z,
+                                             const double *ZM, double *OUT, const double *bbZ, double *bbOUT)
 {
     __shared__ double red[3][GB_WAVES][GB_TILE];
-    const int me = blockIdx.x;
-    if (me >= b.dims[2]) return;
     const int4 tile = b.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
     if (b.done[g] || b.acc[g] >= 0) return;
@@ -346,6 +319,20 @@ __global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b,
     tile_box(valid, nx[0], nx[1], nx[2], bbOUT, me);
 }
 
+// The tiles are visited grid-stride, so that a launch can be sized to the layout at hand
+// (the captured attempt is kept per grid size) rather than to the largest one.
+template <bool LV>
+__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
+                                                                       const double *Z, const double *ZM,
+                                                                       double *OUT, const double *bbZ,
+                                                                       double *bbOUT)
+{
+    for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
+        if (me != (int)blockIdx.x) __syncthreads(); // the previous tile's LDS is free again
+        substep_tile<LV>(b, me, k, mode, Z, ZM, OUT, bbZ, bbOUT);
+    }
+}
+
 // Error estimate of column k: per member max(|T(k,k) - T(k,k-1)| / scale) over its six
 // elements, into the group's maximum.
 __global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
@@ -461,12 +448,12 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
     return hipGetLastError();
 }
 
-hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStream_t stream)
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream)
 {
     // grids for the largest layout: launches past the current one (sizes in b.dims) return at
     // once, so one captured sequence serves every step
     const int gg = (b.cap_G + 63) / 64, gm = (b.cap_M + GB_THREADS - 1) / GB_THREADS;
-    const int nt = b.cap_T;
+    const int nt = std::max(1, std::min(tile_grid, b.cap_T));
     const size_t M6 = 6 * (size_t)b.cap_M;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
     double *box[3] = {b.bb, b.bb + 8 * (size_t)b.cap_T, b.bb + 16 * (size_t)b.cap_T};

@@ -216,6 +216,21 @@ __device__ __forceinline__ int find_root(int32_t *lab, int a)
     return r;
 }
 
+// Root of a with path halving: every visited node is pointed at its grandparent.  Labels only
+// ever move to a smaller index of the same tree (hooks link a root under a smaller root), so
+// a halving step that races with a hook or another halving still leaves a valid ancestor.
+__device__ __forceinline__ int find_root_halving(int32_t *lab, int a)
+{
+    int p = lab_load(lab, a);
+    while (p != a) {
+        const int gp = lab_load(lab, p);
+        if (gp != p) __hip_atomic_store(&lab[a], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a = gp;
+        p = lab_load(lab, a);
+    }
+    return a;
+}
+
 // Grid-wide union-find over the encounter pairs, for the large-group mode, where the host
 // reads the labels back: every body of a pair becomes its own root, rounds of hooking (the
 // larger root under the smaller) run until a round changes nothing, then every member's label
@@ -237,8 +252,8 @@ __global__ __launch_bounds__(256) void uf_hook_kernel(const int32_t *pairs, cons
     const int np = min(*pair_count, pair_cap);
     int ch = 0;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < np; p += gridDim.x * 256) {
-        const int a = find_root(lab, pairs[2 * p]);
-        const int b = find_root(lab, pairs[2 * p + 1]);
+        const int a = find_root_halving(lab, pairs[2 * p]);
+        const int b = find_root_halving(lab, pairs[2 * p + 1]);
         if (a != b) {
             atomicMin(&lab[max(a, b)], min(a, b));
             ch = 1;
@@ -424,7 +439,9 @@ struct BsShared {
     double pos[BS_LANES][4];                   // positions published for the pair forces
     double m[BS_LANES];                        // member masses
     double rc[BS_LANES], r01[BS_LANES], i09[BS_LANES]; // r_crit, 0.1 r_crit, 1 / (0.9 r_crit)
+    double rcl[LEVELS_MAX - 1][BS_LANES];      // hierarchical levels 1..nlev-1: r_crit of each
     int32_t test[BS_LANES];                    // member is a test body (TP2)
+    int32_t nlev;                              // symplectic levels (1: the plain step)
 };
 
 // This lane's member: its constants and which lanes hold its partners' positions.
@@ -434,9 +451,28 @@ struct BsMember {
     double mstar, rc, r01, i09;
 };
 
+// With LV (hierarchical levels), the pair weight (1 - K) of level 0 times prod over levels
+// 1..nlev-1 of (1 - K_k) with the pair's level-k radius; the pair counts while closer than the
+// deepest level's radius (the radii do not grow with the level).  The factor of the deeper
+// levels, or 0 beyond the deepest radius; ra / rb give member a's / b's level radii.
+template <bool LV>
+__device__ __forceinline__ double deeper_levels(double r, double q, int nlev, const double *ra, const double *rb,
+                                                int stride)
+{
+    if constexpr (!LV) return 1.0;
+    double w = 1.0;
+    for (int k = 1; k < nlev; ++k) {
+        const double rck = fmax(ra[(k - 1) * stride], rb[(k - 1) * stride]);
+        if (!(q < sq_rn(rck))) return 0.0;
+        w *= 1.0 - changeover_k((r - 0.1 * rck) / (0.9 * rck));
+    }
+    return w;
+}
+
 // dY/dt: Kepler term about the Sun plus the (1 - K) share of the Newtonian forces from the
 // other members (K of Chambers 1999 over [0.1, 1] r_crit,ab; two test bodies do not
 // interact).  Every lane of the wave calls it.
+template <bool LV>
 __device__ void bs_forces(const BsMember &me, BsShared &S, int slot, const double z[6], double d[6])
 {
     S.pos[slot][0] = z[0];
@@ -458,7 +494,8 @@ __device__ void bs_forces(const BsMember &me, BsShared &S, int slot, const doubl
         const double rcab = own ? me.rc : S.rc[b];
         if (!(q < sq_rn(rcab))) continue;
         const double rq = inv_sqrt64(q);
-        const double w = 1.0 - changeover_k((q * rq - (own ? me.r01 : S.r01[b])) * (own ? me.i09 : S.i09[b]));
+        double w = 1.0 - changeover_k((q * rq - (own ? me.r01 : S.r01[b])) * (own ? me.i09 : S.i09[b]));
+        if constexpr (LV) w *= deeper_levels<LV>(q * rq, q, S.nlev, &S.rcl[0][me.a], &S.rcl[0][b], BS_LANES);
         const double t = S.m[b] * w * (rq * rq) * rq;
         ax = fma(t, dx, ax);
         ay = fma(t, dy, ay);
@@ -478,6 +515,7 @@ __device__ void bs_forces(const BsMember &me, BsShared &S, int slot, const doubl
 // after n_k + 1 passes; its lanes then extend the tableau by row k (reading row k-1 from LDS)
 // and the wave ends the attempt as soon as a column has converged.  The accepted column is
 // the first converged one, as in the sequential scheme.
+template <bool LV>
 __device__ bool bs_columns(const BsMember &me, int k, BsShared &S, double (*row)[BS_KMAX][CP_MEM][6],
                            double Y[6], double dt, double tol)
 {
@@ -499,7 +537,7 @@ __device__ bool bs_columns(const BsMember &me, int k, BsShared &S, double (*row)
 #pragma unroll 1
         for (int i = 0; i <= 2 * BS_KMAX; ++i) {
             double dd[6];
-            bs_forces(me, S, slot, zc, dd);
+            bs_forces<LV>(me, S, slot, zc, dd);
             if (i == 0) {
                 for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
             } else if (i < nsub) {
@@ -560,6 +598,7 @@ __device__ bool bs_columns(const BsMember &me, int k, BsShared &S, double (*row)
 
 // Groups of CP_MEM + 1 .. BS_LANES members: one lane per member, columns in sequence, each
 // lane's tableau in its own LDS column tab[l][q][lane].
+template <bool LV>
 __device__ bool bs_lanes(const BsMember &me, BsShared &S, double (*tab)[6][BS_LANES], double Y[6],
                          double dt, double tol)
 {
@@ -583,7 +622,7 @@ __device__ bool bs_lanes(const BsMember &me, BsShared &S, double (*tab)[6][BS_LA
 #pragma unroll 1
             for (int i = 0; i <= nsub; ++i) {
                 double dd[6];
-                bs_forces(me, S, me.a, zc, dd);
+                bs_forces<LV>(me, S, me.a, zc, dd);
                 if (i == 0) {
                     for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
                 } else if (i < nsub) {
@@ -648,9 +687,11 @@ struct SmallGroup {
     double m[NB];
     double rc2[NB][NB], r01[NB][NB], i09[NB][NB]; // per pair a < b, from r_crit,ab
     bool skip[NB][NB];                            // both are test bodies (TP2)
+    int nlev;                                     // hierarchical levels
+    double rcl[LEVELS_MAX - 1][NB];               // levels 1..nlev-1: r_crit of each member
 };
 
-template <int NB>
+template <int NB, bool LV>
 __device__ __forceinline__ void small_forces(const SmallGroup<NB> &g, const double (&z)[NB][6],
                                              double (&d)[NB][6])
 {
@@ -674,7 +715,8 @@ __device__ __forceinline__ void small_forces(const SmallGroup<NB> &g, const doub
             const double q = sep2_rn(dx, dy, dz);
             if (!(q < g.rc2[a][b])) continue;
             const double rq = inv_sqrt64(q);
-            const double w = 1.0 - changeover_k((q * rq - g.r01[a][b]) * g.i09[a][b]);
+            double w = 1.0 - changeover_k((q * rq - g.r01[a][b]) * g.i09[a][b]);
+            if constexpr (LV) w *= deeper_levels<LV>(q * rq, q, g.nlev, &g.rcl[0][a], &g.rcl[0][b], NB);
             const double u = w * (rq * rq) * rq;
             const double ua = g.m[b] * u, ub = g.m[a] * u;
             d[a][3] = fma(ua, dx, d[a][3]);
@@ -709,7 +751,7 @@ __device__ __forceinline__ double lagrange_sum(const double *tcol, const double 
 
 // ybuf: the group state [NB][6] in LDS (read at entry, holds the result on return);
 // tcol: LDS [BS_KMAX][NB * 6] for T(k, 0); lag: LAGRANGE copied to LDS (w, then d).
-template <int NB>
+template <int NB, bool LV>
 __device__ bool bs_small(const SmallGroup<NB> &g, int lane, double *ybuf, double *tcol, const double *lag,
                          double dt, double tol)
 {
@@ -741,7 +783,7 @@ __device__ bool bs_small(const SmallGroup<NB> &g, int lane, double *ybuf, double
 #pragma unroll 1
         for (int i = 0; i <= 2 * BS_KMAX; ++i) {
             double dd[NB][6];
-            small_forces<NB>(g, zc, dd);
+            small_forces<NB, LV>(g, zc, dd);
             if (i == 0) {
 #pragma unroll
                 for (int a = 0; a < NB; ++a)
@@ -788,7 +830,7 @@ __device__ bool bs_small(const SmallGroup<NB> &g, int lane, double *ybuf, double
     return true;
 }
 
-template <int NB>
+template <int NB, bool LV>
 __device__ bool run_small(const BsShared &S, int lane, double ms, double *x, double *y, double *z,
                           double *vx, double *vy, double *vz, const int32_t *mem, double *ybuf,
                           double *tcol, double *lag, double dt)
@@ -808,6 +850,11 @@ __device__ bool run_small(const BsShared &S, int lane, double ms, double *x, dou
             g.skip[a][b] = S.test[a] && S.test[b];
         }
     }
+    g.nlev = S.nlev;
+    if constexpr (LV)
+        for (int k = 1; k < S.nlev; ++k)
+#pragma unroll
+            for (int a = 0; a < NB; ++a) g.rcl[k - 1][a] = S.rcl[k - 1][a];
     if (lane < NB) {
         const int b = mem[lane];
         ybuf[6 * lane + 0] = x[b];
@@ -820,7 +867,7 @@ __device__ bool run_small(const BsShared &S, int lane, double ms, double *x, dou
     lag[lane] = (&LAGRANGE.w[0][0])[lane];
     lag[BS_LANES + lane] = (&LAGRANGE.d[0][0])[lane];
     __syncthreads();
-    const bool ok = bs_small<NB>(g, lane, ybuf, tcol, lag, dt, 1e-12);
+    const bool ok = bs_small<NB, LV>(g, lane, ybuf, tcol, lag, dt, 1e-12);
     __syncthreads();
     if (lane < NB) store_state(x, y, z, vx, vy, vz, mem[lane], ybuf + 6 * lane);
     return ok;
@@ -830,6 +877,7 @@ __device__ bool run_small(const BsShared &S, int lane, double ms, double *x, dou
 // Bulirsch-Stoer, the blocks after them Kepler-drift 64 bodies each and skip the group
 // members.  Each body is read and written by one block only.
 
+template <bool LV>
 __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, const int32_t *sys_off,
                                                          const int32_t *n_massive, const double *mstar,
                                                          int n_total, double *x, double *y, double *z,
@@ -838,7 +886,8 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
                                                          const int32_t *members,
                                                          const int32_t *group_start,
                                                          const int32_t *n_groups, int32_t *member_slot,
-                                                         int32_t *flags, int big_groups, int bs_blocks)
+                                                         int32_t *flags, int big_groups, int bs_blocks,
+                                                         const double *rc_lv, int nlev)
 {
     __shared__ BsShared S;
     __shared__ double tab[BS_KMAX * 6 * BS_LANES];
@@ -879,13 +928,16 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
         S.r01[lane] = 0.1 * rc[b];
         S.i09[lane] = 1.0 / (0.9 * rc[b]);
         S.test[lane] = b - sys_off[sb] >= n_massive[sb];
+        if constexpr (LV)
+            for (int l = 1; l < nlev; ++l) S.rcl[l - 1][lane] = rc_lv[(size_t)(l - 1) * n_total + b];
     }
+    if (lane == 0) S.nlev = nlev;
     __syncthreads();
     if (nb <= 3) {
         __shared__ double ybuf[3 * 6];
         double *lag = tab + BS_KMAX * 3 * 6;
-        const bool ok = nb == 2 ? run_small<2>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt)
-                                : run_small<3>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt);
+        const bool ok = nb == 2 ? run_small<2, LV>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt)
+                                : run_small<3, LV>(S, lane, ms, x, y, z, vx, vy, vz, members + k0, ybuf, tab, lag, dt);
         if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
         return;
     }
@@ -904,8 +956,8 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
     me.i09 = S.i09[ai];
     const int b = members[k0 + ai];
     double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
-    const bool ok = cols ? bs_columns(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12)
-                         : bs_lanes(me, S, (double(*)[6][BS_LANES])tab, Y, dt, 1e-12);
+    const bool ok = cols ? bs_columns<LV>(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12)
+                         : bs_lanes<LV>(me, S, (double(*)[6][BS_LANES])tab, Y, dt, 1e-12);
     // every lane has read its member's state before the first force evaluation's barrier
     if (me.act && k == 0) store_state(x, y, z, vx, vy, vz, b, Y);
     if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
@@ -998,17 +1050,20 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream)
+                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream, const double *rc_lv,
+                        int nlev, bool kepler)
 {
     if (L.n_total == 0) return hipSuccess;
     // one block per possible group: every group has >= 2 members; bs_blocks < 0: no group
     // blocks (the groups are integrated elsewhere), only the Kepler drift of non-members
     if (bs_blocks == 0) bs_blocks = CE_MAX_MEMBERS / 2;
     if (bs_blocks < 0) bs_blocks = 0;
-    const int grid = bs_blocks + (L.n_total + BS_LANES - 1) / BS_LANES;
-    drift_kernel<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z,
-                                                vx, vy, vz, m, rc, dt, members, group_start, n_groups,
-                                                member_slot, flags, big_groups, bs_blocks);
+    const int grid = bs_blocks + (kepler ? (L.n_total + BS_LANES - 1) / BS_LANES : 0);
+    if (grid == 0) return hipSuccess;
+    auto kern = nlev > 1 ? drift_kernel<true> : drift_kernel<false>;
+    kern<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy, vz, m,
+                                        rc, dt, members, group_start, n_groups, member_slot, flags, big_groups,
+                                        bs_blocks, rc_lv, nlev);
     return hipGetLastError();
 }
 

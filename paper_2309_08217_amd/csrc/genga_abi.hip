@@ -86,7 +86,9 @@ struct genga_ctx {
     BigBs big;
     int32_t *pin = nullptr;            // pinned host words for the per-attempt status reads
     hipStream_t big_stream = nullptr;  // private stream to capture one attempt
-    hipGraphExec_t big_exec = nullptr; // the captured attempt, replayed on the caller's stream
+    // the captured attempt, replayed on the caller's stream: one per tile-launch grid (a power
+    // of two that covers the layout's tiles)
+    hipGraphExec_t big_exec[32] = {};
     int32_t *big_changed = nullptr;    // device word of the union-find rounds
     int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
@@ -94,9 +96,9 @@ struct genga_ctx {
     // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
     int32_t n_levels = 1, n_sub = 1;
     double *rc_lv = nullptr;           // [n_levels - 1][n_total]
-    struct LevelGroups {
-        int32_t *mem = nullptr, *mgrp = nullptr, *gs = nullptr; // groups of one level, on the device
-    } lv[LEVELS_MAX];
+    LevelTiles lt[LEVELS_MAX - 1];     // parent groups of levels 1..n_levels-1, in tiles
+    int32_t lt_cap_G = 0, lt_cap_T = 0;
+    int32_t *lv_mem = nullptr, *lv_gs = nullptr, *lv_ng = nullptr; // the deepest level's groups
     int32_t *lv_pairs = nullptr, *lv_count = nullptr, *lv_list = nullptr; // a level's pairs; Kepler list
     // graph
     hipGraph_t graph = nullptr;
@@ -132,19 +134,33 @@ struct genga_ctx {
         dfree(big.rcl);
         big.nlev = 1;
         dfree(rc_lv);
-        for (auto &g : lv) {
-            dfree(g.mem);
-            dfree(g.mgrp);
-            dfree(g.gs);
+        for (auto &t : lt) {
+            dfree(t.off);
+            dfree(t.tfirst);
+            dfree(t.tiles);
+            dfree(t.body);
+            dfree(t.test);
+            dfree(t.X);
+            dfree(t.Y);
+            dfree(t.Z);
+            dfree(t.mass);
+            dfree(t.rc);
+            dfree(t.bb);
+            dfree(t.cut2);
+            t.G = t.M = t.n_tiles = t.cap_M = 0;
         }
+        dfree(lv_mem);
+        dfree(lv_gs);
+        dfree(lv_ng);
         dfree(lv_pairs);
         dfree(lv_count);
         dfree(lv_list);
         n_levels = n_sub = 1;
         if (pin) (void)hipHostFree(pin);
-        if (big_exec) (void)hipGraphExecDestroy(big_exec);
+        for (auto &e : big_exec)
+            if (e) (void)hipGraphExecDestroy(e);
         if (big_stream) (void)hipStreamDestroy(big_stream);
-        big_exec = nullptr;
+        for (auto &e : big_exec) e = nullptr;
         big_stream = nullptr;
         dfree(big.dims);
         dfree(big.dtp);
@@ -333,11 +349,27 @@ int alloc_big(genga_ctx *ctx)
         const size_t nt = (size_t)std::max(ctx->L.n_total, 1);
         HIP_TRY(dalloc(b.rcl, (size_t)(LEVELS_MAX - 1) * b.cap_M));
         HIP_TRY(dalloc(ctx->rc_lv, (size_t)(LEVELS_MAX - 1) * nt));
-        for (auto &g : ctx->lv) {
-            HIP_TRY(dalloc(g.mem, nt));
-            HIP_TRY(dalloc(g.mgrp, nt));
-            HIP_TRY(dalloc(g.gs, nt + 1));
+        ctx->lt_cap_G = (int32_t)nt / 2 + 1;
+        ctx->lt_cap_T = (int32_t)nt / 64 + ctx->lt_cap_G + 1;
+        const size_t G = (size_t)ctx->lt_cap_G, T = (size_t)ctx->lt_cap_T;
+        for (auto &t : ctx->lt) {
+            t.cap_M = (int32_t)nt;
+            HIP_TRY(dalloc(t.off, G + 1));
+            HIP_TRY(dalloc(t.tfirst, G + 1));
+            HIP_TRY(dalloc(t.tiles, T));
+            HIP_TRY(dalloc(t.body, nt));
+            HIP_TRY(dalloc(t.test, nt));
+            HIP_TRY(dalloc(t.X, nt));
+            HIP_TRY(dalloc(t.Y, nt));
+            HIP_TRY(dalloc(t.Z, nt));
+            HIP_TRY(dalloc(t.mass, nt));
+            HIP_TRY(dalloc(t.rc, (size_t)LEVELS_MAX * nt));
+            HIP_TRY(dalloc(t.bb, 8 * T));
+            HIP_TRY(dalloc(t.cut2, G));
         }
+        HIP_TRY(dalloc(ctx->lv_mem, nt));
+        HIP_TRY(dalloc(ctx->lv_gs, nt + 1));
+        HIP_TRY(dalloc(ctx->lv_ng, 1));
         HIP_TRY(dalloc(ctx->lv_pairs, 2 * (size_t)ctx->pair_cap));
         HIP_TRY(dalloc(ctx->lv_count, 1));
         HIP_TRY(dalloc(ctx->lv_list, nt));
@@ -400,16 +432,20 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
     mem.clear();
     if (np <= 0) return GENGA_OK;
     HIP_TRY(launch_uf_init(pairs, count, cap, ctx->lab, s));
+    // rounds of (hook, compress) x 2 until a round changes nothing; compressing after each
+    // hook keeps the trees flat, so few rounds are needed
     for (int round = 0;; ++round) {
         if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
         ctx->pin[2] = 0;
         HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_uf_hook(pairs, count, cap, ctx->lab, ctx->big_changed, s));
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(launch_uf_hook(pairs, count, cap, ctx->lab, ctx->big_changed, s));
+            HIP_TRY(launch_uf_compress(L, ctx->lab, s));
+        }
         HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[2] == 0) break;
     }
-    HIP_TRY(launch_uf_compress(L, ctx->lab, s));
     const size_t nt = (size_t)L.n_total;
     std::vector<int32_t> lab(nt), cnt(nt, 0);
     HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -459,6 +495,64 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
+// The groups of gs / mem with at least min_nb members, each ordered by ring (equal-width bands
+// of distance to the star, as many as make a tile of 64 members about as wide as long) and then
+// by azimuth, so that 64 consecutive members are close together and force tiles can skip
+// distant tiles; cut into tiles of 64.
+struct TileOrder {
+    std::vector<int32_t> k0, off{0}, tfirst{0}, body;
+    std::vector<int4> tiles;
+};
+
+int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vector<int32_t> &gs,
+                const std::vector<int32_t> &mem, int min_nb, TileOrder &o)
+{
+    const int ng = (int)gs.size() - 1;
+    for (int g = 0; g < ng; ++g) {
+        const int nb = gs[g + 1] - gs[g];
+        if (nb < min_nb) continue;
+        const int gi = (int)o.k0.size(), f0 = o.off.back();
+        o.k0.push_back(gs[g]);
+        o.off.push_back(f0 + nb);
+        for (int f = 0; f < nb; f += 64) o.tiles.push_back(make_int4(gi, f0 + f, std::min(64, nb - f), 0));
+        o.tfirst.push_back((int32_t)o.tiles.size());
+    }
+    for (size_t gi = 0; gi + 1 < o.tfirst.size(); ++gi)
+        if (o.tfirst[gi + 1] - o.tfirst[gi] > BIG_TILES_PER_GROUP)
+            return fail(GENGA_ERR_CAPACITY, "an encounter group of more than %d bodies", 64 * BIG_TILES_PER_GROUP);
+    if (o.k0.empty()) return GENGA_OK;
+    const size_t nt = (size_t)ctx->L.n_total;
+    std::vector<double> hx(nt), hy(nt);
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
+    o.body.resize((size_t)o.off.back());
+    std::vector<std::pair<double, int32_t>> key;
+    for (size_t gi = 0; gi < o.k0.size(); ++gi) {
+        const int nb = o.off[gi + 1] - o.off[gi];
+        double r0 = INFINITY, r1 = 0.0, rs = 0.0;
+        for (int l = 0; l < nb; ++l) {
+            const int32_t bi = mem[o.k0[gi] + l];
+            const double r = std::hypot(hx[bi], hy[bi]);
+            r0 = std::min(r0, r);
+            r1 = std::max(r1, r);
+            rs += r;
+        }
+        const double rmean = rs / nb, width = std::max(r1 - r0, 1e-300);
+        const int rings = std::max(1, (int)std::lround(std::sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
+        key.resize(nb);
+        for (int l = 0; l < nb; ++l) {
+            const int32_t bi = mem[o.k0[gi] + l];
+            const double r = std::hypot(hx[bi], hy[bi]);
+            const int ring = std::min(rings - 1, (int)((r - r0) / width * rings));
+            key[l] = {ring * 8.0 + std::atan2(hy[bi], hx[bi]), bi};
+        }
+        std::sort(key.begin(), key.end());
+        for (int l = 0; l < nb; ++l) o.body[o.off[gi] + l] = key[l].second;
+    }
+    return GENGA_OK;
+}
+
 // ------------------------------------------------------------------------------------------
 // Hierarchical levels (Sect. 1): level l integrates each group of level l-1 over tau in n_sub
 // Strang sub-steps of h = tau / n_sub: kick(h/2) with the level-l share of the pair forces
@@ -474,27 +568,13 @@ int upload_i32(int32_t *dst, const std::vector<int32_t> &v, hipStream_t s)
     return GENGA_OK;
 }
 
-int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const genga_ctx::LevelGroups &P, int n_mem,
-               double tau, bool emit, hipStream_t s)
+int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const LevelTiles &T, double tau, bool emit,
+               hipStream_t s)
 {
     LevelKickArgs a;
-    a.n_mem = n_mem;
-    a.mem = P.mem;
-    a.mgrp = P.mgrp;
-    a.gs = P.gs;
-    a.sys_of = ctx->L.sys_of;
-    a.sys_off = ctx->L.sys_off;
-    a.n_massive = ctx->L.n_massive;
-    a.x = b->x;
-    a.y = b->y;
-    a.z = b->z;
-    a.m = b->m;
     a.vx = b->vx;
     a.vy = b->vy;
     a.vz = b->vz;
-    a.rc0 = b->rcrit;
-    a.rcl = ctx->rc_lv;
-    a.n_total = ctx->L.n_total;
     a.level = level;
     a.emit = emit ? 1 : 0;
     a.tau = tau;
@@ -502,30 +582,37 @@ int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const genga_ctx::Leve
     a.pair_count = ctx->lv_count;
     a.flags = ctx->flags;
     a.pair_cap = ctx->pair_cap;
-    HIP_TRY(launch_level_kick(a, s));
+    HIP_TRY(launch_level_kick(T, a, b->x, b->y, b->z, s));
     return GENGA_OK;
 }
 
 int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int32_t> &pgs,
               const std::vector<int32_t> &pmem, double tau, hipStream_t s)
 {
-    const int ng = (int)pgs.size() - 1, n_mem = (int)pmem.size();
+    const int ng = (int)pgs.size() - 1;
     if (ng <= 0) return GENGA_OK;
-    // the parent groups (level - 1) on the device
-    const genga_ctx::LevelGroups &P = ctx->lv[level - 1];
-    std::vector<int32_t> mgrp(n_mem);
-    for (int g = 0; g < ng; ++g)
-        for (int k = pgs[g]; k < pgs[g + 1]; ++k) mgrp[k] = g;
-    int rc;
-    if ((rc = upload_i32(P.mem, pmem, s)) || (rc = upload_i32(P.mgrp, mgrp, s)) || (rc = upload_i32(P.gs, pgs, s)))
-        return rc;
+    // the parent groups (level - 1) in tiles, fixed over the level's interval
+    LevelTiles &T = ctx->lt[level - 1];
+    TileOrder o;
+    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o);
+    if (rc) return rc;
+    if ((int)o.k0.size() > ctx->lt_cap_G || o.off.back() > T.cap_M || (int)o.tiles.size() > ctx->lt_cap_T)
+        return fail(GENGA_ERR_STATE, "level layout exceeds its allocation");
+    T.G = (int32_t)o.k0.size();
+    T.M = o.off.back();
+    T.n_tiles = (int32_t)o.tiles.size();
+    HIP_TRY(hipMemcpy(T.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(T.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(launch_level_tiles_setup(ctx->L, T, b->m, b->rcrit, ctx->rc_lv, level, s));
     const double h = tau / ctx->n_sub;
     const bool deepest = level + 1 == ctx->n_levels;
     std::vector<int32_t> cgs, cmem, kep;
     std::vector<uint8_t> in_child((size_t)ctx->L.n_total, 0);
     for (int sub = 0; sub < ctx->n_sub; ++sub) {
         HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
-        if ((rc = level_kick(ctx, b, level, P, n_mem, 0.5 * h, true, s))) return rc;
+        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
         if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true))) return rc;
         // parent members in no pair of this level: Kepler drift over h
         for (int32_t i : cmem) in_child[i] = 1;
@@ -538,14 +625,21 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
                                    h, ctx->flags, s));
         if (!cmem.empty()) {
             if (deepest) {
-                const genga_ctx::LevelGroups &C = ctx->lv[level];
-                if ((rc = upload_i32(C.mem, cmem, s))) return rc;
-                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, C.mem, 2))) return rc;
+                // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members,
+                // the grid-wide path for larger ones
+                const int ncg = (int)cgs.size() - 1;
+                if ((rc = upload_i32(ctx->lv_mem, cmem, s)) || (rc = upload_i32(ctx->lv_gs, cgs, s)) ||
+                    (rc = upload_i32(ctx->lv_ng, std::vector<int32_t>{ncg}, s)))
+                    return rc;
+                HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
+                                     ctx->lv_gs, ctx->lv_ng, ctx->member_slot, ctx->flags, 1, ncg, s, ctx->rc_lv,
+                                     ctx->n_levels, false));
+                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, ctx->lv_mem, CE_MAX_GROUP + 1))) return rc;
             } else if ((rc = run_level(ctx, b, level + 1, cgs, cmem, h, s))) {
                 return rc;
             }
         }
-        if ((rc = level_kick(ctx, b, level, P, n_mem, 0.5 * h, false, s))) return rc;
+        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, false, s))) return rc;
     }
     return GENGA_OK;
 }
@@ -563,82 +657,36 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
 {
     BigBs &bg = ctx->big;
     bg.G = bg.M = bg.n_tiles = 0;
-    const int ng = (int)gs.size() - 1;
-    if (ng <= 0) return GENGA_OK;
-    std::vector<int32_t> k0, off(1, 0);
-    std::vector<int4> tiles;
-    std::vector<int32_t> tfirst(1, 0);
-    for (int g = 0; g < ng; ++g) {
-        const int nb = gs[g + 1] - gs[g];
-        if (nb < min_nb) continue;
-        const int gi = (int)k0.size(), o = off.back();
-        k0.push_back(gs[g]);
-        off.push_back(o + nb);
-        for (int f = 0; f < nb; f += 64) tiles.push_back(make_int4(gi, o + f, std::min(64, nb - f), 0));
-        tfirst.push_back((int32_t)tiles.size());
-    }
-    if (k0.empty()) return GENGA_OK;
-    if ((int)k0.size() > bg.cap_G || off.back() > bg.cap_M || (int)tiles.size() > bg.cap_T)
+    TileOrder o;
+    int rc = order_tiles(ctx, b, s, gs, mem_h, min_nb, o);
+    if (rc) return rc;
+    if (o.k0.empty()) return GENGA_OK;
+    if ((int)o.k0.size() > bg.cap_G || o.off.back() > bg.cap_M || (int)o.tiles.size() > bg.cap_T)
         return fail(GENGA_ERR_STATE, "large-group layout exceeds its allocation");
-    for (size_t gi = 0; gi + 1 < tfirst.size(); ++gi)
-        if (tfirst[gi + 1] - tfirst[gi] > BIG_TILES_PER_GROUP)
-            return fail(GENGA_ERR_CAPACITY, "an encounter group of more than %d bodies", 64 * BIG_TILES_PER_GROUP);
-    bg.G = (int32_t)k0.size();
-    bg.M = off.back();
-    bg.n_tiles = (int32_t)tiles.size();
-    HIP_TRY(hipMemcpy(bg.k0, k0.data(), k0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.tfirst, tfirst.data(), tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    bg.G = (int32_t)o.k0.size();
+    bg.M = o.off.back();
+    bg.n_tiles = (int32_t)o.tiles.size();
+    HIP_TRY(hipMemcpy(bg.k0, o.k0.data(), o.k0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bg.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     const int32_t dims[4] = {bg.G, bg.M, bg.n_tiles, 0};
     HIP_TRY(hipMemcpy(bg.dims, dims, sizeof(dims), hipMemcpyHostToDevice));
-    // members of each large group ordered by ring (equal-width bands of distance to the star,
-    // as many as make a tile of 64 members about as wide as long) and then by azimuth, so that
-    // 64 consecutive members are close together and the force tiles can skip distant tiles
-    {
-        const size_t nt = (size_t)ctx->L.n_total;
-        const std::vector<int32_t> &mem = mem_h;
-        std::vector<double> hx(nt), hy(nt);
-        HIP_TRY(hipStreamSynchronize(s));
-        HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
-        std::vector<int32_t> body((size_t)bg.M);
-        std::vector<std::pair<double, int32_t>> key;
-        for (int gi = 0; gi < bg.G; ++gi) {
-            const int nb = off[gi + 1] - off[gi];
-            double r0 = INFINITY, r1 = 0.0, rs = 0.0;
-            for (int l = 0; l < nb; ++l) {
-                const int32_t bi = mem[k0[gi] + l];
-                const double r = std::hypot(hx[bi], hy[bi]);
-                r0 = std::min(r0, r);
-                r1 = std::max(r1, r);
-                rs += r;
-            }
-            const double rmean = rs / nb, width = std::max(r1 - r0, 1e-300);
-            const int rings = std::max(1, (int)std::lround(std::sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
-            key.resize(nb);
-            for (int l = 0; l < nb; ++l) {
-                const int32_t bi = mem[k0[gi] + l];
-                const double r = std::hypot(hx[bi], hy[bi]);
-                const int ring = std::min(rings - 1, (int)((r - r0) / width * rings));
-                key[l] = {ring * 8.0 + std::atan2(hy[bi], hx[bi]), bi};
-            }
-            std::sort(key.begin(), key.end());
-            for (int l = 0; l < nb; ++l) body[off[gi] + l] = key[l].second;
-        }
-        HIP_TRY(hipMemcpy(bg.body, body.data(), body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
+    HIP_TRY(hipMemcpy(bg.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     const Layout &L = ctx->L;
     HIP_TRY(launch_big_setup(L, bg, members_dev, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, ctx->rc_lv,
                              dt, s));
     // every attempt ends with the count of groups still short of dt; the device gives up on a
     // group after 20000 attempts, so the loop ends
-    if (!ctx->big_exec) {
-        // one attempt's launch sequence, captured once per context (sizes and dt live in
-        // device memory, every buffer address is fixed)
+    int gl = 6;
+    while ((1 << gl) < bg.n_tiles && (1 << gl) < bg.cap_T) ++gl;
+    hipGraphExec_t &exec = ctx->big_exec[gl];
+    if (!exec) {
+        // one attempt's launch sequence, captured once per context and grid (sizes and dt live
+        // in device memory, every buffer address is fixed)
         if (!ctx->big_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->big_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(ctx->big_stream, hipStreamCaptureModeThreadLocal));
-        const hipError_t le = launch_big_attempt(bg, 1e-12, ctx->flags, ctx->big_stream);
+        const hipError_t le = launch_big_attempt(bg, 1e-12, ctx->flags, 1 << gl, ctx->big_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(ctx->big_stream, &g);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -646,15 +694,15 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
             return fail(GENGA_ERR_HIP, "capturing the large-group attempt failed: %s",
                         hipGetErrorString(le != hipSuccess ? le : ce));
         }
-        const hipError_t ie = hipGraphInstantiate(&ctx->big_exec, g, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
-            ctx->big_exec = nullptr;
+            exec = nullptr;
             return fail(GENGA_ERR_HIP, "hipGraphInstantiate (large-group attempt) failed: %s", hipGetErrorString(ie));
         }
     }
     for (int attempt = 0; attempt <= 20001; ++attempt) {
-        HIP_TRY(hipGraphLaunch(ctx->big_exec, s));
+        HIP_TRY(hipGraphLaunch(exec, s));
         HIP_TRY(hipMemcpyAsync(ctx->pin + 1, bg.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[1] == 0) break;

@@ -142,7 +142,8 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream);
+                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream,
+                        const double *rc_lv = nullptr, int nlev = 1, bool kepler = true);
 // Grid-wide union-find of the encounter pairs (large-group mode; the host reads lab back):
 // init (lab = body for the bodies of a pair), hook rounds (changed |= 1 while a round hooks),
 // compress (every member's lab = its root), slots (member_slot for members[0..n), lab = -1).
@@ -193,28 +194,40 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
                             double dt, hipStream_t stream);
 // One attempt of every active group: a fixed sequence of launches that takes its sizes and dt
 // from device memory, so it can be captured once and replayed.
-hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, hipStream_t stream);
+// tile_grid: workgroups of the per-tile launches (they visit the tiles grid-stride).
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream);
 hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, hipStream_t stream);
+// Members of the parent groups of a hierarchical level, laid out as the grid-wide
+// Bulirsch-Stoer lays out its groups: group g holds members [off[g], off[g+1]) (body[f], in an
+// order the host chooses), cut into tiles of 64 (group, first member, count, 0).
+struct LevelTiles {
+    int32_t G = 0, M = 0, n_tiles = 0, cap_M = 0; // sizes (host and kernel arguments)
+    int32_t *off = nullptr, *tfirst = nullptr;   // [G + 1]
+    int4 *tiles = nullptr;                       // [n_tiles]
+    int32_t *body = nullptr, *test = nullptr;    // [M]
+    double *X = nullptr, *Y = nullptr, *Z = nullptr, *mass = nullptr; // [M]
+    double *rc = nullptr;                        // [LEVELS_MAX][cap_M]: radii of levels 0..
+    double *bb = nullptr;                        // [n_tiles][8] tile boxes of X, Y, Z
+    double *cut2 = nullptr;                      // [G] largest level-(l-1) radius^2 of the group
+};
+
 // Kick of level `level` (1 <= level < nlev) over the members of the parent groups:
 // v += tau * sum over the member's group of m_j W_l K_l (r_j - r_i) / r^3 (FP64), and with
-// emit the pairs of a group closer than the level's radius (i < j) into pairs / pair_count.
+// emit the pairs of a group closer than the level's radius (body i < body j) into pairs.
 struct LevelKickArgs {
-    int32_t n_mem = 0;             // members of all parent groups
-    const int32_t *mem = nullptr;  // [n_mem] body of each member, groups contiguous, ascending
-    const int32_t *mgrp = nullptr; // [n_mem] group of each member
-    const int32_t *gs = nullptr;   // [n_groups + 1] group g = mem[gs[g] .. gs[g+1])
-    const int32_t *sys_of = nullptr, *sys_off = nullptr, *n_massive = nullptr;
-    const double *x = nullptr, *y = nullptr, *z = nullptr, *m = nullptr;
     double *vx = nullptr, *vy = nullptr, *vz = nullptr;
-    const double *rc0 = nullptr;   // [n_total] level 0 (the bodies' r_crit)
-    const double *rcl = nullptr;   // [nlev - 1][n_total] levels 1..nlev-1
-    int32_t n_total = 0, level = 1, emit = 0;
+    int32_t level = 1, emit = 0;
     double tau = 0.0;
     int32_t *pairs = nullptr, *pair_count = nullptr, *flags = nullptr;
     int32_t pair_cap = 0;
 };
-hipError_t launch_level_kick(const LevelKickArgs &a, hipStream_t stream);
+// Constants of the members (mass, TP2 flag, radii of levels 0..level) and each group's cut-off.
+hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const double *m, const double *rc0,
+                                    const double *rcl, int level, hipStream_t stream);
+// Gather the members' positions and tile boxes, then kick.
+hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
+                             const double *z, hipStream_t stream);
 // Kepler drift over dt of the bodies list[0..n-1].
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,

@@ -80,4 +80,30 @@ struct LagrangeTable {
 };
 __constant__ constexpr LagrangeTable LAGRANGE{};
 
+// Minimum / maximum over the 64 lanes of a wave.
+__device__ __forceinline__ double wave_minv(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_maxv(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Bounding box of the positions held by the lanes with v = true, into
+// out[t * 8 + 0..5] = (min x, y, z, max x, y, z).  Every lane of the wave calls it.
+__device__ __forceinline__ void tile_box(bool v, double x, double y, double z, double *out, int t)
+{
+    const int lane = threadIdx.x & 63;
+    const double lo[3] = {wave_minv(v ? x : INFINITY), wave_minv(v ? y : INFINITY), wave_minv(v ? z : INFINITY)};
+    const double hi[3] = {wave_maxv(v ? x : -INFINITY), wave_maxv(v ? y : -INFINITY), wave_maxv(v ? z : -INFINITY)};
+    if (lane < 3) {
+        out[t * 8 + lane] = lo[lane];
+        out[t * 8 + 3 + lane] = hi[lane];
+    }
+}
+
+
 } // namespace genga
