@@ -193,11 +193,15 @@ def batched(torch, stream, steps=10, warmup=2):
             "speedup_vs_loop": t_loop / t, "status": status, **drift_stats(e_init, e_rec)}
 
 
+_D40K = ("dense annulus N=40322, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
+         "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 13")
+# name: (workload, disc, (symplectic levels, sub-steps per level))
 DENSE_WORKLOADS = {
     "dense": ("dense annulus N=6600, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
-              "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11", discs.disc_dense),
-    "dense_40k": ("dense annulus N=40322, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
-                  "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 13", discs.disc_dense_40k),
+              "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11", discs.disc_dense, (1, 1)),
+    "dense_40k": (_D40K, discs.disc_dense_40k, (1, 1)),
+    "dense_40k_levels": (_D40K + "; 4 hierarchical levels of 2 sub-steps, level k's r_crit from eq. (1) "
+                         "with dt / 2^k", discs.disc_dense_40k, (4, 2)),
 }
 
 
@@ -209,7 +213,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     40322-body disc of the paper's high-resolution run."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
-    label, make = DENSE_WORKLOADS[which]
+    label, make, (nlev, nsub) = DENSE_WORKLOADS[which]
     d = make()
     st, off, mstar = discs.concat([d])
     cap = 64 * d.n
@@ -220,6 +224,12 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     rc = torch.zeros_like(b.x)
     genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS, rc)
     b.rcrit = rc
+    if nlev > 1:
+        # level k's critical radius: eq. (1) with the level's step dt / nsub^k
+        rcl = torch.zeros((nlev - 1, d.n), dtype=torch.float64, device="cuda:0")
+        for k in range(1, nlev):
+            genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS / nsub ** k, rcl[k - 1])
+        genga.genga_set_levels(ctx.handle, nlev, nsub, rcl)
     genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
     # group sizes of the initial state, from the GPU's encounter list
     genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32)
@@ -250,7 +260,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
     E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
     ctx.close()
-    return {"workload": label, "n": d.n,
+    return {"workload": label, "n": d.n, "levels": [nlev, nsub],
             "encounter_pairs_at_start": npair, "largest_group_at_start": int(sizes.max()),
             "groups_above_64_at_start": int((sizes > 64).sum()),
             "steps": steps, "warmup": warmup, "steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps,

@@ -293,7 +293,8 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
 }
 
 int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, const std::vector<int32_t> &gs,
-                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb);
+                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb,
+                   const std::vector<int32_t> *prev = nullptr);
 int build_groups_large(genga_ctx *ctx, hipStream_t s);
 int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
 
@@ -495,17 +496,28 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
-// The groups of gs / mem with at least min_nb members, each ordered by ring (equal-width bands
-// of distance to the star, as many as make a tile of 64 members about as wide as long) and then
-// by azimuth, so that 64 consecutive members are close together and force tiles can skip
-// distant tiles; cut into tiles of 64.
+// The groups of gs / mem with at least min_nb members, each ordered so that 64 consecutive
+// members are close together and force tiles can skip distant tiles; cut into tiles of 64.
+// Without prev: by ring (equal-width bands of distance to the star, as many as make a tile of
+// 64 members about as wide as long), then by azimuth.  With prev (an order of bodies that
+// contains every member, e.g. the parent level's): in that order, which keeps its locality.
 struct TileOrder {
     std::vector<int32_t> k0, off{0}, tfirst{0}, body;
     std::vector<int4> tiles;
 };
 
+// a monotone stand-in for atan2(y, x) on [0, 4)
+static inline double pseudo_angle(double x, double y)
+{
+    const double s = std::fabs(x) + std::fabs(y);
+    if (!(s > 0.0)) return 0.0;
+    const double t = y / s; // in [-1, 1]
+    return x >= 0.0 ? (y >= 0.0 ? t : 4.0 + t) : 2.0 - t;
+}
+
 int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vector<int32_t> &gs,
-                const std::vector<int32_t> &mem, int min_nb, TileOrder &o)
+                const std::vector<int32_t> &mem, int min_nb, TileOrder &o,
+                const std::vector<int32_t> *prev = nullptr)
 {
     const int ng = (int)gs.size() - 1;
     for (int g = 0; g < ng; ++g) {
@@ -522,18 +534,30 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
             return fail(GENGA_ERR_CAPACITY, "an encounter group of more than %d bodies", 64 * BIG_TILES_PER_GROUP);
     if (o.k0.empty()) return GENGA_OK;
     const size_t nt = (size_t)ctx->L.n_total;
+    o.body.resize((size_t)o.off.back());
+    if (prev) {
+        std::vector<int32_t> grp(nt, -1), fill(o.k0.size());
+        for (size_t gi = 0; gi < o.k0.size(); ++gi) {
+            for (int l = 0; l < o.off[gi + 1] - o.off[gi]; ++l) grp[mem[o.k0[gi] + l]] = (int32_t)gi;
+            fill[gi] = o.off[gi];
+        }
+        for (int32_t bi : *prev)
+            if (grp[bi] >= 0) o.body[fill[grp[bi]]++] = bi;
+        for (size_t gi = 0; gi < o.k0.size(); ++gi)
+            if (fill[gi] != o.off[gi + 1]) return fail(GENGA_ERR_STATE, "tile order misses group members");
+        return GENGA_OK;
+    }
     std::vector<double> hx(nt), hy(nt);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
-    o.body.resize((size_t)o.off.back());
-    std::vector<std::pair<double, int32_t>> key;
+    std::vector<uint64_t> key;
     for (size_t gi = 0; gi < o.k0.size(); ++gi) {
         const int nb = o.off[gi + 1] - o.off[gi];
         double r0 = INFINITY, r1 = 0.0, rs = 0.0;
         for (int l = 0; l < nb; ++l) {
             const int32_t bi = mem[o.k0[gi] + l];
-            const double r = std::hypot(hx[bi], hy[bi]);
+            const double r = std::sqrt(hx[bi] * hx[bi] + hy[bi] * hy[bi]);
             r0 = std::min(r0, r);
             r1 = std::max(r1, r);
             rs += r;
@@ -543,12 +567,15 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
         key.resize(nb);
         for (int l = 0; l < nb; ++l) {
             const int32_t bi = mem[o.k0[gi] + l];
-            const double r = std::hypot(hx[bi], hy[bi]);
+            const double r = std::sqrt(hx[bi] * hx[bi] + hy[bi] * hy[bi]);
             const int ring = std::min(rings - 1, (int)((r - r0) / width * rings));
-            key[l] = {ring * 8.0 + std::atan2(hy[bi], hx[bi]), bi};
+            // (ring, azimuth) quantised into the high 32 bits, the body in the low ones
+            const double u = (ring + 0.25 * pseudo_angle(hx[bi], hy[bi])) / rings; // [0, 1]
+            const uint64_t q = (uint64_t)std::min(4294967295.0, std::max(0.0, u * 4294967295.0));
+            key[l] = q << 32 | (uint32_t)bi;
         }
         std::sort(key.begin(), key.end());
-        for (int l = 0; l < nb; ++l) o.body[o.off[gi] + l] = key[l].second;
+        for (int l = 0; l < nb; ++l) o.body[o.off[gi] + l] = (int32_t)(key[l] & 0xffffffffu);
     }
     return GENGA_OK;
 }
@@ -587,14 +614,15 @@ int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const LevelTiles &T, 
 }
 
 int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int32_t> &pgs,
-              const std::vector<int32_t> &pmem, double tau, hipStream_t s)
+              const std::vector<int32_t> &pmem, double tau, hipStream_t s,
+              const std::vector<int32_t> *prev = nullptr)
 {
     const int ng = (int)pgs.size() - 1;
     if (ng <= 0) return GENGA_OK;
     // the parent groups (level - 1) in tiles, fixed over the level's interval
     LevelTiles &T = ctx->lt[level - 1];
     TileOrder o;
-    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o);
+    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o, prev);
     if (rc) return rc;
     if ((int)o.k0.size() > ctx->lt_cap_G || o.off.back() > T.cap_M || (int)o.tiles.size() > ctx->lt_cap_T)
         return fail(GENGA_ERR_STATE, "level layout exceeds its allocation");
@@ -634,8 +662,8 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
                 HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
                                      ctx->lv_gs, ctx->lv_ng, ctx->member_slot, ctx->flags, 1, ncg, s, ctx->rc_lv,
                                      ctx->n_levels, false));
-                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, ctx->lv_mem, CE_MAX_GROUP + 1))) return rc;
-            } else if ((rc = run_level(ctx, b, level + 1, cgs, cmem, h, s))) {
+                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, ctx->lv_mem, CE_MAX_GROUP + 1, &o.body))) return rc;
+            } else if ((rc = run_level(ctx, b, level + 1, cgs, cmem, h, s, &o.body))) {
                 return rc;
             }
         }
@@ -653,12 +681,13 @@ int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
 // Grid-wide Bulirsch-Stoer over dt for the groups gs / mem (host copies; members_dev the
 // device copy of mem) of at least min_nb members.
 int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, const std::vector<int32_t> &gs,
-                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb)
+                   const std::vector<int32_t> &mem_h, const int32_t *members_dev, int min_nb,
+                   const std::vector<int32_t> *prev)
 {
     BigBs &bg = ctx->big;
     bg.G = bg.M = bg.n_tiles = 0;
     TileOrder o;
-    int rc = order_tiles(ctx, b, s, gs, mem_h, min_nb, o);
+    int rc = order_tiles(ctx, b, s, gs, mem_h, min_nb, o, prev);
     if (rc) return rc;
     if (o.k0.empty()) return GENGA_OK;
     if ((int)o.k0.size() > bg.cap_G || o.off.back() > bg.cap_M || (int)o.tiles.size() > bg.cap_T)
