@@ -122,6 +122,19 @@ int genga_set_large_groups(genga_ctx *ctx, int32_t enable);
  * may be NULL when n_levels = 1. */
 int genga_set_levels(genga_ctx *ctx, int32_t n_levels, int32_t n_sub, const double *rcrit_levels);
 
+/* Self-tuning of the hierarchical levels (Sect. 1: before a run GENGA tries configurations of
+ * levels and sub-steps and keeps the fastest).  Tries 1 level, and n_levels = 2..max_levels
+ * (<= 4) with n_sub = 2..max_sub (<= 64): for each, level k's radii are eq. (1) with n1, n2
+ * and the step dt / n_sub^k from the bodies' current state (b->rcrit stays level 0's), and
+ * trial_steps (>= 1) steps of genga_step in precision prec are timed from that state, which is
+ * restored afterwards (bit for bit).  A configuration that raises a device condition or a
+ * capacity error is not a candidate.  The fastest is set as by genga_set_levels and written to
+ * *levels_out / *sub_out (host).  Needs genga_set_large_groups on; allocates and frees about
+ * 72 B per body of device memory; synchronises the device. */
+int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, double n2, int32_t max_levels,
+                      int32_t max_sub, int32_t trial_steps, int prec, int32_t *levels_out, int32_t *sub_out,
+                      void *stream);
+
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
  * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).

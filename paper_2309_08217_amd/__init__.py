@@ -33,7 +33,7 @@ GENGA_KICK_FP32 = 1
 # every entry point of include/genga.h
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
-    "genga_set_levels",
+    "genga_set_levels", "genga_tune_levels",
     "genga_rcrit", "genga_accel",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
@@ -72,6 +72,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_set_test_bodies": [vp, ctypes.POINTER(i32)],
         "genga_set_large_groups": [vp, i32],
         "genga_set_levels": [vp, i32, i32, vp],
+        "genga_tune_levels": [vp, bp, dbl, dbl, dbl, i32, i32, i32, ctypes.c_int, ctypes.POINTER(i32),
+                              ctypes.POINTER(i32), vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
         "genga_accel": [vp, bp, ctypes.c_int, vp, vp, vp, vp],
         "genga_kick": [vp, bp, dbl, ctypes.c_int, vp],
@@ -197,6 +199,17 @@ def genga_set_levels(ctx: int, n_levels: int, n_sub: int, rcrit_levels=None) -> 
         assert rcrit_levels.is_cuda and rcrit_levels.dtype.is_floating_point and rcrit_levels.is_contiguous()
         ptr = rcrit_levels.data_ptr()
     _check(load_library().genga_set_levels(ctx, int(n_levels), int(n_sub), ptr))
+
+
+def genga_tune_levels(ctx: int, b: Bodies, dt: float, n1: float, n2: float, max_levels: int, max_sub: int,
+                      trial_steps: int, prec: int, stream=None):
+    """Try the level configurations, keep the fastest; returns (n_levels, n_sub)."""
+    cb = b.c()
+    lv, sub = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load_library().genga_tune_levels(ctx, ctypes.byref(cb), float(dt), float(n1), float(n2), int(max_levels),
+                                            int(max_sub), int(trial_steps), int(prec), ctypes.byref(lv),
+                                            ctypes.byref(sub), _stream(stream)))
+    return lv.value, sub.value
 
 
 def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:

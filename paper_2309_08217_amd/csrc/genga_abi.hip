@@ -1,6 +1,7 @@
 // C ABI of the kick library: argument checks, the context (layout, scratch, launch plan,
 // deferred device status), the step sequence and HIP graph capture.  Host code.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -969,6 +970,101 @@ int genga_set_levels(genga_ctx *ctx, int32_t n_levels, int32_t n_sub, const doub
     if (n_levels > 1 && nt)
         HIP_TRY(hipMemcpy(ctx->rc_lv, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipDeviceSynchronize());
+    return GENGA_OK;
+}
+
+int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, double n2, int32_t max_levels,
+                      int32_t max_sub, int32_t trial_steps, int prec, int32_t *levels_out, int32_t *sub_out,
+                      void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if (max_levels < 1 || max_levels > LEVELS_MAX) return fail(GENGA_ERR_ARG, "max_levels must be in 1..%d", LEVELS_MAX);
+    if (max_levels > 1 && (max_sub < 2 || max_sub > 64)) return fail(GENGA_ERR_ARG, "max_sub must be in 2..64");
+    if (trial_steps < 1) return fail(GENGA_ERR_ARG, "trial_steps must be >= 1");
+    if (!levels_out || !sub_out) return fail(GENGA_ERR_ARG, "null output");
+    if (!(n1 >= 0.0) || !(n2 >= 0.0) || !(dt > 0.0)) return fail(GENGA_ERR_ARG, "n1, n2 >= 0 and dt > 0 required");
+    if (!ctx->large_groups) return fail(GENGA_ERR_STATE, "levels need the large-group mode (genga_set_large_groups)");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)ctx->L.n_total;
+    double *save = nullptr, *rcl = nullptr;
+    HIP_TRY(dalloc(save, 6 * std::max<size_t>(n, 1)));
+    if (dalloc(rcl, (LEVELS_MAX - 1) * std::max<size_t>(n, 1)) != hipSuccess) {
+        dfree(save);
+        return fail(GENGA_ERR_HIP, "allocation of the tuning buffers failed");
+    }
+    double *st[6] = {b->x, b->y, b->z, b->vx, b->vy, b->vz};
+    auto copy_state = [&](bool to_save) -> hipError_t {
+        for (int q = 0; q < 6; ++q) {
+            const hipError_t e = hipMemcpyAsync(to_save ? save + q * n : st[q], to_save ? st[q] : save + q * n,
+                                                n * sizeof(double), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipStreamSynchronize(s);
+    };
+    // the level radii of a configuration: eq. (1) with the level's step dt / n_sub^k
+    auto set_config = [&](int nl, int ns) -> int {
+        for (int k = 1; k < nl; ++k) {
+            const hipError_t e = launch_rcrit(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, n1, n2,
+                                              dt / std::pow((double)ns, k), rcl + (size_t)(k - 1) * n, s);
+            if (e != hipSuccess) return fail(GENGA_ERR_HIP, "r_crit of the levels: %s", hipGetErrorString(e));
+        }
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return fail(GENGA_ERR_HIP, "%s", hipGetErrorString(e));
+        return genga_set_levels(ctx, nl, ns, nl > 1 ? rcl : nullptr);
+    };
+    int best_l = 1, best_s = 1;
+    double best_t = INFINITY;
+    hipError_t he = copy_state(true);
+    rc = he == hipSuccess ? GENGA_OK : fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+    for (int nl = 1; nl <= max_levels && !rc; ++nl)
+        for (int ns = nl == 1 ? 1 : 2; ns <= (nl == 1 ? 1 : max_sub) && !rc; ++ns) {
+            // radii from the starting state; the trial runs from it too
+            if ((he = copy_state(false)) != hipSuccess) {
+                rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+                break;
+            }
+            if ((rc = set_config(nl, ns))) break;
+            if ((he = hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), s)) != hipSuccess) {
+                rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+                break;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const int r = enqueue_step(ctx, b, dt, trial_steps, prec, 0, nullptr, s);
+            if ((he = hipStreamSynchronize(s)) != hipSuccess) {
+                rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+                break;
+            }
+            const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            int32_t flags = 0;
+            if ((he = hipMemcpy(&flags, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess) {
+                rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+                break;
+            }
+            if (r == GENGA_ERR_CAPACITY) continue; // this configuration does not fit: not a candidate
+            if (r) {
+                rc = r;
+                break;
+            }
+            if (flags == 0 && t < best_t) {
+                best_t = t;
+                best_l = nl;
+                best_s = ns;
+            }
+        }
+    // back to the starting state, with the fastest configuration that ran clean
+    if (!rc && (he = copy_state(false)) != hipSuccess) rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+    if (!rc) rc = set_config(best_l, best_s);
+    if (!rc && ((he = hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), s)) != hipSuccess ||
+                (he = hipStreamSynchronize(s)) != hipSuccess))
+        rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+    dfree(save);
+    dfree(rcl);
+    if (rc) return rc;
+    if (!(best_t < INFINITY)) return fail(GENGA_ERR_NOCONVERGE, "no configuration ran without a device condition");
+    *levels_out = best_l;
+    *sub_out = best_s;
     return GENGA_OK;
 }
 

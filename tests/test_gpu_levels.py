@@ -128,3 +128,37 @@ def test_set_levels_argument_and_state_checks():
         genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream)
     assert e.value.status == genga.GENGA_ERR_STATE
     s.close()
+
+
+def test_tune_levels_keeps_the_state_and_sets_the_fastest():
+    """Self-tuning (Sect. 1): every configuration up to 3 levels x 3 sub-steps is tried from
+    the current state; the state comes back bit for bit and the chosen configuration is then
+    the one genga_drift uses (checked against the oracle's drift_levels)."""
+    d = discs.ring_dense(1000)
+    s, rc0 = level_system(d, 1, 1)
+    b0 = s.numpy_state()
+    nl, ns = genga.genga_tune_levels(s.ctx.handle, s.b, DT5, discs.DENSE_N1, discs.DENSE_N2, 3, 3, 2, FP64)
+    print(f"[tune] chose {nl} levels x {ns} sub-steps", flush=True)
+    assert 1 <= nl <= 3 and (ns == 1 if nl == 1 else 2 <= ns <= 3)
+    after = s.numpy_state()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(after[k], b0[k])
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK
+    rcl = oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, nl, max(ns, 1))
+    s.accel(FP64)
+    pairs, _ = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    exp = oracle.drift_levels(b0, rcl, max(ns, 1), 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    compare(f"tuned {nl}x{ns}", got, exp, gid)
+    for bad in ((0, 3, 2), (5, 3, 2), (3, 1, 2), (3, 3, 0)):
+        with pytest.raises(genga.GengaError) as e:
+            genga.genga_tune_levels(s.ctx.handle, s.b, DT5, 3.0, 0.4, *bad, FP64)
+        assert e.value.status == genga.GENGA_ERR_ARG
+    genga.genga_set_large_groups(s.ctx.handle, False)
+    with pytest.raises(genga.GengaError) as e:
+        genga.genga_tune_levels(s.ctx.handle, s.b, DT5, 3.0, 0.4, 3, 3, 2, FP64)
+    assert e.value.status == genga.GENGA_ERR_STATE
+    s.close()
