@@ -85,6 +85,14 @@ def lib() -> ctypes.CDLL:
         L.oracle_step_levels.restype = ctypes.c_int
         L.oracle_step_levels.argtypes = [i64, i64] + [d] * 8 + [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                                 ctypes.c_double, i64, ctypes.c_double, i64, d]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_collisions.restype = i64
+        L.oracle_collisions.argtypes = [i64, i32p] + [d] * 7 + [i32p, ctypes.c_double, i32p]
+        L.oracle_merge.argtypes = [i64, i32p] + [d] * 8 + [i32p]
+        L.oracle_remove.argtypes = [i64] + [d] * 4 + [i32p, ctypes.c_double, ctypes.c_double]
+        L.oracle_step_collide.restype = ctypes.c_int
+        L.oracle_step_collide.argtypes = [i64, i64] + [d] * 9 + [i32p] + [ctypes.c_double] * 2 + \
+            [i64] + [ctypes.c_double] * 3
         _lib = L
     return _lib
 
@@ -301,3 +309,54 @@ def step_levels(st, rcl: np.ndarray, nsub: int, mstar: float, dt: float, nsteps:
     if bad:
         raise RuntimeError("oracle step failed")
     return s, e
+
+
+# -------------------------------------------------------------------------------------------
+# Collisions and removal (Sect. 2: perfect mergers; removal inside r_min / beyond r_max).  The
+# reading is stated in oracle.c.  status: 0 live, 1 merged into another body, 2 removed.
+# -------------------------------------------------------------------------------------------
+
+def collisions(st, pairs: np.ndarray, radius, status, dt: float) -> np.ndarray:
+    """Encounter pairs whose straight-line relative motion over dt comes within R_i + R_j."""
+    p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros((max(len(p), 1), 2), dtype=np.int32)
+    stt = np.ascontiguousarray(status, dtype=np.int32)
+    a = [_f64(st[k]) for k in ("x", "y", "z", "vx", "vy", "vz")]
+    nc = lib().oracle_collisions(len(p), _p(p, ctypes.c_int32), *[_p(v) for v in a], _p(_f64(radius)),
+                                 _p(stt, ctypes.c_int32), float(dt), _p(out, ctypes.c_int32))
+    return out[:nc].copy()
+
+
+def merge(st, col: np.ndarray, radius, status):
+    """Perfect mergers of the colliding pairs in order; returns (state, radius, status)."""
+    s = _mut(st)
+    rad = np.array(radius, dtype=np.float64)
+    stt = np.array(status, dtype=np.int32)
+    c = np.ascontiguousarray(col, dtype=np.int32).reshape(-1, 2)
+    lib().oracle_merge(len(c), _p(c, ctypes.c_int32), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
+                       _p(rad), _p(stt, ctypes.c_int32))
+    return s, rad, stt
+
+
+def remove(st, status, r_min: float, r_max: float):
+    """Removal by distance to the star; returns (state, status)."""
+    s = _mut(st)
+    stt = np.array(status, dtype=np.int32)
+    lib().oracle_remove(len(s["x"]), *[_p(s[k]) for k in ("x", "y", "z", "m")], _p(stt, ctypes.c_int32),
+                        float(r_min), float(r_max))
+    return s, stt
+
+
+def step_collide(st, rc, radius, status, mstar: float, dt: float, nsteps: int, r_min: float, r_max: float,
+                 tol: float = BS_TOL, n_massive: Optional[int] = None):
+    """nsteps full steps with collisions and removal; returns (state, radius, status)."""
+    s = _mut(st)
+    n = len(s["x"])
+    rad = np.array(radius, dtype=np.float64)
+    stt = np.array(status, dtype=np.int32)
+    bad = lib().oracle_step_collide(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
+                                    _p(_f64(rc)), _p(rad), _p(stt, ctypes.c_int32), float(mstar), float(dt),
+                                    int(nsteps), float(tol), float(r_min), float(r_max))
+    if bad:
+        raise RuntimeError("oracle step failed")
+    return s, rad, stt

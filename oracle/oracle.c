@@ -692,6 +692,84 @@ int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double 
     return oracle_drift_levels(n, nm, x, y, z, vx, vy, vz, m, rc, 1, 1, mstar, dt, npairs, pairs, tol);
 }
 
+/* ------------------------------------------------------------------------------------
+ * Collisions and removal (Sect. 2: collisions are taken as perfect mergers; bodies are
+ * removed when they come closer to the star than r_min or farther than r_max).  The paper
+ * gives no detection scheme; the reading taken here:
+ *  - only encounter pairs can collide within a step; at the start of the drift, a pair (i, j)
+ *    of two live bodies collides if the straight-line relative motion brings it within
+ *    R_i + R_j during the drift: t* = clamp(-(dr . dv) / |dv|^2, 0, dt), and
+ *    |dr + t* dv|^2 < (R_i + R_j)^2;
+ *  - after the drift the colliding pairs merge in ascending (i, j) order, skipping a pair with
+ *    a body already merged in this step: body i keeps m_i + m_j, the mass-weighted position
+ *    and velocity (momentum is kept) and radius (R_i^3 + R_j^3)^(1/3); body j gets m = 0 and
+ *    status 1;
+ *  - then every live body with |r| < r_min or |r| > r_max gets m = 0 and status 2.
+ * status: 0 live, 1 merged into another body, 2 removed by distance.
+ * ---------------------------------------------------------------------------------- */
+int64_t oracle_collisions(int64_t npairs, const int32_t *pairs, const double *x, const double *y,
+                          const double *z, const double *vx, const double *vy, const double *vz,
+                          const double *radius, const int32_t *status, double dt, int32_t *out)
+{
+    int64_t nc = 0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        if (status[i] || status[j]) continue;
+        double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+        double ux = vx[j] - vx[i], uy = vy[j] - vy[i], uz = vz[j] - vz[i];
+        double uu = sep2(ux, uy, uz);
+        double t = 0.0;
+        if (uu > 0.0) {
+            t = -((dx * ux + dy * uy) + dz * uz) / uu;
+            if (t < 0.0) t = 0.0;
+            if (t > dt) t = dt;
+        }
+        double ex = dx + t * ux, ey = dy + t * uy, ez = dz + t * uz;
+        double rs = radius[i] + radius[j];
+        if (sep2(ex, ey, ez) < rs * rs) {
+            out[2 * nc] = i;
+            out[2 * nc + 1] = j;
+            ++nc;
+        }
+    }
+    return nc;
+}
+
+void oracle_merge(int64_t ncol, const int32_t *col, double *x, double *y, double *z, double *vx,
+                  double *vy, double *vz, double *m, double *radius, int32_t *status)
+{
+    for (int64_t c = 0; c < ncol; ++c) {
+        int32_t i = col[2 * c], j = col[2 * c + 1];
+        if (status[i] || status[j]) continue;
+        double mi = m[i], mj = m[j], mt = mi + mj;
+        if (mt > 0.0) {
+            x[i] = (mi * x[i] + mj * x[j]) / mt;
+            y[i] = (mi * y[i] + mj * y[j]) / mt;
+            z[i] = (mi * z[i] + mj * z[j]) / mt;
+            vx[i] = (mi * vx[i] + mj * vx[j]) / mt;
+            vy[i] = (mi * vy[i] + mj * vy[j]) / mt;
+            vz[i] = (mi * vz[i] + mj * vz[j]) / mt;
+        }
+        m[i] = mt;
+        radius[i] = cbrt(radius[i] * radius[i] * radius[i] + radius[j] * radius[j] * radius[j]);
+        m[j] = 0.0;
+        status[j] = 1;
+    }
+}
+
+void oracle_remove(int64_t n, const double *x, const double *y, const double *z, double *m,
+                   int32_t *status, double r_min, double r_max)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (status[i]) continue;
+        double r2 = sep2(x[i], y[i], z[i]);
+        if (r2 < r_min * r_min || r2 > r_max * r_max) {
+            m[i] = 0.0;
+            status[i] = 2;
+        }
+    }
+}
+
 /* v += tau * a_K */
 static void kick(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
                  double *vx, double *vy, double *vz, const double *m, const double *rc, double tau,
@@ -750,4 +828,40 @@ int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *
                 int64_t nsteps, double tol, int64_t cadence, double *energy)
 {
     return oracle_step_levels(n, nm, x, y, z, vx, vy, vz, m, rc, 1, 1, mstar, dt, nsteps, tol, cadence, energy);
+}
+
+/* Full steps with collisions and removal: as oracle_step (one level), with the colliding
+ * pairs found at the start of each drift (from the encounter list of the first half-kick)
+ * and merged after it, then removal by distance.  m, radius and status are updated. */
+int oracle_step_collide(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
+                        double *vz, double *m, const double *rc, double *radius, int32_t *status,
+                        double mstar, double dt, int64_t nsteps, double tol, double r_min, double r_max)
+{
+    double *ax = (double *)malloc(sizeof(double) * (size_t)(3 * (n > 0 ? n : 1)));
+    double *ay = ax + n, *az = ay + n;
+    int64_t cap = 16 * n + 16;
+    int32_t *pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
+    int32_t *col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
+    int bad = 0;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
+        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
+        if (np > cap) {
+            free(pairs);
+            free(col);
+            cap = np;
+            pairs = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
+            col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
+            np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
+        }
+        int64_t nc = oracle_collisions(np, pairs, x, y, z, vx, vy, vz, radius, status, dt, col);
+        bad |= oracle_drift(n, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, np, pairs, tol);
+        oracle_merge(nc, col, x, y, z, vx, vy, vz, m, radius, status);
+        oracle_remove(n, x, y, z, m, status, r_min, r_max);
+        kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);
+    }
+    free(col);
+    free(pairs);
+    free(ax);
+    return bad;
 }

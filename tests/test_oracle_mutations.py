@@ -61,6 +61,13 @@ MUTATIONS = [
     ("level members left undrifted", "if (gid[idx[a]] < 0)\n                bad |= kepler_one",
      "if (gid[idx[a]] < -1)\n                bad |= kepler_one"),
     ("level kick target mass", "double s = m[j] * w / (r2 * r);", "double s = m[i] * w / (r2 * r);"),
+    ("collision closest approach unclamped", "            if (t > dt) t = dt;\n", ""),
+    ("collision radius sum", "double rs = radius[i] + radius[j];", "double rs = radius[i];"),
+    ("merge velocity weights swapped", "vx[i] = (mi * vx[i] + mj * vx[j]) / mt;", "vx[i] = (mj * vx[i] + mi * vx[j]) / mt;"),
+    ("merge radius adds radii", "radius[i] = cbrt(radius[i] * radius[i] * radius[i] + radius[j] * radius[j] * radius[j]);",
+     "radius[i] = radius[i] + radius[j];"),
+    ("removal inner radius unsquared", "if (r2 < r_min * r_min || r2 > r_max * r_max) {", "if (r2 < r_min || r2 > r_max * r_max) {"),
+    ("merge of an already merged body", "        if (status[i] || status[j]) continue;\n        double mi = m[i]", "        double mi = m[i]"),
     ("encounter self pairs", "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i + 1;",
      "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i;"),
 ]
@@ -69,10 +76,17 @@ MUTATIONS = [
 PIN_FILES = {"pins": "test_oracle_pins.py", "levels": "test_oracle_levels.py"}
 
 
+PIN_FILES["collisions"] = "test_oracle_collisions.py"
+
+
 def pin_file(name):
-    """Mistakes in the level code are run against the level pins, the others against the
-    main pin suite."""
-    return PIN_FILES["levels" if name.startswith(("level", "deepest")) else "pins"]
+    """Mistakes in the level code are run against the level pins, those in the collision code
+    against the collision pins, the others against the main pin suite."""
+    if name.startswith(("level", "deepest")):
+        return PIN_FILES["levels"]
+    if name.startswith(("collision", "merge", "removal")):
+        return PIN_FILES["collisions"]
+    return PIN_FILES["pins"]
 
 
 @pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
