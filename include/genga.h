@@ -135,6 +135,31 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
                       int32_t max_sub, int32_t trial_steps, int prec, int32_t *levels_out, int32_t *sub_out,
                       void *stream);
 
+/* Collisions and removal (Sect. 2: collisions are perfect mergers; bodies are removed when
+ * they come closer to the star than r_min or farther than r_max).  mass is the device array
+ * passed as the bodies' m (the library then writes it: const in genga_bodies notwithstanding);
+ * radius (physical radii, au) and status (int32: 0 live, 1 merged into another body, 2 removed
+ * by distance) are caller-owned device arrays of n_total entries, written by genga_drift /
+ * genga_step.  At the start of each drift, an encounter pair of two live bodies collides when
+ * its straight-line relative motion over dt comes within R_i + R_j; after the drift the
+ * colliding pairs merge in ascending (i, j) order, a pair with an already merged body skipped:
+ * body i keeps m_i + m_j, the mass-weighted position and velocity and radius
+ * (R_i^3 + R_j^3)^(1/3); body j gets m = 0 and status 1.  Then live bodies outside
+ * [r_min, r_max] get m = 0 and status 2.  Bodies with m = 0 stay in the arrays (they exert no
+ * force) until genga_compact.  At most 4096 colliding pairs per drift (more raise
+ * GENGA_ERR_CAPACITY).  mass = NULL turns collisions off.  0 <= r_min < r_max.  The launches
+ * stay capturable; refused (GENGA_ERR_STATE) while a captured graph exists.  Synchronises. */
+int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *status, double r_min,
+                         double r_max);
+
+/* Remove the bodies with status != 0: the bodies' arrays (x..vz, m, rcrit; the library writes
+ * them), radius (may be NULL) and status are compacted in place, keeping the order of the
+ * survivors, and the context takes the new layout (as genga_set_systems with the same central
+ * masses and pair capacity; large groups and collisions stay on, TP2 counts follow the removed
+ * massive bodies, hierarchical levels start again at 1).  Writes the new n_total to
+ * *n_total_out (host).  Synchronises the device. */
+int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *status, int32_t *n_total_out);
+
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
  * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).

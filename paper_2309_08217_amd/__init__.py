@@ -33,7 +33,7 @@ GENGA_KICK_FP32 = 1
 # every entry point of include/genga.h
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
-    "genga_set_levels", "genga_tune_levels",
+    "genga_set_levels", "genga_tune_levels", "genga_set_collisions", "genga_compact",
     "genga_rcrit", "genga_accel",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
@@ -72,6 +72,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_set_test_bodies": [vp, ctypes.POINTER(i32)],
         "genga_set_large_groups": [vp, i32],
         "genga_set_levels": [vp, i32, i32, vp],
+        "genga_set_collisions": [vp, vp, vp, vp, dbl, dbl],
+        "genga_compact": [vp, bp, vp, vp, ctypes.POINTER(i32)],
         "genga_tune_levels": [vp, bp, dbl, dbl, dbl, i32, i32, i32, ctypes.c_int, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
@@ -210,6 +212,25 @@ def genga_tune_levels(ctx: int, b: Bodies, dt: float, n1: float, n2: float, max_
                                             int(max_sub), int(trial_steps), int(prec), ctypes.byref(lv),
                                             ctypes.byref(sub), _stream(stream)))
     return lv.value, sub.value
+
+
+def genga_set_collisions(ctx: int, b: Bodies, radius, status, r_min: float, r_max: float) -> None:
+    """Perfect mergers and removal by distance on b's masses; radius (float64) and status
+    (int32) device tensors of n_total entries.  b = None turns collisions off."""
+    if b is None:
+        _check(load_library().genga_set_collisions(ctx, None, None, None, 0.0, 0.0))
+        return
+    _check(load_library().genga_set_collisions(ctx, _ptr(b.m), _ptr(radius), _ptr(status), float(r_min),
+                                               float(r_max)))
+
+
+def genga_compact(ctx: int, b: Bodies, radius, status) -> int:
+    """Remove the bodies with status != 0 in place; returns the new n_total (the tensors keep
+    their length, the first n_total entries hold the survivors)."""
+    cb = b.c()
+    n = ctypes.c_int32(0)
+    _check(load_library().genga_compact(ctx, ctypes.byref(cb), _ptr(radius), _ptr(status), ctypes.byref(n)))
+    return n.value
 
 
 def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:

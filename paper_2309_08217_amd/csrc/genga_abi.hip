@@ -101,6 +101,10 @@ struct genga_ctx {
     int32_t lt_cap_G = 0, lt_cap_T = 0;
     int32_t *lv_mem = nullptr, *lv_gs = nullptr, *lv_ng = nullptr; // the deepest level's groups
     int32_t *lv_pairs = nullptr, *lv_count = nullptr, *lv_list = nullptr; // a level's pairs; Kepler list
+    // collisions and removal (opt-in)
+    CollideArgs col;
+    int32_t pair_cap_req = 0;          // pair capacity asked for at genga_set_systems
+    std::vector<double> mstar_h;       // central masses (host copy)
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -198,6 +202,9 @@ struct genga_ctx {
         dfree(member_slot);
         dfree(epartial);
         dfree(kpart);
+        dfree(col.list);
+        dfree(col.count);
+        col = CollideArgs{};
         release_big();
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -306,6 +313,16 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
 {
     const Layout &L = ctx->L;
     if (L.n_total == 0) return GENGA_OK;
+    const bool collide = ctx->col.mass != nullptr;
+    if (collide) {
+        if (b->m != ctx->col.mass)
+            return fail(GENGA_ERR_ARG, "with collisions on, the bodies' m must be the mass array given to "
+                                       "genga_set_collisions");
+        if (defer_shift) return fail(GENGA_ERR_STATE, "collisions need the whole Sun drift inside the drift");
+        // colliding encounter pairs, from the state at the start of the drift
+        HIP_TRY(launch_collide_check(ctx->col, ctx->pairs, ctx->pair_count, ctx->pair_cap, b->x, b->y, b->z, b->vx,
+                                     b->vy, b->vz, dt, s));
+    }
     int bs_blocks = 0; // default: the one-workgroup group builder's maximum
     if (ctx->large_groups) {
         // the groups depend on the pair list only; built first, so that a group too large
@@ -334,6 +351,7 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
         HIP_TRY(launch_momentum(L, b->vx, b->vy, b->vz, b->m, ctx->mom_part, s));
     else
         HIP_TRY(launch_sun_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, 0.5 * dt, ctx->mom_part, s));
+    if (collide) HIP_TRY(launch_collide_resolve(ctx->col, L.n_total, b->x, b->y, b->z, b->vx, b->vy, b->vz, s));
     return GENGA_OK;
 }
 
@@ -759,10 +777,13 @@ int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int pre
     if (rc) return rc;
     int rec = 0;
     for (int k = 1; k <= nsteps; ++k) {
-        rc = enqueue_drift(ctx, b, dt, s, true);
+        // the second half Sun drift is left to the next kick's source pass, except with
+        // collisions, which are resolved on the drifted state
+        const bool defer = ctx->col.mass == nullptr;
+        rc = enqueue_drift(ctx, b, dt, s, defer);
         if (rc) return rc;
         const bool last = k == nsteps;
-        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s, 0.5 * dt);
+        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s, defer ? 0.5 * dt : 0.0);
         if (rc) return rc;
         if (cadence > 0 && d_energy && k % cadence == 0) {
             rc = enqueue_energy(ctx, b, last ? 0.0 : 0.5 * dt, d_energy + (size_t)rec * 4 * ctx->L.n_sys, s);
@@ -854,6 +875,8 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     const int32_t keep_large = ctx->large_groups;
     ctx->release();
     ctx->sys_off_h.assign(sys_off_host, sys_off_host + n_sys + 1);
+    ctx->mstar_h.assign(mstar_host, mstar_host + n_sys);
+    ctx->pair_cap_req = pair_capacity;
 
     // work items: 64 consecutive bodies of one system
     std::vector<Chunk> chunks;
@@ -1065,6 +1088,91 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
     if (!(best_t < INFINITY)) return fail(GENGA_ERR_NOCONVERGE, "no configuration ran without a device condition");
     *levels_out = best_l;
     *sub_out = best_s;
+    return GENGA_OK;
+}
+
+int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *status, double r_min, double r_max)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipDeviceSynchronize());
+    if (!mass) {
+        dfree(ctx->col.list);
+        dfree(ctx->col.count);
+        ctx->col = CollideArgs{};
+        return GENGA_OK;
+    }
+    if (!radius || !status) return fail(GENGA_ERR_ARG, "null radius or status");
+    if (!(r_min >= 0.0) || !(r_max > r_min)) return fail(GENGA_ERR_ARG, "need 0 <= r_min < r_max");
+    if (ctx->graph_exec) return fail(GENGA_ERR_STATE, "a captured graph exists: capture again after enabling collisions");
+    if (!ctx->col.list) {
+        HIP_TRY(dalloc(ctx->col.list, 2 * (size_t)COLLIDE_CAP));
+        HIP_TRY(dalloc(ctx->col.count, 1));
+        HIP_TRY(hipMemset(ctx->col.count, 0, sizeof(int32_t)));
+    }
+    ctx->col.mass = mass;
+    ctx->col.radius = radius;
+    ctx->col.status = status;
+    ctx->col.flags = ctx->flags;
+    ctx->col.cap = COLLIDE_CAP;
+    ctx->col.r_min = r_min;
+    ctx->col.r_max = r_max;
+    HIP_TRY(hipDeviceSynchronize());
+    return GENGA_OK;
+}
+
+int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *status, int32_t *n_total_out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_bodies(ctx, b, true, true))) return rc;
+    if (!status || !n_total_out) return fail(GENGA_ERR_ARG, "null status or n_total_out");
+    const int n = ctx->L.n_total, n_sys = ctx->L.n_sys;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<int32_t> st(n), idx, off(n_sys + 1, 0), nm(n_sys, 0);
+    if (n) HIP_TRY(hipMemcpy(st.data(), status, n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    bool any_test = false;
+    for (int sy = 0; sy < n_sys; ++sy) {
+        const int b0 = ctx->sys_off_h[sy], b1 = ctx->sys_off_h[sy + 1], nmass = ctx->n_massive_h[sy];
+        any_test |= nmass < b1 - b0;
+        for (int i = b0; i < b1; ++i)
+            if (st[i] == 0) {
+                idx.push_back(i);
+                if (i - b0 < nmass) ++nm[sy];
+            }
+        off[sy + 1] = (int32_t)idx.size();
+    }
+    const int nk = (int)idx.size();
+    if (nk < n) {
+        int32_t *d_idx = nullptr;
+        double *tmp = nullptr;
+        HIP_TRY(dalloc(d_idx, std::max(nk, 1)));
+        if (dalloc(tmp, std::max(nk, 1)) != hipSuccess) {
+            dfree(d_idx);
+            return fail(GENGA_ERR_HIP, "allocation for the compaction failed");
+        }
+        hipError_t e = nk ? hipMemcpy(d_idx, idx.data(), nk * sizeof(int32_t), hipMemcpyHostToDevice) : hipSuccess;
+        double *arr[9] = {b->x, b->y, b->z, b->vx, b->vy, b->vz, const_cast<double *>(b->m),
+                          const_cast<double *>(b->rcrit), radius};
+        for (int a = 0; a < 9 && e == hipSuccess; ++a) {
+            if (!arr[a]) continue;
+            e = launch_gather(d_idx, nk, arr[a], tmp, nullptr);
+            if (e == hipSuccess && nk) e = hipMemcpy(arr[a], tmp, nk * sizeof(double), hipMemcpyDeviceToDevice);
+        }
+        if (e == hipSuccess && nk) e = hipMemset(status, 0, nk * sizeof(int32_t));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        dfree(d_idx);
+        dfree(tmp);
+        if (e != hipSuccess) return fail(GENGA_ERR_HIP, "compaction: %s", hipGetErrorString(e));
+    }
+    // the new layout, with the context's settings carried over (levels start again at 1)
+    const CollideArgs col = ctx->col;
+    const std::vector<double> mstar = ctx->mstar_h;
+    if ((rc = genga_set_systems(ctx, n_sys, off.data(), mstar.data(), ctx->pair_cap_req))) return rc;
+    if (any_test && (rc = genga_set_test_bodies(ctx, nm.data()))) return rc;
+    if (col.mass && (rc = genga_set_collisions(ctx, col.mass, col.radius, col.status, col.r_min, col.r_max)))
+        return rc;
+    *n_total_out = nk;
     return GENGA_OK;
 }
 

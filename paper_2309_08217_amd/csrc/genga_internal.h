@@ -38,6 +38,7 @@ enum DeviceFlag : int32_t {
 
 // Maximum sizes of the close-encounter step (one workgroup builds the groups in LDS).
 constexpr int CE_MAX_MEMBERS = 8192;
+constexpr int COLLIDE_CAP = 4096;          // colliding pairs per drift
 constexpr int CE_MAX_GROUP = 64;
 constexpr int BS_KMAX = 8;
 
@@ -232,6 +233,27 @@ hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const 
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
                               hipStream_t stream);
+
+// Collisions (perfect mergers) and removal by distance: caller-owned mass (the bodies' m),
+// radius and status arrays; a list of the colliding pairs of the current drift.
+struct CollideArgs {
+    double *mass = nullptr, *radius = nullptr;
+    int32_t *status = nullptr;   // 0 live, 1 merged into another body, 2 removed by distance
+    int32_t *list = nullptr, *count = nullptr, *flags = nullptr;
+    int32_t cap = 0;
+    double r_min = 0.0, r_max = 0.0;
+};
+// Colliding encounter pairs at the start of a drift over dt (appended to c.list).
+hipError_t launch_collide_check(const CollideArgs &c, const int32_t *pairs, const int32_t *pair_count,
+                                int32_t pair_cap, const double *x, const double *y, const double *z,
+                                const double *vx, const double *vy, const double *vz, double dt,
+                                hipStream_t stream);
+// After the drift: merge the listed pairs in order (the count is cleared), then removal.
+hipError_t launch_collide_resolve(const CollideArgs &c, int n_total, double *x, double *y, double *z, double *vx,
+                                  double *vy, double *vz, hipStream_t stream);
+
+// dst[k] = src[idx[k]], k < n.
+hipError_t launch_gather(const int32_t *idx, int n, const double *src, double *dst, hipStream_t stream);
 
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,

@@ -1,0 +1,103 @@
+"""Collisions as perfect mergers and removal by distance (Sect. 2) on the GPU against the
+oracle's step_collide, and the compaction of the arrays afterwards.  The ring's radii are
+inflated (2e-3 au) so that a few tens of steps see several mergers."""
+import numpy as np
+import pytest
+
+import discs
+import oracle
+import paper_2309_08217_amd as genga
+from gpu_helpers import System
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = genga.GENGA_KICK_FP64, genga.GENGA_KICK_FP32
+DT5 = discs.DT_5_DAYS
+R = 2e-3
+
+
+def collide_system(d, r_min, r_max):
+    rc = oracle.rcrit(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5)
+    s = System([d], rcrit=rc)
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    torch = s.torch
+    rad = torch.full((d.n,), R, dtype=torch.float64, device="cuda")
+    status = torch.zeros(d.n, dtype=torch.int32, device="cuda")
+    genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, r_min, r_max)
+    return s, rc, rad, status
+
+
+def check_against_oracle(label, s, rad, status, exp, erad, est, bar, n=None):
+    got = s.numpy_state()
+    n = len(est) if n is None else n
+    gst = status.cpu().numpy()[:n]
+    print(f"[{label}] merged {int((est == 1).sum())} removed {int((est == 2).sum())}", flush=True)
+    assert np.array_equal(gst, est)
+    assert np.array_equal(got["m"][:n], exp["m"])
+    assert np.allclose(rad.cpu().numpy()[:n], erad, rtol=4e-16, atol=0)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        err = np.max(np.abs(got[k][:n] - exp[k]))
+        print(f"[{label}] {k} max err {err:.2e}", flush=True)
+        assert err <= bar
+
+
+@pytest.mark.parametrize("prec,bar", [(FP64, 1e-10), (FP32, 1e-8)])
+def test_mergers_against_oracle(prec, bar):
+    d = discs.ring_dense(300)
+    s, rc, rad, status = collide_system(d, 0.0, 1e9)
+    exp, erad, est = oracle.step_collide(d.state(), rc, np.full(d.n, R), np.zeros(d.n, np.int32), 1.0, DT5, 20,
+                                         0.0, 1e9)
+    assert (est == 1).sum() >= 3
+    genga.genga_step(s.ctx.handle, s.b, DT5, 20, prec)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle(f"mergers prec={prec}", s, rad, status, exp, erad, est, bar)
+    s.close()
+
+
+def test_removal_compaction_and_more_steps():
+    """Removal inside 0.82 au and beyond 0.88 au together with mergers over 10 steps; then the
+    arrays are compacted and 5 more steps run on the survivors, against the oracle."""
+    d = discs.ring_dense(300)
+    s, rc, rad, status = collide_system(d, 0.82, 0.88)
+    exp, erad, est = oracle.step_collide(d.state(), rc, np.full(d.n, R), np.zeros(d.n, np.int32), 1.0, DT5, 10,
+                                         0.82, 0.88)
+    assert (est == 2).sum() >= 1
+    genga.genga_step(s.ctx.handle, s.b, DT5, 10, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("removal", s, rad, status, exp, erad, est, 1e-10)
+    before = s.numpy_state()
+    keep = est == 0
+    n_new = genga.genga_compact(s.ctx.handle, s.b, rad, status)
+    assert n_new == int(keep.sum())
+    after = s.numpy_state()
+    for k in ("x", "y", "z", "vx", "vy", "vz", "m"):
+        assert np.array_equal(after[k][:n_new], before[k][keep])
+    assert np.array_equal(s.b.rcrit.cpu().numpy()[:n_new], rc[keep])
+    assert np.all(status.cpu().numpy()[:n_new] == 0)
+    # five more steps on the survivors
+    st2 = {k: exp[k][keep] for k in exp}
+    exp2, erad2, est2 = oracle.step_collide(st2, rc[keep], erad[keep], np.zeros(n_new, np.int32), 1.0, DT5, 5,
+                                            0.82, 0.88)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 5, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("after compaction", s, rad, status, exp2, erad2, est2, 1e-10, n=n_new)
+    s.close()
+
+
+def test_collision_argument_checks():
+    d = discs.ring_dense(300)
+    s, rc, rad, status = collide_system(d, 0.0, 1e9)
+    torch = s.torch
+    with pytest.raises(genga.GengaError) as e:
+        genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, 1.0, 0.5)
+    assert e.value.status == genga.GENGA_ERR_ARG
+    other = genga.Bodies.from_numpy(d.state(), rc)
+    genga.genga_set_collisions(s.ctx.handle, other, rad, status, 0.0, 1e9)
+    s.accel(FP64)
+    with pytest.raises(genga.GengaError) as e:       # the bodies' m is not the collision mass array
+        genga.genga_drift(s.ctx.handle, s.b, DT5)
+    assert e.value.status == genga.GENGA_ERR_ARG
+    genga.genga_set_collisions(s.ctx.handle, None, None, None, 0.0, 0.0)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)          # off again: a plain drift
+    torch.cuda.synchronize()
+    s.close()
