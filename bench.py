@@ -203,6 +203,11 @@ DENSE_WORKLOADS = {
     "dense_40k_levels": (_D40K + "; 4 hierarchical levels of 2 sub-steps, level k's r_crit from eq. (1) "
                          "with dt / 2^k", discs.disc_dense_40k, (4, 2)),
 }
+# the 6600-body annulus again with collisions (perfect mergers) and removal inside 0.4 au /
+# beyond 40 au, every body of radius 500 km
+COLLIDE_RADIUS_AU = 500.0 / 1.495978707e8
+DENSE_WORKLOADS["dense_collisions"] = (DENSE_WORKLOADS["dense"][0] + "; perfect mergers (radius 500 km) and "
+                                       "removal inside 0.4 au / beyond 40 au", discs.disc_dense, (1, 1))
 
 
 def dense(torch, stream, which="dense", steps=10, warmup=2):
@@ -224,6 +229,11 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     rc = torch.zeros_like(b.x)
     genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS, rc)
     b.rcrit = rc
+    collide = which == "dense_collisions"
+    if collide:
+        radius = torch.full((d.n,), COLLIDE_RADIUS_AU, dtype=torch.float64, device="cuda:0")
+        col_status = torch.zeros(d.n, dtype=torch.int32, device="cuda:0")
+        genga.genga_set_collisions(ctx.handle, b, radius, col_status, 0.4, 40.0)
     if nlev > 1:
         # level k's critical radius: eq. (1) with the level's step dt / nsub^k
         rcl = torch.zeros((nlev - 1, d.n), dtype=torch.float64, device="cuda:0")
@@ -260,7 +270,11 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
     E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
     ctx.close()
-    return {"workload": label, "n": d.n, "levels": [nlev, nsub],
+    extra = {}
+    if collide:
+        stt = col_status.cpu().numpy()
+        extra = {"merged": int((stt == 1).sum()), "removed": int((stt == 2).sum())}
+    return {"workload": label, "n": d.n, "levels": [nlev, nsub], **extra,
             "encounter_pairs_at_start": npair, "largest_group_at_start": int(sizes.max()),
             "groups_above_64_at_start": int((sizes > 64).sum()),
             "steps": steps, "warmup": warmup, "steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps,
