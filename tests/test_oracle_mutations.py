@@ -43,8 +43,9 @@ MUTATIONS = [
     ("BS midpoint end correction", "out[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);", "out[q] = 0.5 * (zm[q] + zc[q]);"),
     ("drift full sun step", "oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, 0.5 * dt);\n    int64_t *gid",
      "oracle_sun_drift(n, x, y, z, vx, vy, vz, m, mstar, dt);\n    int64_t *gid"),
-    ("first half-kick length", "kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);\n        int64_t np",
-     "kick(n, nm, x, y, z, vx, vy, vz, m, rc, dt, ax, ay, az);\n        int64_t np"),
+    ("first half-kick length",
+     "kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);\n        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);\n        if (np > cap) {\n            free(pairs);\n            cap = np;",
+     "kick(n, nm, x, y, z, vx, vy, vz, m, rc, dt, ax, ay, az);\n        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);\n        if (np > cap) {\n            free(pairs);\n            cap = np;"),
     ("Hill radius factor 3", "double rh = a * cbrt(m[i] / (3.0 * mstar));", "double rh = a * cbrt(m[i] / mstar);"),
     ("TP2 test bodies interact", "        if (i >= nm && j >= nm) continue; /* two test bodies */\n", ""),
     ("TP2 energy keeps test pairs", "            if (i >= nm && j >= nm) continue;\n            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]",
