@@ -128,7 +128,8 @@ int genga_set_levels(genga_ctx *ctx, int32_t n_levels, int32_t n_sub, const doub
  * and the step dt / n_sub^k from the bodies' current state (b->rcrit stays level 0's), and
  * trial_steps (>= 1) steps of genga_step in precision prec are timed from that state, which is
  * restored afterwards (bit for bit).  A configuration that raises a device condition or a
- * capacity error is not a candidate.  The fastest is set as by genga_set_levels and written to
+ * capacity error is not a candidate; collisions (genga_set_collisions) are left out of the
+ * trials.  The fastest is set as by genga_set_levels and written to
  * *levels_out / *sub_out (host).  Needs genga_set_large_groups on; allocates and frees about
  * 72 B per body of device memory; synchronises the device. */
 int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, double n2, int32_t max_levels,

@@ -1039,6 +1039,9 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
     };
     int best_l = 1, best_s = 1;
     double best_t = INFINITY;
+    // the trials run without collisions, which would change masses, radii and statuses
+    const CollideArgs col = ctx->col;
+    ctx->col.mass = nullptr;
     hipError_t he = copy_state(true);
     rc = he == hipSuccess ? GENGA_OK : fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
     for (int nl = 1; nl <= max_levels && !rc; ++nl)
@@ -1082,6 +1085,7 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
     if (!rc && ((he = hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), s)) != hipSuccess ||
                 (he = hipStreamSynchronize(s)) != hipSuccess))
         rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
+    ctx->col = col;
     dfree(save);
     dfree(rcl);
     if (rc) return rc;
