@@ -101,3 +101,22 @@ def test_collision_argument_checks():
     genga.genga_drift(s.ctx.handle, s.b, DT5)          # off again: a plain drift
     torch.cuda.synchronize()
     s.close()
+
+
+def test_mergers_with_test_bodies():
+    """TP2 mode: the last 100 of 300 ring bodies are massless test bodies (no mutual forces or
+    encounters); a test body that hits a massive one merges into it with weight zero."""
+    d = discs.ring_dense(300)
+    nm = 200
+    s, rc, rad, status = collide_system(d, 0.0, 1e9)
+    genga.genga_set_test_bodies(s.ctx.handle, np.array([nm], dtype=np.int32))
+    st = d.state()
+    st["m"] = st["m"].copy()
+    st["m"][nm:] = 0.0
+    s.b.m.copy_(s.torch.tensor(st["m"], dtype=s.torch.float64, device="cuda"))
+    exp, erad, est = oracle.step_collide(st, rc, np.full(d.n, R), np.zeros(d.n, np.int32), 1.0, DT5, 20, 0.0, 1e9,
+                                         n_massive=nm)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 20, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("mergers TP2", s, rad, status, exp, erad, est, 1e-10)
+    s.close()

@@ -162,3 +162,25 @@ def test_tune_levels_keeps_the_state_and_sets_the_fastest():
         genga.genga_tune_levels(s.ctx.handle, s.b, DT5, 3.0, 0.4, 3, 3, 2, FP64)
     assert e.value.status == genga.GENGA_ERR_STATE
     s.close()
+
+
+def test_levels_with_test_bodies():
+    """TP2 mode (Sect. 3.3) under 3 levels of 2 sub-steps: the last 400 of 1000 ring bodies
+    are test bodies, which never interact with each other at any level."""
+    d = discs.ring_dense(1000)
+    nm = 600
+    s, rcl = level_system(d, 3, 2)
+    genga.genga_set_test_bodies(s.ctx.handle, np.array([nm], dtype=np.int32))
+    t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+    genga.genga_set_levels(s.ctx.handle, 3, 2, t)
+    s.accel(FP64)
+    pairs, _ = s.encounter_list()
+    assert not np.any((pairs[:, 0] >= nm) & (pairs[:, 1] >= nm))
+    gid = oracle.groups(d.n, pairs)
+    b0 = s.numpy_state()
+    exp = oracle.drift_levels(b0, rcl, 2, 1.0, DT5, pairs, n_massive=nm)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    compare("ring 3x2 TP2", got, exp, gid)
+    s.close()
