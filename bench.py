@@ -200,8 +200,9 @@ DENSE_WORKLOADS = {
     "dense": ("dense annulus N=6600, 0.7-1 au, 2 Earth masses, e~R(0.002), i~R(0.001), "
               "r_crit = max(3 R_H, 0.4 dt v), dt = 5 d, seed 11", discs.disc_dense, (1, 1)),
     "dense_40k": (_D40K, discs.disc_dense_40k, (1, 1)),
-    "dense_40k_levels": (_D40K + "; 4 hierarchical levels of 2 sub-steps, level k's r_crit from eq. (1) "
-                         "with dt / 2^k", discs.disc_dense_40k, (4, 2)),
+    "dense_40k_levels": (_D40K + "; hierarchical levels and sub-steps chosen by genga_tune_levels (up to 4 "
+                         "levels x 3 sub-steps, 2 trial steps each), level k's r_crit from eq. (1) with "
+                         "dt / n_sub^k", discs.disc_dense_40k, ("tune", 4, 3)),
 }
 # the 6600-body annulus again with collisions (perfect mergers) and removal inside 0.4 au /
 # beyond 40 au, every body of radius 500 km
@@ -218,7 +219,9 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     40322-body disc of the paper's high-resolution run."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
-    label, make, (nlev, nsub) = DENSE_WORKLOADS[which]
+    label, make, lv = DENSE_WORKLOADS[which]
+    tune = lv[0] == "tune"
+    nlev, nsub = (1, 1) if tune else lv
     d = make()
     st, off, mstar = discs.concat([d])
     cap = 64 * d.n
@@ -240,6 +243,13 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
         for k in range(1, nlev):
             genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS / nsub ** k, rcl[k - 1])
         genga.genga_set_levels(ctx.handle, nlev, nsub, rcl)
+    tune_s = None
+    if tune:
+        # GENGA-style self-tuning before the run (trial steps of every configuration)
+        t_tune = time.perf_counter()
+        nlev, nsub = genga.genga_tune_levels(ctx.handle, b, discs.DT_5_DAYS, discs.DENSE_N1, discs.DENSE_N2,
+                                             lv[1], lv[2], 2, genga.GENGA_KICK_FP32)
+        tune_s = time.perf_counter() - t_tune
     genga.genga_autotune(ctx.handle, b, genga.GENGA_KICK_FP32)
     # group sizes of the initial state, from the GPU's encounter list
     genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32)
@@ -270,7 +280,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
     E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
     ctx.close()
-    extra = {}
+    extra = {"tuning_s": tune_s} if tune else {}
     if collide:
         stt = col_status.cpu().numpy()
         extra = {"merged": int((stt == 1).sum()), "removed": int((stt == 2).sum())}
