@@ -198,8 +198,10 @@ def genga_set_levels(ctx: int, n_levels: int, n_sub: int, rcrit_levels=None) -> 
     critical radii of levels 1..n_levels-1 (copied)."""
     ptr = None
     if rcrit_levels is not None:
-        assert rcrit_levels.is_cuda and rcrit_levels.dtype.is_floating_point and rcrit_levels.is_contiguous()
-        ptr = rcrit_levels.data_ptr()
+        import torch
+        if rcrit_levels.dtype != torch.float64:
+            raise TypeError("rcrit_levels must be float64")
+        ptr = _ptr(rcrit_levels)
     _check(load_library().genga_set_levels(ctx, int(n_levels), int(n_sub), ptr))
 
 
@@ -220,6 +222,9 @@ def genga_set_collisions(ctx: int, b: Bodies, radius, status, r_min: float, r_ma
     if b is None:
         _check(load_library().genga_set_collisions(ctx, None, None, None, 0.0, 0.0))
         return
+    import torch
+    if radius.dtype != torch.float64 or status.dtype != torch.int32:
+        raise TypeError("radius must be float64 and status int32")
     _check(load_library().genga_set_collisions(ctx, _ptr(b.m), _ptr(radius), _ptr(status), float(r_min),
                                                float(r_max)))
 
