@@ -274,20 +274,33 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
     if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
     static_assert(BIG_TILES_PER_GROUP <= GB_TILE * GB_WAVES, "one thread per source tile");
     __syncthreads();
-    // units of 16 sources (quarters of the near tiles), dealt out to the waves
+    // units of 16 sources (quarters of the near tiles), dealt out to the waves; whole quads
+    // index the sources directly, so the four sources' words come in one scalar load per array
     for (int u = wave; u < 4 * n_near; u += GB_WAVES) {
         const int st = near_tile[u >> 2];
         const int jb = o + GB_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
-        for (int j = jb; j < je; j += 4) {
-            const int cnt = min(4, je - j);
+        int j = jb;
+        for (; j + 4 <= je; j += 4) {
             double dx[4], dy[4], dz[4], q[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int jj = min(j + u, je - 1);
-                dx[u] = ZX[jj] - xa;
-                dy[u] = ZY[jj] - ya;
-                dz[u] = ZZ[jj] - za;
-                q[u] = u < cnt ? fma(dx[u], dx[u], fma(dy[u], dy[u], dz[u] * dz[u])) : INFINITY;
+            for (int v = 0; v < 4; ++v) {
+                dx[v] = ZX[j + v] - xa;
+                dy[v] = ZY[j + v] - ya;
+                dz[v] = ZZ[j + v] - za;
+                q[v] = fma(dx[v], dx[v], fma(dy[v], dy[v], dz[v] * dz[v]));
+            }
+            if (fmin(fmin(q[0], q[1]), fmin(q[2], q[3])) < T) pairs4(j, 4, dx, dy, dz);
+        }
+        if (j < je) {
+            const int cnt = je - j;
+            double dx[4], dy[4], dz[4], q[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int jj = min(j + v, je - 1);
+                dx[v] = ZX[jj] - xa;
+                dy[v] = ZY[jj] - ya;
+                dz[v] = ZZ[jj] - za;
+                q[v] = v < cnt ? fma(dx[v], dx[v], fma(dy[v], dy[v], dz[v] * dz[v])) : INFINITY;
             }
             if (fmin(fmin(q[0], q[1]), fmin(q[2], q[3])) < T) pairs4(j, cnt, dx, dy, dz);
         }
