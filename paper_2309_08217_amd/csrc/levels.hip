@@ -130,10 +130,10 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
     for (int u = wave; u < 4 * n_near; u += LT_WAVES) {
         const int st = near_tile[u >> 2];
         const int jb = o + LT_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
-        for (int j = jb; j < je; ++j) {
-            const double dx = SX[j] - xa, dy = SY[j] - ya, dz = SZ[j] - za;
+        // one source: its term if inside level (l-1)'s radius, and the level's pair
+        auto source = [&](int j, double dx, double dy, double dz, double rcj_up) {
             const double q = sep2_rn(dx, dy, dz);
-            const double rc_up = fmax(rca[lv - 1], SR[(size_t)(lv - 1) * t.cap_M + j]);
+            const double rc_up = fmax(rca[lv - 1], rcj_up);
             bool em = false;
             if (valid && j != fa && !(testa && ST[j] != 0) && q < sq_rn(rc_up)) {
                 double rcab[LEVELS_MAX];
@@ -165,7 +165,23 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
                     }
                 }
             }
+        };
+        // whole quads: the four sources' words in one scalar load per array
+        int j = jb;
+        for (; j + 4 <= je; j += 4) {
+            double dx[4], dy[4], dz[4], ru[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                dx[v] = SX[j + v] - xa;
+                dy[v] = SY[j + v] - ya;
+                dz[v] = SZ[j + v] - za;
+                ru[v] = SR[(size_t)(lv - 1) * t.cap_M + j + v];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) source(j + v, dx[v], dy[v], dz[v], ru[v]);
         }
+        for (; j < je; ++j)
+            source(j, SX[j] - xa, SY[j] - ya, SZ[j] - za, SR[(size_t)(lv - 1) * t.cap_M + j]);
     }
     red[0][wave][lane] = ax;
     red[1][wave][lane] = ay;
