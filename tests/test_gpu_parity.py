@@ -250,6 +250,51 @@ def test_batched_systems_match_single_systems():
     s.close()
 
 
+def _empty_disc():
+    return discs.Disc(*(np.zeros(0) for _ in range(7)))
+
+
+def test_empty_systems_in_a_batch():
+    """Systems with no bodies between and around non-empty ones: the others' forces, lists,
+    energies and steps are exactly those of the batch without the empty systems, the empty
+    systems' energy rows are zero."""
+    full = [_sizes_disc(n, seed=400 + n, a_in=0.7, a_out=1.0) for n in (90, 65)]
+    ds = [_empty_disc(), full[0], _empty_disc(), _empty_disc(), full[1], _empty_disc()]
+    s, t = System(ds), System(full)
+    ref = oracle_accel_systems(t)
+    for prec, bar in ((FP64, 1e-12), (FP32, 1e-5)):
+        a, b = s.accel(prec), t.accel(prec)
+        np.testing.assert_array_equal(a, b)
+        assert force_errors(a, ref)[0] <= bar
+    np.testing.assert_array_equal(s.encounter_list()[0], t.encounter_list()[0])
+    E, F = s.energy(), t.energy()
+    assert np.all(E[[0, 2, 3, 5]] == 0.0)
+    np.testing.assert_array_equal(E[[1, 4]], F)
+    for prec in (FP64, FP32):
+        genga.genga_step(s.ctx.handle, s.b, DT, 3, prec)
+        genga.genga_step(t.ctx.handle, t.b, DT, 3, prec)
+        assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+        got, exp = s.numpy_state(), t.numpy_state()
+        for k in got:
+            np.testing.assert_array_equal(got[k], exp[k])
+    s.close()
+    t.close()
+
+
+def test_all_systems_empty():
+    """n_total = 0: every call is a successful no-op; the energy rows are zero."""
+    s = System([_empty_disc(), _empty_disc()])
+    assert s.n == 0
+    for prec in (FP64, FP32):
+        genga.genga_kick(s.ctx.handle, s.b, DT, prec)
+        genga.genga_step(s.ctx.handle, s.b, DT, 2, prec)
+    genga.genga_drift(s.ctx.handle, s.b, DT)
+    assert s.encounter_list()[1] == 0
+    assert np.all(s.energy() == 0.0)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    s.close()
+
+
 def test_deterministic_reruns():
     d = discs.disc_c1()
     s = System([d])
