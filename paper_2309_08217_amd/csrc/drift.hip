@@ -255,7 +255,10 @@ __global__ __launch_bounds__(256) void uf_hook_kernel(const int32_t *pairs, cons
         const int a = find_root_halving(lab, pairs[2 * p]);
         const int b = find_root_halving(lab, pairs[2 * p + 1]);
         if (a != b) {
-            atomicMin(&lab[max(a, b)], min(a, b));
+            // a hook that would change nothing skips the atomic: pairs of two large trees
+            // all hook the same root, and the atomics would queue on that one address
+            const int lo = min(a, b), hi = max(a, b);
+            if (lab_load(lab, hi) > lo) atomicMin(&lab[hi], lo);
             ch = 1;
         }
     }
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(CE_THREADS) void ce_groups_kernel(
             int b = find_root(lab, pairs[2 * p + 1]);
             if (a != b) {
                 const int lo = min(a, b), hi = max(a, b);
-                atomicMin(&lab[hi], lo);
+                if (lab_load(lab, hi) > lo) atomicMin(&lab[hi], lo);
                 s_changed = 1;
             }
         }
