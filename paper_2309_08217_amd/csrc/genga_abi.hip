@@ -525,6 +525,30 @@ struct TileOrder {
     std::vector<int4> tiles;
 };
 
+// Ascending sort of distinct 64-bit keys: least-significant-digit radix, 8 bits per pass,
+// for long lists (a comparison sort of ~40000 keys costs milliseconds of host time per call);
+// the passes over the low 32 bits are skipped when the keys already ascend in them, since the
+// later passes are stable.
+static void sort_keys(std::vector<uint64_t> &key, std::vector<uint64_t> &tmp)
+{
+    const size_t n = key.size();
+    if (n < 1024) {
+        std::sort(key.begin(), key.end());
+        return;
+    }
+    bool low_sorted = true;
+    for (size_t i = 1; i < n && low_sorted; ++i) low_sorted = (uint32_t)key[i - 1] < (uint32_t)key[i];
+    tmp.resize(n);
+    for (int pass = low_sorted ? 4 : 0; pass < 8; ++pass) {
+        const int sh = 8 * pass;
+        size_t c[257] = {0};
+        for (size_t i = 0; i < n; ++i) ++c[((key[i] >> sh) & 255) + 1];
+        for (int d = 0; d < 256; ++d) c[d + 1] += c[d];
+        for (size_t i = 0; i < n; ++i) tmp[c[(key[i] >> sh) & 255]++] = key[i];
+        key.swap(tmp);
+    }
+}
+
 // a monotone stand-in for atan2(y, x) on [0, 4)
 static inline double pseudo_angle(double x, double y)
 {
@@ -570,7 +594,7 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<uint64_t> key;
+    std::vector<uint64_t> key, tmp;
     for (size_t gi = 0; gi < o.k0.size(); ++gi) {
         const int nb = o.off[gi + 1] - o.off[gi];
         double r0 = INFINITY, r1 = 0.0, rs = 0.0;
@@ -593,7 +617,7 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
             const uint64_t q = (uint64_t)std::min(4294967295.0, std::max(0.0, u * 4294967295.0));
             key[l] = q << 32 | (uint32_t)bi;
         }
-        std::sort(key.begin(), key.end());
+        sort_keys(key, tmp);
         for (int l = 0; l < nb; ++l) o.body[o.off[gi] + l] = (int32_t)(key[l] & 0xffffffffu);
     }
     return GENGA_OK;

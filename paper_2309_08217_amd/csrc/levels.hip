@@ -25,29 +25,33 @@ using CD = const __attribute__((address_space(4))) double;
 using CI = const __attribute__((address_space(4))) int32_t;
 
 // Per member f: mass, TP2 flag, the radii of levels 0..level; per group: the largest
-// level-(level-1) radius squared.  One workgroup per group.
-__global__ __launch_bounds__(256) void level_tiles_setup_kernel(LevelTiles t, const int32_t *sys_of,
-                                                                const int32_t *sys_off,
-                                                                const int32_t *n_massive, const double *m,
-                                                                const double *rc0, const double *rcl,
-                                                                int n_total, int level)
+// level-(level-1) radius squared, as the maximum over its tiles (bit patterns of non-negative
+// doubles order as the values, so an integer atomic max gives the exact maximum).  One wave
+// per tile; cut2 cleared first.
+__global__ __launch_bounds__(256) void level_cut_clear_kernel(double *cut2, int G)
 {
-    __shared__ double red[4];
-    const int g = blockIdx.x;
-    const int o = t.off[g], nb = t.off[g + 1] - o;
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g < G) cut2[g] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void level_tiles_setup_kernel(LevelTiles t, const int32_t *sys_of,
+                                                               const int32_t *sys_off, const int32_t *n_massive,
+                                                               const double *m, const double *rc0,
+                                                               const double *rcl, int n_total, int level)
+{
+    const int4 tile = t.tiles[blockIdx.x];
     double mx = 0.0;
-    for (int l = threadIdx.x; l < nb; l += 256) {
-        const int f = o + l, body = t.body[f], s = sys_of[body];
+    if ((int)threadIdx.x < tile.z) {
+        const int f = tile.y + threadIdx.x, body = t.body[f], s = sys_of[body];
         t.mass[f] = m[body];
         t.test[f] = body - sys_off[s] >= n_massive[s];
         t.rc[f] = rc0[body];
         for (int k = 1; k <= level; ++k) t.rc[(size_t)k * t.cap_M + f] = rcl[(size_t)(k - 1) * n_total + body];
-        mx = fmax(mx, sq_rn(t.rc[(size_t)(level - 1) * t.cap_M + f]));
+        mx = fmax(0.0, sq_rn(t.rc[(size_t)(level - 1) * t.cap_M + f]));
     }
     mx = wave_maxv(mx);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) t.cut2[g] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (threadIdx.x == 0)
+        atomicMax((unsigned long long *)&t.cut2[tile.x], (unsigned long long)__double_as_longlong(mx));
 }
 
 // Positions of the members of each tile, and the tile's box.  One wave per tile.
@@ -204,9 +208,10 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
 hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const double *m, const double *rc0,
                                     const double *rcl, int level, hipStream_t stream)
 {
-    if (t.G == 0) return hipSuccess;
-    level_tiles_setup_kernel<<<t.G, 256, 0, stream>>>(t, L.sys_of, L.sys_off, L.n_massive, m, rc0, rcl, L.n_total,
-                                                      level);
+    if (t.G == 0 || t.n_tiles == 0) return hipSuccess;
+    level_cut_clear_kernel<<<(t.G + 255) / 256, 256, 0, stream>>>(t.cut2, t.G);
+    level_tiles_setup_kernel<<<t.n_tiles, 64, 0, stream>>>(t, L.sys_of, L.sys_off, L.n_massive, m, rc0, rcl,
+                                                           L.n_total, level);
     return hipGetLastError();
 }
 
