@@ -94,6 +94,11 @@ struct genga_ctx {
     int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
     std::vector<int32_t> mem_h;        // members copied to the host
+    // host scratch of the grouping and tile ordering, kept so that the per-call vectors of
+    // n_total entries are not allocated (and faulted in) again on every call
+    std::vector<int32_t> h_lab, h_cnt, h_first;
+    std::vector<double> h_x, h_y;
+    std::vector<uint64_t> h_key, h_tmp;
     // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
     int32_t n_levels = 1, n_sub = 1;
     double *rc_lv = nullptr;           // [n_levels - 1][n_total]
@@ -436,8 +441,9 @@ int alloc_big(genga_ctx *ctx)
 // as the one-workgroup kernel orders them) and sent back with group_start and n_groups.
 // Connected components of a pair list on the device (grid-wide union-find, labels read back,
 // bucketed on the host): gs / mem receive the groups (members ascending by body within each
-// group, groups by smallest member).  Leaves lab all -1.  A group above the grid-wide path's
-// limit is refused.
+// group, groups by smallest member).  Leaves lab all -1 on the device; the labels read back
+// (the group's smallest member, -1 outside every pair) stay in ctx->h_lab until the next call.
+// A group above the grid-wide path's limit is refused.
 int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int32_t cap,
                 std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict)
 {
@@ -467,13 +473,15 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
         if (ctx->pin[2] == 0) break;
     }
     const size_t nt = (size_t)L.n_total;
-    std::vector<int32_t> lab(nt), cnt(nt, 0);
+    std::vector<int32_t> &lab = ctx->h_lab, &cnt = ctx->h_cnt, &first = ctx->h_first;
+    lab.resize(nt);
+    cnt.assign(nt, 0);
+    first.assign(nt, -1);
     HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
     for (size_t i = 0; i < nt; ++i)
         if (lab[i] >= 0) ++cnt[lab[i]];
-    std::vector<int32_t> first(nt, -1);
     mem.reserve(2 * (size_t)np);
     for (size_t r = 0; r < nt; ++r)
         if (cnt[r] > 0) {
@@ -590,11 +598,13 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
             if (fill[gi] != o.off[gi + 1]) return fail(GENGA_ERR_STATE, "tile order misses group members");
         return GENGA_OK;
     }
-    std::vector<double> hx(nt), hy(nt);
+    std::vector<double> &hx = ctx->h_x, &hy = ctx->h_y;
+    hx.resize(nt);
+    hy.resize(nt);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
-    std::vector<uint64_t> key, tmp;
+    std::vector<uint64_t> &key = ctx->h_key, &tmp = ctx->h_tmp;
     for (size_t gi = 0; gi < o.k0.size(); ++gi) {
         const int nb = o.off[gi + 1] - o.off[gi];
         double r0 = INFINITY, r1 = 0.0, rs = 0.0;
@@ -680,17 +690,20 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
     const double h = tau / ctx->n_sub;
     const bool deepest = level + 1 == ctx->n_levels;
     std::vector<int32_t> cgs, cmem, kep;
-    std::vector<uint8_t> in_child((size_t)ctx->L.n_total, 0);
     for (int sub = 0; sub < ctx->n_sub; ++sub) {
         HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
         if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
         if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true))) return rc;
-        // parent members in no pair of this level: Kepler drift over h
-        for (int32_t i : cmem) in_child[i] = 1;
+        // parent members in no pair of this level (label -1; no labels read: no pair at all):
+        // Kepler drift over h
         kep.clear();
-        for (int32_t i : pmem)
-            if (!in_child[i]) kep.push_back(i);
-        for (int32_t i : cmem) in_child[i] = 0;
+        if (cmem.empty()) {
+            kep = pmem;
+        } else {
+            const std::vector<int32_t> &lab = ctx->h_lab;
+            for (int32_t i : pmem)
+                if (lab[i] < 0) kep.push_back(i);
+        }
         if ((rc = upload_i32(ctx->lv_list, kep, s))) return rc;
         HIP_TRY(launch_kepler_list(ctx->L, ctx->lv_list, (int32_t)kep.size(), b->x, b->y, b->z, b->vx, b->vy, b->vz,
                                    h, ctx->flags, s));
