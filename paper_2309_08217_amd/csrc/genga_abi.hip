@@ -448,18 +448,16 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
                 std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict)
 {
     const Layout &L = ctx->L;
-    HIP_TRY(hipMemcpyAsync(ctx->pin, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    // a list cut at its capacity has been flagged by the launch that filled it; strict: refuse
-    if (strict && ctx->pin[0] > cap)
-        return fail(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
-    const int np = std::min(ctx->pin[0], cap);
+    const size_t nt = (size_t)L.n_total;
+    std::vector<int32_t> &lab = ctx->h_lab, &cnt = ctx->h_cnt, &first = ctx->h_first;
+    lab.resize(nt);
     gs.assign(1, 0);
     mem.clear();
-    if (np <= 0) return GENGA_OK;
+    // Rounds of (hook, compress) x 2 until a round changes nothing; compressing after each
+    // hook keeps the trees flat, so few rounds are needed.  The kernels read the pair count on
+    // the device, so the host waits once per checked round, for the count, the round's flag
+    // and the labels together; the first round (which links every pair) goes unchecked.
     HIP_TRY(launch_uf_init(pairs, count, cap, ctx->lab, s));
-    // rounds of (hook, compress) x 2 until a round changes nothing; compressing after each
-    // hook keeps the trees flat, so few rounds are needed
     for (int round = 0;; ++round) {
         if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
         ctx->pin[2] = 0;
@@ -468,18 +466,21 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
             HIP_TRY(launch_uf_hook(pairs, count, cap, ctx->lab, ctx->big_changed, s));
             HIP_TRY(launch_uf_compress(L, ctx->lab, s));
         }
+        if (round == 0) continue;
+        HIP_TRY(hipMemcpyAsync(ctx->pin, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (nt > 0) HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[2] == 0) break;
     }
-    const size_t nt = (size_t)L.n_total;
-    std::vector<int32_t> &lab = ctx->h_lab, &cnt = ctx->h_cnt, &first = ctx->h_first;
-    lab.resize(nt);
+    if (nt > 0) HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
+    // a list cut at its capacity has been flagged by the launch that filled it; strict: refuse
+    if (strict && ctx->pin[0] > cap)
+        return fail(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
+    const int np = std::min(ctx->pin[0], cap);
+    if (np <= 0) return GENGA_OK;
     cnt.assign(nt, 0);
     first.assign(nt, -1);
-    HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
     for (size_t i = 0; i < nt; ++i)
         if (lab[i] >= 0) ++cnt[lab[i]];
     mem.reserve(2 * (size_t)np);
