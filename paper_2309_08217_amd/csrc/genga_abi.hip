@@ -157,7 +157,8 @@ struct genga_ctx {
             dfree(t.rc);
             dfree(t.bb);
             dfree(t.cut2);
-            t.G = t.M = t.n_tiles = t.cap_M = 0;
+            dfree(t.tl);
+            t.G = t.M = t.n_tiles = t.cap_M = t.n_multi = 0;
         }
         dfree(lv_mem);
         dfree(lv_gs);
@@ -391,6 +392,7 @@ int alloc_big(genga_ctx *ctx)
             HIP_TRY(dalloc(t.rc, (size_t)LEVELS_MAX * nt));
             HIP_TRY(dalloc(t.bb, 8 * T));
             HIP_TRY(dalloc(t.cut2, G));
+            HIP_TRY(dalloc(t.tl, T));
         }
         HIP_TRY(dalloc(ctx->lv_mem, nt));
         HIP_TRY(dalloc(ctx->lv_gs, nt + 1));
@@ -683,6 +685,20 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
     T.G = (int32_t)o.k0.size();
     T.M = o.off.back();
     T.n_tiles = (int32_t)o.tiles.size();
+    // tiles of the groups of more than one tile first (a workgroup each), then the one tile of
+    // every smaller group (a wave each)
+    std::vector<int32_t> tl;
+    tl.reserve(o.tiles.size());
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t gi = 0; gi < o.k0.size(); ++gi) {
+            const int t0 = o.tfirst[gi], t1 = o.tfirst[gi + 1];
+            if ((t1 - t0 > 1) == (pass == 0))
+                for (int k = t0; k < t1; ++k) tl.push_back(k);
+        }
+        if (pass == 0) T.n_multi = (int32_t)tl.size();
+    }
+    if (!tl.empty())
+        HIP_TRY(hipMemcpy(T.tl, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(T.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(T.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(T.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));

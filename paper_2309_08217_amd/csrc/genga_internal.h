@@ -211,6 +211,8 @@ struct LevelTiles {
     double *rc = nullptr;                        // [LEVELS_MAX][cap_M]: radii of levels 0..
     double *bb = nullptr;                        // [n_tiles][8] tile boxes of X, Y, Z
     double *cut2 = nullptr;                      // [G] largest level-(l-1) radius^2 of the group
+    int32_t *tl = nullptr;                       // [n_tiles] tile indices: the n_multi tiles of groups of
+    int32_t n_multi = 0;                         //   more than one tile, then one tile per smaller group
 };
 
 // Kick of level `level` (1 <= level < nlev) over the members of the parent groups:

@@ -7,10 +7,11 @@
 // close-encounter forces.
 //
 // Layout as in the grid-wide Bulirsch-Stoer: the members of the parent groups are ordered by
-// ring and azimuth (by the host, once per level interval) and cut into tiles of 64; a
-// workgroup of 16 waves takes one target tile, lists the source tiles of the group whose box
-// lies within the group's largest level-(l-1) radius of the target tile's box (no pair beyond
-// that radius carries weight at level l), and deals their quarters out to its waves.
+// ring and azimuth (by the host, once per level interval) and cut into tiles of 64.  In a
+// group of several tiles a workgroup of 16 waves takes one target tile, lists the source tiles
+// of the group whose box lies within the group's largest level-(l-1) radius of the target
+// tile's box (no pair beyond that radius carries weight at level l), and deals their quarters
+// out to its waves; a group of one tile is one wave, its members the sources in order.
 #include "genga_internal.h"
 #include "pair_math.h"
 
@@ -72,19 +73,160 @@ __global__ __launch_bounds__(64) void level_tiles_pos_kernel(LevelTiles t, const
     tile_box(v, px, py, pz, t.bb, me);
 }
 
+// W_l K_l = prod_{k<l} (1 - K_k) times K_l (loops over the fixed bound, so the radii stay in
+// registers)
 __device__ __forceinline__ double level_share(double r, int l, const double *rcab)
 {
-    double w = 1.0;
-    for (int k = 0; k < l; ++k) w *= 1.0 - changeover_k((r - 0.1 * rcab[k]) / (0.9 * rcab[k]));
-    return w * changeover_k((r - 0.1 * rcab[l]) / (0.9 * rcab[l]));
+    double w = 1.0, kl = 0.0;
+#pragma unroll
+    for (int k = 0; k < LEVELS_MAX; ++k) {
+        if (k > l) break;
+        const double kk = changeover_k((r - 0.1 * rcab[k]) / (0.9 * rcab[k]));
+        if (k < l)
+            w *= 1.0 - kk;
+        else
+            kl = kk;
+    }
+    return w * kl;
 }
 
+// The level's pairs found by a wave collect in its own LDS buffer and reach the list in
+// blocks, one counter update per block: the pairs of a level kick over a whole disc number
+// ~10^5, and one update per wave and source had queued on the counter.  Every lane of the
+// wave takes part in each call (the fill count is the same in every lane).
+constexpr int LV_BUF = 128;
+
+__device__ __forceinline__ void lv_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void lv_flush(const LevelKickArgs &a, int2 *buf, int &fill)
+{
+    if (fill == 0) return;
+    lv_wave_sync();
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(a.pair_count, fill);
+    base = __shfl(base, 0, 64);
+    for (int k = lane; k < fill; k += 64) {
+        const int idx = base + k;
+        if (idx < a.pair_cap) {
+            a.pairs[2 * idx] = buf[k].x;
+            a.pairs[2 * idx + 1] = buf[k].y;
+        } else {
+            atomicOr(a.flags, FLAG_CAPACITY);
+        }
+    }
+    lv_wave_sync();
+    fill = 0;
+}
+
+__device__ __forceinline__ void lv_emit(const LevelKickArgs &a, int2 *buf, int &fill, bool em, int i, int j)
+{
+    const unsigned long long m = __ballot(em);
+    if (!m) return;
+    const int c = __popcll(m);
+    if (fill + c > LV_BUF) lv_flush(a, buf, fill);
+    if (em) buf[fill + __popcll(m & ((1ull << (threadIdx.x & 63)) - 1))] = make_int2(i, j);
+    fill += c;
+}
+
+// One target member (a lane) of a level kick.
+struct LvTarget {
+    bool valid, test;
+    int f, body;
+    double x, y, z;
+    double rc[LEVELS_MAX]; // radii of levels 0..level (0 above)
+    double rc_up;          // the radius of level - 1
+};
+
+__device__ __forceinline__ LvTarget lv_target(const LevelTiles &t, int4 tile, int lv)
+{
+    LvTarget me;
+    const int lane = threadIdx.x & 63;
+    me.valid = lane < tile.z;
+    me.f = tile.y + (me.valid ? lane : 0);
+    me.body = t.body[me.f];
+    me.x = t.X[me.f];
+    me.y = t.Y[me.f];
+    me.z = t.Z[me.f];
+    me.test = t.test[me.f] != 0;
+#pragma unroll
+    for (int k = 0; k < LEVELS_MAX; ++k) me.rc[k] = k <= lv ? t.rc[(size_t)k * t.cap_M + me.f] : 0.0;
+    me.rc_up = t.rc[(size_t)(lv - 1) * t.cap_M + me.f];
+    return me;
+}
+
+// Source member j (wave-uniform) for the target: its term if inside level (l-1)'s radius, and
+// the level's pair.  Every lane of the wave calls it.
+__device__ __forceinline__ void lv_source(const LevelTiles &t, const LevelKickArgs &a, const LvTarget &me, int lv,
+                                          int j, double dx, double dy, double dz, double rcj_up, double &ax,
+                                          double &ay, double &az, int2 *buf, int &fill)
+{
+    CD *SM = (CD *)t.mass;
+    CD *SR = (CD *)t.rc;
+    CI *ST = (CI *)t.test;
+    CI *SB = (CI *)t.body;
+    const double q = sep2_rn(dx, dy, dz);
+    const double rc_up = fmax(me.rc_up, rcj_up);
+    bool em = false;
+    if (me.valid && j != me.f && !(me.test && ST[j] != 0) && q < sq_rn(rc_up)) {
+        double rcab[LEVELS_MAX];
+#pragma unroll
+        for (int k = 0; k < LEVELS_MAX; ++k) rcab[k] = k <= lv ? fmax(me.rc[k], SR[(size_t)k * t.cap_M + j]) : 1.0;
+        const double r = sqrt(q);
+        const double w = level_share(r, lv, rcab);
+        if (w > 0.0) {
+            const double s = SM[j] * w / (q * r);
+            ax += s * dx;
+            ay += s * dy;
+            az += s * dz;
+        }
+        em = a.emit && me.body < SB[j] && q < sq_rn(fmax(t.rc[(size_t)lv * t.cap_M + me.f], SR[(size_t)lv * t.cap_M + j]));
+    }
+    lv_emit(a, buf, fill, em, me.body, SB[j]);
+}
+
+// Sources [jb, je) of the group for the target: whole quads take the four sources' words in
+// one scalar load per array.
+__device__ __forceinline__ void lv_sources(const LevelTiles &t, const LevelKickArgs &a, const LvTarget &me, int lv,
+                                           int jb, int je, double &ax, double &ay, double &az, int2 *buf,
+                                           int &fill)
+{
+    CD *SX = (CD *)t.X;
+    CD *SY = (CD *)t.Y;
+    CD *SZ = (CD *)t.Z;
+    CD *SR = (CD *)t.rc;
+    const size_t up = (size_t)(lv - 1) * t.cap_M;
+    int j = jb;
+    for (; j + 4 <= je; j += 4) {
+        double dx[4], dy[4], dz[4], ru[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            dx[v] = SX[j + v] - me.x;
+            dy[v] = SY[j + v] - me.y;
+            dz[v] = SZ[j + v] - me.z;
+            ru[v] = SR[up + j + v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) lv_source(t, a, me, lv, j + v, dx[v], dy[v], dz[v], ru[v], ax, ay, az, buf, fill);
+    }
+    for (; j < je; ++j)
+        lv_source(t, a, me, lv, j, SX[j] - me.x, SY[j] - me.y, SZ[j] - me.z, SR[up + j], ax, ay, az, buf, fill);
+}
+
+// Groups of more than one tile: one workgroup of 16 waves per target tile (tiles listed first
+// in t.tl).
 __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(LevelTiles t, LevelKickArgs a)
 {
     __shared__ double red[3][LT_WAVES][LT_TILE];
     __shared__ int near_tile[BIG_TILES_PER_GROUP];
     __shared__ int wave_cnt[LT_WAVES];
-    const int me = blockIdx.x;
+    __shared__ int2 pair_buf[LT_WAVES][LV_BUF];
+    const int me = t.tl[blockIdx.x];
     const int4 tile = t.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
     const int lane = threadIdx.x & 63;
@@ -92,13 +234,7 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
     const int o = t.off[g], nb = t.off[g + 1] - o;
     const int tf = t.tfirst[g], nt = t.tfirst[g + 1] - tf;
     const int lv = a.level;
-    const bool valid = lane < tile.z;
-    const int fa = tile.y + (valid ? lane : 0);
-    const int body_a = t.body[fa];
-    const double xa = t.X[fa], ya = t.Y[fa], za = t.Z[fa];
-    const bool testa = t.test[fa] != 0;
-    double rca[LEVELS_MAX];
-    for (int k = 0; k <= lv; ++k) rca[k] = t.rc[(size_t)k * t.cap_M + fa];
+    const LvTarget tg = lv_target(t, tile, lv);
     const double cut = t.cut2[g] * (1.0 + 0x1p-30);
     const double *bt = t.bb + (size_t)me * 8;
     const double tlx = bt[0], tly = bt[1], tlz = bt[2], thx = bt[3], thy = bt[4], thz = bt[5];
@@ -123,84 +259,45 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
     if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
     static_assert(BIG_TILES_PER_GROUP <= LT_TILE * LT_WAVES, "one thread per source tile");
     __syncthreads();
-    CD *SX = (CD *)t.X;
-    CD *SY = (CD *)t.Y;
-    CD *SZ = (CD *)t.Z;
-    CD *SM = (CD *)t.mass;
-    CD *SR = (CD *)t.rc;
-    CI *ST = (CI *)t.test;
-    CI *SB = (CI *)t.body;
+    int2 *buf = pair_buf[wave];
+    int fill = 0;
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int u = wave; u < 4 * n_near; u += LT_WAVES) {
         const int st = near_tile[u >> 2];
         const int jb = o + LT_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
-        // one source: its term if inside level (l-1)'s radius, and the level's pair
-        auto source = [&](int j, double dx, double dy, double dz, double rcj_up) {
-            const double q = sep2_rn(dx, dy, dz);
-            const double rc_up = fmax(rca[lv - 1], rcj_up);
-            bool em = false;
-            if (valid && j != fa && !(testa && ST[j] != 0) && q < sq_rn(rc_up)) {
-                double rcab[LEVELS_MAX];
-                for (int k = 0; k <= lv; ++k) rcab[k] = fmax(rca[k], SR[(size_t)k * t.cap_M + j]);
-                const double r = sqrt(q);
-                const double w = level_share(r, lv, rcab);
-                if (w > 0.0) {
-                    const double s = SM[j] * w / (q * r);
-                    ax += s * dx;
-                    ay += s * dy;
-                    az += s * dz;
-                }
-                em = a.emit && body_a < SB[j] && q < sq_rn(rcab[lv]);
-            }
-            // the level's pairs: one counter update per wave and source
-            const unsigned long long m = __ballot(em);
-            if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                int pb = 0;
-                if (lane == leader) pb = atomicAdd(a.pair_count, __popcll(m));
-                pb = __shfl(pb, leader, 64);
-                if (em) {
-                    const int idx = pb + __popcll(m & ((1ull << lane) - 1));
-                    if (idx < a.pair_cap) {
-                        a.pairs[2 * idx] = body_a;
-                        a.pairs[2 * idx + 1] = SB[j];
-                    } else {
-                        atomicOr(a.flags, FLAG_CAPACITY);
-                    }
-                }
-            }
-        };
-        // whole quads: the four sources' words in one scalar load per array
-        int j = jb;
-        for (; j + 4 <= je; j += 4) {
-            double dx[4], dy[4], dz[4], ru[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                dx[v] = SX[j + v] - xa;
-                dy[v] = SY[j + v] - ya;
-                dz[v] = SZ[j + v] - za;
-                ru[v] = SR[(size_t)(lv - 1) * t.cap_M + j + v];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) source(j + v, dx[v], dy[v], dz[v], ru[v]);
-        }
-        for (; j < je; ++j)
-            source(j, SX[j] - xa, SY[j] - ya, SZ[j] - za, SR[(size_t)(lv - 1) * t.cap_M + j]);
+        lv_sources(t, a, tg, lv, jb, je, ax, ay, az, buf, fill);
     }
+    lv_flush(a, buf, fill);
     red[0][wave][lane] = ax;
     red[1][wave][lane] = ay;
     red[2][wave][lane] = az;
     __syncthreads();
-    if (wave != 0 || !valid) return;
+    if (wave != 0 || !tg.valid) return;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int w = 0; w < LT_WAVES; ++w) {
         sx += red[0][w][lane];
         sy += red[1][w][lane];
         sz += red[2][w][lane];
     }
-    a.vx[body_a] += a.tau * sx;
-    a.vy[body_a] += a.tau * sy;
-    a.vz[body_a] += a.tau * sz;
+    a.vx[tg.body] += a.tau * sx;
+    a.vy[tg.body] += a.tau * sy;
+    a.vz[tg.body] += a.tau * sz;
+}
+
+// Groups of one tile (up to 64 members): one wave per group, its members the sources in order.
+__global__ __launch_bounds__(LT_TILE) void level_tile_one_kernel(LevelTiles t, LevelKickArgs a)
+{
+    __shared__ int2 buf[LV_BUF];
+    const int4 tile = t.tiles[t.tl[t.n_multi + blockIdx.x]];
+    const LvTarget tg = lv_target(t, tile, a.level);
+    int fill = 0;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    lv_sources(t, a, tg, a.level, tile.y, tile.y + tile.z, ax, ay, az, buf, fill);
+    lv_flush(a, buf, fill);
+    if (!tg.valid) return;
+    a.vx[tg.body] += a.tau * ax;
+    a.vy[tg.body] += a.tau * ay;
+    a.vz[tg.body] += a.tau * az;
 }
 
 } // namespace
@@ -220,7 +317,8 @@ hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const 
 {
     if (t.n_tiles == 0) return hipSuccess;
     level_tiles_pos_kernel<<<t.n_tiles, 64, 0, stream>>>(t, x, y, z);
-    level_tiles_kick_kernel<<<t.n_tiles, LT_TILE * LT_WAVES, 0, stream>>>(t, a);
+    if (t.n_multi > 0) level_tiles_kick_kernel<<<t.n_multi, LT_TILE * LT_WAVES, 0, stream>>>(t, a);
+    if (t.n_tiles > t.n_multi) level_tile_one_kernel<<<t.n_tiles - t.n_multi, LT_TILE, 0, stream>>>(t, a);
     return hipGetLastError();
 }
 
