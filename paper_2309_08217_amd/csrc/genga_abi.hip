@@ -105,7 +105,7 @@ struct genga_ctx {
     LevelTiles lt[LEVELS_MAX - 1];     // parent groups of levels 1..n_levels-1, in tiles
     int32_t lt_cap_G = 0, lt_cap_T = 0;
     int32_t *lv_mem = nullptr, *lv_gs = nullptr, *lv_ng = nullptr; // the deepest level's groups
-    int32_t *lv_pairs = nullptr, *lv_count = nullptr, *lv_list = nullptr; // a level's pairs; Kepler list
+    int32_t *lv_pairs = nullptr, *lv_count = nullptr; // a level's pairs
     // collisions and removal (opt-in)
     CollideArgs col;
     int32_t pair_cap_req = 0;          // pair capacity asked for at genga_set_systems
@@ -165,7 +165,6 @@ struct genga_ctx {
         dfree(lv_ng);
         dfree(lv_pairs);
         dfree(lv_count);
-        dfree(lv_list);
         n_levels = n_sub = 1;
         if (pin) (void)hipHostFree(pin);
         for (auto &e : big_exec)
@@ -399,7 +398,6 @@ int alloc_big(genga_ctx *ctx)
         HIP_TRY(dalloc(ctx->lv_ng, 1));
         HIP_TRY(dalloc(ctx->lv_pairs, 2 * (size_t)ctx->pair_cap));
         HIP_TRY(dalloc(ctx->lv_count, 1));
-        HIP_TRY(dalloc(ctx->lv_list, nt));
     }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
@@ -443,11 +441,12 @@ int alloc_big(genga_ctx *ctx)
 // as the one-workgroup kernel orders them) and sent back with group_start and n_groups.
 // Connected components of a pair list on the device (grid-wide union-find, labels read back,
 // bucketed on the host): gs / mem receive the groups (members ascending by body within each
-// group, groups by smallest member).  Leaves lab all -1 on the device; the labels read back
-// (the group's smallest member, -1 outside every pair) stay in ctx->h_lab until the next call.
-// A group above the grid-wide path's limit is refused.
+// group, groups by smallest member).  Leaves lab all -1 on the device, except with keep_lab
+// after a success: then the labels (the group's smallest member, -1 outside every pair) stay
+// for the caller, who clears them.  A group above the grid-wide path's limit is refused.
 int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int32_t cap,
-                std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict)
+                std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict,
+                bool keep_lab = false)
 {
     const Layout &L = ctx->L;
     const size_t nt = (size_t)L.n_total;
@@ -475,10 +474,17 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
         HIP_TRY(hipStreamSynchronize(s));
         if (ctx->pin[2] == 0) break;
     }
-    if (nt > 0) HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
+    // with keep_lab the device labels stay for the caller, who clears them (on success)
+    if (nt > 0 && !keep_lab) HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
+    const auto refuse = [&](int status, const char *fmt, int a, int b) {
+        if (keep_lab && nt > 0) (void)hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s);
+        gs.assign(1, 0);
+        mem.clear();
+        return fail(status, fmt, a, b);
+    };
     // a list cut at its capacity has been flagged by the launch that filled it; strict: refuse
     if (strict && ctx->pin[0] > cap)
-        return fail(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
+        return refuse(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
     const int np = std::min(ctx->pin[0], cap);
     if (np <= 0) return GENGA_OK;
     cnt.assign(nt, 0);
@@ -489,13 +495,9 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
     for (size_t r = 0; r < nt; ++r)
         if (cnt[r] > 0) {
             first[r] = (int32_t)mem.size();
-            if (cnt[r] > 64 * BIG_TILES_PER_GROUP) {
-                const int nb = cnt[r];
-                gs.assign(1, 0);
-                mem.clear();
-                return fail(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", nb,
-                            64 * BIG_TILES_PER_GROUP);
-            }
+            if (cnt[r] > 64 * BIG_TILES_PER_GROUP)
+                return refuse(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", cnt[r],
+                              64 * BIG_TILES_PER_GROUP);
             gs.back() = first[r];
             gs.push_back(first[r] + cnt[r]);
             mem.resize(mem.size() + cnt[r]);
@@ -643,14 +645,6 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
 // parent members outside them, level l+1 (Bulirsch-Stoer after the last level) for each,
 // kick(h/2).  The host drives the recursion; it reads each level's pair count and labels.
 // ------------------------------------------------------------------------------------------
-int upload_i32(int32_t *dst, const std::vector<int32_t> &v, hipStream_t s)
-{
-    if (v.empty()) return GENGA_OK;
-    HIP_TRY(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return GENGA_OK;
-}
-
 int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const LevelTiles &T, double tau, bool emit,
                hipStream_t s)
 {
@@ -706,32 +700,30 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
     HIP_TRY(launch_level_tiles_setup(ctx->L, T, b->m, b->rcrit, ctx->rc_lv, level, s));
     const double h = tau / ctx->n_sub;
     const bool deepest = level + 1 == ctx->n_levels;
-    std::vector<int32_t> cgs, cmem, kep;
+    std::vector<int32_t> cgs, cmem;
     for (int sub = 0; sub < ctx->n_sub; ++sub) {
         HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
         if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
-        if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true))) return rc;
-        // parent members in no pair of this level (label -1; no labels read: no pair at all):
-        // Kepler drift over h
-        kep.clear();
-        if (cmem.empty()) {
-            kep = pmem;
-        } else {
-            const std::vector<int32_t> &lab = ctx->h_lab;
-            for (int32_t i : pmem)
-                if (lab[i] < 0) kep.push_back(i);
-        }
-        if ((rc = upload_i32(ctx->lv_list, kep, s))) return rc;
-        HIP_TRY(launch_kepler_list(ctx->L, ctx->lv_list, (int32_t)kep.size(), b->x, b->y, b->z, b->vx, b->vy, b->vz,
-                                   h, ctx->flags, s));
+        if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true, true)))
+            return rc;
+        // parent members in no pair of this level (device label -1): Kepler drift over h; then
+        // the labels are cleared
+        HIP_TRY(launch_kepler_list(ctx->L, T.body, T.M, b->x, b->y, b->z, b->vx, b->vy, b->vz, h, ctx->flags, s,
+                                   ctx->lab));
+        HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, (size_t)ctx->L.n_total * sizeof(int32_t), s));
         if (!cmem.empty()) {
             if (deepest) {
                 // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members,
                 // the grid-wide path for larger ones
                 const int ncg = (int)cgs.size() - 1;
-                if ((rc = upload_i32(ctx->lv_mem, cmem, s)) || (rc = upload_i32(ctx->lv_gs, cgs, s)) ||
-                    (rc = upload_i32(ctx->lv_ng, std::vector<int32_t>{ncg}, s)))
-                    return rc;
+                // members, group starts and count in one host wait
+                ctx->pin[3] = ncg;
+                HIP_TRY(hipMemcpyAsync(ctx->lv_mem, cmem.data(), cmem.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(ctx->lv_gs, cgs.data(), cgs.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                       s));
+                HIP_TRY(hipMemcpyAsync(ctx->lv_ng, ctx->pin + 3, sizeof(int32_t), hipMemcpyHostToDevice, s));
+                HIP_TRY(hipStreamSynchronize(s));
                 HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
                                      ctx->lv_gs, ctx->lv_ng, ctx->member_slot, ctx->flags, 1, ncg, s, ctx->rc_lv,
                                      ctx->n_levels, false));

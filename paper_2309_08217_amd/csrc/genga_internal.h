@@ -231,10 +231,10 @@ hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const 
 // Gather the members' positions and tile boxes, then kick.
 hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
                              const double *z, hipStream_t stream);
-// Kepler drift over dt of the bodies list[0..n-1].
+// Kepler drift over dt of the bodies list[0..n-1] (with skip: those with skip[body] < 0).
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
-                              hipStream_t stream);
+                              hipStream_t stream, const int32_t *skip = nullptr);
 
 // Collisions (perfect mergers) and removal by distance: caller-owned mass (the bodies' m),
 // radius and status arrays; a list of the colliding pairs of the current drift.
