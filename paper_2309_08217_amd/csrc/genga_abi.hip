@@ -487,24 +487,38 @@ int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int3
         return refuse(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
     const int np = std::min(ctx->pin[0], cap);
     if (np <= 0) return GENGA_OK;
-    cnt.assign(nt, 0);
-    first.assign(nt, -1);
-    for (size_t i = 0; i < nt; ++i)
-        if (lab[i] >= 0) ++cnt[lab[i]];
-    mem.reserve(2 * (size_t)np);
-    for (size_t r = 0; r < nt; ++r)
-        if (cnt[r] > 0) {
-            first[r] = (int32_t)mem.size();
-            if (cnt[r] > 64 * BIG_TILES_PER_GROUP)
-                return refuse(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", cnt[r],
-                              64 * BIG_TILES_PER_GROUP);
-            gs.back() = first[r];
-            gs.push_back(first[r] + cnt[r]);
-            mem.resize(mem.size() + cnt[r]);
-            cnt[r] = 0;
+    // Labels are compressed to roots and a root is its group's smallest member, so scanning
+    // the bodies in ascending order meets every root before its other members: the roots get
+    // group numbers in that order (first[root]), one pass counts the members per group, and a
+    // second places them, ascending, after the prefix sum of the counts.
+    first.resize(nt);
+    cnt.clear();
+    for (size_t i = 0; i < nt; ++i) {
+        const int32_t r = lab[i];
+        if (r < 0) continue;
+        if (r == (int32_t)i) {
+            first[i] = (int32_t)cnt.size();
+            cnt.push_back(0);
         }
-    for (size_t i = 0; i < nt; ++i)
-        if (lab[i] >= 0) mem[first[lab[i]] + cnt[lab[i]]++] = (int32_t)i;
+        ++cnt[first[r]];
+    }
+    const size_t ng = cnt.size();
+    gs.resize(ng + 1);
+    int32_t total = 0;
+    for (size_t g = 0; g < ng; ++g) {
+        if (cnt[g] > 64 * BIG_TILES_PER_GROUP)
+            return refuse(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", cnt[g],
+                          64 * BIG_TILES_PER_GROUP);
+        gs[g] = total;
+        total += cnt[g];
+        cnt[g] = gs[g]; // next free slot of group g
+    }
+    gs[ng] = total;
+    mem.resize((size_t)total);
+    for (size_t i = 0; i < nt; ++i) {
+        const int32_t r = lab[i];
+        if (r >= 0) mem[cnt[first[r]]++] = (int32_t)i;
+    }
     return GENGA_OK;
 }
 
