@@ -532,13 +532,15 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     if (nmem > ctx->ce_cap) return fail(GENGA_ERR_STATE, "encounter members exceed their allocation");
     ctx->pin[0] = ng;
     ctx->pin[1] = nmem;
+    // uploads on the stream, one host wait (pin is rewritten by the next grouping)
     if (nmem > 0) {
-        HIP_TRY(hipMemcpy(ctx->members, ctx->mem_h.data(), nmem * sizeof(int32_t), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t),
-                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpyAsync(ctx->members, ctx->mem_h.data(), nmem * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
     }
-    HIP_TRY(hipMemcpy(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(ctx->big_changed, ctx->pin + 1, sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 1, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
@@ -620,9 +622,9 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
     std::vector<double> &hx = ctx->h_x, &hy = ctx->h_y;
     hx.resize(nt);
     hy.resize(nt);
+    HIP_TRY(hipMemcpyAsync(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<uint64_t> &key = ctx->h_key, &tmp = ctx->h_tmp;
     for (size_t gi = 0; gi < o.k0.size(); ++gi) {
         const int nb = o.off[gi + 1] - o.off[gi];
@@ -705,12 +707,16 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
         }
         if (pass == 0) T.n_multi = (int32_t)tl.size();
     }
+    // the layout's uploads on the stream, one host wait after the last
     if (!tl.empty())
-        HIP_TRY(hipMemcpy(T.tl, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(T.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(T.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(T.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(T.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpyAsync(T.tl, tl.data(), tl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(T.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(T.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!o.tiles.empty())
+        HIP_TRY(hipMemcpyAsync(T.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    if (!o.body.empty())
+        HIP_TRY(hipMemcpyAsync(T.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(launch_level_tiles_setup(ctx->L, T, b->m, b->rcrit, ctx->rc_lv, level, s));
     const double h = tau / ctx->n_sub;
     const bool deepest = level + 1 == ctx->n_levels;
@@ -774,13 +780,15 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
     bg.G = (int32_t)o.k0.size();
     bg.M = o.off.back();
     bg.n_tiles = (int32_t)o.tiles.size();
-    HIP_TRY(hipMemcpy(bg.k0, o.k0.data(), o.k0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // the layout's uploads on the stream, one host wait after the last
+    HIP_TRY(hipMemcpyAsync(bg.k0, o.k0.data(), o.k0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(bg.off, o.off.data(), o.off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(bg.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(bg.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     const int32_t dims[4] = {bg.G, bg.M, bg.n_tiles, 0};
-    HIP_TRY(hipMemcpy(bg.dims, dims, sizeof(dims), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(bg.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(bg.dims, dims, sizeof(dims), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(bg.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
     const Layout &L = ctx->L;
     HIP_TRY(launch_big_setup(L, bg, members_dev, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, ctx->rc_lv,
                              dt, s));
