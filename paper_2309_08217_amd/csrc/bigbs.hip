@@ -8,7 +8,7 @@
 // doubled / kept / halved, rejected steps shrunk by shrink_factor.
 //
 // One attempt is a fixed sequence of launches over all large groups at once: a force
-// evaluation and midpoint update per sub-step (64 targets per workgroup, GB_WAVES waves that
+// evaluation and midpoint update per sub-step (64 targets per workgroup, 8 or 16 waves that
 // split the group's members as sources), then per column an error launch and a decision
 // launch.  A group that has accepted a column, or reached dt, skips the rest.  The host
 // repeats attempts until no group is active.
@@ -30,7 +30,6 @@ using CD = const __attribute__((address_space(4))) double;
 using CI = const __attribute__((address_space(4))) int32_t;
 
 constexpr int GB_TILE = 64;
-constexpr int GB_WAVES = 16;
 constexpr int GB_THREADS = 256;
 
 __device__ __forceinline__ unsigned long long dbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -174,11 +173,11 @@ __global__ __launch_bounds__(64) void big_box_kernel(BigBs b)
 // quarters (16 members) are dealt out to the waves, so the few near tiles are spread over
 // many waves.  Source positions and boxes come through scalar loads: neither is written by
 // this launch.
-template <bool LV>
+template <bool LV, int W>
 __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int mode, const double *Z,
                                              const double *ZM, double *OUT, const double *bbZ, double *bbOUT)
 {
-    __shared__ double red[3][GB_WAVES][GB_TILE];
+    __shared__ double red[3][W][GB_TILE];
     const int4 tile = b.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
     if (b.done[g] || b.acc[g] >= 0) return;
@@ -250,33 +249,36 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
             az = fma(t[u], dz[u], az);
         }
     };
-    // the source tiles in reach of this target tile, in tile order: one test per thread, then
-    // an ordered compaction (ballots within a wave, wave offsets through LDS)
+    // the source tiles in reach of this target tile, in tile order: one test per thread (in
+    // passes of W * 64 tiles), then an ordered compaction (ballots within a wave, wave offsets
+    // through LDS)
     __shared__ int near_tile[BIG_TILES_PER_GROUP];
-    __shared__ int wave_cnt[GB_WAVES];
-    bool near = false;
-    const int tt = threadIdx.x;
-    if (tt < nt) {
-        const double *bs = bbZ + (size_t)(tf + tt) * 8;
-        const double gx = fmax(0.0, fmax(bs[0] - thx, tlx - bs[3]));
-        const double gy = fmax(0.0, fmax(bs[1] - thy, tly - bs[4]));
-        const double gz = fmax(0.0, fmax(bs[2] - thz, tlz - bs[5]));
-        near = (gx * gx + gy * gy) + gz * gz <= Tcull; // else no pair of the two tiles is close
+    __shared__ int wave_cnt[W];
+    int n_near = 0;
+    for (int t0 = 0; t0 < nt; t0 += W * GB_TILE) {
+        bool near = false;
+        const int tt = t0 + (int)threadIdx.x;
+        if (tt < nt) {
+            const double *bs = bbZ + (size_t)(tf + tt) * 8;
+            const double gx = fmax(0.0, fmax(bs[0] - thx, tlx - bs[3]));
+            const double gy = fmax(0.0, fmax(bs[1] - thy, tly - bs[4]));
+            const double gz = fmax(0.0, fmax(bs[2] - thz, tlz - bs[5]));
+            near = (gx * gx + gy * gy) + gz * gz <= Tcull; // else no pair of the two tiles is close
+        }
+        const unsigned long long bal = __ballot(near);
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        int base = n_near;
+        for (int w = 0; w < W; ++w) {
+            if (w < wave) base += wave_cnt[w];
+            n_near += wave_cnt[w];
+        }
+        if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
+        __syncthreads();
     }
-    const unsigned long long bal = __ballot(near);
-    if (lane == 0) wave_cnt[wave] = __popcll(bal);
-    __syncthreads();
-    int base = 0, n_near = 0;
-    for (int w = 0; w < GB_WAVES; ++w) {
-        if (w < wave) base += wave_cnt[w];
-        n_near += wave_cnt[w];
-    }
-    if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
-    static_assert(BIG_TILES_PER_GROUP <= GB_TILE * GB_WAVES, "one thread per source tile");
-    __syncthreads();
     // units of 16 sources (quarters of the near tiles), dealt out to the waves; whole quads
     // index the sources directly, so the four sources' words come in one scalar load per array
-    for (int u = wave; u < 4 * n_near; u += GB_WAVES) {
+    for (int u = wave; u < 4 * n_near; u += W) {
         const int st = near_tile[u >> 2];
         const int jb = o + GB_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
         int j = jb;
@@ -313,7 +315,7 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
     const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
     const double s = -b.mstar[g] * (ri * ri) * ri;
     double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa, s * ya, s * za};
-    for (int w = 0; w < GB_WAVES; ++w) {
+    for (int w = 0; w < W; ++w) {
         d[3] += red[0][w][lane];
         d[4] += red[1][w][lane];
         d[5] += red[2][w][lane];
@@ -334,15 +336,14 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
 
 // The tiles are visited grid-stride, so that a launch can be sized to the layout at hand
 // (the captured attempt is kept per grid size) rather than to the largest one.
-template <bool LV>
-__global__ __launch_bounds__(GB_TILE *GB_WAVES) void big_substep_kernel(BigBs b, int k, int mode,
-                                                                       const double *Z, const double *ZM,
-                                                                       double *OUT, const double *bbZ,
-                                                                       double *bbOUT)
+template <bool LV, int W>
+__global__ __launch_bounds__(GB_TILE *W) void big_substep_kernel(BigBs b, int k, int mode, const double *Z,
+                                                                const double *ZM, double *OUT, const double *bbZ,
+                                                                double *bbOUT)
 {
     for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
         if (me != (int)blockIdx.x) __syncthreads(); // the previous tile's LDS is free again
-        substep_tile<LV>(b, me, k, mode, Z, ZM, OUT, bbZ, bbOUT);
+        substep_tile<LV, W>(b, me, k, mode, Z, ZM, OUT, bbZ, bbOUT);
     }
 }
 
@@ -461,7 +462,8 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
     return hipGetLastError();
 }
 
-hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream)
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, int waves,
+                              hipStream_t stream)
 {
     // grids for the largest layout: launches past the current one (sizes in b.dims) return at
     // once, so one captured sequence serves every step
@@ -470,7 +472,12 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int ti
     const size_t M6 = 6 * (size_t)b.cap_M;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6};           // Y, B1, B2
     double *box[3] = {b.bb, b.bb + 8 * (size_t)b.cap_T, b.bb + 16 * (size_t)b.cap_T};
-    auto substep = b.nlev > 1 ? big_substep_kernel<true> : big_substep_kernel<false>;
+    // waves per target tile: 16 while the tiles fit the chip in one round of workgroups, fewer
+    // (more workgroups per CU, more sources per wave) for larger layouts
+    if (waves != 8 && waves != 16) return hipErrorInvalidValue;
+    const bool lv = b.nlev > 1;
+    auto substep = waves == 16 ? (lv ? big_substep_kernel<true, 16> : big_substep_kernel<false, 16>)
+                               : (lv ? big_substep_kernel<true, 8> : big_substep_kernel<false, 8>);
     big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
     big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
     big_box_kernel<<<nt, 64, 0, stream>>>(b);
@@ -478,16 +485,16 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int ti
         const int nsub = 2 * (k + 1);
         // sub-step i reads zc_i and zm_i and writes zc_(i+1): zc_1 = B1 (zm_1 = Y), then the
         // new point goes into zm's buffer, B2 first
-        substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[0], box[1]);
+        substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 0, buf[0], buf[0], buf[1], box[0], box[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
-            substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[zc],
+            substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 1, buf[zc], buf[zm], buf[out], box[zc],
                                                                        box[out]);
             zm = zc;
             zc = out;
         }
-        substep<<<nt, GB_TILE * GB_WAVES, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
+        substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
         if (k > 0) {
             big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
             big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);

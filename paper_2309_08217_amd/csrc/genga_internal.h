@@ -195,8 +195,10 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
                             double dt, hipStream_t stream);
 // One attempt of every active group: a fixed sequence of launches that takes its sizes and dt
 // from device memory, so it can be captured once and replayed.
-// tile_grid: workgroups of the per-tile launches (they visit the tiles grid-stride).
-hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream);
+// tile_grid: workgroups of the per-tile launches (they visit the tiles grid-stride); waves: 8
+// or 16 per workgroup (the sources of a target tile split over them).
+hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, int waves,
+                              hipStream_t stream);
 hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, hipStream_t stream);
 // Members of the parent groups of a hierarchical level, laid out as the grid-wide
