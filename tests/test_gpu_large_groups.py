@@ -92,6 +92,38 @@ def ring_chain(n):
     return discs.Disc(c, s, z.copy(), -s, c.copy(), z.copy(), np.full(n, 1e-12), name=f"chain_n{n}")
 
 
+def test_many_large_groups_more_tiles_than_cus():
+    """150 chains of 70 bodies (each body within r_crit of two neighbours on either side, the
+    chains 10 spacings apart): 300 target tiles, more than one workgroup per CU, so the
+    sub-steps run the 8-wave tile kernel.  The drift against the oracle's."""
+    per, gap, ng = 70, 10, 150
+    npos = ng * (per + gap)
+    keep = (np.arange(npos) % (per + gap)) < per
+    full = ring_chain(npos)
+    d = discs.Disc(*(getattr(full, k)[keep] for k in ("x", "y", "z", "vx", "vy", "vz", "m")), name="chains")
+    spacing = 2.0 * np.pi / npos
+    rc = np.full(d.n, 2.5 * spacing)
+    s = System([d], rcrit=rc)
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    sizes = np.bincount(gid[gid >= 0])
+    tiles = int(np.sum((sizes + 63) // 64))
+    print(f"[chains] groups={len(sizes)} sizes {sizes.min()}..{sizes.max()} tiles={tiles}", flush=True)
+    assert len(sizes) == ng and sizes.min() == per and tiles > 256
+    b0 = s.numpy_state()
+    exp = oracle.drift(b0, rc, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        err = np.max(np.abs(got[k] - exp[k]))
+        print(f"[chains] {k} max err {err:.2e}", flush=True)
+        assert err <= 1e-10
+    s.close()
+
+
 def test_group_above_limit_refused_before_drift():
     """66000 bodies in a chain (each within r_crit of its two neighbours on either side) form
     one group above the 65536-body limit: the drift is refused with GENGA_ERR_CAPACITY and the
