@@ -93,14 +93,16 @@ def ring_chain(n):
 
 
 def test_many_large_groups_more_tiles_than_cus():
-    """150 chains of 70 bodies (each body within r_crit of two neighbours on either side, the
-    chains 10 spacings apart): 300 target tiles, more than one workgroup per CU, so the
-    sub-steps run the 8-wave tile kernel.  The drift against the oracle's."""
+    """150 chains of 70 bodies of 1e-10 solar masses (each body within r_crit of two neighbours
+    on either side, the chains 10 spacings apart): 300 target tiles, more than one workgroup
+    per CU, so the sub-steps run the 8-wave tile kernel.  The drift against the oracle's (the
+    pair forces move the bodies by about 1e-6 au over the step)."""
     per, gap, ng = 70, 10, 150
     npos = ng * (per + gap)
     keep = (np.arange(npos) % (per + gap)) < per
     full = ring_chain(npos)
-    d = discs.Disc(*(getattr(full, k)[keep] for k in ("x", "y", "z", "vx", "vy", "vz", "m")), name="chains")
+    d = discs.Disc(*(getattr(full, k)[keep] for k in ("x", "y", "z", "vx", "vy", "vz")),
+                   np.full(int(keep.sum()), 1e-10), name="chains")
     spacing = 2.0 * np.pi / npos
     rc = np.full(d.n, 2.5 * spacing)
     s = System([d], rcrit=rc)
