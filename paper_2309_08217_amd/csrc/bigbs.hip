@@ -322,9 +322,31 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
     }
     const double h = b.H[g] / (2 * (k + 1));
     if (mode == 2) {
-        if (!valid) return;
-        double *T0 = b.tcol + (size_t)k * 6 * M;
-        for (int q = 0; q < 6; ++q) T0[q * M + fa] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
+        double tk[6];
+        for (int q = 0; q < 6; ++q) tk[q] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
+        if (valid) {
+            double *T0 = b.tcol + (size_t)k * 6 * M;
+            for (int q = 0; q < 6; ++q) T0[q * M + fa] = tk[q];
+        }
+        if (k == 0) return;
+        // the column's error estimate for this member (Lagrange form of T(k, k) - T(k, k-1),
+        // relative to T(0, 0)) into the group's maximum: per position / velocity element over
+        // the group's scales; a non-finite estimate is kept as the all-ones pattern
+        double dp = 0.0, dv = 0.0;
+        bool bad = false;
+        for (int q = 0; q < 6; ++q) {
+            const double t0 = b.tcol[q * M + fa];
+            double sum = 0.0;
+            for (int jj = 1; jj <= k; ++jj) {
+                const double v = jj == k ? tk[q] : b.tcol[((size_t)jj * 6 + q) * M + fa];
+                sum = fma(LAGRANGE.d[k][jj], v - t0, sum);
+            }
+            if (q < 3) dp = fmax(dp, fabs(sum));
+            else dv = fmax(dv, fabs(sum));
+            bad |= !(sum == sum);
+        }
+        const double e = fmax(dp / bitsd(b.sr[g]), dv / bitsd(b.sv[g]));
+        wave_atomic_max(b.err + k, g * BS_KMAX, valid, (bad || !(e == e)) ? ~0ull : dbits(e));
         return;
     }
     double nx[6];
@@ -345,31 +367,6 @@ __global__ __launch_bounds__(GB_TILE *W) void big_substep_kernel(BigBs b, int k,
         if (me != (int)blockIdx.x) __syncthreads(); // the previous tile's LDS is free again
         substep_tile<LV, W>(b, me, k, mode, Z, ZM, OUT, bbZ, bbOUT);
     }
-}
-
-// Error estimate of column k: per member max(|T(k,k) - T(k,k-1)| / scale) over its six
-// elements, into the group's maximum.
-__global__ __launch_bounds__(GB_THREADS) void big_err_kernel(BigBs b, int k)
-{
-    const int f0 = blockIdx.x * GB_THREADS + threadIdx.x;
-    const bool in = f0 < b.dims[1];
-    const int f = in ? f0 : 0;
-    const int g = b.grp[f];
-    const bool use = in && !b.done[g] && b.acc[g] < 0;
-    const size_t M = (size_t)b.dims[1];
-    double dp = 0.0, dv = 0.0;
-    bool bad = false;
-    for (int q = 0; q < 6; ++q) {
-        const double t0 = b.tcol[q * M + f];
-        double s = 0.0;
-        for (int jj = 1; jj <= k; ++jj) s = fma(LAGRANGE.d[k][jj], b.tcol[((size_t)jj * 6 + q) * M + f] - t0, s);
-        if (q < 3) dp = fmax(dp, fabs(s));
-        else dv = fmax(dv, fabs(s));
-        bad |= !(s == s);
-    }
-    const double e = fmax(dp / bitsd(b.sr[g]), dv / bitsd(b.sv[g]));
-    // a non-finite estimate is kept as the all-ones pattern, above every finite one
-    wave_atomic_max(b.err + k, g * BS_KMAX, use, (bad || !(e == e)) ? ~0ull : dbits(e));
 }
 
 __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double tol)
@@ -495,10 +492,7 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int ti
             zc = out;
         }
         substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
-        if (k > 0) {
-            big_err_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k);
-            big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);
-        }
+        if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol); // the estimates came with T(k, 0)
     }
     big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
     big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);
