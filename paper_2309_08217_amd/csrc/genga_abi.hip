@@ -675,7 +675,8 @@ int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const LevelTiles &T, 
     a.pair_count = ctx->lv_count;
     a.flags = ctx->flags;
     a.pair_cap = ctx->pair_cap;
-    HIP_TRY(launch_level_kick(T, a, b->x, b->y, b->z, s));
+    // 16 waves per target tile while the tiles fit one workgroup per CU, else 8 (several per CU)
+    HIP_TRY(launch_level_kick(T, a, b->x, b->y, b->z, T.n_multi <= ctx->n_cu ? 16 : 8, s));
     return GENGA_OK;
 }
 

@@ -230,9 +230,10 @@ struct LevelKickArgs {
 // Constants of the members (mass, TP2 flag, radii of levels 0..level) and each group's cut-off.
 hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const double *m, const double *rc0,
                                     const double *rcl, int level, hipStream_t stream);
-// Gather the members' positions and tile boxes, then kick.
+// Gather the members' positions and tile boxes, then kick (waves: 8 or 16 per workgroup of a
+// multi-tile group's target tile).
 hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
-                             const double *z, hipStream_t stream);
+                             const double *z, int waves, hipStream_t stream);
 // Kepler drift over dt of the bodies list[0..n-1] (with skip: those with skip[body] < 0).
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,

@@ -8,7 +8,8 @@
 //
 // Layout as in the grid-wide Bulirsch-Stoer: the members of the parent groups are ordered by
 // ring and azimuth (by the host, once per level interval) and cut into tiles of 64.  In a
-// group of several tiles a workgroup of 16 waves takes one target tile, lists the source tiles
+// group of several tiles a workgroup of 16 waves (8 when such tiles outnumber the CUs, so that
+// several workgroups share a CU) takes one target tile, lists the source tiles
 // of the group whose box lies within the group's largest level-(l-1) radius of the target
 // tile's box (no pair beyond that radius carries weight at level l), and deals their quarters
 // out to its waves; a group of one tile is one wave, its members the sources in order.
@@ -20,7 +21,6 @@ namespace genga {
 namespace {
 
 constexpr int LT_TILE = 64;
-constexpr int LT_WAVES = 16;
 
 using CD = const __attribute__((address_space(4))) double;
 using CI = const __attribute__((address_space(4))) int32_t;
@@ -218,14 +218,15 @@ __device__ __forceinline__ void lv_sources(const LevelTiles &t, const LevelKickA
         lv_source(t, a, me, lv, j, SX[j] - me.x, SY[j] - me.y, SZ[j] - me.z, SR[up + j], ax, ay, az, buf, fill);
 }
 
-// Groups of more than one tile: one workgroup of 16 waves per target tile (tiles listed first
+// Groups of more than one tile: one workgroup of W waves per target tile (tiles listed first
 // in t.tl).
-__global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(LevelTiles t, LevelKickArgs a)
+template <int W>
+__global__ __launch_bounds__(LT_TILE *W) void level_tiles_kick_kernel(LevelTiles t, LevelKickArgs a)
 {
-    __shared__ double red[3][LT_WAVES][LT_TILE];
+    __shared__ double red[3][W][LT_TILE];
     __shared__ int near_tile[BIG_TILES_PER_GROUP];
-    __shared__ int wave_cnt[LT_WAVES];
-    __shared__ int2 pair_buf[LT_WAVES][LV_BUF];
+    __shared__ int wave_cnt[W];
+    __shared__ int2 pair_buf[W][LV_BUF];
     const int me = t.tl[blockIdx.x];
     const int4 tile = t.tiles[me]; // (group, first member, count, -)
     const int g = tile.x;
@@ -238,31 +239,34 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
     const double cut = t.cut2[g] * (1.0 + 0x1p-30);
     const double *bt = t.bb + (size_t)me * 8;
     const double tlx = bt[0], tly = bt[1], tlz = bt[2], thx = bt[3], thy = bt[4], thz = bt[5];
-    // source tiles of the group in reach: one test per thread, ordered compaction
-    bool near = false;
-    const int tt = threadIdx.x;
-    if (tt < nt) {
-        const double *bs = t.bb + (size_t)(tf + tt) * 8;
-        const double gx = fmax(0.0, fmax(bs[0] - thx, tlx - bs[3]));
-        const double gy = fmax(0.0, fmax(bs[1] - thy, tly - bs[4]));
-        const double gz = fmax(0.0, fmax(bs[2] - thz, tlz - bs[5]));
-        near = (gx * gx + gy * gy) + gz * gz <= cut;
+    // source tiles of the group in reach: one test per thread (in passes of W * 64 tiles),
+    // ordered compaction
+    int n_near = 0;
+    for (int t0 = 0; t0 < nt; t0 += W * LT_TILE) {
+        bool near = false;
+        const int tt = t0 + (int)threadIdx.x;
+        if (tt < nt) {
+            const double *bs = t.bb + (size_t)(tf + tt) * 8;
+            const double gx = fmax(0.0, fmax(bs[0] - thx, tlx - bs[3]));
+            const double gy = fmax(0.0, fmax(bs[1] - thy, tly - bs[4]));
+            const double gz = fmax(0.0, fmax(bs[2] - thz, tlz - bs[5]));
+            near = (gx * gx + gy * gy) + gz * gz <= cut;
+        }
+        const unsigned long long bal = __ballot(near);
+        if (lane == 0) wave_cnt[wave] = __popcll(bal);
+        __syncthreads();
+        int base = n_near;
+        for (int w = 0; w < W; ++w) {
+            if (w < wave) base += wave_cnt[w];
+            n_near += wave_cnt[w];
+        }
+        if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
+        __syncthreads();
     }
-    const unsigned long long bal = __ballot(near);
-    if (lane == 0) wave_cnt[wave] = __popcll(bal);
-    __syncthreads();
-    int base = 0, n_near = 0;
-    for (int w = 0; w < LT_WAVES; ++w) {
-        if (w < wave) base += wave_cnt[w];
-        n_near += wave_cnt[w];
-    }
-    if (near) near_tile[base + __popcll(bal & ((1ull << lane) - 1))] = tt;
-    static_assert(BIG_TILES_PER_GROUP <= LT_TILE * LT_WAVES, "one thread per source tile");
-    __syncthreads();
     int2 *buf = pair_buf[wave];
     int fill = 0;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int u = wave; u < 4 * n_near; u += LT_WAVES) {
+    for (int u = wave; u < 4 * n_near; u += W) {
         const int st = near_tile[u >> 2];
         const int jb = o + LT_TILE * st + 16 * (u & 3), je = min(jb + 16, o + nb);
         lv_sources(t, a, tg, lv, jb, je, ax, ay, az, buf, fill);
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(LT_TILE *LT_WAVES) void level_tiles_kick_kernel(Lev
     __syncthreads();
     if (wave != 0 || !tg.valid) return;
     double sx = 0.0, sy = 0.0, sz = 0.0;
-    for (int w = 0; w < LT_WAVES; ++w) {
+    for (int w = 0; w < W; ++w) {
         sx += red[0][w][lane];
         sy += red[1][w][lane];
         sz += red[2][w][lane];
@@ -313,11 +317,18 @@ hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const 
 }
 
 hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
-                             const double *z, hipStream_t stream)
+                             const double *z, int waves, hipStream_t stream)
 {
     if (t.n_tiles == 0) return hipSuccess;
     level_tiles_pos_kernel<<<t.n_tiles, 64, 0, stream>>>(t, x, y, z);
-    if (t.n_multi > 0) level_tiles_kick_kernel<<<t.n_multi, LT_TILE * LT_WAVES, 0, stream>>>(t, a);
+    if (t.n_multi > 0) {
+        if (waves == 16)
+            level_tiles_kick_kernel<16><<<t.n_multi, LT_TILE * 16, 0, stream>>>(t, a);
+        else if (waves == 8)
+            level_tiles_kick_kernel<8><<<t.n_multi, LT_TILE * 8, 0, stream>>>(t, a);
+        else
+            return hipErrorInvalidValue;
+    }
     if (t.n_tiles > t.n_multi) level_tile_one_kernel<<<t.n_tiles - t.n_multi, LT_TILE, 0, stream>>>(t, a);
     return hipGetLastError();
 }
