@@ -37,6 +37,39 @@ def compare(label, got, exp, gid, bar_in=1e-10, bar_out=1e-13):
         assert e_out <= bar_out
 
 
+def test_chains_two_levels_more_tiles_than_cus():
+    """150 chains of 70 bodies of 1e-10 solar masses on a circle (level 0: r_crit 2.5
+    spacings, level 1: 1.5; the chains 10 spacings apart), 2 levels x 2 sub-steps: 300 target
+    tiles in multi-tile groups, more than one workgroup per CU, so the level kick runs 8 waves
+    per tile, and the level-1 groups of 70 go to the grid-wide Bulirsch-Stoer."""
+    per, gap, ng = 70, 10, 150
+    npos = ng * (per + gap)
+    keep = (np.arange(npos) % (per + gap)) < per
+    th = 2.0 * np.pi * np.arange(npos)[keep] / npos
+    c, sn, z = np.cos(th), np.sin(th), np.zeros(len(th))
+    d = discs.Disc(c, sn, z.copy(), -sn, c.copy(), z.copy(), np.full(len(th), 1e-10), name="chains")
+    spacing = 2.0 * np.pi / npos
+    rcl = np.stack([np.full(d.n, 2.5 * spacing), np.full(d.n, 1.5 * spacing)])
+    s = System([d], rcrit=rcl[0])
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+    genga.genga_set_levels(s.ctx.handle, 2, 2, t)
+    s.torch.cuda.synchronize()
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    gid = oracle.groups(d.n, pairs)
+    sizes = np.bincount(gid[gid >= 0])
+    print(f"[chains 2x2] pairs={cnt} groups={len(sizes)} sizes {sizes.min()}..{sizes.max()}", flush=True)
+    assert len(sizes) == ng and sizes.min() == per and int(np.sum((sizes + 63) // 64)) > 256
+    b0 = s.numpy_state()
+    exp = oracle.drift_levels(b0, rcl, 2, 1.0, DT5, pairs)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    compare("chains 2x2", got, exp, gid)
+    s.close()
+
+
 @pytest.mark.parametrize("nlev,nsub", [(2, 2), (3, 2), (2, 3), (4, 2)])
 def test_ring_drift_with_levels(nlev, nsub):
     d = discs.ring_dense(1000)
