@@ -126,6 +126,27 @@ def test_many_large_groups_more_tiles_than_cus():
     s.close()
 
 
+def test_large_groups_with_no_encounters_equal_the_plain_path():
+    """Degenerate case: r_crit so small that no pair is listed; with the large-group mode on,
+    three steps equal those of the plain path bit for bit (Kepler and Sun drifts only), in
+    both kick precisions."""
+    d = discs.ring_dense(1000)
+    rc = np.full(d.n, 1e-9)
+    for prec in (FP64, FP32):
+        out = []
+        for large in (False, True):
+            s = System([d], rcrit=rc)
+            genga.genga_set_large_groups(s.ctx.handle, large)
+            genga.genga_set_kick_shape(s.ctx.handle, prec, 8, 1)
+            genga.genga_step(s.ctx.handle, s.b, DT5, 3, prec)
+            assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+            assert s.encounter_list()[1] == 0
+            out.append(s.numpy_state())
+            s.close()
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 def test_group_above_limit_refused_before_drift():
     """66000 bodies in a chain (each within r_crit of its two neighbours on either side) form
     one group above the 65536-body limit: the drift is refused with GENGA_ERR_CAPACITY and the
