@@ -70,6 +70,26 @@ def test_chains_two_levels_more_tiles_than_cus():
     s.close()
 
 
+def test_levels_with_no_encounters_equal_the_plain_path():
+    """Degenerate case: radii so small that no pair is listed at any level; three steps with
+    3 levels x 2 sub-steps equal those of the plain path bit for bit."""
+    d = discs.ring_dense(1000)
+    out = []
+    for nlev in (1, 3):
+        s = System([d], rcrit=np.full(d.n, 1e-9))
+        genga.genga_set_large_groups(s.ctx.handle, True)
+        if nlev > 1:
+            t = s.torch.full((nlev - 1, d.n), 1e-10, dtype=s.torch.float64, device="cuda")
+            genga.genga_set_levels(s.ctx.handle, nlev, 2, t)
+        genga.genga_set_kick_shape(s.ctx.handle, FP64, 8, 1)
+        genga.genga_step(s.ctx.handle, s.b, DT5, 3, FP64)
+        assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+        out.append(s.numpy_state())
+        s.close()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 @pytest.mark.parametrize("nlev,nsub", [(2, 2), (3, 2), (2, 3), (4, 2)])
 def test_ring_drift_with_levels(nlev, nsub):
     d = discs.ring_dense(1000)
