@@ -91,7 +91,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_merge.argtypes = [i64, i32p] + [d] * 8 + [i32p]
         L.oracle_remove.argtypes = [i64] + [d] * 4 + [i32p, ctypes.c_double, ctypes.c_double]
         L.oracle_step_collide.restype = ctypes.c_int
-        L.oracle_step_collide.argtypes = [i64, i64] + [d] * 9 + [i32p] + [ctypes.c_double] * 2 + \
+        L.oracle_step_collide.argtypes = [i64, i64] + [d] * 8 + [i64, i64, d, i32p] + [ctypes.c_double] * 2 + \
             [i64] + [ctypes.c_double] * 3
         _lib = L
     return _lib
@@ -348,15 +348,20 @@ def remove(st, status, r_min: float, r_max: float):
 
 
 def step_collide(st, rc, radius, status, mstar: float, dt: float, nsteps: int, r_min: float, r_max: float,
-                 tol: float = BS_TOL, n_massive: Optional[int] = None):
-    """nsteps full steps with collisions and removal; returns (state, radius, status)."""
+                 tol: float = BS_TOL, n_massive: Optional[int] = None, nsub: int = 1):
+    """nsteps full steps with collisions and removal; returns (state, radius, status).  rc is
+    the r_crit array, or [nlev][n] radii of levels 0..nlev-1 for the hierarchical step with
+    nsub sub-steps per level."""
     s = _mut(st)
     n = len(s["x"])
+    rcl = np.ascontiguousarray(np.atleast_2d(np.asarray(rc, dtype=np.float64)))
+    nlev = rcl.shape[0]
     rad = np.array(radius, dtype=np.float64)
     stt = np.array(status, dtype=np.int32)
     bad = lib().oracle_step_collide(n, _nm(n, n_massive), *[_p(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m")],
-                                    _p(_f64(rc)), _p(rad), _p(stt, ctypes.c_int32), float(mstar), float(dt),
-                                    int(nsteps), float(tol), float(r_min), float(r_max))
+                                    _p(rcl), int(nlev), int(nsub if nlev > 1 else 1), _p(rad),
+                                    _p(stt, ctypes.c_int32), float(mstar), float(dt), int(nsteps), float(tol),
+                                    float(r_min), float(r_max))
     if bad:
         raise RuntimeError("oracle step failed")
     return s, rad, stt

@@ -830,13 +830,16 @@ int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *
     return oracle_step_levels(n, nm, x, y, z, vx, vy, vz, m, rc, 1, 1, mstar, dt, nsteps, tol, cadence, energy);
 }
 
-/* Full steps with collisions and removal: as oracle_step (one level), with the colliding
- * pairs found at the start of each drift (from the encounter list of the first half-kick)
- * and merged after it, then removal by distance.  m, radius and status are updated. */
+/* Full steps with collisions and removal: as oracle_step_levels (rcl holds the radii of
+ * levels 0..nlev-1, nlev = nsub = 1 for the plain step), with the colliding pairs found at the
+ * start of each drift (from the encounter list of the first half-kick) and merged after it,
+ * then removal by distance.  m, radius and status are updated. */
 int oracle_step_collide(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
-                        double *vz, double *m, const double *rc, double *radius, int32_t *status,
-                        double mstar, double dt, int64_t nsteps, double tol, double r_min, double r_max)
+                        double *vz, double *m, const double *rcl, int64_t nlev, int64_t nsub, double *radius,
+                        int32_t *status, double mstar, double dt, int64_t nsteps, double tol, double r_min,
+                        double r_max)
 {
+    const double *rc = rcl; /* level 0: the kick's changeover and the encounter list */
     double *ax = (double *)malloc(sizeof(double) * (size_t)(3 * (n > 0 ? n : 1)));
     double *ay = ax + n, *az = ay + n;
     int64_t cap = 16 * n + 16;
@@ -855,7 +858,7 @@ int oracle_step_collide(int64_t n, int64_t nm, double *x, double *y, double *z, 
             np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
         }
         int64_t nc = oracle_collisions(np, pairs, x, y, z, vx, vy, vz, radius, status, dt, col);
-        bad |= oracle_drift(n, nm, x, y, z, vx, vy, vz, m, rc, mstar, dt, np, pairs, tol);
+        bad |= oracle_drift_levels(n, nm, x, y, z, vx, vy, vz, m, rcl, nlev, nsub, mstar, dt, np, pairs, tol);
         oracle_merge(nc, col, x, y, z, vx, vy, vz, m, radius, status);
         oracle_remove(n, x, y, z, m, status, r_min, r_max);
         kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);

@@ -120,3 +120,25 @@ def test_mergers_with_test_bodies():
     assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
     check_against_oracle("mergers TP2", s, rad, status, exp, erad, est, 1e-10)
     s.close()
+
+
+def test_mergers_with_levels():
+    """Collisions with the hierarchical step (2 levels x 2 sub-steps): 10 FP64 steps of the
+    ring with inflated radii against the oracle's step_collide over the same levels."""
+    d = discs.ring_dense(300)
+    rcl = oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, 2, 2)
+    s = System([d], rcrit=rcl[0])
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    torch = s.torch
+    t = torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=torch.float64, device="cuda")
+    genga.genga_set_levels(s.ctx.handle, 2, 2, t)
+    rad = torch.full((d.n,), R, dtype=torch.float64, device="cuda")
+    status = torch.zeros(d.n, dtype=torch.int32, device="cuda")
+    genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, 0.0, 1e9)
+    exp, erad, est = oracle.step_collide(d.state(), rcl, np.full(d.n, R), np.zeros(d.n, np.int32), 1.0, DT5, 10,
+                                         0.0, 1e9, nsub=2)
+    assert (est == 1).sum() >= 1
+    genga.genga_step(s.ctx.handle, s.b, DT5, 10, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("mergers with levels", s, rad, status, exp, erad, est, 1e-10)
+    s.close()

@@ -111,3 +111,24 @@ def test_collide_steps_conserve_mass_and_merge_some_bodies():
     assert np.all(out["m"][stt != 0] == 0.0) and np.all(out["m"][stt == 0] > 0.0)
     # merged survivors carry the summed volume
     assert abs(np.sum(rad2[stt == 0] ** 3) - np.sum(rad ** 3)) <= 1e-12 * np.sum(rad ** 3)
+
+
+def test_collide_steps_with_levels():
+    """Collisions composed with the hierarchical step (Sect. 1 levels, Sect. 2 mergers): with
+    radii of zero nothing collides and the steps equal oracle.step_levels bit for bit; with
+    inflated radii mass and volume are conserved and dead bodies have zero mass."""
+    d = discs.ring_dense(300)
+    st = d.state()
+    rcl = oracle.rcrit_levels(st, 1.0, 3.0, 0.4, DT, 2, 2)
+    none, r0, s0 = oracle.step_collide(st, rcl, np.zeros(d.n), np.zeros(d.n, np.int32), 1.0, DT, 3, 0.0, 1e9,
+                                       nsub=2)
+    exp, _ = oracle.step_levels(st, rcl, 2, 1.0, DT, 3)
+    assert np.all(s0 == 0)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(none[k], exp[k])
+    rad = np.full(d.n, 2e-3)
+    out, rad2, stt = oracle.step_collide(st, rcl, rad, np.zeros(d.n, np.int32), 1.0, DT, 10, 0.0, 1e9, nsub=2)
+    assert (stt == 1).sum() >= 1
+    assert abs(out["m"].sum() - st["m"].sum()) <= 1e-15 * st["m"].sum()
+    assert np.all(out["m"][stt != 0] == 0.0)
+    assert abs(np.sum(rad2[stt == 0] ** 3) - np.sum(rad ** 3)) <= 1e-12 * np.sum(rad ** 3)
