@@ -70,6 +70,35 @@ def test_chains_two_levels_more_tiles_than_cus():
     s.close()
 
 
+def test_levels_in_a_batch_of_two_systems():
+    """Two rings in one batch (300 and 500 bodies), 2 levels x 2 sub-steps: each system's
+    drift against the oracle's drift_levels of that system alone."""
+    ds = [discs.ring_dense(300, seed=31), discs.ring_dense(500, seed=32)]
+    rcls = [oracle.rcrit_levels(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5, 2, 2) for d in ds]
+    rcl = np.concatenate(rcls, axis=1)
+    s = System(ds, rcrit=rcl[0])
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+    genga.genga_set_levels(s.ctx.handle, 2, 2, t)
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    b0 = s.numpy_state()
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    for k, d in enumerate(ds):
+        sl = s.system_slice(k)
+        lo, hi = sl.start, sl.stop
+        mine = pairs[(pairs[:, 0] >= lo) & (pairs[:, 0] < hi)] - lo
+        assert np.all((mine >= 0) & (mine < d.n))
+        st0 = {key: b0[key][sl] for key in b0}
+        exp = oracle.drift_levels(st0, rcls[k], 2, d.mstar, DT5, mine)
+        gid = oracle.groups(d.n, mine)
+        print(f"[batch {k}] pairs={len(mine)} groups={gid.max() + 1}", flush=True)
+        compare(f"batch {k}", {key: got[key][sl] for key in got}, exp, gid)
+    s.close()
+
+
 def test_levels_with_no_encounters_equal_the_plain_path():
     """Degenerate case: radii so small that no pair is listed at any level; three steps with
     3 levels x 2 sub-steps equal those of the plain path bit for bit."""
