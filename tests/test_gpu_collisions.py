@@ -142,3 +142,43 @@ def test_mergers_with_levels():
     assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
     check_against_oracle("mergers with levels", s, rad, status, exp, erad, est, 1e-10)
     s.close()
+
+
+def test_collisions_in_a_batch_then_compaction():
+    """Two rings in one batch with mergers and removal inside 0.82 au / beyond 0.88 au over
+    10 steps, each system against the oracle's step_collide of that system alone; then the
+    compaction keeps every system's survivors in order."""
+    ds = [discs.ring_dense(300, seed=41), discs.ring_dense(400, seed=42)]
+    rcs = [oracle.rcrit(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5) for d in ds]
+    s = System(ds, rcrit=np.concatenate(rcs))
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    torch = s.torch
+    rad = torch.full((s.n,), R, dtype=torch.float64, device="cuda")
+    status = torch.zeros(s.n, dtype=torch.int32, device="cuda")
+    genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, 0.82, 0.88)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 10, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    got = s.numpy_state()
+    gst, grad = status.cpu().numpy(), rad.cpu().numpy()
+    keep = []
+    for k, d in enumerate(ds):
+        sl = s.system_slice(k)
+        exp, erad, est = oracle.step_collide(d.state(), rcs[k], np.full(d.n, R), np.zeros(d.n, np.int32), 1.0, DT5,
+                                             10, 0.82, 0.88)
+        print(f"[batch {k}] merged {int((est == 1).sum())} removed {int((est == 2).sum())}", flush=True)
+        assert np.array_equal(gst[sl], est)
+        assert np.array_equal(got["m"][sl], exp["m"])
+        assert np.allclose(grad[sl], erad, rtol=4e-16, atol=0)
+        for key in ("x", "y", "z", "vx", "vy", "vz"):
+            assert np.max(np.abs(got[key][sl] - exp[key])) <= 1e-10
+        keep.append(est == 0)
+    keep = np.concatenate(keep)
+    assert (~keep).sum() >= 2
+    n_new = genga.genga_compact(s.ctx.handle, s.b, rad, status)
+    assert n_new == int(keep.sum())
+    after = s.numpy_state()
+    for key in ("x", "y", "z", "vx", "vy", "vz", "m"):
+        assert np.array_equal(after[key][:n_new], got[key][keep])
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP64)   # the compacted batch steps on
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    s.close()
