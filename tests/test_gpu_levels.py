@@ -99,6 +99,35 @@ def test_levels_in_a_batch_of_two_systems():
     s.close()
 
 
+def test_levels_resume_is_bit_identical():
+    """Two calls of two steps with 3 levels x 2 sub-steps in one context equal two steps, a
+    save of the state to the host, a fresh context from it and two more steps (FP32 kick).
+    The checkpoint sits at a call boundary in both runs: within one call the closing and
+    opening half-kicks of consecutive steps are merged into one kick."""
+    d = discs.ring_dense(1000)
+    s, rcl = level_system(d, 3, 2)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    whole = s.numpy_state()
+    s.close()
+    s, _ = level_system(d, 3, 2)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    saved = s.numpy_state()
+    s.close()
+    d2 = discs.Disc(*(saved[k] for k in ("x", "y", "z", "vx", "vy", "vz", "m")), mstar=d.mstar)
+    s = System([d2], rcrit=rcl[0])
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    t = s.torch.tensor(np.ascontiguousarray(rcl[1:]), dtype=s.torch.float64, device="cuda")
+    genga.genga_set_levels(s.ctx.handle, 3, 2, t)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    resumed = s.numpy_state()
+    s.close()
+    for k in whole:
+        np.testing.assert_array_equal(whole[k], resumed[k])
+
+
 def test_levels_with_no_encounters_equal_the_plain_path():
     """Degenerate case: radii so small that no pair is listed at any level; three steps with
     3 levels x 2 sub-steps equal those of the plain path bit for bit."""
