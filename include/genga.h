@@ -91,7 +91,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
  * synchronises the device and drops any captured graph. */
 int genga_set_test_bodies(genga_ctx *ctx, const int32_t *n_massive_host);
 
-/* Encounter groups of more than 64 bodies (the encounter-dominated phase of Sect. 4, where
+/* Encounter groups of more than 64 bodies (the encounter-dominated phase of Sect. 3.5, where
  * with the full eq. (1) the groups can span most of a disc).  enable = 0 (the default): such a
  * group raises GENGA_ERR_CAPACITY and its bodies are only Kepler-drifted.  enable = 1: they
  * are integrated by the same FP64 Bulirsch-Stoer method as the small groups, with the group's

@@ -1,5 +1,5 @@
 // Bulirsch-Stoer over dt for encounter groups larger than one wavefront.  In the
-// encounter-dominated phase (Sect. 4: many planetesimals form almost one large close-encounter
+// encounter-dominated phase (Sect. 3.5: many planetesimals form almost one large close-encounter
 // group and the run is bound by the Bulirsch-Stoer step) a group can hold most of a disc, so
 // its state is spread over the whole GPU.  Method, tolerance and step control are those of
 // the one-wave path and the oracle: modified midpoint with n_k = 2(k+1) sub-steps, polynomial

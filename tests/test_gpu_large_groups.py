@@ -1,4 +1,4 @@
-"""Encounter-dominated regime (Sect. 4): with the full eq. (1) (n1 = 3, n2 = 0.4) on the
+"""Encounter-dominated regime (Sect. 3.5): with the full eq. (1) (n1 = 3, n2 = 0.4) on the
 paper's dense annulus the encounter groups grow past one wavefront, up to the whole disc.
 The grid-wide Bulirsch-Stoer path (genga_set_large_groups) against the oracle's drift and
 steps, on the GPU's own input state."""

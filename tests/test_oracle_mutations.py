@@ -47,6 +47,12 @@ MUTATIONS = [
      "kick(n, nm, x, y, z, vx, vy, vz, m, rc, 0.5 * dt, ax, ay, az);\n        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);\n        if (np > cap) {\n            free(pairs);\n            cap = np;",
      "kick(n, nm, x, y, z, vx, vy, vz, m, rc, dt, ax, ay, az);\n        int64_t np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);\n        if (np > cap) {\n            free(pairs);\n            cap = np;"),
     ("Hill radius factor 3", "double rh = a * cbrt(m[i] / (3.0 * mstar));", "double rh = a * cbrt(m[i] / mstar);"),
+    ("Hill radius with the distance for a", "double a = (inv_a > 0.0) ? 1.0 / inv_a : r;", "double a = r;"),
+    ("Kepler velocity read as the speed", "double vk = sqrt(mstar / a);", "double vk = sqrt(v2);"),
+    ("unbound body keeps |1/inv_a|", "double a = (inv_a > 0.0) ? 1.0 / inv_a : r;",
+     "double a = (inv_a > 0.0) ? 1.0 / inv_a : -1.0 / inv_a;"),
+    ("osculating 1/a with the speed unsquared", "double inv_a = 2.0 / r - v2 / mstar;",
+     "double inv_a = 2.0 / r - sqrt(v2) / mstar;"),
     ("TP2 test bodies interact", "        if (i >= nm && j >= nm) continue; /* two test bodies */\n", ""),
     ("TP2 energy keeps test pairs", "            if (i >= nm && j >= nm) continue;\n            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]",
      "            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];\n            s += m[j]"),

@@ -214,6 +214,63 @@ def test_rcrit_eq1_circular_orbits():
     np.testing.assert_allclose(oracle.rcrit(st, 1.0, 3.0, 0.4, dt), expect, rtol=1e-14)
 
 
+def _rotation(seed):
+    """A proper rotation matrix from a seeded Gaussian matrix (QR, sign-fixed)."""
+    q, r = np.linalg.qr(np.random.default_rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+@pytest.mark.parametrize("where", ["pericentre", "apocentre"])
+def test_rcrit_eq1_eccentric_orbits(where):
+    """eq. (1) off the circle: at pericentre r = a(1 - e) with v^2 = M(1 + e)/r, at apocentre
+    r = a(1 + e) with v^2 = M(1 - e)/r (Kepler's ellipse, textbook).  R_H uses the semi-major
+    axis a, not the distance, and the velocity term the Kepler velocity sqrt(M/a), not |v|;
+    on a circle both readings agree; here r/a = 1 -+ e and |v|/sqrt(M/a) = sqrt((1 +- e)/(1 -+ e))
+    (upper signs at pericentre)."""
+    mstar = 1.3
+    a = np.array([0.6, 1.0, 1.7, 3.2])
+    e = np.array([0.05, 0.3, 0.6, 0.9])
+    m = np.array([2e-9, 4e-10, 3e-7, 1e-12])
+    sgn = -1.0 if where == "pericentre" else 1.0
+    r = a * (1.0 + sgn * e)
+    v = np.sqrt(mstar * (1.0 - sgn * e) / r)
+    R = _rotation(7 if where == "pericentre" else 8)
+    pos = (R @ np.stack([r, np.zeros(4), np.zeros(4)])).T
+    vel = (R @ np.stack([np.zeros(4), v, np.zeros(4)])).T
+    st = state(pos, vel, m)
+    dt = discs.DT_6_DAYS
+    rh = a * np.cbrt(m / (3.0 * mstar))
+    np.testing.assert_allclose(oracle.rcrit(st, mstar, 3.0, 0.0, dt), 3.0 * rh, rtol=1e-12)
+    # n2 large enough that the velocity term decides every body
+    vk = np.sqrt(mstar / a)
+    np.testing.assert_allclose(oracle.rcrit(st, mstar, 0.0, 0.4, dt), 0.4 * dt * vk, rtol=1e-12)
+    np.testing.assert_allclose(oracle.rcrit(st, mstar, 3.0, 0.4, dt),
+                               np.maximum(3.0 * rh, 0.4 * dt * vk), rtol=1e-12)
+
+
+def test_rcrit_eq1_unbound_orbits():
+    """eq. (1) for a body that is not bound to the star (v^2 >= 2M/r: no semi-major axis):
+    the distance |r| stands in for a, in R_H and in the Kepler velocity sqrt(M/|r|).  The
+    parabolic speed sqrt(2M/r) is the boundary case, a hyperbolic speed the general one."""
+    mstar = 1.0
+    r = np.array([0.8, 1.5, 2.0])
+    v = np.array([1.0, 1.5, 3.0]) * np.sqrt(2.0 * mstar / r)
+    m = np.array([3e-9, 1e-6, 5e-10])
+    R = _rotation(9)
+    pos = (R @ np.stack([r, np.zeros(3), np.zeros(3)])).T
+    # the velocity at 60 degrees to the radius: the unbound test must not depend on direction
+    vel = (R @ np.stack([0.5 * v, np.sqrt(0.75) * v, np.zeros(3)])).T
+    st = state(pos, vel, m)
+    dt = discs.DT_6_DAYS
+    rh = r * np.cbrt(m / (3.0 * mstar))
+    np.testing.assert_allclose(oracle.rcrit(st, mstar, 3.0, 0.0, dt), 3.0 * rh, rtol=1e-12)
+    np.testing.assert_allclose(oracle.rcrit(st, mstar, 0.0, 0.4, dt), 0.4 * dt * np.sqrt(mstar / r),
+                               rtol=1e-12)
+
+
 # ------------------------------------------------------------------------------------------
 # Encounter list and groups
 # ------------------------------------------------------------------------------------------
