@@ -140,24 +140,43 @@ void oracle_accel_rows(int64_t n, int64_t nm, const double *x, const double *y, 
  * lexicographic order.  Returns the number of pairs (which may exceed cap; only the
  * first cap are written).
  * ---------------------------------------------------------------------------------- */
+static int is_encounter(int64_t nm, int64_t i, int64_t j, const double *x, const double *y, const double *z,
+                        const double *rc)
+{
+    if (i >= nm && j >= nm) return 0; /* test bodies do not meet each other */
+    double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+    double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+    return sep2(dx, dy, dz) < rcij * rcij;
+}
+
+/* Rows i in parallel: a first pass counts each row's pairs, their prefix sums place every row
+ * in the output, a second pass writes the pairs (i ascending, then j): the order and the
+ * decisions are those of the plain double loop. */
 int64_t oracle_encounters(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
                           const double *rc, int64_t cap, int32_t *pairs)
 {
-    int64_t cnt = 0;
+    int64_t *first = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i) {
-        for (int64_t j = i + 1; j < n; ++j) {
-            if (i >= nm && j >= nm) continue; /* test bodies do not meet each other */
-            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
-            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
-            if (sep2(dx, dy, dz) < rcij * rcij) {
-                if (cnt < cap) {
-                    pairs[2 * cnt] = (int32_t)i;
-                    pairs[2 * cnt + 1] = (int32_t)j;
-                }
-                cnt++;
-            }
-        }
+        int64_t c = 0;
+        for (int64_t j = i + 1; j < n; ++j) c += is_encounter(nm, i, j, x, y, z, rc);
+        first[i + 1] = c;
     }
+    first[0] = 0;
+    for (int64_t i = 0; i < n; ++i) first[i + 1] += first[i];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        if (first[i] == first[i + 1] || first[i] >= cap) continue;
+        int64_t k = first[i];
+        for (int64_t j = i + 1; j < n && k < cap; ++j)
+            if (is_encounter(nm, i, j, x, y, z, rc)) {
+                pairs[2 * k] = (int32_t)i;
+                pairs[2 * k + 1] = (int32_t)j;
+                ++k;
+            }
+    }
+    int64_t cnt = first[n];
+    free(first);
     return cnt;
 }
 
@@ -704,7 +723,10 @@ int oracle_drift(int64_t n, int64_t nm, double *x, double *y, double *z, double 
  *    a body already merged in this step: body i keeps m_i + m_j, the mass-weighted position
  *    and velocity (momentum is kept) and radius (R_i^3 + R_j^3)^(1/3); body j gets m = 0 and
  *    status 1;
- *  - then every live body with |r| < r_min or |r| > r_max gets m = 0 and status 2.
+ *  - then every live body with |r| < r_min or |r| > r_max gets m = 0 and status 2;
+ *  - a body with status != 0 is in no encounter pair from then on: with m = 0 it exerts no
+ *    force, and it moves on as a massless particle (kicked by the live bodies' K-weighted
+ *    forces, Kepler-drifted) until the arrays are compacted.
  * status: 0 live, 1 merged into another body, 2 removed by distance.
  * ---------------------------------------------------------------------------------- */
 int64_t oracle_collisions(int64_t npairs, const int32_t *pairs, const double *x, const double *y,
@@ -755,6 +777,20 @@ void oracle_merge(int64_t ncol, const int32_t *col, double *x, double *y, double
         m[j] = 0.0;
         status[j] = 1;
     }
+}
+
+/* Keep the pairs of two live bodies (order kept); returns their number. */
+static int64_t live_pairs(int64_t npairs, int32_t *pairs, const int32_t *status)
+{
+    int64_t k = 0;
+    for (int64_t p = 0; p < npairs; ++p) {
+        int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        if (status[i] || status[j]) continue;
+        pairs[2 * k] = i;
+        pairs[2 * k + 1] = j;
+        ++k;
+    }
+    return k;
 }
 
 void oracle_remove(int64_t n, const double *x, const double *y, const double *z, double *m,
@@ -832,8 +868,9 @@ int oracle_step(int64_t n, int64_t nm, double *x, double *y, double *z, double *
 
 /* Full steps with collisions and removal: as oracle_step_levels (rcl holds the radii of
  * levels 0..nlev-1, nlev = nsub = 1 for the plain step), with the colliding pairs found at the
- * start of each drift (from the encounter list of the first half-kick) and merged after it,
- * then removal by distance.  m, radius and status are updated. */
+ * start of each drift (from the encounter list of the first half-kick, pairs with a body of
+ * status != 0 left out) and merged after it, then removal by distance.  m, radius and status
+ * are updated. */
 int oracle_step_collide(int64_t n, int64_t nm, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, double *m, const double *rcl, int64_t nlev, int64_t nsub, double *radius,
                         int32_t *status, double mstar, double dt, int64_t nsteps, double tol, double r_min,
@@ -857,6 +894,7 @@ int oracle_step_collide(int64_t n, int64_t nm, double *x, double *y, double *z, 
             col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * cap));
             np = oracle_encounters(n, nm, x, y, z, rc, cap, pairs);
         }
+        np = live_pairs(np, pairs, status);
         int64_t nc = oracle_collisions(np, pairs, x, y, z, vx, vy, vz, radius, status, dt, col);
         bad |= oracle_drift_levels(n, nm, x, y, z, vx, vy, vz, m, rcl, nlev, nsub, mstar, dt, np, pairs, tol);
         oracle_merge(nc, col, x, y, z, vx, vy, vz, m, radius, status);

@@ -132,3 +132,34 @@ def test_collide_steps_with_levels():
     assert abs(out["m"].sum() - st["m"].sum()) <= 1e-15 * st["m"].sum()
     assert np.all(out["m"][stt != 0] == 0.0)
     assert abs(np.sum(rad2[stt == 0] ** 3) - np.sum(rad ** 3)) <= 1e-12 * np.sum(rad ** 3)
+
+
+def test_dead_body_leaves_the_encounter_groups():
+    """A body that has merged (status 1, m = 0) takes part in no encounter pair.  Placed
+    1e-4 au ahead of a live body on the same circular orbit (K = 0 there: well inside
+    0.1 r_crit), it must not be integrated with that body, whose (1 - K) force would pull it
+    in within a step; it moves on as a massless particle.  With a second live body on the
+    opposite side of the orbit (total momentum zero, so the Sun drift is nil) the only force
+    on it besides the Sun's is the far body's K = 1 pull (about 2.5e-10), so it follows the
+    Sun-only Kepler orbit (scipy DOP853) to 1e-9 au over 10 steps."""
+    from scipy.integrate import solve_ivp
+
+    phi = 1e-4
+    pos = np.array([[1.0, 0.0, 0.0], [np.cos(phi), np.sin(phi), 0.0], [-1.0, 0.0, 0.0]])
+    vel = np.array([[0.0, 1.0, 0.0], [-np.sin(phi), np.cos(phi), 0.0], [0.0, -1.0, 0.0]])
+    m = np.array([1e-9, 0.0, 1e-9])
+    st = dict(x=pos[:, 0].copy(), y=pos[:, 1].copy(), z=pos[:, 2].copy(), vx=vel[:, 0].copy(),
+              vy=vel[:, 1].copy(), vz=vel[:, 2].copy(), m=m)
+    dt = discs.DT_6_DAYS
+    rc = oracle.rcrit(dict(st, m=np.array([1e-9, 1e-9, 1e-9])), 1.0, 3.0, 0.0, dt)
+    assert phi < 0.1 * rc[0]
+    out, rad, stt = oracle.step_collide(st, rc, [0.0, 0.0, 0.0], [0, 1, 0], 1.0, dt, 10, 0.0, 1e9)
+    assert list(stt) == [0, 1, 0]
+
+    def f(t, y):
+        r3 = np.linalg.norm(y[:3]) ** 3
+        return np.concatenate([y[3:], -y[:3] / r3])
+
+    sol = solve_ivp(f, (0.0, 10 * dt), np.concatenate([pos[1], vel[1]]), method="DOP853", rtol=1e-13, atol=1e-15)
+    got = np.array([out["x"][1], out["y"][1], out["z"][1]])
+    assert np.max(np.abs(got - sol.y[:3, -1])) < 1e-9

@@ -70,13 +70,18 @@ MUTATIONS = [
     ("level kick target mass", "double s = m[j] * w / (r2 * r);", "double s = m[i] * w / (r2 * r);"),
     ("collision closest approach unclamped", "            if (t > dt) t = dt;\n", ""),
     ("collision radius sum", "double rs = radius[i] + radius[j];", "double rs = radius[i];"),
+    ("collision groups keep dead bodies", "        np = live_pairs(np, pairs, status);\n", ""),
     ("merge velocity weights swapped", "vx[i] = (mi * vx[i] + mj * vx[j]) / mt;", "vx[i] = (mj * vx[i] + mi * vx[j]) / mt;"),
     ("merge radius adds radii", "radius[i] = cbrt(radius[i] * radius[i] * radius[i] + radius[j] * radius[j] * radius[j]);",
      "radius[i] = radius[i] + radius[j];"),
     ("removal inner radius unsquared", "if (r2 < r_min * r_min || r2 > r_max * r_max) {", "if (r2 < r_min || r2 > r_max * r_max) {"),
     ("merge of an already merged body", "        if (status[i] || status[j]) continue;\n        double mi = m[i]", "        double mi = m[i]"),
-    ("encounter self pairs", "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i + 1;",
-     "int64_t cnt = 0;\n    for (int64_t i = 0; i < n; ++i) {\n        for (int64_t j = i;"),
+    ("encounter self pairs counted", "for (int64_t j = i + 1; j < n; ++j) c += is_encounter",
+     "for (int64_t j = i; j < n; ++j) c += is_encounter"),
+    ("encounter self pairs listed", "for (int64_t j = i + 1; j < n && k < cap; ++j)",
+     "for (int64_t j = i; j < n && k < cap; ++j)"),
+    ("encounter pair radius min", "    double rcij = rc[i] > rc[j] ? rc[i] : rc[j];\n    return sep2",
+     "    double rcij = rc[i] < rc[j] ? rc[i] : rc[j];\n    return sep2"),
 ]
 
 
