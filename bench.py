@@ -86,7 +86,7 @@ def time_steps(ctx, b, prec, steps, warmup, n_sys, torch, stream):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        genga.genga_step(ctx.handle, b, DT, steps, prec, CADENCE, e_rec, stream=stream)
+        genga.genga_step(ctx.handle, b, DT, steps, prec, energy_cadence=CADENCE, d_energy=e_rec, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     status = genga.genga_poll_status(ctx.handle)
@@ -255,7 +255,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     genga.genga_kick(ctx.handle, b, 0.0, genga.GENGA_KICK_FP32)
     pairs = torch.zeros(2 * cap, dtype=torch.int32, device="cuda:0")
     cnt = torch.zeros(1, dtype=torch.int32, device="cuda:0")
-    genga.genga_encounter_list(ctx.handle, pairs, cap, cnt)
+    genga.genga_encounter_list(ctx.handle, None, pairs, cap, cnt)
     torch.cuda.synchronize()
     npair = int(cnt.item())
     assert npair <= cap, "encounter list above its capacity"

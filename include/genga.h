@@ -60,6 +60,13 @@ typedef enum {
  * always evaluated in FP64 (Sect. 1: encounter forces are always FP64). */
 typedef enum { GENGA_KICK_FP64 = 0, GENGA_KICK_FP32 = 1 } genga_kick_prec;
 
+/* Accumulator of the FP32 kick across blocks of 64 sources (the paper fixes none; the per-body
+ * sum is exact enough either way, see the kick below).  FP64: each block's FP32 partial sum is
+ * rounded into an FP64 accumulator.  KAHAN32: the partial sums are added into an FP32 sum with
+ * Kahan compensation, whose two FP32 words are combined in FP64 at the end.  The FP64 kick
+ * ignores the selector. */
+typedef enum { GENGA_ACC_FP64 = 0, GENGA_ACC_KAHAN32 = 1 } genga_acc_mode;
+
 /* State of all bodies (device SoA, float64, length n_total). */
 typedef struct {
     double *x, *y, *z;      /* heliocentric positions [au] */
@@ -168,34 +175,50 @@ int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *stat
 int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, double dt,
                 double *rc_out, void *stream);
 
-/* Long-range accelerations only (no velocity update), Sect. 1:
+/* Long-range accelerations only (no velocity update), Sect. 1 (the level-0 force of the
+ * hybrid step; FP32 pair arithmetic is the "Do Kick in single precision" switch of Sect. 4):
  *   a_i = sum_{j != i, same system} m_j K(r_ij) (r_j - r_i) / r_ij^3
  * with the changeover weight K of Chambers (1999), y = (r - 0.1 r_crit,ij)/(0.9 r_crit,ij),
- * r_crit,ij = max(r_crit,i, r_crit,j).  Writes ax, ay, az [n_total] (device).  Also
- * refreshes the context's encounter list for these positions. */
-int genga_accel(genga_ctx *ctx, const genga_bodies *b, int prec, double *ax, double *ay,
-                double *az, void *stream);
+ * r_crit,ij = max(r_crit,i, r_crit,j).  prec: genga_kick_prec; acc: genga_acc_mode (FP32 only).
+ * Writes ax, ay, az [n_total] (device).  Also refreshes the context's encounter list for these
+ * positions. */
+int genga_accel(genga_ctx *ctx, const genga_bodies *b, double *ax, double *ay, double *az, int prec,
+                int acc, void *stream);
 
 /* The kick (Sect. 1, level 0): v_i += tau * a_i with a_i as in genga_accel, in the given
- * precision.  The same launch records every pair (i < j) with r_ij^2 < r_crit,ij^2
- * (decided in FP64) into the context's encounter list, which the next genga_drift uses. */
-int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, void *stream);
+ * precision and accumulator.  The same launch records every pair (i < j) with
+ * r_ij^2 < r_crit,ij^2 (decided in FP64) into the context's encounter list, which the next
+ * genga_drift uses.  With collisions on, pairs with a body of status != 0 are not recorded. */
+int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, int acc, void *stream);
 
-/* Copy the encounter list of the last kick/accel into pairs[cap][2] (device int32, global
- * body indices, i < j), sorted lexicographically, and its full length into *d_count
- * (device int32; may exceed cap, or the context's capacity, in which case the list is
- * incomplete and GENGA_ERR_CAPACITY is also flagged). */
-int genga_encounter_list(genga_ctx *ctx, int32_t *pairs, int32_t cap, int32_t *d_count,
-                         void *stream);
+/* The close-encounter pair list (Sect. 1: the pairs closer than r_crit,ij, whose motion the
+ * encounter step integrates; GENGA keeps such a list per level):
+ *  - b == NULL: the list of the last genga_kick / genga_accel / genga_step of this context,
+ *    which must have run on the current positions (GENGA_ERR_STATE after a genga_drift,
+ *    a layout change or before any kick);
+ *  - b != NULL: the list for b's positions and r_crit, computed standalone (FP64 decision, no
+ *    forces); it also becomes the context's list, which the next genga_drift uses.
+ * Writes pairs[cap][2] (device int32, global body indices, i < j, one system), sorted
+ * lexicographically, and the list's full length into *d_count (device int32; it may exceed
+ * cap, or the context's capacity, in which case the list is incomplete and
+ * GENGA_ERR_CAPACITY is also flagged). */
+int genga_encounter_list(genga_ctx *ctx, const genga_bodies *b, int32_t *pairs, int32_t cap,
+                         int32_t *d_count, void *stream);
 
 /* The drift over dt (Sect. 1): Sun drift dt/2 (r_i += dt/2 * sum_j m_j v_j / Mstar), then the
  * FP64 Kepler drift about Mstar for bodies outside encounter groups and an FP64
- * Bulirsch-Stoer integration over dt of each group (connected component of the context's
- * encounter list) under the Sun's force plus the (1 - K) share of the members' mutual
- * forces, then Sun drift dt/2.  Unless genga_set_large_groups is on, groups larger than 64
- * bodies or more than 8192 bodies in encounters raise GENGA_ERR_CAPACITY (those bodies are
- * then only Kepler-drifted). */
-int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream);
+ * Bulirsch-Stoer integration over dt of each group (connected component of the encounter
+ * list) under the Sun's force plus the (1 - K) share of the members' mutual forces, then Sun
+ * drift dt/2.  pairs == NULL: the context's list (that of the last kick or of
+ * genga_encounter_list).  Otherwise the caller's list pairs[*d_count][2] (device int32, in any
+ * order; d_count a device int32) replaces it: it is checked on the device, and a pair that is
+ * not 0 <= i < j < n_total within one system drops the whole list (the drift then treats no
+ * body as in an encounter) and makes genga_poll_status report GENGA_ERR_ARG; entries beyond
+ * the context's pair capacity are ignored and flagged GENGA_ERR_CAPACITY.  Unless
+ * genga_set_large_groups is on, groups larger than 64 bodies or more than 8192 bodies in
+ * encounters raise GENGA_ERR_CAPACITY (those bodies are then only Kepler-drifted). */
+int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, const int32_t *pairs, const int32_t *d_count,
+                void *stream);
 
 /* Energy and angular momentum per system (Sect. 3.1 diagnostics), FP64:
  *   E = sum m v^2/2 + |sum m v|^2 / (2 Mstar) - sum Mstar m / r - sum_{i<j} m_i m_j / r_ij
@@ -203,27 +226,34 @@ int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream);
  * Writes d_out[n_sys][4] = (E, Lx, Ly, Lz) (device). */
 int genga_energy(genga_ctx *ctx, const genga_bodies *b, double *d_out, void *stream);
 
-/* nsteps full steps of the split Kick(dt/2) Drift(dt) Kick(dt/2), adjacent half-kicks
- * merged (nsteps + 1 force evaluations).  Velocities are synchronised on entry and exit.
- * If energy_cadence > 0 and d_energy != NULL, record k (k = 0, 1, ...) of
- * d_energy[nsteps / energy_cadence][n_sys][4] receives (E, Lx, Ly, Lz) after
+/* nsteps full steps of the level-0 step of Sect. 1 in democratic heliocentric form,
+ * Kick(dt/2) Drift(dt) Kick(dt/2) with the kick and drift above, adjacent half-kicks merged
+ * (nsteps + 1 force evaluations).  Velocities are synchronised on entry and exit.  If
+ * energy_cadence > 0 and d_energy != NULL, record k (k = 0, 1, ...) of
+ * d_energy[nsteps / energy_cadence][n_sys][4] receives (E, Lx, Ly, Lz) of Sect. 3.1 after
  * (k + 1) * energy_cadence steps, for the synchronised velocities (the half-kicked
  * velocities minus dt/2 times the accelerations of the last kick). */
-int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec,
+int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int acc,
                int energy_cadence, double *d_energy, void *stream);
 
-/* Capture genga_step(ctx, b, dt, nsteps, prec, 0, NULL) into a HIP graph held by the
- * context (replacing any earlier one).  Synchronises `stream` before capture. */
-int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec,
-                        void *stream);
+/* Capture genga_step(ctx, b, dt, nsteps, prec, acc, energy_cadence, d_energy) into a HIP graph
+ * held by the context (replacing any earlier one); every replay runs those nsteps steps and
+ * rewrites the same d_energy records.  Synchronises `stream` before capture. */
+int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int acc,
+                        int energy_cadence, double *d_energy, void *stream);
 
 /* Launch the captured graph `repeats` times on `stream`. */
 int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream);
 
 /* Time the kick's launch shapes (waves per workgroup x source split) on the current layout
  * and keep the fastest for `prec` (synchronises `stream`; computes accelerations only, the
- * velocities are not changed). */
-int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream);
+ * velocities are not changed).  cache_path (host string, may be NULL): a text file of earlier
+ * results, one line per (device, precision, layout); a line matching the device's
+ * architecture and compute-unit count, prec and the layout's system sizes and TP2 counts is
+ * applied without timing, otherwise the shapes are timed and a line is appended (the file is
+ * created if missing; a file that cannot be read or written returns GENGA_ERR_ARG, with the
+ * timed shape still applied). */
+int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, const char *cache_path, void *stream);
 
 /* Launch shape of the kick for `prec`: `waves` per workgroup (4, 8 or 16; 0 = default) and
  * `split`, the number of workgroups that share one block of 64 targets' sources (1..4;
@@ -232,8 +262,9 @@ int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream);
 int genga_set_kick_shape(genga_ctx *ctx, int prec, int waves, int split);
 int genga_get_kick_shape(genga_ctx *ctx, int prec, int *waves, int *split);
 
-/* Synchronise the device, then return and clear the deferred device status:
- * GENGA_ERR_CAPACITY, GENGA_ERR_NONFINITE, GENGA_ERR_NOCONVERGE or GENGA_OK. */
+/* Synchronise the stream of the context's last call, then return and clear the deferred
+ * device status: GENGA_ERR_ARG (an invalid pair in a caller's list), GENGA_ERR_CAPACITY,
+ * GENGA_ERR_NONFINITE, GENGA_ERR_NOCONVERGE or GENGA_OK. */
 int genga_poll_status(genga_ctx *ctx);
 
 /* Message for the last failing call on this thread ("" if none).  Owned by the library. */

@@ -30,6 +30,9 @@ GENGA_ERR_STATE = -6
 GENGA_KICK_FP64 = 0
 GENGA_KICK_FP32 = 1
 
+GENGA_ACC_FP64 = 0
+GENGA_ACC_KAHAN32 = 1
+
 # every entry point of include/genga.h
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
@@ -77,15 +80,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_tune_levels": [vp, bp, dbl, dbl, dbl, i32, i32, i32, ctypes.c_int, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
-        "genga_accel": [vp, bp, ctypes.c_int, vp, vp, vp, vp],
-        "genga_kick": [vp, bp, dbl, ctypes.c_int, vp],
-        "genga_encounter_list": [vp, vp, i32, vp, vp],
-        "genga_drift": [vp, bp, dbl, vp],
+        "genga_accel": [vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp],
+        "genga_kick": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, vp],
+        "genga_encounter_list": [vp, bp, vp, i32, vp, vp],
+        "genga_drift": [vp, bp, dbl, vp, vp, vp],
         "genga_energy": [vp, bp, vp, vp],
-        "genga_step": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
-        "genga_graph_capture": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, vp],
+        "genga_step": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
+        "genga_graph_capture": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp],
         "genga_graph_launch": [vp, ctypes.c_int, vp],
-        "genga_autotune": [vp, bp, ctypes.c_int, vp],
+        "genga_autotune": [vp, bp, ctypes.c_int, ctypes.c_char_p, vp],
         "genga_set_kick_shape": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int],
         "genga_get_kick_shape": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
         "genga_poll_status": [vp],
@@ -244,24 +247,30 @@ def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, st
                                       _stream(stream)))
 
 
-def genga_accel(ctx: int, b: Bodies, prec: int, ax, ay, az, stream=None) -> None:
+def genga_accel(ctx: int, b: Bodies, ax, ay, az, prec: int, acc: int = GENGA_ACC_FP64, stream=None) -> None:
     cb = b.c()
-    _check(load_library().genga_accel(ctx, ctypes.byref(cb), int(prec), _ptr(ax), _ptr(ay), _ptr(az),
+    _check(load_library().genga_accel(ctx, ctypes.byref(cb), _ptr(ax), _ptr(ay), _ptr(az), int(prec), int(acc),
                                       _stream(stream)))
 
 
-def genga_kick(ctx: int, b: Bodies, tau: float, prec: int, stream=None) -> None:
+def genga_kick(ctx: int, b: Bodies, tau: float, prec: int, acc: int = GENGA_ACC_FP64, stream=None) -> None:
     cb = b.c()
-    _check(load_library().genga_kick(ctx, ctypes.byref(cb), float(tau), int(prec), _stream(stream)))
+    _check(load_library().genga_kick(ctx, ctypes.byref(cb), float(tau), int(prec), int(acc), _stream(stream)))
 
 
-def genga_encounter_list(ctx: int, pairs, cap: int, d_count, stream=None) -> None:
-    _check(load_library().genga_encounter_list(ctx, _ptr(pairs), int(cap), _ptr(d_count), _stream(stream)))
+def genga_encounter_list(ctx: int, b: Optional[Bodies], pairs, cap: int, d_count, stream=None) -> None:
+    """b = None: the list of the last kick; else the list of b's positions, computed alone."""
+    cb = b.c() if b is not None else None
+    _check(load_library().genga_encounter_list(ctx, ctypes.byref(cb) if cb is not None else None, _ptr(pairs),
+                                               int(cap), _ptr(d_count), _stream(stream)))
 
 
-def genga_drift(ctx: int, b: Bodies, dt: float, stream=None) -> None:
+def genga_drift(ctx: int, b: Bodies, dt: float, pairs=None, d_count=None, stream=None) -> None:
+    """pairs = None: the context's encounter list; else a device int32 tensor of pairs and a
+    device int32 count."""
     cb = b.c()
-    _check(load_library().genga_drift(ctx, ctypes.byref(cb), float(dt), _stream(stream)))
+    _check(load_library().genga_drift(ctx, ctypes.byref(cb), float(dt), _ptr(pairs), _ptr(d_count),
+                                      _stream(stream)))
 
 
 def genga_energy(ctx: int, b: Bodies, d_out, stream=None) -> None:
@@ -269,26 +278,30 @@ def genga_energy(ctx: int, b: Bodies, d_out, stream=None) -> None:
     _check(load_library().genga_energy(ctx, ctypes.byref(cb), _ptr(d_out), _stream(stream)))
 
 
-def genga_step(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, energy_cadence: int = 0,
-               d_energy=None, stream=None) -> None:
+def genga_step(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, acc: int = GENGA_ACC_FP64,
+               energy_cadence: int = 0, d_energy=None, stream=None) -> None:
     cb = b.c()
-    _check(load_library().genga_step(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec),
+    _check(load_library().genga_step(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec), int(acc),
                                      int(energy_cadence), _ptr(d_energy), _stream(stream)))
 
 
-def genga_graph_capture(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, stream=None) -> None:
+def genga_graph_capture(ctx: int, b: Bodies, dt: float, nsteps: int, prec: int, acc: int = GENGA_ACC_FP64,
+                        energy_cadence: int = 0, d_energy=None, stream=None) -> None:
     cb = b.c()
-    _check(load_library().genga_graph_capture(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec),
-                                              _stream(stream)))
+    _check(load_library().genga_graph_capture(ctx, ctypes.byref(cb), float(dt), int(nsteps), int(prec), int(acc),
+                                              int(energy_cadence), _ptr(d_energy), _stream(stream)))
 
 
 def genga_graph_launch(ctx: int, repeats: int, stream=None) -> None:
     _check(load_library().genga_graph_launch(ctx, int(repeats), _stream(stream)))
 
 
-def genga_autotune(ctx: int, b: Bodies, prec: int, stream=None) -> None:
+def genga_autotune(ctx: int, b: Bodies, prec: int, cache_path: Optional[str] = None, stream=None) -> None:
+    """Time the kick's launch shapes and keep the fastest; cache_path: a text file of earlier
+    results (read, and appended to on a miss)."""
     cb = b.c()
-    _check(load_library().genga_autotune(ctx, ctypes.byref(cb), int(prec), _stream(stream)))
+    path = os.fsencode(cache_path) if cache_path is not None else None
+    _check(load_library().genga_autotune(ctx, ctypes.byref(cb), int(prec), path, _stream(stream)))
 
 
 def genga_set_kick_shape(ctx: int, prec: int, waves: int, split: int = 0) -> None:

@@ -208,7 +208,51 @@ __global__ __launch_bounds__(SORT_THREADS) void sort_pairs_kernel(const int32_t 
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// A pair list handed in by the caller: every pair is checked before any launch indexes bodies
+// with it; one invalid pair drops the list.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void import_pairs_kernel(const int32_t *sys_of, int n_total, const int32_t *src,
+                                                           const int32_t *src_count, int32_t *dst, int32_t cap,
+                                                           int32_t *bad)
+{
+    const int n = min(*src_count, cap);
+    bool ok = true;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < n; p += gridDim.x * 256) {
+        const int i = src[2 * p], j = src[2 * p + 1];
+        const bool good = i >= 0 && i < j && j < n_total && sys_of[i] == sys_of[j];
+        ok = ok && good;
+        dst[2 * p] = good ? i : 0;
+        dst[2 * p + 1] = good ? j : 0;
+    }
+    if (!ok) atomicOr(bad, 1);
+}
+
+__global__ __launch_bounds__(64) void import_finish_kernel(const int32_t *src_count, int32_t *dst_count, int32_t cap,
+                                                           int32_t *bad, int32_t *flags)
+{
+    if (threadIdx.x != 0) return;
+    const int c = *src_count;
+    if (*bad || c < 0) {
+        *dst_count = 0;
+        atomicOr(flags, FLAG_BADPAIR);
+    } else {
+        *dst_count = c;
+        if (c > cap) atomicOr(flags, FLAG_CAPACITY);
+    }
+    *bad = 0;
+}
+
 } // namespace
+
+hipError_t launch_import_pairs(const Layout &L, const int32_t *src, const int32_t *src_count, int32_t *dst,
+                               int32_t *dst_count, int32_t cap, int32_t *bad, int32_t *flags, hipStream_t stream)
+{
+    const int blocks = std::max(1, std::min(1024, (cap + 255) / 256));
+    import_pairs_kernel<<<blocks, 256, 0, stream>>>(L.sys_of, L.n_total, src, src_count, dst, cap, bad);
+    import_finish_kernel<<<1, 64, 0, stream>>>(src_count, dst_count, cap, bad, flags);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,

@@ -56,6 +56,7 @@ hipError_t dalloc(T *&p, size_t count)
 struct genga_ctx {
     int device = 0;
     int n_cu = 256;
+    char arch[64] = "unknown";      // gcnArchName of the device (autotune cache key)
     Layout L;
     std::vector<int32_t> sys_off_h;
     std::vector<int32_t> n_massive_h; // per system; bodies beyond are TP2 test bodies
@@ -113,6 +114,12 @@ struct genga_ctx {
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // the context's encounter list belongs to the current positions (a kick or a standalone
+    // list ran on them, no drift since)
+    bool list_valid = false;
+    int32_t *import_bad = nullptr;     // device word of the pair-list import
+    hipStream_t last_stream = nullptr; // stream of the last enqueuing call (genga_poll_status)
+    int32_t *hpin = nullptr;           // pinned host word for genga_poll_status
 
     void release_big()
     {
@@ -207,6 +214,8 @@ struct genga_ctx {
         dfree(member_slot);
         dfree(epartial);
         dfree(kpart);
+        dfree(import_bad);
+        list_valid = false;
         dfree(col.list);
         dfree(col.count);
         col = CollideArgs{};
@@ -264,17 +273,24 @@ int check_prec(int prec)
     return GENGA_OK;
 }
 
+int check_acc(int acc)
+{
+    if (acc != GENGA_ACC_FP64 && acc != GENGA_ACC_KAHAN32) return fail(GENGA_ERR_ARG, "bad accumulator %d", acc);
+    return GENGA_OK;
+}
+
 // shift_tau != 0: the source-record pass first applies the pending second half of a Sun drift
 // (see enqueue_drift with defer_shift)
-int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v, int prec, double *ax,
+int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v, int prec, int acc, double *ax,
                  double *ay, double *az, hipStream_t s, double shift_tau = 0.0)
 {
     const Layout &L = ctx->L;
+    ctx->list_valid = true;
     if (L.n_total == 0) return GENGA_OK;
     const int fp32 = prec == GENGA_KICK_FP32;
     HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, fp32, ctx->rc2_part, ctx->pair_count,
                         ctx->mom_part, shift_tau, s));
-    KickArgs a;
+    KickArgs a{};
     a.items = ctx->items;
     a.n_items = ctx->n_items;
     a.sys_off = L.sys_off;
@@ -301,7 +317,42 @@ int enqueue_kick(genga_ctx *ctx, const genga_bodies *b, double tau, int update_v
     a.split = ctx->split[fp32];
     a.n_total = L.n_total;
     a.part = ctx->kpart;
-    HIP_TRY(launch_kick(a, fp32, ctx->waves[fp32], ctx->grid[fp32], s));
+    a.status = ctx->col.mass ? ctx->col.status : nullptr;
+    HIP_TRY(launch_kick(a, fp32, acc == GENGA_ACC_KAHAN32, ctx->waves[fp32], ctx->grid[fp32], s));
+    return GENGA_OK;
+}
+
+// The encounter list of b's positions alone (FP64 decision, no forces) into the context's list.
+int enqueue_pair_list(genga_ctx *ctx, const genga_bodies *b, hipStream_t s)
+{
+    const Layout &L = ctx->L;
+    ctx->list_valid = true;
+    if (L.n_total == 0) {
+        HIP_TRY(hipMemsetAsync(ctx->pair_count, 0, sizeof(int32_t), s));
+        return GENGA_OK;
+    }
+    HIP_TRY(launch_prep(L, b->x, b->y, b->z, b->m, b->rcrit, ctx->jrec, 0, ctx->rc2_part, ctx->pair_count, nullptr,
+                        0.0, s));
+    KickArgs a{};
+    a.items = ctx->items;
+    a.n_items = ctx->n_items;
+    a.sys_off = L.sys_off;
+    a.x = b->x;
+    a.y = b->y;
+    a.z = b->z;
+    a.m = b->m;
+    a.rc = b->rcrit;
+    a.jrec = ctx->jrec;
+    a.rc2_part = ctx->rc2_part;
+    a.chunk_first = L.chunk_first;
+    a.pairs = ctx->pairs;
+    a.pair_count = ctx->pair_count;
+    a.pair_cap = ctx->pair_cap;
+    a.flags = ctx->flags;
+    a.split = 1;
+    a.n_total = L.n_total;
+    a.status = ctx->col.mass ? ctx->col.status : nullptr;
+    HIP_TRY(launch_pair_list(a, 0, s));
     return GENGA_OK;
 }
 
@@ -317,6 +368,7 @@ int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
 int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, bool defer_shift = false)
 {
     const Layout &L = ctx->L;
+    ctx->list_valid = false;
     if (L.n_total == 0) return GENGA_OK;
     const bool collide = ctx->col.mass != nullptr;
     if (collide) {
@@ -840,12 +892,12 @@ int enqueue_energy(genga_ctx *ctx, const genga_bodies *b, double vshift, double 
     return GENGA_OK;
 }
 
-int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int cadence, double *d_energy,
-                 hipStream_t s)
+int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int acc, int cadence,
+                 double *d_energy, hipStream_t s)
 {
     const size_t n = (size_t)ctx->L.n_total;
     double *ax = ctx->acc, *ay = ctx->acc + n, *az = ctx->acc + 2 * n;
-    int rc = enqueue_kick(ctx, b, 0.5 * dt, 1, prec, ax, ay, az, s);
+    int rc = enqueue_kick(ctx, b, 0.5 * dt, 1, prec, acc, ax, ay, az, s);
     if (rc) return rc;
     int rec = 0;
     for (int k = 1; k <= nsteps; ++k) {
@@ -855,7 +907,7 @@ int enqueue_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int pre
         rc = enqueue_drift(ctx, b, dt, s, defer);
         if (rc) return rc;
         const bool last = k == nsteps;
-        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, ax, ay, az, s, defer ? 0.5 * dt : 0.0);
+        rc = enqueue_kick(ctx, b, last ? 0.5 * dt : dt, 1, prec, acc, ax, ay, az, s, defer ? 0.5 * dt : 0.0);
         if (rc) return rc;
         if (cadence > 0 && d_energy && k % cadence == 0) {
             rc = enqueue_energy(ctx, b, last ? 0.0 : 0.5 * dt, d_energy + (size_t)rec * 4 * ctx->L.n_sys, s);
@@ -912,8 +964,19 @@ int genga_create(genga_ctx **out, int device)
     HIP_TRY(hipSetDevice(device));
     genga_ctx *c = new genga_ctx();
     c->device = device;
+    if (hipHostMalloc((void **)&c->hpin, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(GENGA_ERR_HIP, "hipHostMalloc of the status word failed");
+    }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->n_cu = prop.multiProcessorCount;
+        // the architecture name up to its first ':' (feature suffixes), spaces excluded
+        int k = 0;
+        for (; k < 63 && prop.gcnArchName[k] && prop.gcnArchName[k] != ':' && prop.gcnArchName[k] != ' '; ++k)
+            c->arch[k] = prop.gcnArchName[k];
+        if (k > 0) c->arch[k] = 0;
+    }
     *out = c;
     return GENGA_OK;
 }
@@ -924,6 +987,7 @@ int genga_destroy(genga_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->release();
+    if (ctx->hpin) (void)hipHostFree(ctx->hpin);
     delete ctx;
     return GENGA_OK;
 }
@@ -1000,6 +1064,8 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->member_slot, nt));
     HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * max_items));
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
+    HIP_TRY(dalloc(ctx->import_bad, 1));
+    HIP_TRY(hipMemset(ctx->import_bad, 0, sizeof(int32_t)));
 
     HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nt) HIP_TRY(hipMemcpy(ctx->L.sys_of, sys_of.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -1082,7 +1148,12 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
     if (!(n1 >= 0.0) || !(n2 >= 0.0) || !(dt > 0.0)) return fail(GENGA_ERR_ARG, "n1, n2 >= 0 and dt > 0 required");
     if (!ctx->large_groups) return fail(GENGA_ERR_STATE, "levels need the large-group mode (genga_set_large_groups)");
     hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
     const size_t n = (size_t)ctx->L.n_total;
+    // device conditions raised before the tuning and not yet polled are kept for the caller
+    int32_t pending = 0;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(&pending, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost));
     double *save = nullptr, *rcl = nullptr;
     HIP_TRY(dalloc(save, 6 * std::max<size_t>(n, 1)));
     if (dalloc(rcl, (LEVELS_MAX - 1) * std::max<size_t>(n, 1)) != hipSuccess) {
@@ -1129,7 +1200,7 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
                 break;
             }
             const auto t0 = std::chrono::steady_clock::now();
-            const int r = enqueue_step(ctx, b, dt, trial_steps, prec, 0, nullptr, s);
+            const int r = enqueue_step(ctx, b, dt, trial_steps, prec, GENGA_ACC_FP64, 0, nullptr, s);
             if ((he = hipStreamSynchronize(s)) != hipSuccess) {
                 rc = fail(GENGA_ERR_HIP, "%s", hipGetErrorString(he));
                 break;
@@ -1160,6 +1231,8 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
     ctx->col = col;
     dfree(save);
     dfree(rcl);
+    if (pending && hipMemcpy(ctx->flags, &pending, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess && !rc)
+        rc = fail(GENGA_ERR_HIP, "restoring the pending device status failed");
     if (rc) return rc;
     if (!(best_t < INFINITY)) return fail(GENGA_ERR_NOCONVERGE, "no configuration ran without a device condition");
     *levels_out = best_l;
@@ -1171,6 +1244,11 @@ int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
+    // a captured graph holds the collision launches (or lacks them): refused either way
+    if (ctx->graph_exec)
+        return fail(GENGA_ERR_STATE, "a captured graph exists: collisions cannot be switched while it does");
+    if (mass && (!radius || !status)) return fail(GENGA_ERR_ARG, "null radius or status");
+    if (mass && (!(r_min >= 0.0) || !(r_max > r_min))) return fail(GENGA_ERR_ARG, "need 0 <= r_min < r_max");
     HIP_TRY(hipDeviceSynchronize());
     if (!mass) {
         dfree(ctx->col.list);
@@ -1178,9 +1256,6 @@ int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *
         ctx->col = CollideArgs{};
         return GENGA_OK;
     }
-    if (!radius || !status) return fail(GENGA_ERR_ARG, "null radius or status");
-    if (!(r_min >= 0.0) || !(r_max > r_min)) return fail(GENGA_ERR_ARG, "need 0 <= r_min < r_max");
-    if (ctx->graph_exec) return fail(GENGA_ERR_STATE, "a captured graph exists: capture again after enabling collisions");
     if (!ctx->col.list) {
         HIP_TRY(dalloc(ctx->col.list, 2 * (size_t)COLLIDE_CAP));
         HIP_TRY(dalloc(ctx->col.count, 1));
@@ -1304,41 +1379,61 @@ int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, dou
     return GENGA_OK;
 }
 
-int genga_accel(genga_ctx *ctx, const genga_bodies *b, int prec, double *ax, double *ay, double *az, void *stream)
+int genga_accel(genga_ctx *ctx, const genga_bodies *b, double *ax, double *ay, double *az, int prec, int acc,
+                void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, false, true))) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_acc(acc)) || (rc = check_bodies(ctx, b, false, true))) return rc;
     if (ctx->L.n_total && (!ax || !ay || !az)) return fail(GENGA_ERR_ARG, "null acceleration output");
-    return enqueue_kick(ctx, b, 0.0, 0, prec, ax, ay, az, (hipStream_t)stream);
+    ctx->last_stream = (hipStream_t)stream;
+    return enqueue_kick(ctx, b, 0.0, 0, prec, acc, ax, ay, az, (hipStream_t)stream);
 }
 
-int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, void *stream)
+int genga_kick(genga_ctx *ctx, genga_bodies *b, double tau, int prec, int acc, void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_acc(acc)) || (rc = check_bodies(ctx, b, true, true))) return rc;
     const size_t n = (size_t)ctx->L.n_total;
-    return enqueue_kick(ctx, b, tau, 1, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, (hipStream_t)stream);
+    ctx->last_stream = (hipStream_t)stream;
+    return enqueue_kick(ctx, b, tau, 1, prec, acc, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, (hipStream_t)stream);
 }
 
-int genga_encounter_list(genga_ctx *ctx, int32_t *pairs, int32_t cap, int32_t *d_count, void *stream)
+int genga_encounter_list(genga_ctx *ctx, const genga_bodies *b, int32_t *pairs, int32_t cap, int32_t *d_count,
+                         void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!d_count) return fail(GENGA_ERR_ARG, "null d_count");
     if (cap < 0 || (cap > 0 && !pairs)) return fail(GENGA_ERR_ARG, "bad pairs buffer");
+    if (b && (rc = check_bodies(ctx, b, false, true))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    if (b) {
+        if ((rc = enqueue_pair_list(ctx, b, s))) return rc;
+    } else if (!ctx->list_valid) {
+        return fail(GENGA_ERR_STATE, "no kick has run on the current positions: pass the bodies to list their "
+                                     "encounter pairs");
+    }
     HIP_TRY(launch_sort_pairs(ctx->pairs, ctx->pair_count, ctx->pair_cap, pairs, cap, d_count, ctx->sort_keys,
-                              ctx->flags, (hipStream_t)stream));
+                              ctx->flags, s));
     return GENGA_OK;
 }
 
-int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, void *stream)
+int genga_drift(genga_ctx *ctx, genga_bodies *b, double dt, const int32_t *pairs, const int32_t *d_count,
+                void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if ((rc = check_bodies(ctx, b, true, true))) return rc;
-    return enqueue_drift(ctx, b, dt, (hipStream_t)stream);
+    if (pairs && !d_count) return fail(GENGA_ERR_ARG, "a pair list needs its device count");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    if (pairs)
+        HIP_TRY(launch_import_pairs(ctx->L, pairs, d_count, ctx->pairs, ctx->pair_count, ctx->pair_cap,
+                                    ctx->import_bad, ctx->flags, s));
+    return enqueue_drift(ctx, b, dt, s);
 }
 
 int genga_energy(genga_ctx *ctx, const genga_bodies *b, double *d_out, void *stream)
@@ -1347,28 +1442,32 @@ int genga_energy(genga_ctx *ctx, const genga_bodies *b, double *d_out, void *str
     if (rc) return rc;
     if ((rc = check_bodies(ctx, b, true, false))) return rc;
     if (!d_out) return fail(GENGA_ERR_ARG, "null d_out");
+    ctx->last_stream = (hipStream_t)stream;
     return enqueue_energy(ctx, b, 0.0, d_out, (hipStream_t)stream);
 }
 
-int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int energy_cadence,
+int genga_step(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int acc, int energy_cadence,
                double *d_energy, void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_acc(acc)) || (rc = check_bodies(ctx, b, true, true))) return rc;
     if (nsteps < 0) return fail(GENGA_ERR_ARG, "nsteps must be >= 0");
     if (nsteps == 0) return GENGA_OK;
-    return enqueue_step(ctx, b, dt, nsteps, prec, energy_cadence, d_energy, (hipStream_t)stream);
+    ctx->last_stream = (hipStream_t)stream;
+    return enqueue_step(ctx, b, dt, nsteps, prec, acc, energy_cadence, d_energy, (hipStream_t)stream);
 }
 
-int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, void *stream)
+int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, int prec, int acc,
+                        int energy_cadence, double *d_energy, void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, true, true))) return rc;
+    if ((rc = check_prec(prec)) || (rc = check_acc(acc)) || (rc = check_bodies(ctx, b, true, true))) return rc;
     if (nsteps < 1) return fail(GENGA_ERR_ARG, "nsteps must be >= 1");
     hipStream_t s = (hipStream_t)stream;
     if (!s) return fail(GENGA_ERR_ARG, "graph capture needs a non-default stream");
+    ctx->last_stream = s;
     if (ctx->large_groups)
         return fail(GENGA_ERR_STATE, "graph capture is not available while large groups are enabled (host round trips)");
     HIP_TRY(hipStreamSynchronize(s));
@@ -1377,7 +1476,7 @@ int genga_graph_capture(genga_ctx *ctx, genga_bodies *b, double dt, int nsteps, 
     ctx->graph_exec = nullptr;
     ctx->graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = enqueue_step(ctx, b, dt, nsteps, prec, 0, nullptr, s);
+    rc = enqueue_step(ctx, b, dt, nsteps, prec, acc, energy_cadence, d_energy, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
@@ -1396,6 +1495,7 @@ int genga_graph_launch(genga_ctx *ctx, int repeats, void *stream)
     if (rc) return rc;
     if (!ctx->graph_exec) return fail(GENGA_ERR_STATE, "no captured graph");
     if (repeats < 0) return fail(GENGA_ERR_ARG, "repeats must be >= 0");
+    ctx->last_stream = (hipStream_t)stream;
     for (int r = 0; r < repeats; ++r) HIP_TRY(hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream));
     return GENGA_OK;
 }
@@ -1424,15 +1524,51 @@ int genga_get_kick_shape(genga_ctx *ctx, int prec, int *waves, int *split)
     return GENGA_OK;
 }
 
-int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
+int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, const char *cache_path, void *stream)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if ((rc = check_prec(prec)) || (rc = check_bodies(ctx, b, false, true))) return rc;
     if (ctx->L.n_total == 0) return GENGA_OK;
     hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
     const int fp32 = prec == GENGA_KICK_FP32;
     const size_t n = (size_t)ctx->L.n_total;
+    // the cache key: device architecture and compute units, precision, and the layout (system
+    // sizes and TP2 counts, hashed with 64-bit FNV-1a)
+    char key[256] = {0};
+    if (cache_path) {
+        uint64_t h = 1469598103934665603ull;
+        const auto mix = [&h](int32_t v) {
+            for (int k = 0; k < 4; ++k) {
+                h ^= (uint8_t)(v >> (8 * k));
+                h *= 1099511628211ull;
+            }
+        };
+        for (int32_t v : ctx->sys_off_h) mix(v);
+        for (int32_t v : ctx->n_massive_h) mix(v);
+        snprintf(key, sizeof(key), "genga-autotune v1 %s %d %d %d %d %016llx", ctx->arch, ctx->n_cu, prec,
+                 ctx->L.n_sys, ctx->L.n_total, (unsigned long long)h);
+        if (FILE *f = fopen(cache_path, "r")) {
+            char line[512];
+            bool hit = false;
+            int cw = 0, cs = 0;
+            const size_t kl = strlen(key);
+            while (fgets(line, sizeof(line), f)) {
+                if (strncmp(line, key, kl) == 0 && line[kl] == ' ' && sscanf(line + kl, "%d %d", &cw, &cs) == 2 &&
+                    (cw == 4 || cw == 8 || cw == 16) && cs >= 1 && cs <= KICK_MAX_SPLIT)
+                    hit = true; // the last matching line wins
+            }
+            const bool read_err = ferror(f) != 0;
+            fclose(f);
+            if (read_err) return fail(GENGA_ERR_ARG, "cannot read the autotune cache %s", cache_path);
+            if (hit) {
+                ctx->waves[fp32] = cw;
+                ctx->split[fp32] = cs;
+                return GENGA_OK;
+            }
+        }
+    }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1443,11 +1579,11 @@ int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
             ctx->waves[fp32] = w;
             ctx->split[fp32] = sp;
             // accelerations only (velocities untouched); one warm-up then three timed launches
-            rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
+            rc = enqueue_kick(ctx, b, 0.0, 0, prec, GENGA_ACC_FP64, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
             if (rc) break;
             (void)hipEventRecord(e0, s);
             for (int r = 0; r < 3 && !rc; ++r)
-                rc = enqueue_kick(ctx, b, 0.0, 0, prec, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
+                rc = enqueue_kick(ctx, b, 0.0, 0, prec, GENGA_ACC_FP64, ctx->acc, ctx->acc + n, ctx->acc + 2 * n, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1463,18 +1599,24 @@ int genga_autotune(genga_ctx *ctx, genga_bodies *b, int prec, void *stream)
     ctx->split[fp32] = best_s;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return rc;
+    if (rc || !cache_path) return rc;
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return fail(GENGA_ERR_ARG, "cannot write the autotune cache %s", cache_path);
+    const bool ok = fprintf(f, "%s %d %d\n", key, best_w, best_s) > 0;
+    if (fclose(f) != 0 || !ok) return fail(GENGA_ERR_ARG, "cannot write the autotune cache %s", cache_path);
+    return GENGA_OK;
 }
 
 int genga_poll_status(genga_ctx *ctx)
 {
     int rc = check_ctx(ctx);
     if (rc) return rc;
-    HIP_TRY(hipDeviceSynchronize());
-    int32_t f = 0;
-    HIP_TRY(hipMemcpy(&f, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemset(ctx->flags, 0, sizeof(int32_t)));
-    HIP_TRY(hipDeviceSynchronize());
+    hipStream_t s = ctx->last_stream;
+    HIP_TRY(hipMemcpyAsync(ctx->hpin, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int32_t f = *ctx->hpin;
+    if (f & FLAG_BADPAIR) return fail(GENGA_ERR_ARG, "a pair list given to genga_drift held an invalid pair");
     if (f & FLAG_NONFINITE) return fail(GENGA_ERR_NONFINITE, "non-finite acceleration");
     if (f & FLAG_NOCONVERGE) return fail(GENGA_ERR_NOCONVERGE, "Bulirsch-Stoer step did not converge");
     if (f & FLAG_KEPLER) return fail(GENGA_ERR_NOCONVERGE, "Kepler solve did not converge");

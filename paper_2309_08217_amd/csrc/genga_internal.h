@@ -34,6 +34,7 @@ enum DeviceFlag : int32_t {
     FLAG_NONFINITE = 2,
     FLAG_NOCONVERGE = 4,   // Bulirsch-Stoer step
     FLAG_KEPLER = 8,       // Kepler solve
+    FLAG_BADPAIR = 16,     // a caller's pair list held an invalid pair
 };
 
 // Maximum sizes of the close-encounter step (one workgroup builds the groups in LDS).
@@ -81,6 +82,7 @@ struct KickArgs {
     int32_t split;                // workgroups sharing one item's sources (>= 1)
     int32_t n_total;
     double *part;                 // [split][3][n_total] shares when split > 1
+    const int32_t *status;        // with collisions: bodies with status != 0 are in no pair
 };
 
 constexpr int KICK_MAX_SPLIT = 4;
@@ -93,7 +95,11 @@ constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in th
 hipError_t launch_prep(const Layout &L, double *x, double *y, double *z, const double *m,
                        const double *rc, void *jrec, int fp32, double *rc2_part, int32_t *pair_count,
                        const double *mom_part, double shift_tau, hipStream_t stream);
-hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream);
+// kahan: the FP32 kick's blocks are summed with Kahan compensation in FP32 (else in FP64)
+hipError_t launch_kick(const KickArgs &a, int fp32, int kahan, int waves, int grid, hipStream_t stream);
+// The encounter pairs of the state only (FP64 source records from launch_prep; no forces,
+// nothing written but a.pairs / a.pair_count), 8 waves per workgroup.
+hipError_t launch_pair_list(const KickArgs &a, int grid, hipStream_t stream);
 hipError_t launch_rcrit(const Layout &L, const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz, const double *m,
                         double n1, double n2, double dt, double *rc, hipStream_t stream);
@@ -265,6 +271,11 @@ hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items
                          const double *vz, const double *m, const double *ax, const double *ay,
                          const double *az, double vshift, double *partial,
                          const int32_t *item_first, double *out, hipStream_t stream);
+// A caller's pair list src[min(*src_count, cap)][2] checked (0 <= i < j < n_total, one system)
+// and copied to dst; *dst_count = *src_count, or 0 with FLAG_BADPAIR when a pair is invalid
+// (bad: a device word, zero on entry and left zero).
+hipError_t launch_import_pairs(const Layout &L, const int32_t *src, const int32_t *src_count, int32_t *dst,
+                               int32_t *dst_count, int32_t cap, int32_t *bad, int32_t *flags, hipStream_t stream);
 hipError_t launch_sort_pairs(const int32_t *src, const int32_t *src_count, int32_t src_cap,
                              int32_t *dst, int32_t dst_cap, int32_t *dst_count, uint64_t *keys,
                              int32_t *flags, hipStream_t stream);

@@ -15,9 +15,11 @@
 //    largest r_crit^2 per pair, and only a group of four that has a candidate takes the
 //    slow path, which decides "inside r_crit,ij" in FP64 exactly as the definition states,
 //    evaluates K and the pair term in FP64 and appends (i, j) to the encounter list.
-//  * FP32 path: FP32 partial sums over blocks of 64 sources, folded into FP64 accumulators.
-//    FP64 path: r^-3 from v_rsq_f64 (about 2^-24) and a second-order series correction of
-//    its cube.
+//  * FP32 path: FP32 partial sums over blocks of 64 sources, folded into FP64 accumulators
+//    or into Kahan-compensated FP32 sums.  FP64 path: r^-3 from v_rsq_f64 (about 2^-24) and a
+//    second-order series correction of its cube.
+//  * the same FP64 loop without the force terms lists the encounter pairs of a state on its
+//    own (no kick has run on it).
 #include "genga_internal.h"
 #include "pair_math.h"
 
@@ -144,7 +146,7 @@ __device__ __forceinline__ bool close_pair(const KickArgs &a, double xj, double 
         sy += s * dy;
         sz += s * dz;
     }
-    emit_pair(a, pb, valid && i < j, i, j);
+    emit_pair(a, pb, valid && i < j && (!a.status || (a.status[i] == 0 && a.status[j] == 0)), i, j);
     return true;
 }
 
@@ -159,6 +161,16 @@ __device__ __forceinline__ double system_rc2max(const KickArgs &a, int s)
 struct Acc32 {
     float fx, fy, fz;
 };
+
+// S + v with Kahan compensation: after the call S - C equals the exact sum of the values added
+// so far up to the rounding of the last C
+__device__ __forceinline__ void kahan_add(float &S, float &C, float v)
+{
+    const float y = v - C;
+    const float t = S + y;
+    C = (t - S) - y;
+    S = t;
+}
 
 __device__ __forceinline__ void far32(float mj, float dx, float dy, float dz, float q, Acc32 &c)
 {
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(256) void kick_finish_kernel(KickArgs a)
     }
 }
 
-template <int W>
+template <int W, bool KAHAN>
 __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
 {
     __shared__ double red[3][W][64];
@@ -288,8 +300,9 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
         const float T = (float)(system_rc2max(a, w.sys) * 1.0001) + 1e-30f;
         const int chunk = (j1 - j0 + W - 1) / W;
         const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
-        double sx = 0.0, sy = 0.0, sz = 0.0;
+        double sx = 0.0, sy = 0.0, sz = 0.0;  // the pairs inside r_crit; with FP64 folding all
         Acc32 c{0.f, 0.f, 0.f};
+        Acc32 S{0.f, 0.f, 0.f}, C{0.f, 0.f, 0.f}; // Kahan sums of the blocks (KAHAN only)
         int j = jb;
         while (j < je) {
             const int jend = min(j + 64, je);
@@ -327,18 +340,30 @@ __global__ __launch_bounds__(64 * W) void kick32_kernel(KickArgs a)
                 if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
                     far32(r0.m, dx0, dy0, dz0, q0, c);
             }
-            // fold the block's FP32 partial sums into the FP64 accumulators
-            sx += (double)c.fx;
-            sy += (double)c.fy;
-            sz += (double)c.fz;
+            // fold the block's FP32 partial sums into the accumulators
+            if (KAHAN) {
+                kahan_add(S.fx, C.fx, c.fx);
+                kahan_add(S.fy, C.fy, c.fy);
+                kahan_add(S.fz, C.fz, c.fz);
+            } else {
+                sx += (double)c.fx;
+                sy += (double)c.fy;
+                sz += (double)c.fz;
+            }
             c.fx = c.fy = c.fz = 0.f;
+        }
+        if (KAHAN) {
+            sx += (double)S.fx - (double)C.fx;
+            sy += (double)S.fy - (double)C.fy;
+            sz += (double)S.fz - (double)C.fz;
         }
         flush_pairs(a, pb);
         finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
 
-template <int W>
+// LIST: the encounter pairs only (no far terms, nothing written but the list)
+template <int W, bool LIST>
 __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
 {
     __shared__ double red[3][W][64];
@@ -359,7 +384,9 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
         const bool valid = lane < w.ni;
         const int i = w.i0 + (valid ? lane : 0);
         const double xi = a.x[i], yi = a.y[i], zi = a.z[i], rci = a.rc[i];
-        const double T = system_rc2max(a, w.sys) + 1e-300;
+        // candidate threshold with a relative margin: q below is formed with fused
+        // multiply-adds, the exact decision in close_pair without them
+        const double T = system_rc2max(a, w.sys) * (1.0 + 1e-12) + 1e-300;
         const int chunk = (j1 - j0 + W - 1) / W;
         const int jb = min(j0 + wave * chunk, j1), je = min(jb + chunk, j1);
         double sx = 0.0, sy = 0.0, sz = 0.0;
@@ -376,15 +403,15 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             double q3 = fma(dx3, dx3, fma(dy3, dy3, dz3 * dz3));
             const bool near = fmin(fmin(q0, q1), fmin(q2, q3)) < T;
             if (__builtin_expect(near, 0)) {
-                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
+                if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)) && !LIST)
                     far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
-                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
+                if (!(q1 < T && close_pair(a, r1.x, r1.y, r1.z, j + 1, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)) && !LIST)
                     far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
-                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
+                if (!(q2 < T && close_pair(a, r2.x, r2.y, r2.z, j + 2, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)) && !LIST)
                     far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
-                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
+                if (!(q3 < T && close_pair(a, r3.x, r3.y, r3.z, j + 3, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)) && !LIST)
                     far64(r3.m, dx3, dy3, dz3, q3, sx, sy, sz);
-            } else {
+            } else if (!LIST) {
                 far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
                 far64(r1.m, dx1, dy1, dz1, q1, sx, sy, sz);
                 far64(r2.m, dx2, dy2, dz2, q2, sx, sy, sz);
@@ -395,11 +422,11 @@ __global__ __launch_bounds__(64 * W) void kick64_kernel(KickArgs a)
             const JRec64 r0 = ldj(J, j);
             double dx0 = r0.x - xi, dy0 = r0.y - yi, dz0 = r0.z - zi;
             double q0 = fma(dx0, dx0, fma(dy0, dy0, dz0 * dz0));
-            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)))
+            if (!(q0 < T && close_pair(a, r0.x, r0.y, r0.z, j, i, valid, xi, yi, zi, rci, sx, sy, sz, pb)) && !LIST)
                 far64(r0.m, dx0, dy0, dz0, q0, sx, sy, sz);
         }
         flush_pairs(a, pb);
-        finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
+        if (!LIST) finish<W>(a, red, wave, lane, valid, i, part, sx, sy, sz);
     }
 }
 
@@ -497,17 +524,19 @@ hipError_t launch_prep(const Layout &L, double *x, double *y, double *z, const d
     return hipGetLastError();
 }
 
-hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStream_t stream)
+hipError_t launch_kick(const KickArgs &a, int fp32, int kahan, int waves, int grid, hipStream_t stream)
 {
     if (a.n_items == 0) return hipSuccess;
     const int n_tasks = a.n_items * a.split;
     if (grid <= 0 || grid > n_tasks) grid = n_tasks;
 #define GENGA_KICK_CASE(Wv)                                                                   \
     case Wv:                                                                                  \
-        if (fp32)                                                                             \
-            kick32_kernel<Wv><<<grid, 64 * Wv, 0, stream>>>(a);                              \
+        if (fp32 && kahan)                                                                    \
+            kick32_kernel<Wv, true><<<grid, 64 * Wv, 0, stream>>>(a);                        \
+        else if (fp32)                                                                        \
+            kick32_kernel<Wv, false><<<grid, 64 * Wv, 0, stream>>>(a);                       \
         else                                                                                  \
-            kick64_kernel<Wv><<<grid, 64 * Wv, 0, stream>>>(a);                              \
+            kick64_kernel<Wv, false><<<grid, 64 * Wv, 0, stream>>>(a);                       \
         break;
     switch (waves) {
         GENGA_KICK_CASE(4)
@@ -518,6 +547,15 @@ hipError_t launch_kick(const KickArgs &a, int fp32, int waves, int grid, hipStre
     }
 #undef GENGA_KICK_CASE
     if (a.split > 1) kick_finish_kernel<<<(a.n_total + 255) / 256, 256, 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_list(const KickArgs &a, int grid, hipStream_t stream)
+{
+    if (a.n_items == 0) return hipSuccess;
+    const int n_tasks = a.n_items * a.split;
+    if (grid <= 0 || grid > n_tasks) grid = n_tasks;
+    kick64_kernel<8, true><<<grid, 64 * 8, 0, stream>>>(a);
     return hipGetLastError();
 }
 

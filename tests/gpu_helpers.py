@@ -42,7 +42,7 @@ class System:
 
     def accel(self, prec):
         ax, ay, az = self.zeros(), self.zeros(), self.zeros()
-        genga.genga_accel(self.ctx.handle, self.b, prec, ax, ay, az)
+        genga.genga_accel(self.ctx.handle, self.b, ax, ay, az, prec)
         self.torch.cuda.synchronize()
         return np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], axis=1)
 
@@ -51,7 +51,7 @@ class System:
         cap = 16 * self.n + 16 if cap is None else cap
         pairs = torch.zeros(max(cap, 1) * 2, dtype=torch.int32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
-        genga.genga_encounter_list(self.ctx.handle, pairs, cap, cnt)
+        genga.genga_encounter_list(self.ctx.handle, None, pairs, cap, cnt)
         torch.cuda.synchronize()
         c = int(cnt.item())
         return pairs[: 2 * min(c, cap)].cpu().numpy().reshape(-1, 2), c

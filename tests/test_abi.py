@@ -34,11 +34,45 @@ def test_host_side_argument_errors_without_gpu():
     lib = genga.load_library()
     assert lib.genga_destroy(None) == genga.GENGA_OK
     assert lib.genga_poll_status(None) == genga.GENGA_ERR_ARG
-    assert lib.genga_kick(None, None, 0.1, 1, None) == genga.GENGA_ERR_ARG
+    assert lib.genga_kick(None, None, 0.1, 1, 0, None) == genga.GENGA_ERR_ARG
+    assert lib.genga_encounter_list(None, None, None, 0, None, None) == genga.GENGA_ERR_ARG
+    assert lib.genga_drift(None, None, 0.1, None, None, None) == genga.GENGA_ERR_ARG
+    assert lib.genga_autotune(None, None, 1, None, None) == genga.GENGA_ERR_ARG
     assert b"null context" in lib.genga_last_error()
     assert lib.genga_set_systems(None, 1, None, None, 0) == genga.GENGA_ERR_ARG
     assert lib.genga_set_kick_shape(None, 1, 8, 1) == genga.GENGA_ERR_ARG
     assert lib.genga_create(None, 0) == genga.GENGA_ERR_ARG
+
+
+def declared_signatures():
+    """name -> parameter list of every function the header declares"""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(genga_\w+)\s*\(([^)]*)\)\s*;", src):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        out[m.group(1)] = params
+    return out
+
+
+def test_binding_argument_lists_match_the_header():
+    """The binding declares every C function with the header's number of parameters, and the
+    kick path takes the precision and accumulator selectors, the drift a caller's pair list and
+    the encounter list the bodies (NULL: the last kick's list)."""
+    lib = genga.load_library()
+    sigs = declared_signatures()
+    for name, params in sigs.items():
+        if name == "genga_last_error":
+            continue
+        assert len(getattr(lib, name).argtypes) == len(params), (name, params)
+    assert [p.split()[-1] for p in sigs["genga_accel"]][-3:] == ["prec", "acc", "*stream"]
+    assert [p.split()[-1] for p in sigs["genga_kick"]][-3:] == ["prec", "acc", "*stream"]
+    assert [p.split()[-1] for p in sigs["genga_step"]][4:6] == ["prec", "acc"]
+    assert [p.split()[-1] for p in sigs["genga_drift"]][3:5] == ["*pairs", "*d_count"]
+    assert sigs["genga_encounter_list"][1].startswith("const genga_bodies")
+    assert [p.split()[-1] for p in sigs["genga_autotune"]][3] == "*cache_path"
+    assert genga.GENGA_ACC_FP64 == 0 and genga.GENGA_ACC_KAHAN32 == 1
+    src = open(HEADER).read()
+    assert "GENGA_ACC_FP64 = 0, GENGA_ACC_KAHAN32 = 1" in src
 
 
 def test_python_binding_refuses_cpu_tensors():

@@ -219,5 +219,51 @@ def test_collisions_in_graph_replays_match_eager():
         print(f"[graph collisions] replay {rep} identical to eager, merged so far {merged}", flush=True)
     assert genga.genga_poll_status(g.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
     assert merged >= 1
+    # collisions cannot be switched off under a graph that holds their launches
+    with pytest.raises(genga.GengaError) as err:
+        genga.genga_set_collisions(g.ctx.handle, None, None, None, 0.0, 0.0)
+    assert err.value.status == genga.GENGA_ERR_STATE
+    with torch.cuda.stream(stream):
+        genga.genga_graph_launch(g.ctx.handle, 1, stream=stream)     # the graph still runs
+    stream.synchronize()
+    assert genga.genga_poll_status(g.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
     g.close()
     e.close()
+
+
+def test_physical_radius_mergers_and_dead_bodies():
+    """Radii of 500 km (3.3e-6 au, the paper's planetesimal sizes) on the ring, with three
+    pairs planted on colliding paths (impact parameter 4e-6 au < R_i + R_j, relative speed
+    0.05 above the mutual escape speed): 10 FP64 steps against the oracle's step_collide, the
+    three mergers happen, and afterwards no absorbed body is in an encounter pair (it moves on
+    as a massless particle, outside every Bulirsch-Stoer group)."""
+    d0 = discs.ring_dense(300)
+    st = d0.state()
+    rng = np.random.default_rng(77)
+    rad0 = 500.0 / 1.495978707e8
+    for k, j in ((0, 250), (1, 251), (2, 252)):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        w = np.cross(u, rng.normal(size=3))
+        w /= np.linalg.norm(w)
+        pos = np.array([st["x"][k], st["y"][k], st["z"][k]]) + 2e-5 * u + 4e-6 * w
+        vel = np.array([st["vx"][k], st["vy"][k], st["vz"][k]]) - 0.05 * u
+        for q, key in enumerate(("x", "y", "z")):
+            st[key][j] = pos[q]
+            st["v" + key][j] = vel[q]
+    d = discs.Disc(**st)
+    rc = oracle.rcrit(st, d.mstar, 3.0, 0.0, DT5)
+    s = System([d], rcrit=rc)
+    torch = s.torch
+    rad = torch.full((d.n,), rad0, dtype=torch.float64, device="cuda")
+    status = torch.zeros(d.n, dtype=torch.int32, device="cuda")
+    genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, 0.0, 1e9)
+    exp, erad, est = oracle.step_collide(st, rc, np.full(d.n, rad0), np.zeros(d.n, np.int32), 1.0, DT5, 10, 0.0, 1e9)
+    assert (est[250:253] == 1).all() or (est[:3] == 1).all()
+    genga.genga_step(s.ctx.handle, s.b, DT5, 10, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("physical radius", s, rad, status, exp, erad, est, 1e-10)
+    dead = np.flatnonzero(status.cpu().numpy() != 0)
+    pairs, cnt = s.encounter_list()
+    assert len(dead) >= 3 and not np.isin(pairs, dead).any()
+    s.close()

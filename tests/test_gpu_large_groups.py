@@ -199,7 +199,7 @@ def test_large_groups_off_flags_capacity_and_graph_refused():
     genga.genga_set_large_groups(s.ctx.handle, True)
     stream = s.torch.cuda.Stream()
     with pytest.raises(genga.GengaError) as e:
-        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream)
+        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream=stream)
     assert e.value.status == genga.GENGA_ERR_STATE
     with pytest.raises(genga.GengaError):
         genga.genga_set_large_groups(s.ctx.handle, 2)

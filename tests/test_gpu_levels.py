@@ -236,7 +236,7 @@ def test_set_levels_argument_and_state_checks():
     genga.genga_set_levels(s.ctx.handle, 3, 2, t)
     stream = s.torch.cuda.Stream()
     with pytest.raises(genga.GengaError) as e:          # host round trips: no graph capture
-        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream)
+        genga.genga_graph_capture(s.ctx.handle, s.b, DT5, 2, FP32, stream=stream)
     assert e.value.status == genga.GENGA_ERR_STATE
     s.close()
 

@@ -358,28 +358,32 @@ def test_graph_replays_match_eager():
     e.close()
 
 
-def test_c3_full_size_sampled_rows():
-    """N = 40000 disc, the benchmark's launch configuration, checked on 256 sampled rows."""
+def test_c3_full_size_all_rows():
+    """N = 40000 disc in the benchmark's launch configuration (autotuned shape): every row of
+    the FP64 kick, the FP32 kick with FP64 folding and with Kahan-compensated FP32 folding,
+    against the oracle's full sum; the encounter list bit-exact; momentum balance."""
     d = discs.disc_c3()
     s = System([d])
-    rows = np.random.default_rng(0).choice(d.n, 256, replace=False)
-    ax, ay, az = oracle.accel_rows(d.state(), s.rc, rows)
-    ref = np.stack([ax, ay, az], axis=1)
-    for prec, bar in ((FP64, 1e-12), (FP32, 1e-5)):
+    ref = np.stack(oracle.accel(d.state(), s.rc), axis=1)
+    for prec, acc, bar in ((FP64, genga.GENGA_ACC_FP64, 1e-12), (FP32, genga.GENGA_ACC_FP64, 1e-5),
+                           (FP32, genga.GENGA_ACC_KAHAN32, 1e-5)):
         genga.genga_autotune(s.ctx.handle, s.b, prec)
-        a = s.accel(prec)[rows]
+        ax, ay, az = s.zeros(), s.zeros(), s.zeros()
+        genga.genga_accel(s.ctx.handle, s.b, ax, ay, az, prec, acc)
+        s.torch.cuda.synchronize()
+        a = np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], axis=1)
         rms, mx = force_errors(a, ref)
-        print(f"[c3 sampled] prec={prec} shape={genga.genga_get_kick_shape(s.ctx.handle, prec)} "
+        print(f"[c3 all rows] prec={prec} acc={acc} shape={genga.genga_get_kick_shape(s.ctx.handle, prec)} "
               f"rms={rms:.3e} max={mx:.3e}", flush=True)
         assert rms <= bar
-    got, cnt = s.encounter_list()
-    exp = oracle.encounters(d.state(), s.rc)
-    assert cnt == len(exp)
-    np.testing.assert_array_equal(got, exp)
-    # momentum balance of the whole FP32 sum
-    a = s.accel(FP32)
-    p = (d.m[:, None] * a).sum(axis=0)
-    assert np.max(np.abs(p)) <= 1e-6 * np.sum(d.m[:, None] * np.abs(a))
+        assert mx <= (1e-11 if prec == FP64 else 1e-3)
+        if prec == FP32:
+            p = (d.m[:, None] * a).sum(axis=0)
+            assert np.max(np.abs(p)) <= 1e-6 * np.sum(d.m[:, None] * np.abs(a))
+        got, cnt = s.encounter_list()
+        exp = oracle.encounters(d.state(), s.rc)
+        assert cnt == len(exp)
+        np.testing.assert_array_equal(got, exp)
     s.close()
 
 
