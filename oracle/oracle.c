@@ -120,7 +120,7 @@ static void accel_row(int64_t n, int64_t nm, int64_t i, const double *x, const d
 void oracle_accel(int64_t n, int64_t nm, const double *x, const double *y, const double *z,
                   const double *m, const double *rc, double *ax, double *ay, double *az)
 {
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (n >= 256)
     for (int64_t i = 0; i < n; ++i)
         accel_row(n, nm, i, x, y, z, m, rc, &ax[i], &ay[i], &az[i]);
 }
@@ -130,7 +130,7 @@ void oracle_accel_rows(int64_t n, int64_t nm, const double *x, const double *y, 
                        const double *m, const double *rc, int64_t nrows, const int64_t *rows,
                        double *ax, double *ay, double *az)
 {
-#pragma omp parallel for schedule(dynamic, 4)
+#pragma omp parallel for schedule(dynamic, 4) if (nrows >= 64)
     for (int64_t k = 0; k < nrows; ++k)
         accel_row(n, nm, rows[k], x, y, z, m, rc, &ax[k], &ay[k], &az[k]);
 }
@@ -156,7 +156,7 @@ int64_t oracle_encounters(int64_t n, int64_t nm, const double *x, const double *
                           const double *rc, int64_t cap, int32_t *pairs)
 {
     int64_t *first = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) if (n >= 256)
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = 0;
         for (int64_t j = i + 1; j < n; ++j) c += is_encounter(nm, i, j, x, y, z, rc);
@@ -164,7 +164,7 @@ int64_t oracle_encounters(int64_t n, int64_t nm, const double *x, const double *
     }
     first[0] = 0;
     for (int64_t i = 0; i < n; ++i) first[i + 1] += first[i];
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) if (n >= 256)
     for (int64_t i = 0; i < n; ++i) {
         if (first[i] == first[i + 1] || first[i] >= cap) continue;
         int64_t k = first[i];
@@ -203,7 +203,7 @@ void oracle_energy(int64_t n, int64_t nm, const double *x, const double *y, cons
         lz += m[i] * (x[i] * vy[i] - y[i] * vx[i]);
     }
     double *row = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (n >= 256)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t j = i + 1; j < n; ++j) {
