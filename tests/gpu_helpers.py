@@ -46,12 +46,14 @@ class System:
         self.torch.cuda.synchronize()
         return np.stack([ax.cpu().numpy(), ay.cpu().numpy(), az.cpu().numpy()], axis=1)
 
-    def encounter_list(self, cap=None):
+    def encounter_list(self, cap=None, standalone=False):
+        """Canonical pair list: the last kick's (standalone=False) or computed from the
+        current positions (standalone=True)."""
         torch = self.torch
         cap = 16 * self.n + 16 if cap is None else cap
         pairs = torch.zeros(max(cap, 1) * 2, dtype=torch.int32, device="cuda")
         cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
-        genga.genga_encounter_list(self.ctx.handle, None, pairs, cap, cnt)
+        genga.genga_encounter_list(self.ctx.handle, self.b if standalone else None, pairs, cap, cnt)
         torch.cuda.synchronize()
         c = int(cnt.item())
         return pairs[: 2 * min(c, cap)].cpu().numpy().reshape(-1, 2), c
