@@ -267,3 +267,52 @@ def test_physical_radius_mergers_and_dead_bodies():
     pairs, cnt = s.encounter_list()
     assert len(dead) >= 3 and not np.isin(pairs, dead).any()
     s.close()
+
+
+def _cluster_ring(n_clusters=600, m=1e-9):
+    """Clusters of 4 bodies on a circular ring at 1 au, each cluster moving with one velocity
+    (radii 1e-3 au, inside r_crit = 2.1e-3 au): even clusters are stars (every pair closer than
+    R_i + R_j), odd clusters chains with only neighbours touching.  In a star the first body absorbs the three others; in a chain
+    (0,1) merges, (1,2) is skipped (1 was absorbed), (2,3) merges."""
+    x, y, z, vx, vy, vz = ([] for _ in range(6))
+    for k in range(n_clusters):
+        th = 2 * np.pi * k / n_clusters
+        c = np.array([np.cos(th), np.sin(th), 0.0])
+        t = np.array([-np.sin(th), np.cos(th), 0.0])
+        v = t * np.sqrt(1.0 / 1.0)
+        if k % 2 == 0:
+            offs = [np.zeros(3), 1e-3 * c, 1e-3 * t, 1e-3 * np.array([0.0, 0.0, 1.0])]
+        else:
+            offs = [q * 1.5e-3 * t for q in range(4)]
+        for o in offs:
+            p = c + o
+            x.append(p[0]); y.append(p[1]); z.append(p[2])
+            vx.append(v[0]); vy.append(v[1]); vz.append(v[2])
+    n = len(x)
+    return discs.Disc(np.array(x), np.array(y), np.array(z), np.array(vx), np.array(vy), np.array(vz),
+                      np.full(n, m))
+
+
+def test_many_mergers_in_one_drift():
+    """About 2700 colliding pairs in the first drift (stars and chains of 4): the merges follow
+    the ascending (i, j) order with already-absorbed bodies skipped, as the oracle's, over two
+    FP64 steps."""
+    d = _cluster_ring()
+    st = d.state()
+    rc = oracle.rcrit(st, d.mstar, 3.0, 0.0, DT5)
+    rad0 = 1e-3
+    s = System([d], rcrit=rc)
+    torch = s.torch
+    rad = torch.full((d.n,), rad0, dtype=torch.float64, device="cuda")
+    status = torch.zeros(d.n, dtype=torch.int32, device="cuda")
+    genga.genga_set_collisions(s.ctx.handle, s.b, rad, status, 0.0, 1e9)
+    exp, erad, est = oracle.step_collide(st, rc, np.full(d.n, rad0), np.zeros(d.n, np.int32), 1.0, DT5, 2, 0.0, 1e9)
+    stars = np.arange(0, d.n, 8)
+    assert (est[stars] == 0).all() and (est[stars + 1] == 1).all() and (est[stars + 3] == 1).all()
+    chains = np.arange(4, d.n, 8)
+    assert (est[chains] == 0).all() and (est[chains + 1] == 1).all() and (est[chains + 2] == 0).all()
+    assert (est[chains + 3] == 1).all()
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP64)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    check_against_oracle("many mergers", s, rad, status, exp, erad, est, 1e-10)
+    s.close()
