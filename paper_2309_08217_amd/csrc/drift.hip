@@ -247,8 +247,10 @@ __global__ __launch_bounds__(256) void uf_init_kernel(const int32_t *pairs, cons
 }
 
 __global__ __launch_bounds__(256) void uf_hook_kernel(const int32_t *pairs, const int32_t *pair_count,
-                                                      int32_t pair_cap, int32_t *lab, int32_t *changed)
+                                                      int32_t pair_cap, int32_t *lab, int32_t *changed,
+                                                      const int32_t *run_if)
 {
+    if (run_if && *run_if == 0) return;
     const int np = min(*pair_count, pair_cap);
     int ch = 0;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < np; p += gridDim.x * 256) {
@@ -265,8 +267,9 @@ __global__ __launch_bounds__(256) void uf_hook_kernel(const int32_t *pairs, cons
     if (__ballot(ch) && (threadIdx.x & 63) == 0) atomicOr(changed, 1);
 }
 
-__global__ __launch_bounds__(256) void uf_compress_kernel(int n_total, int32_t *lab)
+__global__ __launch_bounds__(256) void uf_compress_kernel(int n_total, int32_t *lab, const int32_t *run_if)
 {
+    if (run_if && *run_if == 0) return;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n_total || lab_load(lab, i) < 0) return;
     __hip_atomic_store(&lab[i], find_root(lab, i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1019,16 +1022,16 @@ hipError_t launch_uf_init(const int32_t *pairs, const int32_t *pair_count, int32
 }
 
 hipError_t launch_uf_hook(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
-                          int32_t *changed, hipStream_t stream)
+                          int32_t *changed, hipStream_t stream, const int32_t *run_if)
 {
-    uf_hook_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab, changed);
+    uf_hook_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab, changed, run_if);
     return hipGetLastError();
 }
 
-hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream)
+hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream, const int32_t *run_if)
 {
     if (L.n_total == 0) return hipSuccess;
-    uf_compress_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, lab);
+    uf_compress_kernel<<<(L.n_total + 255) / 256, 256, 0, stream>>>(L.n_total, lab, run_if);
     return hipGetLastError();
 }
 

@@ -107,6 +107,8 @@ struct genga_ctx {
     int32_t lt_cap_G = 0, lt_cap_T = 0;
     int32_t *lv_mem = nullptr, *lv_gs = nullptr, *lv_ng = nullptr; // the deepest level's groups
     int32_t *lv_pairs = nullptr, *lv_count = nullptr; // a level's pairs
+    GroupWork gw;                      // device layout of a level's groups
+    GroupHeader *ghdr = nullptr;       // pinned host copy of its header
     // collisions and removal (opt-in)
     CollideArgs col;
     int32_t pair_cap_req = 0;          // pair capacity asked for at genga_set_systems
@@ -170,6 +172,7 @@ struct genga_ctx {
         dfree(lv_mem);
         dfree(lv_gs);
         dfree(lv_ng);
+        group_work_free(gw);
         dfree(lv_pairs);
         dfree(lv_count);
         n_levels = n_sub = 1;
@@ -450,6 +453,8 @@ int alloc_big(genga_ctx *ctx)
         HIP_TRY(dalloc(ctx->lv_ng, 1));
         HIP_TRY(dalloc(ctx->lv_pairs, 2 * (size_t)ctx->pair_cap));
         HIP_TRY(dalloc(ctx->lv_count, 1));
+        HIP_TRY(group_work_alloc(ctx->gw, (int)nt));
+        if (!ctx->ghdr) HIP_TRY(hipHostMalloc((void **)&ctx->ghdr, sizeof(GroupHeader), hipHostMallocDefault));
     }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
@@ -732,22 +737,134 @@ int level_kick(genga_ctx *ctx, genga_bodies *b, int level, const LevelTiles &T, 
     return GENGA_OK;
 }
 
-int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int32_t> &pgs,
-              const std::vector<int32_t> &pmem, double tau, hipStream_t s,
-              const std::vector<int32_t> *prev = nullptr)
+// The groups of the level-`level` pairs (ctx->lv_pairs), laid out on the device in the order of
+// the parent layout T (members of each group in T's order): into the child level's tiles, or,
+// for the deepest level, into lv_mem / lv_gs.  One host wait, for the header.  A union-find
+// that has not settled within the enqueued rounds is finished with checked rounds (one wait
+// each) and laid out again.
+int group_level(genga_ctx *ctx, int level, const LevelTiles &T, bool deepest, hipStream_t s)
 {
-    const int ng = (int)pgs.size() - 1;
-    if (ng <= 0) return GENGA_OK;
-    // the parent groups (level - 1) in tiles, fixed over the level's interval
+    GroupOut out;
+    if (deepest) {
+        out.body = ctx->lv_mem;
+        out.off = ctx->lv_gs;
+    } else {
+        LevelTiles &C = ctx->lt[level];
+        out.body = C.body;
+        out.off = C.off;
+        out.tfirst = C.tfirst;
+        out.tiles = C.tiles;
+        out.tl = C.tl;
+    }
+    HIP_TRY(launch_group_layout(ctx->L, ctx->gw, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, ctx->lab, T.body, T.M,
+                                out, s, true));
+    HIP_TRY(hipMemcpyAsync(ctx->ghdr, ctx->gw.hdr, sizeof(GroupHeader), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int round = 0; ctx->ghdr->unconverged; ++round) {
+        if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the level pairs did not settle");
+        ctx->pin[2] = 0;
+        HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(launch_uf_hook(ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, ctx->lab, ctx->big_changed, s));
+            HIP_TRY(launch_uf_compress(ctx->L, ctx->lab, s));
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ctx->pin[2] == 0) {
+            HIP_TRY(launch_group_layout(ctx->L, ctx->gw, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, ctx->lab,
+                                        T.body, T.M, out, s, false));
+            HIP_TRY(hipMemcpyAsync(ctx->ghdr, ctx->gw.hdr, sizeof(GroupHeader), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
+    const GroupHeader &h = *ctx->ghdr;
+    const auto refuse = [&](int status, const char *fmt, int a, int b) {
+        if (ctx->L.n_total > 0)
+            (void)hipMemsetAsync(ctx->lab, 0xff, (size_t)ctx->L.n_total * sizeof(int32_t), s);
+        return fail(status, fmt, a, b);
+    };
+    // a list cut at its capacity has been flagged by the kick that filled it: refused
+    if (h.pair_count > ctx->pair_cap)
+        return refuse(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", h.pair_count, ctx->pair_cap);
+    if (h.max_nb > 64 * BIG_TILES_PER_GROUP)
+        return refuse(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", h.max_nb,
+                      64 * BIG_TILES_PER_GROUP);
+    if (!deepest && (h.G > ctx->lt_cap_G || h.n_tiles > ctx->lt_cap_T || h.M > ctx->lt[level].cap_M))
+        return refuse(GENGA_ERR_STATE, "level layout of %d groups exceeds its allocation (%d)", h.G, ctx->lt_cap_G);
+    return GENGA_OK;
+}
+
+// Level `level` (>= 1) over tau for the parent groups laid out in ctx->lt[level - 1].
+int run_level(genga_ctx *ctx, genga_bodies *b, int level, double tau, hipStream_t s)
+{
     LevelTiles &T = ctx->lt[level - 1];
+    if (T.G <= 0) return GENGA_OK;
+    HIP_TRY(launch_level_tiles_setup(ctx->L, T, b->m, b->rcrit, ctx->rc_lv, level, s));
+    const double h = tau / ctx->n_sub;
+    const bool deepest = level + 1 == ctx->n_levels;
+    int rc;
+    for (int sub = 0; sub < ctx->n_sub; ++sub) {
+        HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
+        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
+        if ((rc = group_level(ctx, level, T, deepest, s))) return rc;
+        const GroupHeader hd = *ctx->ghdr;
+        // parent members in no pair of this level (device label -1): Kepler drift over h; then
+        // the labels are cleared
+        HIP_TRY(launch_kepler_list(ctx->L, T.body, T.M, b->x, b->y, b->z, b->vx, b->vy, b->vz, h, ctx->flags, s,
+                                   ctx->lab));
+        HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, (size_t)ctx->L.n_total * sizeof(int32_t), s));
+        if (hd.G > 0) {
+            if (deepest) {
+                // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members
+                // (the group count read on the device), the grid-wide path for larger ones
+                HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
+                                     ctx->lv_gs, &ctx->gw.hdr->G, ctx->member_slot, ctx->flags, 1, hd.G, s,
+                                     ctx->rc_lv, ctx->n_levels, false));
+                if (hd.max_nb > CE_MAX_GROUP) {
+                    // rare: the groups and the parent order go to the host for the grid-wide path
+                    std::vector<int32_t> cgs(hd.G + 1), cmem(hd.M), prev(T.M);
+                    HIP_TRY(hipMemcpyAsync(cgs.data(), ctx->lv_gs, cgs.size() * sizeof(int32_t),
+                                           hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipMemcpyAsync(cmem.data(), ctx->lv_mem, cmem.size() * sizeof(int32_t),
+                                           hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipMemcpyAsync(prev.data(), T.body, prev.size() * sizeof(int32_t),
+                                           hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipStreamSynchronize(s));
+                    if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, ctx->lv_mem, CE_MAX_GROUP + 1, &prev)))
+                        return rc;
+                }
+            } else {
+                LevelTiles &C = ctx->lt[level];
+                C.G = hd.G;
+                C.M = hd.M;
+                C.n_tiles = hd.n_tiles;
+                C.n_multi = hd.n_multi;
+                if ((rc = run_level(ctx, b, level + 1, h, s))) return rc;
+            }
+        }
+        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, false, s))) return rc;
+    }
+    return GENGA_OK;
+}
+
+// Level 1 over dt for the groups of the context's encounter list (built by enqueue_drift): the
+// groups are ordered by ring and azimuth on the host, once per step, and laid out in tiles; the
+// deeper levels inherit that order through the device layout.
+int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
+{
+    const std::vector<int32_t> &pgs = ctx->gs_h, &pmem = ctx->mem_h;
+    LevelTiles &T = ctx->lt[0];
+    T.G = T.M = T.n_tiles = T.n_multi = 0;
+    if ((int)pgs.size() <= 1) return GENGA_OK;
     TileOrder o;
-    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o, prev);
+    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o);
     if (rc) return rc;
     if ((int)o.k0.size() > ctx->lt_cap_G || o.off.back() > T.cap_M || (int)o.tiles.size() > ctx->lt_cap_T)
         return fail(GENGA_ERR_STATE, "level layout exceeds its allocation");
     T.G = (int32_t)o.k0.size();
     T.M = o.off.back();
     T.n_tiles = (int32_t)o.tiles.size();
+    if (T.G == 0) return GENGA_OK;
     // tiles of the groups of more than one tile first (a workgroup each), then the one tile of
     // every smaller group (a wave each)
     std::vector<int32_t> tl;
@@ -770,50 +887,7 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, const std::vector<int3
     if (!o.body.empty())
         HIP_TRY(hipMemcpyAsync(T.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(launch_level_tiles_setup(ctx->L, T, b->m, b->rcrit, ctx->rc_lv, level, s));
-    const double h = tau / ctx->n_sub;
-    const bool deepest = level + 1 == ctx->n_levels;
-    std::vector<int32_t> cgs, cmem;
-    for (int sub = 0; sub < ctx->n_sub; ++sub) {
-        HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
-        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
-        if ((rc = group_pairs(ctx, ctx->lv_pairs, ctx->lv_count, ctx->pair_cap, cgs, cmem, s, true, true)))
-            return rc;
-        // parent members in no pair of this level (device label -1): Kepler drift over h; then
-        // the labels are cleared
-        HIP_TRY(launch_kepler_list(ctx->L, T.body, T.M, b->x, b->y, b->z, b->vx, b->vy, b->vz, h, ctx->flags, s,
-                                   ctx->lab));
-        HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, (size_t)ctx->L.n_total * sizeof(int32_t), s));
-        if (!cmem.empty()) {
-            if (deepest) {
-                // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members,
-                // the grid-wide path for larger ones
-                const int ncg = (int)cgs.size() - 1;
-                // members, group starts and count in one host wait
-                ctx->pin[3] = ncg;
-                HIP_TRY(hipMemcpyAsync(ctx->lv_mem, cmem.data(), cmem.size() * sizeof(int32_t),
-                                       hipMemcpyHostToDevice, s));
-                HIP_TRY(hipMemcpyAsync(ctx->lv_gs, cgs.data(), cgs.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                       s));
-                HIP_TRY(hipMemcpyAsync(ctx->lv_ng, ctx->pin + 3, sizeof(int32_t), hipMemcpyHostToDevice, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
-                                     ctx->lv_gs, ctx->lv_ng, ctx->member_slot, ctx->flags, 1, ncg, s, ctx->rc_lv,
-                                     ctx->n_levels, false));
-                if ((rc = run_big_groups(ctx, b, h, s, cgs, cmem, ctx->lv_mem, CE_MAX_GROUP + 1, &o.body))) return rc;
-            } else if ((rc = run_level(ctx, b, level + 1, cgs, cmem, h, s, &o.body))) {
-                return rc;
-            }
-        }
-        if ((rc = level_kick(ctx, b, level, T, 0.5 * h, false, s))) return rc;
-    }
-    return GENGA_OK;
-}
-
-// Level 1 over dt for the groups of the context's encounter list (built by enqueue_drift).
-int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
-{
-    return run_level(ctx, b, 1, ctx->gs_h, ctx->mem_h, dt, s);
+    return run_level(ctx, b, 1, dt, s);
 }
 
 // Grid-wide Bulirsch-Stoer over dt for the groups gs / mem (host copies; members_dev the
@@ -988,6 +1062,7 @@ int genga_destroy(genga_ctx *ctx)
     (void)hipDeviceSynchronize();
     ctx->release();
     if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+    if (ctx->ghdr) (void)hipHostFree(ctx->ghdr);
     delete ctx;
     return GENGA_OK;
 }

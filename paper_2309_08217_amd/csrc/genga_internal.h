@@ -86,6 +86,7 @@ struct KickArgs {
 };
 
 constexpr int KICK_MAX_SPLIT = 4;
+
 constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in the energy sum
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
@@ -156,9 +157,11 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
 // compress (every member's lab = its root), slots (member_slot for members[0..n), lab = -1).
 hipError_t launch_uf_init(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
                           hipStream_t stream);
+// run_if (device word, may be null): the launch does nothing when *run_if == 0 (the previous
+// round changed nothing), so a fixed number of rounds can be enqueued without host waits.
 hipError_t launch_uf_hook(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
-                          int32_t *changed, hipStream_t stream);
-hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream);
+                          int32_t *changed, hipStream_t stream, const int32_t *run_if = nullptr);
+hipError_t launch_uf_compress(const Layout &L, int32_t *lab, hipStream_t stream, const int32_t *run_if = nullptr);
 hipError_t launch_uf_slots(int n_members_max, const int32_t *members, const int32_t *n_members,
                            int32_t *member_slot, int32_t *lab, hipStream_t stream);
 
@@ -244,6 +247,45 @@ hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const 
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
                               hipStream_t stream, const int32_t *skip = nullptr);
+
+// Encounter groups of a level's pair list laid out on the device (groups.hip).  The host reads
+// only the header, once per grouping.
+constexpr int UF_ROUNDS = 4; // union-find rounds enqueued at once; more only if the last still hooked
+struct GroupHeader {
+    int32_t G, M;            // groups, members
+    int32_t n_tiles, n_multi; // tiles of 64; of them in groups of several tiles
+    int32_t max_nb;          // largest group
+    int32_t unconverged;     // the last union-find round still hooked: more rounds are needed
+    int32_t pair_count;      // length of the pair list (may exceed its capacity)
+    int32_t pad;
+};
+// Where the layout goes: body[M] the members group by group, each group in the parent order;
+// off[G + 1]; with tiles != null also tfirst[G + 1], tiles[n_tiles] (group, first member, count,
+// 0) in group order, and tl[n_tiles]: the tiles of groups of several tiles first, then the one
+// tile of each smaller group.
+struct GroupOut {
+    int32_t *body = nullptr, *off = nullptr, *tfirst = nullptr, *tl = nullptr;
+    int4 *tiles = nullptr;
+};
+struct GroupWork {
+    uint64_t *keys = nullptr, *keys_sorted = nullptr; // [cap]
+    int32_t *flag = nullptr, *gidx = nullptr;         // [cap]
+    uint64_t *tv = nullptr, *tscan = nullptr;         // [cap / 2 + 2]
+    int32_t *changed = nullptr;                       // [UF_ROUNDS]
+    GroupHeader *hdr = nullptr;                       // device
+    void *temp = nullptr;                             // sort / scan temporary storage
+    size_t temp_bytes = 0;
+    int cap = 0;                                      // largest parent layout
+};
+hipError_t group_work_alloc(GroupWork &w, int cap);
+void group_work_free(GroupWork &w);
+// With union_find: union-find of pairs (lab all -1 on entry; afterwards every body of a pair
+// holds its component's smallest body, the caller clears it); then the components' members in
+// the order of the parent layout pbody[Mp] into `out`, and the header.  Without: the layout of
+// the labels as they are (after further rounds by the caller).
+hipError_t launch_group_layout(const Layout &L, GroupWork &w, const int32_t *pairs, const int32_t *pair_count,
+                               int32_t pair_cap, int32_t *lab, const int32_t *pbody, int Mp, const GroupOut &out,
+                               hipStream_t stream, bool union_find);
 
 // Collisions (perfect mergers) and removal by distance: caller-owned mass (the bodies' m),
 // radius and status arrays; a list of the colliding pairs of the current drift.

@@ -1,0 +1,240 @@
+// Encounter groups of a level's pair list laid out on the device (hierarchical levels,
+// Brasser et al. 2023, Sect. 1: the pairs closer than a level's critical radius form the groups
+// that the next level integrates).  The groups are the connected components of the pairs, found
+// by the grid-wide union-find (a fixed number of rounds, each skipped once the previous one
+// changed nothing); their members are taken in the order of the parent level's layout, grouped
+// by a stable radix sort of (root, parent position), and cut into tiles of 64 for the next
+// level's kick.  Everything stays on the device; the host reads one small header per grouping
+// (the sizes it needs to size the next launches).
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "genga_internal.h"
+
+namespace genga {
+
+namespace {
+
+constexpr int GL_THREADS = 256;
+
+__device__ __forceinline__ int32_t lab_of(const int32_t *lab, int32_t b)
+{
+    return __hip_atomic_load(&lab[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Header cleared; with full, also the pair count of the list recorded and the round words cleared.
+__global__ __launch_bounds__(64) void group_begin_kernel(GroupHeader *hdr, const int32_t *pair_count,
+                                                         int32_t *changed, int full)
+{
+    if (threadIdx.x == 0) {
+        hdr->G = 0;
+        hdr->M = 0;
+        hdr->n_tiles = 0;
+        hdr->n_multi = 0;
+        hdr->max_nb = 0;
+        hdr->unconverged = 0;
+        if (full) hdr->pair_count = *pair_count;
+        hdr->pad = 0;
+    }
+    if (full && (int)threadIdx.x < UF_ROUNDS) changed[threadIdx.x] = 0;
+}
+
+// The round words: unconverged when the last round still hooked something.
+__global__ __launch_bounds__(64) void group_rounds_kernel(GroupHeader *hdr, const int32_t *changed)
+{
+    if (threadIdx.x == 0) hdr->unconverged = changed[UF_ROUNDS - 1] != 0;
+}
+
+// Sort key of parent position p: (root of its body) * Mp + p, or the sentinel for a body in no
+// pair.
+__global__ __launch_bounds__(GL_THREADS) void group_keys_kernel(const int32_t *pbody, int Mp, const int32_t *lab,
+                                                                uint64_t sentinel, uint64_t *keys)
+{
+    const int p = blockIdx.x * GL_THREADS + threadIdx.x;
+    if (p >= Mp) return;
+    const int32_t r = lab_of(lab, pbody[p]);
+    keys[p] = r >= 0 ? (uint64_t)(uint32_t)r * (uint64_t)Mp + (uint64_t)p : sentinel;
+}
+
+// Members in sorted order and the first member of each group.
+__global__ __launch_bounds__(GL_THREADS) void group_mark_kernel(const uint64_t *sorted, int Mp, uint64_t sentinel,
+                                                                const int32_t *pbody, int32_t *body_out,
+                                                                int32_t *flag)
+{
+    const int q = blockIdx.x * GL_THREADS + threadIdx.x;
+    if (q >= Mp) return;
+    const uint64_t k = sorted[q];
+    const bool valid = k < sentinel;
+    bool start = false;
+    if (valid) {
+        body_out[q] = pbody[(int)(k % (uint64_t)Mp)];
+        start = q == 0 || sorted[q - 1] / (uint64_t)Mp != k / (uint64_t)Mp;
+    }
+    flag[q] = start ? 1 : 0;
+}
+
+// Group offsets; the last member writes the totals.
+__global__ __launch_bounds__(GL_THREADS) void group_offsets_kernel(const uint64_t *sorted, int Mp, uint64_t sentinel,
+                                                                   const int32_t *flag, const int32_t *gidx,
+                                                                   int32_t *off, GroupHeader *hdr)
+{
+    const int q = blockIdx.x * GL_THREADS + threadIdx.x;
+    if (q >= Mp) return;
+    const bool valid = sorted[q] < sentinel;
+    if (q == 0 && !valid) { // no member at all
+        off[0] = 0;
+        return;
+    }
+    if (!valid) return;
+    if (flag[q]) off[gidx[q]] = q;
+    if (q + 1 == Mp || sorted[q + 1] >= sentinel) {
+        const int G = gidx[q] + flag[q];
+        off[G] = q + 1;
+        hdr->G = G;
+        hdr->M = q + 1;
+    }
+}
+
+// Per group: its size into the header's maximum and its tiles as (tiles of groups of several
+// tiles) << 32 | (1 for a group of one tile), for the scan below.
+__global__ __launch_bounds__(GL_THREADS) void group_sizes_kernel(const int32_t *off, GroupHeader *hdr, int Gcap,
+                                                                 uint64_t *tv)
+{
+    const int g = blockIdx.x * GL_THREADS + threadIdx.x;
+    if (g >= Gcap) return;
+    const int G = hdr->G;
+    uint64_t v = 0;
+    if (g < G) {
+        const int nb = off[g + 1] - off[g];
+        const int nt = (nb + 63) / 64;
+        v = nt > 1 ? (uint64_t)nt << 32 : 1ull;
+        atomicMax(&hdr->max_nb, nb);
+    }
+    tv[g] = v;
+}
+
+// Tiles of 64 members, group by group (tfirst), and the launch list tl: the tiles of groups of
+// several tiles first (a workgroup each), then the tile of every group of one tile (a wave each).
+__global__ __launch_bounds__(GL_THREADS) void group_tiles_kernel(const int32_t *off, GroupHeader *hdr, int Gcap,
+                                                                 const uint64_t *tv, const uint64_t *tscan,
+                                                                 int32_t *tfirst, int4 *tiles, int32_t *tl)
+{
+    const int g = blockIdx.x * GL_THREADS + threadIdx.x;
+    if (g >= Gcap) return;
+    const int G = hdr->G;
+    if (g >= G) return;
+    const uint64_t tot = tscan[G - 1] + tv[G - 1];
+    const int n_multi = (int)(tot >> 32), n_tiles = n_multi + (int)(tot & 0xffffffffu);
+    const uint64_t e = tscan[g];
+    const int mo = (int)(e >> 32), so = (int)(e & 0xffffffffu);
+    const int tf = mo + so;
+    const int o = off[g], nb = off[g + 1] - o, nt = (nb + 63) / 64;
+    tfirst[g] = tf;
+    for (int k = 0; k < nt; ++k) {
+        tiles[tf + k] = make_int4(g, o + 64 * k, min(64, nb - 64 * k), 0);
+        tl[nt > 1 ? mo + k : n_multi + so] = tf + k;
+    }
+    if (g == G - 1) {
+        tfirst[G] = n_tiles;
+        hdr->n_tiles = n_tiles;
+        hdr->n_multi = n_multi;
+    }
+}
+
+int bits_for(uint64_t v)
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+} // namespace
+
+hipError_t group_work_alloc(GroupWork &w, int cap)
+{
+    group_work_free(w);
+    w.cap = cap > 1 ? cap : 2;
+    const size_t n = (size_t)w.cap, ng = n / 2 + 2;
+    hipError_t e;
+    if ((e = hipMalloc((void **)&w.keys, n * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.keys_sorted, n * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.flag, n * sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.gidx, n * sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.tv, ng * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.tscan, ng * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.changed, UF_ROUNDS * sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.hdr, sizeof(GroupHeader))) != hipSuccess) return e;
+    // temporary storage of the sort and the two scans, for the largest sizes
+    size_t b0 = 0, b1 = 0, b2 = 0;
+    if ((e = rocprim::radix_sort_keys(nullptr, b0, w.keys, w.keys_sorted, (unsigned int)n, 0, 64)) != hipSuccess)
+        return e;
+    if ((e = rocprim::exclusive_scan(nullptr, b1, w.flag, w.gidx, 0, n, rocprim::plus<int32_t>())) != hipSuccess)
+        return e;
+    if ((e = rocprim::exclusive_scan(nullptr, b2, w.tv, w.tscan, (uint64_t)0, ng, rocprim::plus<uint64_t>())) !=
+        hipSuccess)
+        return e;
+    w.temp_bytes = std::max(b0, std::max(b1, b2));
+    if ((e = hipMalloc(&w.temp, w.temp_bytes ? w.temp_bytes : 1)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void group_work_free(GroupWork &w)
+{
+    for (void *p : {(void *)w.keys, (void *)w.keys_sorted, (void *)w.flag, (void *)w.gidx, (void *)w.tv,
+                    (void *)w.tscan, (void *)w.changed, (void *)w.hdr, w.temp})
+        if (p) (void)hipFree(p);
+    w = GroupWork{};
+}
+
+hipError_t launch_group_layout(const Layout &L, GroupWork &w, const int32_t *pairs, const int32_t *pair_count,
+                               int32_t pair_cap, int32_t *lab, const int32_t *pbody, int Mp, const GroupOut &out,
+                               hipStream_t stream, bool union_find)
+{
+    if (Mp > w.cap) return hipErrorInvalidValue;
+    group_begin_kernel<<<1, 64, 0, stream>>>(w.hdr, pair_count, w.changed, union_find ? 1 : 0);
+    hipError_t e;
+    if (union_find) {
+        if ((e = launch_uf_init(pairs, pair_count, pair_cap, lab, stream)) != hipSuccess) return e;
+        // rounds of two (hook, compress) passes; a round whose predecessor changed nothing is skipped
+        for (int r = 0; r < UF_ROUNDS; ++r) {
+            const int32_t *run_if = r > 0 ? w.changed + r - 1 : nullptr;
+            for (int rep = 0; rep < 2; ++rep) {
+                if ((e = launch_uf_hook(pairs, pair_count, pair_cap, lab, w.changed + r, stream, run_if)) !=
+                    hipSuccess)
+                    return e;
+                if ((e = launch_uf_compress(L, lab, stream, run_if)) != hipSuccess) return e;
+            }
+        }
+        group_rounds_kernel<<<1, 64, 0, stream>>>(w.hdr, w.changed);
+    }
+    if (Mp == 0) return hipGetLastError();
+    const uint64_t sentinel = (uint64_t)(uint32_t)L.n_total * (uint64_t)Mp;
+    const int nb = (Mp + GL_THREADS - 1) / GL_THREADS;
+    group_keys_kernel<<<nb, GL_THREADS, 0, stream>>>(pbody, Mp, lab, sentinel, w.keys);
+    size_t bytes = w.temp_bytes;
+    if ((e = rocprim::radix_sort_keys(w.temp, bytes, w.keys, w.keys_sorted, (unsigned int)Mp, 0, bits_for(sentinel),
+                                      stream)) != hipSuccess)
+        return e;
+    group_mark_kernel<<<nb, GL_THREADS, 0, stream>>>(w.keys_sorted, Mp, sentinel, pbody, out.body, w.flag);
+    bytes = w.temp_bytes;
+    if ((e = rocprim::exclusive_scan(w.temp, bytes, w.flag, w.gidx, 0, (size_t)Mp, rocprim::plus<int32_t>(),
+                                     stream)) != hipSuccess)
+        return e;
+    group_offsets_kernel<<<nb, GL_THREADS, 0, stream>>>(w.keys_sorted, Mp, sentinel, w.flag, w.gidx, out.off, w.hdr);
+    // groups have at least two members
+    const int Gcap = Mp / 2 + 1, ng = (Gcap + GL_THREADS - 1) / GL_THREADS;
+    group_sizes_kernel<<<ng, GL_THREADS, 0, stream>>>(out.off, w.hdr, Gcap, w.tv);
+    if (out.tiles) {
+        bytes = w.temp_bytes;
+        if ((e = rocprim::exclusive_scan(w.temp, bytes, w.tv, w.tscan, (uint64_t)0, (size_t)Gcap,
+                                         rocprim::plus<uint64_t>(), stream)) != hipSuccess)
+            return e;
+        group_tiles_kernel<<<ng, GL_THREADS, 0, stream>>>(out.off, w.hdr, Gcap, w.tv, w.tscan, out.tfirst, out.tiles,
+                                                          out.tl);
+    }
+    return hipGetLastError();
+}
+
+} // namespace genga
