@@ -5,14 +5,17 @@ masses, 0.5-4 au, Sigma ~ a^-1.5, Rayleigh e and i), r_crit = 3 Hill radii, dt =
 A step is the whole hot path: the FP32-pair-arithmetic kick with its encounter list, the
 Sun drift, the FP64 Kepler drift and close-encounter step, and the FP64 energy /
 angular-momentum diagnostic every 10 steps.  `value` is pair interactions N(N-1) per step
-times steps per second, for state already resident in HBM.
+times steps per second, for state already resident in HBM.  The K timed steps are one
+captured HIP graph of K steps with the energy diagnostic inside it (replayed once untimed
+after the W eager warm-up steps, then once timed); eager steps are reported beside it.
 
 Also reported: the FP64 kick path, kick-only rates and their ratio, the roofline of the
 kick kernel (HIP events on the launch stream), a batched run of 64 uneven discs in one
 launch per kernel vs a loop of single-disc launches, the encounter-dominated regime (dense
 0.7-1 au annuli of 6600 and 40322 bodies with the full eq. (1), whose encounter groups span
 most of the disc, on the grid-wide Bulirsch-Stoer path), Delta E/E and Delta L/L over the
-timed steps, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+timed steps, collisions with merging radii, and the FP64 CPU oracle timed on a bounded
+sample of the same workload (on the host's cores and on one thread, with the CPU model).
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -108,6 +112,29 @@ def time_graph(ctx, b, prec, steps, torch, stream, per_graph=50):
     return (time.perf_counter() - t0) / (reps * per_graph)
 
 
+def time_graph_steps(ctx, b, prec, steps, n_sys, torch, stream):
+    """The timed steps as one captured HIP graph of `steps` steps with the energy diagnostic at
+    the cadence inside it: captured after the eager warm-up, replayed once untimed (the graph's
+    first launch uploads it), then replayed once timed.  Returns (seconds, energy records,
+    energy before the timed replay, status)."""
+    nrec = max(steps // CADENCE, 0)
+    e_rec = torch.zeros(max(nrec, 1) * 4 * n_sys, dtype=torch.float64, device="cuda:0")
+    e_init = torch.zeros(4 * n_sys, dtype=torch.float64, device="cuda:0")
+    with torch.cuda.stream(stream):
+        genga.genga_graph_capture(ctx.handle, b, DT, steps, prec, energy_cadence=CADENCE, d_energy=e_rec,
+                                  stream=stream)
+        genga.genga_graph_launch(ctx.handle, 1, stream=stream)
+        genga.genga_energy(ctx.handle, b, e_init, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        genga.genga_graph_launch(ctx.handle, 1, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    status = genga.genga_poll_status(ctx.handle)
+    return t, e_rec.cpu().numpy().reshape(-1, n_sys, 4)[:nrec], e_init.cpu().numpy().reshape(n_sys, 4), status
+
+
 def drift_stats(e_init, e_rec):
     E0 = e_init[:, 0]
     L0 = np.linalg.norm(e_init[:, 1:], axis=1)
@@ -150,10 +177,36 @@ def cpu_baseline(st, n):
         t_total += time.perf_counter() - t0
         reps += 1
     pairs = float(n) * (n - 1) * reps
-    return {"value": pairs / t_total / 1e9, "unit": "G pair-interactions/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # the same oracle on one thread, over rows of the same disc (each row is n - 1 pairs)
+    rows = np.arange(0, n, max(1, n // 5000), dtype=np.int64)
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.accel_rows(st, rc, rows)
+        t1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(cores)
+    one = len(rows) * float(n - 1) / t1 / 1e9
+    return {"value": pairs / t_total / 1e9, "unit": "G pair-interactions/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{reps} full FP64 oracle kick(s) of the N={n} disc ({pairs:.3e} pair interactions, "
-                      f"{t_total:.1f} s); the oracle's drift is O(N) and not included"}
+                      f"{t_total:.1f} s); the oracle's drift is O(N) and not included",
+            "one_thread": {"value": one, "unit": "G pair-interactions/s", "cores": 1,
+                           "sample": f"{len(rows)} rows of the same disc ({len(rows) * (n - 1):.3e} pair "
+                                     f"interactions, {t1:.1f} s)"},
+            "host_cpu": host_cpu_model(), "host_cpus_visible": os.cpu_count()}
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def batched(torch, stream, steps=10, warmup=2):
@@ -205,10 +258,13 @@ DENSE_WORKLOADS = {
                          "dt / n_sub^k", discs.disc_dense_40k, ("tune", 4, 3)),
 }
 # the 6600-body annulus again with collisions (perfect mergers) and removal inside 0.4 au /
-# beyond 40 au, every body of radius 500 km
-COLLIDE_RADIUS_AU = 500.0 / 1.495978707e8
+# beyond 40 au: every body of radius 500 km (the paper's planetesimal sizes; mergers are rare),
+# and with radii of 2e-3 au, where tens of pairs merge in every step
+COLLIDE_RADII_AU = {"dense_collisions": 500.0 / 1.495978707e8, "dense_collisions_merging": 2e-3}
 DENSE_WORKLOADS["dense_collisions"] = (DENSE_WORKLOADS["dense"][0] + "; perfect mergers (radius 500 km) and "
                                        "removal inside 0.4 au / beyond 40 au", discs.disc_dense, (1, 1))
+DENSE_WORKLOADS["dense_collisions_merging"] = (DENSE_WORKLOADS["dense"][0] + "; perfect mergers (radius 2e-3 au) "
+                                               "and removal inside 0.4 au / beyond 40 au", discs.disc_dense, (1, 1))
 
 
 def dense(torch, stream, which="dense", steps=10, warmup=2):
@@ -232,9 +288,9 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     rc = torch.zeros_like(b.x)
     genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS, rc)
     b.rcrit = rc
-    collide = which == "dense_collisions"
+    collide = which in COLLIDE_RADII_AU
     if collide:
-        radius = torch.full((d.n,), COLLIDE_RADIUS_AU, dtype=torch.float64, device="cuda:0")
+        radius = torch.full((d.n,), COLLIDE_RADII_AU[which], dtype=torch.float64, device="cuda:0")
         col_status = torch.zeros(d.n, dtype=torch.int32, device="cuda:0")
         genga.genga_set_collisions(ctx.handle, b, radius, col_status, 0.4, 40.0)
     if nlev > 1:
@@ -268,6 +324,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     with torch.cuda.stream(stream):
         genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, warmup, genga.GENGA_KICK_FP32, stream=stream)
     torch.cuda.synchronize()
+    dead_before = int((col_status != 0).sum().item()) if collide else 0
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, steps, genga.GENGA_KICK_FP32, stream=stream)
@@ -283,7 +340,9 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     extra = {"tuning_s": tune_s} if tune else {}
     if collide:
         stt = col_status.cpu().numpy()
-        extra = {"merged": int((stt == 1).sum()), "removed": int((stt == 2).sum())}
+        extra = {"radius_au": COLLIDE_RADII_AU[which], "merged": int((stt == 1).sum()),
+                 "removed": int((stt == 2).sum()),
+                 "merged_or_removed_in_timed_steps": int((stt != 0).sum()) - dead_before}
     return {"workload": label, "n": d.n, "levels": [nlev, nsub], **extra,
             "encounter_pairs_at_start": npair, "largest_group_at_start": int(sizes.max()),
             "groups_above_64_at_start": int((sizes > 64).sum()),
@@ -312,6 +371,8 @@ def main():
                     help="skip the encounter-dominated dense-annulus measurement")
     ap.add_argument("--dense-only", action="store_true",
                     help="profiling aid: run only the dense-annulus measurement")
+    ap.add_argument("--dense-which", default="",
+                    help="profiling aid: with --dense-only, run only these dense workloads (comma-separated)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling aid: copy a 256 MiB buffer 4 times (a plain copy of known size, "
                          "to scale HBM byte counters) and exit")
@@ -338,7 +399,8 @@ def main():
         print(json.dumps(batched(torch, stream)))
         return
     if args.dense_only:
-        print(json.dumps({w: dense(torch, stream, w) for w in DENSE_WORKLOADS}))
+        which = [w for w in args.dense_which.split(",") if w] or list(DENSE_WORKLOADS)
+        print(json.dumps({w: dense(torch, stream, w) for w in which}))
         return
     d = discs.disc_c3()
     if args.only_kick > 0:
@@ -360,9 +422,13 @@ def main():
         ctx, b, st, _ = setup([d], torch)
         genga.genga_autotune(ctx.handle, b, prec)
         kick_ms = time_kicks(ctx, b, prec, args.kick_reps, torch, stream)
-        t, e_rec, e_init, status = time_steps(ctx, b, prec, args.steps, args.warmup, 1, torch, stream)
+        t_eager, e_rec, e_init, status = time_steps(ctx, b, prec, args.steps, args.warmup, 1, torch, stream)
+        eager_stats = drift_stats(e_init, e_rec)
+        t, e_rec, e_init, status_g = time_graph_steps(ctx, b, prec, args.steps, 1, torch, stream)
+        status = status or status_g
         t_graph = time_graph(ctx, b, prec, args.steps, torch, stream)
         result[name] = {"step_seconds": t, "ms_per_step": 1e3 * t / args.steps,
+                        "eager_ms_per_step": 1e3 * t_eager / args.steps, "eager_energy": eager_stats,
                         "graph_ms_per_step_no_diagnostics": 1e3 * t_graph,
                         "value": pairs * args.steps / t / 1e9,
                         "kick_ms": kick_ms, "kick_G_pairs_per_s": pairs / (kick_ms * 1e-3) / 1e9,
@@ -396,9 +462,13 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": pairs,
                      "launch_ms": f32["kick_ms"], "traffic": kick_traffic(pairs)},
         "fp32_kick": {"G_pair_interactions_per_s": f32["kick_G_pairs_per_s"], "kick_ms": f32["kick_ms"]},
-        "graph": {"fp32_ms_per_step": f32["graph_ms_per_step_no_diagnostics"],
-                  "fp64_ms_per_step": f64["graph_ms_per_step_no_diagnostics"],
-                  "note": "50-step HIP graphs (51 force evaluations each) replayed, no energy diagnostics"},
+        "timing": {"method": "the K timed steps are one captured HIP graph holding the energy diagnostic every "
+                             "10 steps (K + 1 force evaluations), replayed once untimed after the W eager warm-up "
+                             "steps, then once timed",
+                   "eager_fp32_ms_per_step": f32["eager_ms_per_step"],
+                   "eager_fp64_ms_per_step": f64["eager_ms_per_step"],
+                   "graph_50_steps_no_diagnostics_fp32_ms_per_step": f32["graph_ms_per_step_no_diagnostics"],
+                   "graph_50_steps_no_diagnostics_fp64_ms_per_step": f64["graph_ms_per_step_no_diagnostics"]},
         "fp64": {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                  "G_pair_interactions_per_s_kick": f64["kick_G_pairs_per_s"], "kick_ms": f64["kick_ms"],
                  "roofline": {"bound": "alu", "achieved": f64["kick_tflops"], "peak": PEAK_FP64_TFLOPS,

@@ -53,6 +53,8 @@ def lib() -> ctypes.CDLL:
         i64 = ctypes.c_int64
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_num_threads.restype = None
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_changeover.restype = ctypes.c_double
         L.oracle_changeover.argtypes = [ctypes.c_double]
         L.oracle_rcrit.argtypes = [i64] + [d] * 7 + [ctypes.c_double] * 4 + [d]
@@ -109,6 +111,11 @@ def _f64(a) -> np.ndarray:
 # Functions on one system (the Sun plus n bodies).  State dicts hold float64 arrays
 # x, y, z, vx, vy, vz, m (heliocentric positions, barycentric velocities).
 # -------------------------------------------------------------------------------------------
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
+
 
 def num_threads() -> int:
     """OpenMP threads used by the oracle's parallel loops."""

@@ -46,6 +46,12 @@ int oracle_num_threads(void)
     return omp_get_max_threads();
 }
 
+/* Threads of the later parallel loops (timings on one core); the results do not depend on it. */
+void oracle_set_num_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
 /* ------------------------------------------------------------------------------------
  * Changeover function (Sect. 1; the Chambers 1999 form cited there).
  * ---------------------------------------------------------------------------------- */
