@@ -185,6 +185,27 @@ int genga_rcrit(genga_ctx *ctx, const genga_bodies *b, double n1, double n2, dou
 int genga_accel(genga_ctx *ctx, const genga_bodies *b, double *ax, double *ay, double *az, int prec,
                 int acc, void *stream);
 
+/* Largest n that genga_accel_noalloc takes. */
+#define GENGA_NOALLOC_MAX_BODIES 65536
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): genga_accel for one system of n bodies, all massive
+ * (0 <= n <= GENGA_NOALLOC_MAX_BODIES), with no context and no allocation.  Its scratch (source
+ * records, launch plan, split shares; about 8.4 MB) is one static device array per GPU, held
+ * until the process ends; its address is looked up on the first call on a device (or by
+ * genga_create).  Reads b->x, b->y, b->z, b->m, b->rcrit (device, n entries; b may be NULL when
+ * n = 0).  Writes ax, ay, az [n] (device), the encounter pairs (i < j, unordered, as the kick
+ * finds them) into pairs[pair_cap][2] (device int32; pairs may be NULL when pair_cap = 0), the
+ * full pair count into *d_count and the device conditions into *d_status (device int32 words,
+ * both cleared by the call): bit 1 the list did not fit in pair_cap, bit 2 a non-finite
+ * acceleration.  The launch shape is the one a context picks by default for the same system,
+ * so the results equal genga_accel's bit for bit.  Everything is enqueued on `stream` (no
+ * memset, no host wait), so the call can be captured.  All calls on one GPU share the scratch:
+ * calls that overlap in time on one GPU (several streams or host threads) race; the caller
+ * orders them. */
+int genga_accel_noalloc(const genga_bodies *b, int32_t n, double *ax, double *ay, double *az, int32_t *pairs,
+                        int32_t pair_cap, int32_t *d_count, int32_t *d_status, int prec, int acc, void *stream);
+
 /* The kick (Sect. 1, level 0): v_i += tau * a_i with a_i as in genga_accel, in the given
  * precision and accumulator.  The same launch records every pair (i < j) with
  * r_ij^2 < r_crit,ij^2 (decided in FP64) into the context's encounter list, which the next

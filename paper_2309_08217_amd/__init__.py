@@ -37,7 +37,7 @@ GENGA_ACC_KAHAN32 = 1
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
     "genga_set_levels", "genga_tune_levels", "genga_set_collisions", "genga_compact",
-    "genga_rcrit", "genga_accel",
+    "genga_rcrit", "genga_accel", "genga_accel_noalloc",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
     "genga_get_kick_shape", "genga_poll_status", "genga_last_error",
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                               ctypes.POINTER(i32), vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
         "genga_accel": [vp, bp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp],
+        "genga_accel_noalloc": [bp, i32, vp, vp, vp, vp, i32, vp, vp, ctypes.c_int, ctypes.c_int, vp],
         "genga_kick": [vp, bp, dbl, ctypes.c_int, ctypes.c_int, vp],
         "genga_encounter_list": [vp, bp, vp, i32, vp, vp],
         "genga_drift": [vp, bp, dbl, vp, vp, vp],
@@ -251,6 +252,19 @@ def genga_accel(ctx: int, b: Bodies, ax, ay, az, prec: int, acc: int = GENGA_ACC
     cb = b.c()
     _check(load_library().genga_accel(ctx, ctypes.byref(cb), _ptr(ax), _ptr(ay), _ptr(az), int(prec), int(acc),
                                       _stream(stream)))
+
+
+GENGA_NOALLOC_MAX_BODIES = 65536
+
+
+def genga_accel_noalloc(b: Optional[Bodies], n: int, ax, ay, az, pairs, pair_cap: int, d_count, d_status,
+                        prec: int, acc: int = GENGA_ACC_FP64, stream=None) -> None:
+    """Accelerations and encounter pairs of one system of n bodies with no context and no
+    allocation (scratch in a static device array); d_count / d_status: device int32 words."""
+    cb = b.c() if b is not None else None
+    _check(load_library().genga_accel_noalloc(ctypes.byref(cb) if cb is not None else None, int(n), _ptr(ax),
+                                              _ptr(ay), _ptr(az), _ptr(pairs), int(pair_cap), _ptr(d_count),
+                                              _ptr(d_status), int(prec), int(acc), _stream(stream)))
 
 
 def genga_kick(ctx: int, b: Bodies, tau: float, prec: int, acc: int = GENGA_ACC_FP64, stream=None) -> None:

@@ -14,10 +14,10 @@
 using namespace genga;
 
 namespace {
-
 thread_local std::string g_last_error;
+} // namespace
 
-int fail(int code, const char *fmt, ...)
+int genga::fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -27,6 +27,8 @@ int fail(int code, const char *fmt, ...)
     g_last_error = buf;
     return code;
 }
+
+namespace {
 
 #define HIP_TRY(expr)                                                                         \
     do {                                                                                      \
@@ -66,7 +68,7 @@ struct genga_ctx {
     int32_t n_items = 0;
     WorkItem *eitems = nullptr; // energy items, in system order
     int32_t *item_first = nullptr;
-    int waves[2] = {8, 16};     // [prec] waves per workgroup of the kick
+    int waves[2] = {default_kick_waves(0), default_kick_waves(1)}; // [prec] waves per workgroup of the kick
     int grid[2] = {0, 0};       // 0: one workgroup per task
     int split[2] = {1, 1};      // [prec] workgroups sharing an item's sources
     double *kpart = nullptr;    // [KICK_MAX_SPLIT][3][n_total]
@@ -252,22 +254,9 @@ int check_bodies(const genga_ctx *ctx, const genga_bodies *b, bool need_v, bool 
     return GENGA_OK;
 }
 
-// Source split that best fills the chip: the kick's workgroups run about one per CU at a
-// time, so pick the split whose number of workgroups wastes the least of the last round.
 int default_split(const genga_ctx *ctx)
 {
-    int best = 1;
-    double best_eff = 0.0;
-    for (int sp = 1; sp <= KICK_MAX_SPLIT; ++sp) {
-        const double tasks = (double)ctx->n_items * sp;
-        const double rounds = std::ceil(tasks / ctx->n_cu);
-        const double eff = tasks / (rounds * ctx->n_cu);
-        if (eff > best_eff + 0.02) {
-            best_eff = eff;
-            best = sp;
-        }
-    }
-    return best;
+    return default_kick_split(ctx->n_items, ctx->n_cu);
 }
 
 int check_prec(int prec)
@@ -1036,6 +1025,9 @@ int genga_create(genga_ctx **out, int device)
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(GENGA_ERR_ARG, "device %d out of range (%d devices)", device, ndev);
     HIP_TRY(hipSetDevice(device));
+    // the allocation-free entry point's scratch address on this device
+    int rc = noalloc_prepare(device, nullptr, nullptr);
+    if (rc) return rc;
     genga_ctx *c = new genga_ctx();
     c->device = device;
     if (hipHostMalloc((void **)&c->hpin, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {

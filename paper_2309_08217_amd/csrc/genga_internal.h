@@ -87,6 +87,33 @@ struct KickArgs {
 
 constexpr int KICK_MAX_SPLIT = 4;
 
+// Error message for genga_last_error(); returns code.
+int fail(int code, const char *fmt, ...);
+
+// Source split that best fills the chip: the kick's workgroups run about one per CU at a
+// time, so pick the split whose number of workgroups wastes the least of the last round.
+inline int default_kick_split(int n_items, int n_cu)
+{
+    int best = 1;
+    double best_eff = 0.0;
+    for (int sp = 1; sp <= KICK_MAX_SPLIT; ++sp) {
+        const double tasks = (double)n_items * sp;
+        const double rounds = __builtin_ceil(tasks / n_cu);
+        const double eff = tasks / (rounds * n_cu);
+        if (eff > best_eff + 0.02) {
+            best_eff = eff;
+            best = sp;
+        }
+    }
+    return best;
+}
+
+// Waves per workgroup of the kick before any tuning.
+inline int default_kick_waves(int fp32) { return fp32 ? 16 : 8; }
+
+// Address of the allocation-free entry point's scratch array on `device` (looked up once).
+int noalloc_prepare(int device, unsigned char **ptr_out, int *n_cu_out);
+
 constexpr int ENERGY_SPLIT = 4;   // workgroups sharing one item's sources in the energy sum
 
 // Kernel launchers (each enqueues on `stream`; return hipError_t of the launch).
