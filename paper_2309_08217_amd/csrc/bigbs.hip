@@ -85,6 +85,13 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
         b.Y[3 * M + f] = vx[body];
         b.Y[4 * M + f] = vy[body];
         b.Y[5 * M + f] = vz[body];
+        if (b.skin) {
+            // every step starts from twice the bound's estimate, so a step's lists depend on its
+            // starting state only (a run resumed from a saved state repeats them bit for bit)
+            b.skin[body] = 2.0;
+            b.crossed[f] = 0;
+            b.amut[f] = 0.0;
+        }
         // candidate radius: the deepest level's r_crit
         double rd = rc[body];
         for (int k = 1; k < b.nlev; ++k) {
@@ -105,6 +112,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
         b.H[g] = dt;
         b.attempts[g] = 0;
         b.done[g] = 0;
+        if (b.skin) b.stale[g] = 0;
     }
 }
 
@@ -120,6 +128,7 @@ __global__ __launch_bounds__(64) void big_begin_kernel(BigBs b, int32_t *flags)
     if (last) H = dt - t;
     const int att = b.attempts[g] + 1;
     b.attempts[g] = att;
+    if (b.skin) b.stale[g] = 0; // a void attempt is repeated with wider margins where they were crossed
     if (H < dt * 0x1p-40 || att > 20000) {
         atomicOr(flags, FLAG_NOCONVERGE);
         b.done[g] = 1;
@@ -320,6 +329,16 @@ __device__ __forceinline__ void substep_tile(const BigBs &b, int me, int k, int 
         d[4] += red[1][w][lane];
         d[5] += red[2][w][lane];
     }
+    if (mode == 0 && k == 0 && valid && b.amut) {
+        // the pair acceleration at the attempt's start, for the list path's bounds
+        double px = 0.0, py = 0.0, pz = 0.0;
+        for (int w = 0; w < W; ++w) {
+            px += red[0][w][lane];
+            py += red[1][w][lane];
+            pz += red[2][w][lane];
+        }
+        b.amut[fa] = sqrt(sep2_rn(px, py, pz));
+    }
     const double h = b.H[g] / (2 * (k + 1));
     if (mode == 2) {
         double tk[6];
@@ -369,10 +388,329 @@ __global__ __launch_bounds__(GB_TILE *W) void big_substep_kernel(BigBs b, int k,
     }
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// The list path.  At an attempt's start each member lists the sources that can come within
+// r_crit,ab during the attempt.  The sub-step states of the modified midpoint method with step h
+// under a constant pull A lie at Y + V tau + A (tau^2 - h^2) / 2 for odd j (tau = j h) and at
+// Y + V tau + A tau^2 / 2 for even j; with A the star's pull at Y that is each member's
+// prediction P_j, and S bounds its departure from it (the change of the star's pull along the
+// path, the jerk 3 Mstar |V| / |Y|^3 over H^3 / 6, and the members' mutual pull a_mut over
+// H^2 / 2, a_mut as the last force evaluation at an attempt's start found it (0 before the
+// step's first), times the body's skin factor, at least 2).  A source is listed when the
+// straight lines Y + V t of the two members come within
+// r_crit,ab + S_a + S_b + |A_a - A_b| H^2 / 2 over [0, H]: then no unlisted pair can be inside
+// r_crit,ab at a state where every member is within S of its prediction.  Every sub-step state
+// checks |Z - P_j| <= S for every member; a crossed bound marks the group stale: the attempt is
+// neither accepted nor counted as rejected, and the next one lists again, with four times the
+// skin of each member that crossed its bound (bodies in close encounters, whose mutual pull the
+// prediction leaves out, get wider margins for the rest of the step; every step starts at 2).
+// The lists are in a fixed order, so the sums are deterministic.
+// ---------------------------------------------------------------------------------------------
+
+// The member's prediction constants: the star's pull A at Y and the bound S for step H.
+struct ListMember {
+    double ax, ay, az, s;
+};
+
+__device__ __forceinline__ ListMember list_member(double skin, double ms, double H, double x, double y, double z,
+                                                  double u, double v, double w, double amut)
+{
+    const double r2 = sep2_rn(x, y, z);
+    const double ri = inv_sqrt64(r2);
+    const double a = ms / r2;                 // |A|
+    const double c = -a * ri;                 // A = -Mstar Y / |Y|^3
+    const double vv = sqrt(sep2_rn(u, v, w));
+    ListMember m;
+    m.ax = c * x;
+    m.ay = c * y;
+    m.az = c * z;
+    m.s = skin * 0.5 * (a * ri * vv * H + amut) * (H * H);
+    return m;
+}
+
+// Constants of the sources for the list sub-step, packed (mass, r_crit, 1 / (0.9 r_crit), TP2).
+__global__ __launch_bounds__(GB_THREADS) void big_src_kernel(BigBs b)
+{
+    const int f = blockIdx.x * GB_THREADS + threadIdx.x;
+    if (f >= b.dims[1]) return;
+    b.src[f] = make_double4(b.mass[f], b.rc[f], b.i09[f], b.test[f] ? 1.0 : 0.0);
+}
+
+// Per tile: the box swept by its members' straight lines over [0, H], and the largest
+// S + |A| H^2 / 2 of its members.
+__global__ __launch_bounds__(64) void big_sweep_kernel(BigBs b)
+{
+    for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
+        const int4 tile = b.tiles[me];
+        const int g = tile.x;
+        if (b.done[g]) continue;
+        const size_t M = (size_t)b.dims[1];
+        const bool v = (int)threadIdx.x < tile.z;
+        const int f = tile.y + (v ? (int)threadIdx.x : 0);
+        const double H = b.H[g];
+        const double x = b.Y[f], y = b.Y[M + f], z = b.Y[2 * M + f];
+        const double u = b.Y[3 * M + f], vy = b.Y[4 * M + f], w = b.Y[5 * M + f];
+        const double x1 = fma(u, H, x), y1 = fma(vy, H, y), z1 = fma(w, H, z);
+        double sk = 2.0;
+        if (v) {
+            const int body = b.body[f];
+            sk = b.skin[body];
+            if (b.crossed[f]) { // the member left its bound in the last attempt: four times wider
+                sk *= 4.0;
+                b.skin[body] = sk;
+                b.crossed[f] = 0;
+            }
+        }
+        const ListMember lm = list_member(sk, b.mstar[g], H, x, y, z, u, vy, w, v ? b.amut[f] : 0.0);
+        if (v) b.pred[f] = make_double4(lm.ax, lm.ay, lm.az, lm.s);
+        const double lo[3] = {wave_minv(v ? fmin(x, x1) : INFINITY), wave_minv(v ? fmin(y, y1) : INFINITY),
+                              wave_minv(v ? fmin(z, z1) : INFINITY)};
+        const double hi[3] = {wave_maxv(v ? fmax(x, x1) : -INFINITY), wave_maxv(v ? fmax(y, y1) : -INFINITY),
+                              wave_maxv(v ? fmax(z, z1) : -INFINITY)};
+        const double ext =
+            wave_maxv(v ? lm.s + 0.5 * sqrt(sep2_rn(lm.ax, lm.ay, lm.az)) * H * H : 0.0);
+        const int lane = threadIdx.x;
+        if (lane < 3) {
+            b.sbb[me * 8 + lane] = lo[lane];
+            b.sbb[me * 8 + 3 + lane] = hi[lane];
+        }
+        if (lane == 0) b.sbb[me * 8 + 6] = ext;
+    }
+}
+
+// One source j for the target lane's list segment (wave-uniform j): listed when the straight
+// lines come within r = r_crit,ab + S_a + S_j + |A_a - A_j|_1 H^2 / 2 over [0, H] (the 1-norm
+// bounds the length of the difference).  The minimum of |d + v t|^2 over [0, H] is taken
+// without a division: at t = 0 when d.v >= 0, at t = H when -d.v >= |v|^2 H, else it is
+// |d|^2 - (d.v)^2 / |v|^2, compared as (|d|^2 - r^2) |v|^2 < (d.v)^2.
+__device__ __forceinline__ void list_source(const BigBs &b, bool valid, int fa, bool testa, double rfa,
+                                            double xa, double ya, double za, double ua, double va, double wa,
+                                            double4 pa, double H, int j, double xj, double yj, double zj, double uj,
+                                            double vj, double wj, double rj, bool testj, double4 pj, int32_t *row,
+                                            int &len, bool &over)
+{
+    const double dx = xj - xa, dy = yj - ya, dz = zj - za;
+    const double du = uj - ua, dv = vj - va, dw = wj - wa;
+    const double dd = sep2_rn(dx, dy, dz), vv = sep2_rn(du, dv, dw);
+    const double dp = (dx * du + dy * dv) + dz * dw;
+    const double r = fmax(rfa, rj) + pa.w + pj.w +
+                     0.5 * (fabs(pj.x - pa.x) + fabs(pj.y - pa.y) + fabs(pj.z - pa.z)) * (H * H);
+    // a margin of 2^-30 covers the rounding of the distance
+    const double r2 = r * r * (1.0 + 0x1p-30);
+    bool close;
+    if (dp >= 0.0 || vv == 0.0) {
+        close = dd < r2;
+    } else if (-dp >= vv * H) {
+        close = sep2_rn(fma(du, H, dx), fma(dv, H, dy), fma(dw, H, dz)) < r2;
+    } else {
+        close = (dd - r2) * vv < dp * dp;
+    }
+    if (valid && close && j != fa && !(testa && testj)) {
+        if (len < BIG_LIST_SEG) row[len] = j;
+        else over = true;
+        ++len;
+    }
+}
+
+// A segment of the lists of a target tile's members (one wave per tile and segment; segment s
+// takes the group's source tiles tt = s, s + BIG_LIST_SEGS, ...): the source tiles whose swept
+// boxes lie within the largest radius plus both tiles' largest extents, then their sources on
+// the straight lines, in quads whose words come through scalar loads.
+template <bool LV>
+__global__ __launch_bounds__(64) void big_list_kernel(BigBs b)
+{
+    CD *YA = (CD *)b.Y;
+    CD *SB = (CD *)b.sbb;
+    CD *RC = (CD *)b.rc;
+    CI *TS = (CI *)b.test;
+    CD *RL = (CD *)b.rcl;
+    CD *PR = (CD *)b.pred; // (A, S) of member j at PR[4 j .. 4 j + 3]
+    for (int ms = blockIdx.x; ms < b.dims[2] * BIG_LIST_SEGS; ms += gridDim.x) {
+        const int me = ms / BIG_LIST_SEGS, seg = ms % BIG_LIST_SEGS;
+        const int4 tile = b.tiles[me];
+        const int g = tile.x;
+        if (b.done[g]) continue;
+        const size_t M = (size_t)b.dims[1];
+        const size_t lvo = LV ? (size_t)(b.nlev - 2) * b.cap_M : 0; // the deepest level's radii
+        const int lane = threadIdx.x;
+        const bool valid = lane < tile.z;
+        const int fa = tile.y + (valid ? lane : 0);
+        const int o = b.off[g], nb = b.off[g + 1] - o;
+        const int tf = b.tfirst[g], nt = b.tfirst[g + 1] - tf;
+        const double H = b.H[g];
+        const double xa = b.Y[fa], ya = b.Y[M + fa], za = b.Y[2 * M + fa];
+        const double ua = b.Y[3 * M + fa], va = b.Y[4 * M + fa], wa = b.Y[5 * M + fa];
+        const double4 pa = b.pred[fa];
+        const bool testa = b.test[fa] != 0;
+        const double rfa = LV ? b.rcl[lvo + fa] : b.rc[fa];
+        const double rmax = sqrt(b.rcmax2[g]);
+        const double tlx = SB[me * 8 + 0], tly = SB[me * 8 + 1], tlz = SB[me * 8 + 2];
+        const double thx = SB[me * 8 + 3], thy = SB[me * 8 + 4], thz = SB[me * 8 + 5], et = SB[me * 8 + 6];
+        int32_t *row = b.nl + (size_t)fa * BIG_LIST_CAP + seg * BIG_LIST_SEG;
+        int len = 0;
+        bool over = false;
+        for (int tt = seg; tt < nt; tt += BIG_LIST_SEGS) {
+            const int st = tf + tt;
+            const double gx = fmax(0.0, fmax(SB[st * 8 + 0] - thx, tlx - SB[st * 8 + 3]));
+            const double gy = fmax(0.0, fmax(SB[st * 8 + 1] - thy, tly - SB[st * 8 + 4]));
+            const double gz = fmax(0.0, fmax(SB[st * 8 + 2] - thz, tlz - SB[st * 8 + 5]));
+            const double cut = rmax + et + SB[st * 8 + 6];
+            if ((gx * gx + gy * gy) + gz * gz > cut * cut * (1.0 + 0x1p-30)) continue;
+            const int jb = o + 64 * tt, je = min(jb + 64, o + nb);
+            int j = jb;
+            for (; j + 4 <= je; j += 4) {
+                double X[4], Yv[4], Zv[4], U[4], V[4], W[4], R[4];
+                double4 Pj[4];
+                bool T[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    X[q] = YA[j + q];
+                    Yv[q] = YA[M + j + q];
+                    Zv[q] = YA[2 * M + j + q];
+                    U[q] = YA[3 * M + j + q];
+                    V[q] = YA[4 * M + j + q];
+                    W[q] = YA[5 * M + j + q];
+                    R[q] = LV ? RL[lvo + j + q] : RC[j + q];
+                    T[q] = TS[j + q] != 0;
+                    Pj[q] = make_double4(PR[4 * (j + q)], PR[4 * (j + q) + 1], PR[4 * (j + q) + 2],
+                                         PR[4 * (j + q) + 3]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    list_source(b, valid, fa, testa, rfa, xa, ya, za, ua, va, wa, pa, H, j + q, X[q], Yv[q], Zv[q],
+                                U[q], V[q], W[q], R[q], T[q], Pj[q], row, len, over);
+            }
+            for (; j < je; ++j)
+                list_source(b, valid, fa, testa, rfa, xa, ya, za, ua, va, wa, pa, H, j, YA[j], YA[M + j],
+                            YA[2 * M + j], YA[3 * M + j], YA[4 * M + j], YA[5 * M + j], LV ? RL[lvo + j] : RC[j],
+                            TS[j] != 0, make_double4(PR[4 * j], PR[4 * j + 1], PR[4 * j + 2], PR[4 * j + 3]),
+                            row, len, over);
+        }
+        if (valid) b.nlen[(size_t)fa * BIG_LIST_SEGS + seg] = min(len, BIG_LIST_SEG);
+        if (__ballot(over) && lane == 0) {
+            atomicOr(b.ovf, 1);
+            b.stale[g] = 1;
+        }
+    }
+}
+
+// One sub-step on the list path (modes and outputs as substep_tile; jstep: Z is the state at
+// tau = jstep * H / (2 (k + 1))).  BIG_LIST_LANES lanes share a member: each sums every
+// BIG_LIST_LANES-th entry of its list, then the parts are added in a fixed tree.
+template <bool LV>
+__global__ __launch_bounds__(256) void big_substep_list_kernel(BigBs b, int k, int mode, int jstep,
+                                                               const double *Z, const double *ZM, double *OUT)
+{
+    constexpr int P = BIG_LIST_LANES;
+    const size_t M = (size_t)b.dims[1];
+    for (int t0 = blockIdx.x * 256; t0 < b.dims[1] * P; t0 += gridDim.x * 256) {
+        const int t = t0 + (int)threadIdx.x;
+        const int part = t % P;
+        const bool valid = t < b.dims[1] * P;
+        const int fa = valid ? t / P : 0;
+        const int g = b.grp[fa];
+        const bool act = valid && !b.done[g] && b.acc[g] < 0;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
+        if (act) {
+            // the bound of the lists: every member stays within S of its prediction
+            if (part == 0 && jstep > 0) {
+                const double H = b.H[g], hs = H / (2 * (k + 1)), tau = hs * jstep;
+                const double4 pm = b.pred[fa];
+                const double h2 = 0.5 * (tau * tau - ((jstep & 1) ? hs * hs : 0.0));
+                const double px = fma(pm.x, h2, fma(b.Y[3 * M + fa], tau, b.Y[fa]));
+                const double py = fma(pm.y, h2, fma(b.Y[4 * M + fa], tau, b.Y[M + fa]));
+                const double pz = fma(pm.z, h2, fma(b.Y[5 * M + fa], tau, b.Y[2 * M + fa]));
+                if (!(sep2_rn(xa - px, ya - py, za - pz) <= pm.w * pm.w * (1.0 - 0x1p-30))) {
+                    b.stale[g] = 1;
+                    b.crossed[fa] = 1;
+                }
+            }
+            const double4 sa = b.src[fa];
+            const double rca = sa.y, i09a = sa.z;
+            const bool testa = sa.w != 0.0;
+            for (int sg = 0; sg < BIG_LIST_SEGS; ++sg) {
+            const int n = b.nlen[(size_t)fa * BIG_LIST_SEGS + sg];
+            const int32_t *L = b.nl + (size_t)fa * BIG_LIST_CAP + sg * BIG_LIST_SEG;
+            for (int e = part; e < n; e += P) {
+                const int j = L[e];
+                const double4 sj = b.src[j];
+                const double dx = Z[j] - xa, dy = Z[M + j] - ya, dz = Z[2 * M + j] - za;
+                const bool own = rca >= sj.y;
+                const double rcab = own ? rca : sj.y;
+                const double q = sep2_rn(dx, dy, dz);
+                const double rq = inv_sqrt64(q);
+                const double yv = (q * rq - 0.1 * rcab) * (own ? i09a : sj.z);
+                const double y2 = yv * yv;
+                const double kv = yv <= 0.0 ? 0.0 : (yv >= 1.0 ? 1.0 : y2 / (2.0 * y2 - 2.0 * yv + 1.0));
+                double w = 1.0 - kv, rdeep = rcab;
+                if constexpr (LV) {
+                    for (int l = 1; l < b.nlev; ++l) {
+                        const double rcl_ab = fmax(b.rcl[(size_t)(l - 1) * b.cap_M + fa],
+                                                   b.rcl[(size_t)(l - 1) * b.cap_M + j]);
+                        w *= 1.0 - changeover_k((q * rq - 0.1 * rcl_ab) / (0.9 * rcl_ab));
+                        rdeep = rcl_ab;
+                    }
+                }
+                const bool in = j != fa && !(testa && sj.w != 0.0) && q < sq_rn(rdeep);
+                const double s = in ? sj.x * w * (rq * rq) * rq : 0.0;
+                ax = fma(s, dx, ax);
+                ay = fma(s, dy, ay);
+                az = fma(s, dz, az);
+            }
+            }
+        }
+        // the parts of a member, in a fixed order
+        for (int off = P / 2; off > 0; off >>= 1) {
+            ax += __shfl_xor(ax, off, 64);
+            ay += __shfl_xor(ay, off, 64);
+            az += __shfl_xor(az, off, 64);
+        }
+        const bool lead = act && part == 0;
+        if (mode == 0 && k == 0 && lead) b.amut[fa] = sqrt(sep2_rn(ax, ay, az));
+        const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
+        const double s = -b.mstar[g] * (ri * ri) * ri;
+        double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa + ax, s * ya + ay, s * za + az};
+        const double h = b.H[g] / (2 * (k + 1));
+        if (mode == 2) {
+            double tk[6];
+            for (int q = 0; q < 6; ++q) tk[q] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
+            if (lead) {
+                double *T0 = b.tcol + (size_t)k * 6 * M;
+                for (int q = 0; q < 6; ++q) T0[q * M + fa] = tk[q];
+            }
+            if (k == 0) continue;
+            double dp = 0.0, dvv = 0.0;
+            bool bad = false;
+            if (lead) {
+                for (int q = 0; q < 6; ++q) {
+                    const double tz = b.tcol[q * M + fa];
+                    double sum = 0.0;
+                    for (int jj = 1; jj <= k; ++jj) {
+                        const double v = jj == k ? tk[q] : b.tcol[((size_t)jj * 6 + q) * M + fa];
+                        sum = fma(LAGRANGE.d[k][jj], v - tz, sum);
+                    }
+                    if (q < 3) dp = fmax(dp, fabs(sum));
+                    else dvv = fmax(dvv, fabs(sum));
+                    bad |= !(sum == sum);
+                }
+            }
+            const double e = fmax(dp / bitsd(b.sr[g]), dvv / bitsd(b.sv[g]));
+            wave_atomic_max(b.err + k, g * BS_KMAX, lead, (bad || !(e == e)) ? ~0ull : dbits(e));
+            continue;
+        }
+        if (lead)
+            for (int q = 0; q < 6; ++q)
+                OUT[q * M + fa] = (mode == 0 ? Z[q * M + fa] : ZM[q * M + fa]) + (mode == 0 ? h : 2.0 * h) * d[q];
+    }
+}
+
 __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double tol)
 {
     const int g = blockIdx.x * 64 + threadIdx.x;
     if (g >= b.dims[0] || b.done[g] || b.acc[g] >= 0) return;
+    if (b.skin && b.stale[g]) return; // a sub-step left the list's bound: no column counts
     const unsigned long long e = b.err[g * BS_KMAX + k];
     if (e != ~0ull && bitsd(e) <= tol) b.acc[g] = k;
 }
@@ -403,6 +741,10 @@ __global__ __launch_bounds__(GB_THREADS) void big_control_kernel(BigBs b, double
     int active = 0;
     for (int g = threadIdx.x; g < b.dims[0]; g += GB_THREADS) {
         if (b.done[g]) continue;
+        if (b.skin && b.stale[g]) { // a void attempt: the same step again (with wider lists)
+            ++active;
+            continue;
+        }
         const int ks = b.acc[g];
         if (ks >= 0) {
             const double t = b.last[g] ? dt : b.t[g] + b.H[g];
@@ -493,6 +835,42 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int ti
         }
         substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
         if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol); // the estimates came with T(k, 0)
+    }
+    big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream)
+{
+    const int gg = (b.cap_G + 63) / 64, gm = (b.cap_M + GB_THREADS - 1) / GB_THREADS;
+    const int nt = std::max(1, std::min(tile_grid, b.cap_T));
+    const int gl = (int)std::min<int64_t>(((int64_t)b.cap_M * BIG_LIST_LANES + 255) / 256, 4096);
+    const size_t M6 = 6 * (size_t)b.cap_M;
+    double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6}; // Y, B1, B2
+    const bool lv = b.nlev > 1;
+    auto substep = lv ? big_substep_list_kernel<true> : big_substep_list_kernel<false>;
+    big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
+    big_scale_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_src_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_sweep_kernel<<<nt, 64, 0, stream>>>(b);
+    const int nl = std::min(nt * BIG_LIST_SEGS, 65536);
+    if (lv)
+        big_list_kernel<true><<<nl, 64, 0, stream>>>(b);
+    else
+        big_list_kernel<false><<<nl, 64, 0, stream>>>(b);
+    for (int k = 0; k < BS_KMAX; ++k) {
+        const int nsub = 2 * (k + 1);
+        substep<<<gl, 256, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1]);
+        int zc = 1, zm = 0;
+        for (int i = 1; i < nsub; ++i) {
+            const int out = zm == 0 ? 2 : zm;
+            substep<<<gl, 256, 0, stream>>>(b, k, 1, i, buf[zc], buf[zm], buf[out]);
+            zm = zc;
+            zc = out;
+        }
+        substep<<<gl, 256, 0, stream>>>(b, k, 2, nsub, buf[zc], buf[zm], nullptr);
+        if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);
     }
     big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
     big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);

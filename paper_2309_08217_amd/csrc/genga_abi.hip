@@ -93,6 +93,7 @@ struct genga_ctx {
     // the captured attempt, replayed on the caller's stream: one per tile-launch grid (a power
     // of two that covers the layout's tiles)
     hipGraphExec_t big_exec[32] = {};
+    hipGraphExec_t big_exec_list[32] = {}; // the same on the list path
     int32_t *big_changed = nullptr;    // device word of the union-find rounds
     int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
@@ -153,6 +154,16 @@ struct genga_ctx {
         dfree(big.err);
         dfree(big.n_active);
         dfree(big.rcl);
+        dfree(big.nl);
+        dfree(big.nlen);
+        dfree(big.pred);
+        dfree(big.skin);
+        dfree(big.crossed);
+        dfree(big.amut);
+        dfree(big.stale);
+        dfree(big.sbb);
+        dfree(big.src);
+        dfree(big.ovf);
         big.nlev = 1;
         dfree(rc_lv);
         for (auto &t : lt) {
@@ -181,8 +192,11 @@ struct genga_ctx {
         if (pin) (void)hipHostFree(pin);
         for (auto &e : big_exec)
             if (e) (void)hipGraphExecDestroy(e);
+        for (auto &e : big_exec_list)
+            if (e) (void)hipGraphExecDestroy(e);
         if (big_stream) (void)hipStreamDestroy(big_stream);
         for (auto &e : big_exec) e = nullptr;
+        for (auto &e : big_exec_list) e = nullptr;
         big_stream = nullptr;
         dfree(big.dims);
         dfree(big.dtp);
@@ -471,6 +485,20 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.sv, G));
     HIP_TRY(dalloc(b.err, G * BS_KMAX));
     HIP_TRY(dalloc(b.n_active, 1));
+    HIP_TRY(dalloc(b.nl, M * BIG_LIST_CAP));
+    HIP_TRY(dalloc(b.nlen, M * BIG_LIST_SEGS));
+    HIP_TRY(dalloc(b.pred, M));
+    HIP_TRY(dalloc(b.skin, M));
+    HIP_TRY(dalloc(b.crossed, M));
+    HIP_TRY(dalloc(b.amut, M));
+    HIP_TRY(hipMemset(b.skin, 0, M * sizeof(double)));
+    HIP_TRY(hipMemset(b.crossed, 0, M * sizeof(int32_t)));
+    HIP_TRY(dalloc(b.stale, G));
+    HIP_TRY(dalloc(b.sbb, 8 * (size_t)b.cap_T));
+    HIP_TRY(dalloc(b.src, M));
+    HIP_TRY(dalloc(b.ovf, 1));
+    HIP_TRY(hipMemset(b.ovf, 0, sizeof(int32_t)));
+    HIP_TRY(hipMemset(b.stale, 0, G * sizeof(int32_t)));
     HIP_TRY(dalloc(b.dims, 4));
     HIP_TRY(dalloc(b.dtp, 1));
     HIP_TRY(dalloc(ctx->big_changed, 1));
@@ -912,16 +940,18 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
     // group after 20000 attempts, so the loop ends
     int gl = 6;
     while ((1 << gl) < bg.n_tiles && (1 << gl) < bg.cap_T) ++gl;
-    hipGraphExec_t &exec = ctx->big_exec[gl];
-    if (!exec) {
-        // one attempt's launch sequence, captured once per context and grid (sizes and dt live
-        // in device memory, every buffer address is fixed)
+    // one attempt's launch sequence, captured once per context, path and grid (sizes and dt live
+    // in device memory, every buffer address is fixed)
+    const auto attempt_graph = [&](bool lists, hipGraphExec_t &exec) -> int {
+        if (exec) return GENGA_OK;
         if (!ctx->big_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->big_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(ctx->big_stream, hipStreamCaptureModeThreadLocal));
-        // 16 waves per tile while the grid fits one workgroup per CU, else 8 (two workgroups
-        // per CU: at N = 40322, 631 tiles, 20.5 steps/s against 18.0 with 16 and 19.4 with 4)
+        // tile path: 16 waves per tile while the grid fits one workgroup per CU, else 8 (two
+        // workgroups per CU: at N = 40322, 631 tiles, 20.5 steps/s against 18.0 with 16 and 19.4
+        // with 4)
         const int tg = 1 << gl, waves = tg <= ctx->n_cu ? 16 : 8;
-        const hipError_t le = launch_big_attempt(bg, 1e-12, ctx->flags, tg, waves, ctx->big_stream);
+        const hipError_t le = lists ? launch_big_attempt_list(bg, 1e-12, ctx->flags, tg, ctx->big_stream)
+                                    : launch_big_attempt(bg, 1e-12, ctx->flags, tg, waves, ctx->big_stream);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(ctx->big_stream, &g);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -935,11 +965,22 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
             exec = nullptr;
             return fail(GENGA_ERR_HIP, "hipGraphInstantiate (large-group attempt) failed: %s", hipGetErrorString(ie));
         }
-    }
+        return GENGA_OK;
+    };
+    // the list path; a list above its capacity sends the rest of the step to the tile path
+    if ((rc = attempt_graph(true, ctx->big_exec_list[gl]))) return rc;
+    bool lists = true;
     for (int attempt = 0; attempt <= 20001; ++attempt) {
-        HIP_TRY(hipGraphLaunch(exec, s));
+        HIP_TRY(hipGraphLaunch(lists ? ctx->big_exec_list[gl] : ctx->big_exec[gl], s));
         HIP_TRY(hipMemcpyAsync(ctx->pin + 1, bg.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (lists) HIP_TRY(hipMemcpyAsync(ctx->pin + 2, bg.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (lists && ctx->pin[2]) {
+            ctx->pin[2] = 0;
+            HIP_TRY(hipMemcpyAsync(bg.ovf, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            if ((rc = attempt_graph(false, ctx->big_exec[gl]))) return rc;
+            lists = false;
+        }
         if (ctx->pin[1] == 0) break;
     }
     HIP_TRY(launch_big_finish(bg, b->x, b->y, b->z, b->vx, b->vy, b->vz, s));

@@ -220,8 +220,27 @@ struct BigBs {
     // level's.  Fixed when the attempt graph is captured.
     int32_t nlev = 1;
     double *rcl = nullptr;         // [LEVELS_MAX - 1][cap_M]
+    // neighbour lists (the list path), built at the start of every attempt (bigbs.hip): member
+    // f's sources in BIG_LIST_SEGS segments, nl[f * BIG_LIST_CAP + s * BIG_LIST_SEG + e],
+    // e < nlen[f * BIG_LIST_SEGS + s]
+    int32_t *nl = nullptr;         // [cap_M][BIG_LIST_CAP]
+    int32_t *nlen = nullptr;       // [cap_M][BIG_LIST_SEGS]
+    double4 *pred = nullptr;       // [cap_M] the star's pull A at the attempt's start and the bound S
+    double *skin = nullptr;        // [cap_M] skin factor of each body's bound (indexed by body): 2 at the
+                                   //   step's start, times 4 after each crossing
+    int32_t *crossed = nullptr;    // [cap_M] the member crossed its bound in the last attempt
+    double *amut = nullptr;        // [cap_M] |pair acceleration| at the last attempt's start (column 0's
+                                   //   first sub-step, on either path)
+    int32_t *stale = nullptr;      // [G] a sub-step crossed a bound: the group's attempt is void
+    double *sbb = nullptr;         // [cap_T][8] box swept over the attempt by a tile, and its largest S
+    double4 *src = nullptr;        // [cap_M] (mass, r_crit, 1 / (0.9 r_crit), TP2 flag) per member
+    int32_t *ovf = nullptr;        // device word: a list exceeded BIG_LIST_CAP (the host falls back to tiles)
 };
 constexpr int BIG_TILES_PER_GROUP = 1024; // a workgroup of 1024 threads tests one source tile each
+constexpr int BIG_LIST_SEGS = 4;          // segments of a member's list (built by separate waves)
+constexpr int BIG_LIST_SEG = 128;         // sources per segment
+constexpr int BIG_LIST_CAP = BIG_LIST_SEGS * BIG_LIST_SEG; // sources per member on the list path
+constexpr int BIG_LIST_LANES = 8;         // lanes that share one member's list in a sub-step
 constexpr int LEVELS_MAX = 4;             // symplectic levels of the hierarchical step
 
 // rc_lv: with b.nlev > 1, the critical radii of levels 1..nlev-1 ([nlev - 1][n_total]).
@@ -235,6 +254,9 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
 // or 16 per workgroup (the sources of a target tile split over them).
 hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int tile_grid, int waves,
                               hipStream_t stream);
+// The same attempt on the list path: lists built at its start (one wave per target tile), then
+// each sub-step sums every member's list (BIG_LIST_LANES lanes per member).
+hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, int tile_grid, hipStream_t stream);
 hipError_t launch_big_finish(const BigBs &b, double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, hipStream_t stream);
 // Members of the parent groups of a hierarchical level, laid out as the grid-wide

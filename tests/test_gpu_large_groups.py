@@ -204,3 +204,77 @@ def test_large_groups_off_flags_capacity_and_graph_refused():
     with pytest.raises(genga.GengaError):
         genga.genga_set_large_groups(s.ctx.handle, 2)
     s.close()
+
+
+def test_tight_binary_inside_a_large_group():
+    """A binary of two 1e-4 solar-mass bodies 3e-3 au apart inside the 0.8-0.9 au ring: their
+    mutual pull (about 10 in these units, against the star's 1.3) bends their paths far from the
+    straight lines the grid-wide step's neighbour lists are built on, so attempts are voided and
+    listed again with wider margins until the bound holds.  The drift against the oracle's."""
+    d0 = discs.ring_dense(1000)
+    st = d0.state()
+    m, sep = 1e-4, 3e-3
+    r0 = np.array([st["x"][0], st["y"][0], st["z"][0]])
+    v0 = np.array([st["vx"][0], st["vy"][0], st["vz"][0]])
+    u = r0 / np.linalg.norm(r0)
+    w = np.cross([0.0, 0.0, 1.0], u)
+    vrel = np.sqrt(2.0 * m / sep)
+    for q, key in enumerate(("x", "y", "z")):
+        st[key][1] = r0[q] + sep * u[q]
+        st["v" + key][1] = v0[q] + vrel * w[q]
+    st["m"][0] = st["m"][1] = m
+    compare_drift(discs.Disc(**st, name="ring with binary"), "tight binary")
+
+
+def test_large_groups_with_test_bodies():
+    """TP2 mode (Sect. 3.3) on the grid-wide path: the last 400 of the 1000 ring bodies are
+    test bodies; groups above 64 bodies mix both kinds, and no two test members exert a force
+    on each other.  The drift against the oracle's."""
+    d = discs.ring_dense(1000)
+    nm = 600
+    s = dense_system(d)
+    genga.genga_set_test_bodies(s.ctx.handle, np.array([nm], dtype=np.int32))
+    s.accel(FP64)
+    pairs, cnt = s.encounter_list()
+    assert not np.any((pairs[:, 0] >= nm) & (pairs[:, 1] >= nm))
+    gid = oracle.groups(d.n, pairs)
+    sizes = np.bincount(gid[gid >= 0])
+    big = np.flatnonzero(sizes > 64)
+    assert len(big) >= 1 and np.any(np.isin(gid[nm:], big))
+    b0 = s.numpy_state()
+    exp = oracle.drift(b0, s.rc, 1.0, DT5, pairs, n_massive=nm)
+    genga.genga_drift(s.ctx.handle, s.b, DT5)
+    got = s.numpy_state()
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        err = np.max(np.abs(got[k] - exp[k]))
+        print(f"[tp2 large groups] {k} max err {err:.2e}", flush=True)
+        assert err <= 1e-10
+    s.close()
+
+
+def test_large_groups_resume_is_bit_identical():
+    """The grid-wide path's neighbour lists depend only on the step's starting state: two calls
+    of two steps in one context equal two steps, a save to the host, a fresh context from it
+    and two more steps (FP32 kick; the ring's groups of hundreds of bodies)."""
+    d = discs.ring_dense(1000)
+    s = dense_system(d)
+    rc = s.rc
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    whole = s.numpy_state()
+    s.close()
+    s = dense_system(d)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    saved = s.numpy_state()
+    s.close()
+    d2 = discs.Disc(*(saved[k] for k in ("x", "y", "z", "vx", "vy", "vz", "m")), mstar=d.mstar)
+    s = System([d2], rcrit=rc)
+    genga.genga_set_large_groups(s.ctx.handle, True)
+    genga.genga_step(s.ctx.handle, s.b, DT5, 2, FP32)
+    assert genga.genga_poll_status(s.ctx.handle) == genga.GENGA_OK, genga.genga_last_error()
+    resumed = s.numpy_state()
+    s.close()
+    for k in whole:
+        np.testing.assert_array_equal(whole[k], resumed[k])
