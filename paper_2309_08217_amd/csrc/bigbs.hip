@@ -112,7 +112,10 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
         b.H[g] = dt;
         b.attempts[g] = 0;
         b.done[g] = 0;
-        if (b.skin) b.stale[g] = 0;
+        if (b.skin) {
+            b.stale[g] = 0;
+            b.keep[g] = 0;
+        }
     }
 }
 
@@ -429,12 +432,16 @@ __device__ __forceinline__ ListMember list_member(double skin, double ms, double
     return m;
 }
 
-// Constants of the sources for the list sub-step, packed (mass, r_crit, 1 / (0.9 r_crit), TP2).
+// The source records of the list sub-steps: the constant words of every state buffer's records
+// and the positions of Y (the sub-steps write those of B1 and B2).
 __global__ __launch_bounds__(GB_THREADS) void big_src_kernel(BigBs b)
 {
     const int f = blockIdx.x * GB_THREADS + threadIdx.x;
     if (f >= b.dims[1]) return;
-    b.src[f] = make_double4(b.mass[f], b.rc[f], b.i09[f], b.test[f] ? 1.0 : 0.0);
+    const size_t M = (size_t)b.dims[1], cm = (size_t)b.cap_M;
+    const double2 c = make_double2(b.rc[f], b.test[f] ? -b.i09[f] : b.i09[f]);
+    for (int i = 0; i < 3; ++i) reinterpret_cast<double2 *>(b.rec + (i * cm + f) * 8)[2] = c;
+    reinterpret_cast<double4 *>(b.rec + (size_t)f * 8)[0] = make_double4(b.Y[f], b.Y[M + f], b.Y[2 * M + f], b.mass[f]);
 }
 
 // Per tile: the box swept by its members' straight lines over [0, H], and the largest
@@ -444,7 +451,7 @@ __global__ __launch_bounds__(64) void big_sweep_kernel(BigBs b)
     for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
         const int4 tile = b.tiles[me];
         const int g = tile.x;
-        if (b.done[g]) continue;
+        if (b.done[g] || b.keep[g]) continue;
         const size_t M = (size_t)b.dims[1];
         const bool v = (int)threadIdx.x < tile.z;
         const int f = tile.y + (v ? (int)threadIdx.x : 0);
@@ -530,7 +537,7 @@ __global__ __launch_bounds__(64) void big_list_kernel(BigBs b)
         const int me = ms / BIG_LIST_SEGS, seg = ms % BIG_LIST_SEGS;
         const int4 tile = b.tiles[me];
         const int g = tile.x;
-        if (b.done[g]) continue;
+        if (b.done[g] || b.keep[g]) continue;
         const size_t M = (size_t)b.dims[1];
         const size_t lvo = LV ? (size_t)(b.nlev - 2) * b.cap_M : 0; // the deepest level's radii
         const int lane = threadIdx.x;
@@ -595,24 +602,180 @@ __global__ __launch_bounds__(64) void big_list_kernel(BigBs b)
     }
 }
 
+// Per target tile (thread = member m, segment s): the source tiles holding an entry of one of
+// its members' lists become the tile's slots, in tile order (more than BIG_LIST_SLOTS void the
+// attempt and send the step to the tile path), and each member's segments are written as one
+// run of slot positions, slot * 64 + the source's position in its tile.
+__global__ __launch_bounds__(256) void big_localize_kernel(BigBs b)
+{
+    static_assert(BIG_LIST_SEGS == 4 && BIG_LIST_SLOTS * 64 <= 65536, "four segments, 16-bit positions");
+    __shared__ int mark[BIG_TILES_PER_GROUP];
+    __shared__ int wsum[4];
+    for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
+        const int4 tile = b.tiles[me];
+        const int g = tile.x;
+        if (b.done[g] || b.keep[g]) continue; // the whole block
+        const int o = b.off[g], nb = b.off[g + 1] - o, nt = b.tfirst[g + 1] - b.tfirst[g];
+        for (int i = threadIdx.x; i < nt; i += 256) mark[i] = 0;
+        __syncthreads();
+        const int m = threadIdx.x >> 2, s = threadIdx.x & 3;
+        const bool valid = m < tile.z;
+        const int f = tile.y + (valid ? m : 0);
+        const int4 nn = reinterpret_cast<const int4 *>(b.nlen)[f];
+        const int len = valid ? (s == 0 ? nn.x : (s == 1 ? nn.y : (s == 2 ? nn.z : nn.w))) : 0;
+        const int start = s == 0 ? 0 : (s == 1 ? nn.x : (s == 2 ? nn.x + nn.y : nn.x + nn.y + nn.z));
+        const int32_t *row = b.nl + (size_t)f * BIG_LIST_CAP + s * BIG_LIST_SEG;
+        for (int e = 0; e < len; ++e) mark[(row[e] - o) >> 6] = 1;
+        __syncthreads();
+        // ordered compaction of the marks: thread t takes tiles [t per, (t + 1) per)
+        const int per = (nt + 255) / 256;
+        const int t0 = (int)threadIdx.x * per, t1 = min(t0 + per, nt);
+        int cnt = 0;
+        for (int i = t0; i < t1; ++i) cnt += mark[i];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        int incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += v;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int pos = incl - cnt, total = 0;
+        for (int w = 0; w < 4; ++w) {
+            pos += w < wave ? wsum[w] : 0;
+            total += wsum[w];
+        }
+        for (int i = t0; i < t1; ++i)
+            if (mark[i]) {
+                if (pos < BIG_LIST_SLOTS) b.slot[me * BIG_LIST_SLOTS + pos] = make_int2(o + 64 * i, min(64, nb - 64 * i));
+                mark[i] = pos++;
+            }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            b.nslot[me] = min(total, BIG_LIST_SLOTS);
+            if (total > BIG_LIST_SLOTS) {
+                atomicOr(b.ovf, 1);
+                b.stale[g] = 1;
+            }
+        }
+        if (total <= BIG_LIST_SLOTS) {
+            uint16_t *out = b.ll + (size_t)f * BIG_LIST_CAP + start;
+            for (int e = 0; e < len; ++e) {
+                const int r = row[e] - o;
+                out[e] = (uint16_t)(mark[r >> 6] * 64 + (r & 63));
+            }
+        }
+        // a tile beyond the slots lists nothing (its attempt is void)
+        if (valid && s == 0) b.ltot[f] = total <= BIG_LIST_SLOTS ? nn.x + nn.y + nn.z + nn.w : 0;
+        __syncthreads(); // the marks are cleared for the next tile
+    }
+}
+
+// What follows a member's pair sum in a sub-step: the star's pull, then the midpoint update of
+// OUT (modes 0 and 1, with the positions of OUT's source records) or, in mode 2, T(k, 0) and
+// the group's error estimate of column k.  Every lane of the wave calls it; `lead` marks the
+// member's first lane, `act` the members of an active group.
+__device__ __forceinline__ void member_tail(const BigBs &b, int k, int mode, int g, int fa, bool act, bool lead,
+                                            double xa, double ya, double za, double ax, double ay, double az,
+                                            const double *Z, const double *ZM, double *OUT, double *ROUT)
+{
+    const size_t M = (size_t)b.dims[1];
+    if (mode == 0 && k == 0 && lead) b.amut[fa] = sqrt(sep2_rn(ax, ay, az));
+    const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
+    const double s = -b.mstar[g] * (ri * ri) * ri;
+    double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa + ax, s * ya + ay, s * za + az};
+    const double h = b.H[g] / (2 * (k + 1));
+    if (mode == 2) {
+        double tk[6];
+        for (int q = 0; q < 6; ++q) tk[q] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
+        if (lead) {
+            double *T0 = b.tcol + (size_t)k * 6 * M;
+            for (int q = 0; q < 6; ++q) T0[q * M + fa] = tk[q];
+        }
+        if (k == 0) return;
+        double dp = 0.0, dvv = 0.0;
+        bool bad = false;
+        if (lead) {
+            for (int q = 0; q < 6; ++q) {
+                const double tz = b.tcol[q * M + fa];
+                double sum = 0.0;
+                for (int jj = 1; jj <= k; ++jj) {
+                    const double v = jj == k ? tk[q] : b.tcol[((size_t)jj * 6 + q) * M + fa];
+                    sum = fma(LAGRANGE.d[k][jj], v - tz, sum);
+                }
+                if (q < 3) dp = fmax(dp, fabs(sum));
+                else dvv = fmax(dvv, fabs(sum));
+                bad |= !(sum == sum);
+            }
+        }
+        const double e = fmax(dp / bitsd(b.sr[g]), dvv / bitsd(b.sv[g]));
+        wave_atomic_max(b.err + k, g * BS_KMAX, lead, (bad || !(e == e)) ? ~0ull : dbits(e));
+        return;
+    }
+    if (lead) {
+        double o[6];
+        for (int q = 0; q < 6; ++q) {
+            o[q] = (mode == 0 ? Z[q * M + fa] : ZM[q * M + fa]) + (mode == 0 ? h : 2.0 * h) * d[q];
+            OUT[q * M + fa] = o[q];
+        }
+        reinterpret_cast<double4 *>(ROUT + (size_t)fa * 8)[0] = make_double4(o[0], o[1], o[2], b.mass[fa]);
+    }
+}
+
 // One sub-step on the list path (modes and outputs as substep_tile; jstep: Z is the state at
-// tau = jstep * H / (2 (k + 1))).  BIG_LIST_LANES lanes share a member: each sums every
-// BIG_LIST_LANES-th entry of its list, then the parts are added in a fixed tree.
+// tau = jstep * H / (2 (k + 1))), one workgroup per target tile: the records of the tile's
+// slots (the sources of RZ, Z's records) are staged in LDS, then BIG_LIST_LANES lanes share a
+// member, each summing every BIG_LIST_LANES-th entry of its list in order, and the parts are
+// added in a fixed tree.  48 bytes per staged source and at most 80 VGPRs: three workgroups
+// fit a CU.
 template <bool LV>
-__global__ __launch_bounds__(256) void big_substep_list_kernel(BigBs b, int k, int mode, int jstep,
-                                                               const double *Z, const double *ZM, double *OUT)
+__global__ __launch_bounds__(64 * BIG_LIST_LANES) __attribute__((amdgpu_waves_per_eu(6))) void big_substep_list_kernel(BigBs b, int k, int mode, int jstep,
+                                                                               const double *Z, const double *ZM,
+                                                                               double *OUT, const double *RZ,
+                                                                               double *ROUT)
 {
     constexpr int P = BIG_LIST_LANES;
+    constexpr int NS = BIG_LIST_SLOTS * 64;
+    __shared__ double2 sxy[NS], szm[NS], sri[NS]; // (x, y), (z, mass), (r_crit, signed 1 / (0.9 r_crit))
+    __shared__ int sgi[LV ? NS : 1];               // member index, for the levels' radii
+    constexpr int PER = NS / (64 * P); // staged sources per thread
+    static_assert(NS % (64 * P) == 0, "whole rounds of staging");
     const size_t M = (size_t)b.dims[1];
-    for (int t0 = blockIdx.x * 256; t0 < b.dims[1] * P; t0 += gridDim.x * 256) {
-        const int t = t0 + (int)threadIdx.x;
-        const int part = t % P;
-        const bool valid = t < b.dims[1] * P;
-        const int fa = valid ? t / P : 0;
-        const int g = b.grp[fa];
-        const bool act = valid && !b.done[g] && b.acc[g] < 0;
+    // one target tile per workgroup (the grid covers the largest layout)
+    const int me = blockIdx.x;
+    if (me >= b.dims[2]) return;
+    // first round of loads: the tile, its slots
+    const int4 tile = b.tiles[me];
+    const int ns = b.nslot[me];
+    int2 si[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) si[u] = b.slot[me * BIG_LIST_SLOTS + ((int)threadIdx.x + u * 64 * P) / 64];
+    const int g = tile.x;
+    const int m = (int)threadIdx.x / P, part = (int)threadIdx.x % P;
+    const bool act = m < tile.z;
+    const int fa = tile.y + (act ? m : 0);
+    // second round: the group's state, the sources to stage and the member's own words
+    if (b.done[g] || b.acc[g] >= 0) return; // the whole workgroup
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = (int)threadIdx.x + u * 64 * P;
+        if (i < ns * 64 && (i & 63) < si[u].y) {
+            const size_t j = (size_t)(si[u].x + (i & 63));
+            const double4 p = reinterpret_cast<const double4 *>(RZ + j * 8)[0];
+            sxy[i] = make_double2(p.x, p.y);
+            szm[i] = make_double2(p.z, p.w);
+            sri[i] = reinterpret_cast<const double2 *>(RZ + j * 8)[2];
+            if constexpr (LV) sgi[i] = (int)j;
+        }
+    }
+    const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
+    const double2 ca = reinterpret_cast<const double2 *>(RZ + (size_t)fa * 8)[2];
+    const int tot = b.ltot[fa];
+    const uint16_t *L = b.ll + (size_t)fa * BIG_LIST_CAP;
+    int l0 = L[part], l1 = L[part + P]; // the first two positions (used only below tot)
+    __syncthreads();
+    {
         double ax = 0.0, ay = 0.0, az = 0.0;
-        const double xa = Z[fa], ya = Z[M + fa], za = Z[2 * M + fa];
         if (act) {
             // the bound of the lists: every member stays within S of its prediction
             if (part == 0 && jstep > 0) {
@@ -627,38 +790,43 @@ __global__ __launch_bounds__(256) void big_substep_list_kernel(BigBs b, int k, i
                     b.crossed[fa] = 1;
                 }
             }
-            const double4 sa = b.src[fa];
-            const double rca = sa.y, i09a = sa.z;
-            const bool testa = sa.w != 0.0;
-            for (int sg = 0; sg < BIG_LIST_SEGS; ++sg) {
-            const int n = b.nlen[(size_t)fa * BIG_LIST_SEGS + sg];
-            const int32_t *L = b.nl + (size_t)fa * BIG_LIST_CAP + sg * BIG_LIST_SEG;
-            for (int e = part; e < n; e += P) {
-                const int j = L[e];
-                const double4 sj = b.src[j];
-                const double dx = Z[j] - xa, dy = Z[M + j] - ya, dz = Z[2 * M + j] - za;
-                const bool own = rca >= sj.y;
-                const double rcab = own ? rca : sj.y;
+            const double rca = ca.x, i09a = fabs(ca.y);
+            const bool testa = signbit(ca.y);
+            const auto term = [&](int l) {
+                const double2 xy = sxy[l], zm = szm[l], cj = sri[l];
+                const double dx = xy.x - xa, dy = xy.y - ya, dz = zm.x - za;
+                const bool own = rca >= cj.x;
+                const double rcab = own ? rca : cj.x;
                 const double q = sep2_rn(dx, dy, dz);
                 const double rq = inv_sqrt64(q);
-                const double yv = (q * rq - 0.1 * rcab) * (own ? i09a : sj.z);
+                const double yv = (q * rq - 0.1 * rcab) * (own ? i09a : fabs(cj.y));
                 const double y2 = yv * yv;
                 const double kv = yv <= 0.0 ? 0.0 : (yv >= 1.0 ? 1.0 : y2 / (2.0 * y2 - 2.0 * yv + 1.0));
                 double w = 1.0 - kv, rdeep = rcab;
                 if constexpr (LV) {
-                    for (int l = 1; l < b.nlev; ++l) {
-                        const double rcl_ab = fmax(b.rcl[(size_t)(l - 1) * b.cap_M + fa],
-                                                   b.rcl[(size_t)(l - 1) * b.cap_M + j]);
+                    const int j = sgi[l];
+                    for (int lv = 1; lv < b.nlev; ++lv) {
+                        const double rcl_ab = fmax(b.rcl[(size_t)(lv - 1) * b.cap_M + fa],
+                                                   b.rcl[(size_t)(lv - 1) * b.cap_M + j]);
                         w *= 1.0 - changeover_k((q * rq - 0.1 * rcl_ab) / (0.9 * rcl_ab));
                         rdeep = rcl_ab;
                     }
                 }
-                const bool in = j != fa && !(testa && sj.w != 0.0) && q < sq_rn(rdeep);
-                const double s = in ? sj.x * w * (rq * rq) * rq : 0.0;
+                // the lists hold no member itself
+                const bool in = !(testa && signbit(cj.y)) && q < sq_rn(rdeep);
+                const double s = in ? zm.y * w * (rq * rq) * rq : 0.0;
                 ax = fma(s, dx, ax);
                 ay = fma(s, dy, ay);
                 az = fma(s, dz, az);
-            }
+            };
+            // lane `part` sums every P-th entry from `part` on, in order; the positions of the
+            // next two are loaded ahead (past the end: entry 0, unused)
+            const auto entry = [&](int e) { return (int)L[e < tot ? e : 0]; };
+            for (int e = part; e < tot; e += P) {
+                const int l = l0;
+                l0 = l1;
+                l1 = entry(e + 2 * P);
+                term(l);
             }
         }
         // the parts of a member, in a fixed order
@@ -667,42 +835,7 @@ __global__ __launch_bounds__(256) void big_substep_list_kernel(BigBs b, int k, i
             ay += __shfl_xor(ay, off, 64);
             az += __shfl_xor(az, off, 64);
         }
-        const bool lead = act && part == 0;
-        if (mode == 0 && k == 0 && lead) b.amut[fa] = sqrt(sep2_rn(ax, ay, az));
-        const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
-        const double s = -b.mstar[g] * (ri * ri) * ri;
-        double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa + ax, s * ya + ay, s * za + az};
-        const double h = b.H[g] / (2 * (k + 1));
-        if (mode == 2) {
-            double tk[6];
-            for (int q = 0; q < 6; ++q) tk[q] = 0.5 * (ZM[q * M + fa] + Z[q * M + fa] + h * d[q]);
-            if (lead) {
-                double *T0 = b.tcol + (size_t)k * 6 * M;
-                for (int q = 0; q < 6; ++q) T0[q * M + fa] = tk[q];
-            }
-            if (k == 0) continue;
-            double dp = 0.0, dvv = 0.0;
-            bool bad = false;
-            if (lead) {
-                for (int q = 0; q < 6; ++q) {
-                    const double tz = b.tcol[q * M + fa];
-                    double sum = 0.0;
-                    for (int jj = 1; jj <= k; ++jj) {
-                        const double v = jj == k ? tk[q] : b.tcol[((size_t)jj * 6 + q) * M + fa];
-                        sum = fma(LAGRANGE.d[k][jj], v - tz, sum);
-                    }
-                    if (q < 3) dp = fmax(dp, fabs(sum));
-                    else dvv = fmax(dvv, fabs(sum));
-                    bad |= !(sum == sum);
-                }
-            }
-            const double e = fmax(dp / bitsd(b.sr[g]), dvv / bitsd(b.sv[g]));
-            wave_atomic_max(b.err + k, g * BS_KMAX, lead, (bad || !(e == e)) ? ~0ull : dbits(e));
-            continue;
-        }
-        if (lead)
-            for (int q = 0; q < 6; ++q)
-                OUT[q * M + fa] = (mode == 0 ? Z[q * M + fa] : ZM[q * M + fa]) + (mode == 0 ? h : 2.0 * h) * d[q];
+        member_tail(b, k, mode, g, fa, act, act && part == 0, xa, ya, za, ax, ay, az, Z, ZM, OUT, ROUT);
     }
 }
 
@@ -742,10 +875,14 @@ __global__ __launch_bounds__(GB_THREADS) void big_control_kernel(BigBs b, double
     for (int g = threadIdx.x; g < b.dims[0]; g += GB_THREADS) {
         if (b.done[g]) continue;
         if (b.skin && b.stale[g]) { // a void attempt: the same step again (with wider lists)
+            b.keep[g] = 0;
             ++active;
             continue;
         }
         const int ks = b.acc[g];
+        // a rejected attempt leaves Y and the skins as they were and only shortens the step: the
+        // next attempt keeps its lists (the prediction and its bound hold over any shorter step)
+        if (b.skin) b.keep[g] = ks < 0;
         if (ks >= 0) {
             const double t = b.last[g] ? dt : b.t[g] + b.H[g];
             b.t[g] = t;
@@ -845,9 +982,9 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
 {
     const int gg = (b.cap_G + 63) / 64, gm = (b.cap_M + GB_THREADS - 1) / GB_THREADS;
     const int nt = std::max(1, std::min(tile_grid, b.cap_T));
-    const int gl = (int)std::min<int64_t>(((int64_t)b.cap_M * BIG_LIST_LANES + 255) / 256, 4096);
     const size_t M6 = 6 * (size_t)b.cap_M;
     double *buf[3] = {b.Y, b.Y + M6, b.Y + 2 * M6}; // Y, B1, B2
+    double *rec[3] = {b.rec, b.rec + 8 * (size_t)b.cap_M, b.rec + 16 * (size_t)b.cap_M};
     const bool lv = b.nlev > 1;
     auto substep = lv ? big_substep_list_kernel<true> : big_substep_list_kernel<false>;
     big_begin_kernel<<<gg, 64, 0, stream>>>(b, flags);
@@ -859,17 +996,18 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
         big_list_kernel<true><<<nl, 64, 0, stream>>>(b);
     else
         big_list_kernel<false><<<nl, 64, 0, stream>>>(b);
+    big_localize_kernel<<<nt, 256, 0, stream>>>(b);
     for (int k = 0; k < BS_KMAX; ++k) {
         const int nsub = 2 * (k + 1);
-        substep<<<gl, 256, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1]);
+        substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1], rec[0], rec[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
-            substep<<<gl, 256, 0, stream>>>(b, k, 1, i, buf[zc], buf[zm], buf[out]);
+            substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 1, i, buf[zc], buf[zm], buf[out], rec[zc], rec[out]);
             zm = zc;
             zc = out;
         }
-        substep<<<gl, 256, 0, stream>>>(b, k, 2, nsub, buf[zc], buf[zm], nullptr);
+        substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 2, nsub, buf[zc], buf[zm], nullptr, rec[zc], nullptr);
         if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);
     }
     big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);

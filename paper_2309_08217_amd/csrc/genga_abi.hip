@@ -156,13 +156,18 @@ struct genga_ctx {
         dfree(big.rcl);
         dfree(big.nl);
         dfree(big.nlen);
+        dfree(big.ltot);
+        dfree(big.ll);
+        dfree(big.slot);
+        dfree(big.nslot);
         dfree(big.pred);
         dfree(big.skin);
         dfree(big.crossed);
         dfree(big.amut);
         dfree(big.stale);
+        dfree(big.keep);
         dfree(big.sbb);
-        dfree(big.src);
+        dfree(big.rec);
         dfree(big.ovf);
         big.nlev = 1;
         dfree(rc_lv);
@@ -487,6 +492,10 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.n_active, 1));
     HIP_TRY(dalloc(b.nl, M * BIG_LIST_CAP));
     HIP_TRY(dalloc(b.nlen, M * BIG_LIST_SEGS));
+    HIP_TRY(dalloc(b.ltot, M));
+    HIP_TRY(dalloc(b.ll, M * BIG_LIST_CAP));
+    HIP_TRY(dalloc(b.slot, (size_t)b.cap_T * BIG_LIST_SLOTS));
+    HIP_TRY(dalloc(b.nslot, (size_t)b.cap_T));
     HIP_TRY(dalloc(b.pred, M));
     HIP_TRY(dalloc(b.skin, M));
     HIP_TRY(dalloc(b.crossed, M));
@@ -494,8 +503,10 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(hipMemset(b.skin, 0, M * sizeof(double)));
     HIP_TRY(hipMemset(b.crossed, 0, M * sizeof(int32_t)));
     HIP_TRY(dalloc(b.stale, G));
+    HIP_TRY(dalloc(b.keep, G));
+    HIP_TRY(hipMemset(b.keep, 0, G * sizeof(int32_t)));
     HIP_TRY(dalloc(b.sbb, 8 * (size_t)b.cap_T));
-    HIP_TRY(dalloc(b.src, M));
+    HIP_TRY(dalloc(b.rec, 3 * 8 * (size_t)M));
     HIP_TRY(dalloc(b.ovf, 1));
     HIP_TRY(hipMemset(b.ovf, 0, sizeof(int32_t)));
     HIP_TRY(hipMemset(b.stale, 0, G * sizeof(int32_t)));

@@ -225,6 +225,13 @@ struct BigBs {
     // e < nlen[f * BIG_LIST_SEGS + s]
     int32_t *nl = nullptr;         // [cap_M][BIG_LIST_CAP]
     int32_t *nlen = nullptr;       // [cap_M][BIG_LIST_SEGS]
+    int32_t *ltot = nullptr;       // [cap_M] the list's length
+    uint16_t *ll = nullptr;        // [cap_M][BIG_LIST_CAP] the list as one run of slot positions
+                                   //   (slot * 64 + position in the slot's source tile)
+    int2 *slot = nullptr;          // [cap_T][BIG_LIST_SLOTS] per target tile: the source tiles holding
+                                   //   an entry of its members' lists, in tile order, as (first
+                                   //   member, members)
+    int32_t *nslot = nullptr;      // [cap_T] their number
     double4 *pred = nullptr;       // [cap_M] the star's pull A at the attempt's start and the bound S
     double *skin = nullptr;        // [cap_M] skin factor of each body's bound (indexed by body): 2 at the
                                    //   step's start, times 4 after each crossing
@@ -232,8 +239,12 @@ struct BigBs {
     double *amut = nullptr;        // [cap_M] |pair acceleration| at the last attempt's start (column 0's
                                    //   first sub-step, on either path)
     int32_t *stale = nullptr;      // [G] a sub-step crossed a bound: the group's attempt is void
+    int32_t *keep = nullptr;       // [G] the group's last attempt was rejected (not void): same start, a
+                                   //   shorter step, so its lists and bounds still hold
     double *sbb = nullptr;         // [cap_T][8] box swept over the attempt by a tile, and its largest S
-    double4 *src = nullptr;        // [cap_M] (mass, r_crit, 1 / (0.9 r_crit), TP2 flag) per member
+    double *rec = nullptr;         // [3][cap_M][8] per state buffer (Y, B1, B2): a source's words in one
+                                   //   64-byte record (x, y, z, mass, r_crit, 1 / (0.9 r_crit), -, -),
+                                   //   the sign of 1 / (0.9 r_crit) set for TP2 bodies
     int32_t *ovf = nullptr;        // device word: a list exceeded BIG_LIST_CAP (the host falls back to tiles)
 };
 constexpr int BIG_TILES_PER_GROUP = 1024; // a workgroup of 1024 threads tests one source tile each
@@ -241,6 +252,7 @@ constexpr int BIG_LIST_SEGS = 4;          // segments of a member's list (built 
 constexpr int BIG_LIST_SEG = 128;         // sources per segment
 constexpr int BIG_LIST_CAP = BIG_LIST_SEGS * BIG_LIST_SEG; // sources per member on the list path
 constexpr int BIG_LIST_LANES = 8;         // lanes that share one member's list in a sub-step
+constexpr int BIG_LIST_SLOTS = 16;        // source tiles a target tile's sub-step stages in LDS
 constexpr int LEVELS_MAX = 4;             // symplectic levels of the hierarchical step
 
 // rc_lv: with b.nlev > 1, the critical radii of levels 1..nlev-1 ([nlev - 1][n_total]).
