@@ -55,25 +55,41 @@ __device__ __forceinline__ void wave_atomic_max(unsigned long long *slot, int g,
     if (use && !same) atomicMax(&slot[g], v);
 }
 
-// Flat member m of large group g: body index, constants, state Y[q * M + m].
-__global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const int32_t *sys_of,
-                                                               const int32_t *sys_off,
-                                                               const int32_t *n_massive,
-                                                               const double *mstar,
-                                                               const int32_t *members,
-                                                               const double *x, const double *y,
-                                                               const double *z, const double *vx,
-                                                               const double *vy, const double *vz,
-                                                               const double *m, const double *rc,
-                                                               const double *rc_lv, int n_total, double dt)
+// Per group: the step's start (t = 0, H = dt) and the star's mass; the largest squared
+// candidate radius starts at 0 for big_setup_kernel's maxima.
+__global__ __launch_bounds__(64) void big_setup_groups_kernel(BigBs b, const int32_t *sys_of, const double *mstar,
+                                                              const int32_t *members, double dt)
 {
-    __shared__ double red[GB_THREADS / 64];
-    const int g = blockIdx.x;
-    const int o = b.off[g], nb = b.off[g + 1] - o, k0 = b.k0[g];
+    const int g = blockIdx.x * 64 + threadIdx.x;
+    if (g >= b.dims[0]) return;
+    if (g == 0) b.dtp[0] = dt;
+    b.rcmax2[g] = 0.0;
+    b.mstar[g] = mstar[sys_of[members[b.k0[g]]]];
+    b.t[g] = 0.0;
+    b.H[g] = dt;
+    b.attempts[g] = 0;
+    b.done[g] = 0;
+    if (b.skin) {
+        b.stale[g] = 0;
+        b.keep[g] = 0;
+    }
+}
+
+// Flat member f of large group g (one wave per tile): body index, constants, state
+// Y[q * M + f], and the group's largest squared candidate radius (a maximum of bit patterns,
+// which order non-negative doubles, so the result does not depend on the order of arrival).
+__global__ __launch_bounds__(64) void big_setup_kernel(BigBs b, const int32_t *sys_of, const int32_t *sys_off,
+                                                       const int32_t *n_massive, const double *x, const double *y,
+                                                       const double *z, const double *vx, const double *vy,
+                                                       const double *vz, const double *m, const double *rc,
+                                                       const double *rc_lv, int n_total)
+{
+    const int4 tile = b.tiles[blockIdx.x];
+    const int g = tile.x;
     const size_t M = (size_t)b.dims[1];
     double mx = 0.0;
-    for (int l = threadIdx.x; l < nb; l += GB_THREADS) {
-        const int f = o + l, body = b.body[f], s = sys_of[body];
+    if ((int)threadIdx.x < tile.z) {
+        const int f = tile.y + threadIdx.x, body = b.body[f], s = sys_of[body];
         b.grp[f] = g;
         b.rc[f] = rc[body];
         b.i09[f] = 1.0 / (0.9 * rc[body]);
@@ -98,25 +114,10 @@ __global__ __launch_bounds__(GB_THREADS) void big_setup_kernel(BigBs b, const in
             rd = rc_lv[(size_t)(k - 1) * n_total + body];
             b.rcl[(size_t)(k - 1) * b.cap_M + f] = rd;
         }
-        mx = fmax(mx, sq_rn(rd));
+        mx = sq_rn(rd);
     }
     for (int s = 32; s > 0; s >>= 1) mx = fmax(mx, __shfl_xor(mx, s, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (g == 0) b.dtp[0] = dt;
-        for (int w = 1; w < GB_THREADS / 64; ++w) mx = fmax(mx, red[w]);
-        b.rcmax2[g] = mx;
-        b.mstar[g] = mstar[sys_of[members[k0]]];
-        b.t[g] = 0.0;
-        b.H[g] = dt;
-        b.attempts[g] = 0;
-        b.done[g] = 0;
-        if (b.skin) {
-            b.stale[g] = 0;
-            b.keep[g] = 0;
-        }
-    }
+    if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned long long *>(b.rcmax2) + g, dbits(mx));
 }
 
 // Start of an attempt, per group.
@@ -680,7 +681,12 @@ __device__ __forceinline__ void member_tail(const BigBs &b, int k, int mode, int
                                             const double *Z, const double *ZM, double *OUT, double *ROUT)
 {
     const size_t M = (size_t)b.dims[1];
-    if (mode == 0 && k == 0 && lead) b.amut[fa] = sqrt(sep2_rn(ax, ay, az));
+    if (mode == 0 && k == 0 && lead) {
+        b.amut[fa] = sqrt(sep2_rn(ax, ay, az));
+        b.a0[fa] = ax;
+        b.a0[M + fa] = ay;
+        b.a0[2 * M + fa] = az;
+    }
     const double ri = inv_sqrt64(sep2_rn(xa, ya, za));
     const double s = -b.mstar[g] * (ri * ri) * ri;
     double d[6] = {Z[3 * M + fa], Z[4 * M + fa], Z[5 * M + fa], s * xa + ax, s * ya + ay, s * za + az};
@@ -839,6 +845,21 @@ __global__ __launch_bounds__(64 * BIG_LIST_LANES) __attribute__((amdgpu_waves_pe
     }
 }
 
+// The first sub-step of column k >= 1 on the list path: the pair sums at Y are column 0's
+// (a0), so only the update runs, one thread per member.
+__global__ __launch_bounds__(GB_THREADS) void big_substep_start_kernel(BigBs b, int k, double *OUT, double *ROUT)
+{
+    const int f = blockIdx.x * GB_THREADS + threadIdx.x;
+    const bool valid = f < b.dims[1];
+    const int fa = valid ? f : 0;
+    const int g = b.grp[fa];
+    const bool act = valid && !b.done[g] && b.acc[g] < 0;
+    const size_t M = (size_t)b.dims[1];
+    const double *Y = b.Y;
+    member_tail(b, k, 0, g, fa, act, act, Y[fa], Y[M + fa], Y[2 * M + fa], act ? b.a0[fa] : 0.0,
+                act ? b.a0[M + fa] : 0.0, act ? b.a0[2 * M + fa] : 0.0, Y, Y, OUT, ROUT);
+}
+
 __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double tol)
 {
     const int g = blockIdx.x * 64 + threadIdx.x;
@@ -933,8 +954,9 @@ hipError_t launch_big_setup(const Layout &L, const BigBs &b, const int32_t *memb
                             double dt, hipStream_t stream)
 {
     if (b.G == 0) return hipSuccess;
-    big_setup_kernel<<<b.G, GB_THREADS, 0, stream>>>(b, L.sys_of, L.sys_off, L.n_massive, L.mstar, members, x, y,
-                                                     z, vx, vy, vz, m, rc, rc_lv, L.n_total, dt);
+    big_setup_groups_kernel<<<(b.G + 63) / 64, 64, 0, stream>>>(b, L.sys_of, L.mstar, members, dt);
+    big_setup_kernel<<<b.n_tiles, 64, 0, stream>>>(b, L.sys_of, L.sys_off, L.n_massive, x, y, z, vx, vy, vz, m, rc,
+                                                   rc_lv, L.n_total);
     return hipGetLastError();
 }
 
@@ -999,7 +1021,10 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
     big_localize_kernel<<<nt, 256, 0, stream>>>(b);
     for (int k = 0; k < BS_KMAX; ++k) {
         const int nsub = 2 * (k + 1);
-        substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1], rec[0], rec[1]);
+        if (k == 0)
+            substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1], rec[0], rec[1]);
+        else
+            big_substep_start_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k, buf[1], rec[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;

@@ -157,6 +157,7 @@ struct genga_ctx {
         dfree(big.nl);
         dfree(big.nlen);
         dfree(big.ltot);
+        dfree(big.a0);
         dfree(big.ll);
         dfree(big.slot);
         dfree(big.nslot);
@@ -493,6 +494,7 @@ int alloc_big(genga_ctx *ctx)
     HIP_TRY(dalloc(b.nl, M * BIG_LIST_CAP));
     HIP_TRY(dalloc(b.nlen, M * BIG_LIST_SEGS));
     HIP_TRY(dalloc(b.ltot, M));
+    HIP_TRY(dalloc(b.a0, 3 * (size_t)M));
     HIP_TRY(dalloc(b.ll, M * BIG_LIST_CAP));
     HIP_TRY(dalloc(b.slot, (size_t)b.cap_T * BIG_LIST_SLOTS));
     HIP_TRY(dalloc(b.nslot, (size_t)b.cap_T));

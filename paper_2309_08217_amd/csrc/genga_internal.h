@@ -236,6 +236,8 @@ struct BigBs {
     double *skin = nullptr;        // [cap_M] skin factor of each body's bound (indexed by body): 2 at the
                                    //   step's start, times 4 after each crossing
     int32_t *crossed = nullptr;    // [cap_M] the member crossed its bound in the last attempt
+    double *a0 = nullptr;          // [3][cap_M] the members' pair sums at the attempt's start state Y
+                                   //   (list path: column 0's first sub-step; the later columns reuse them)
     double *amut = nullptr;        // [cap_M] |pair acceleration| at the last attempt's start (column 0's
                                    //   first sub-step, on either path)
     int32_t *stale = nullptr;      // [G] a sub-step crossed a bound: the group's attempt is void
