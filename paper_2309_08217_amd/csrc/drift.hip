@@ -602,82 +602,163 @@ __device__ bool bs_columns(const BsMember &me, int k, BsShared &S, double (*row)
     return true;
 }
 
-// Groups of CP_MEM + 1 .. BS_LANES members: one lane per member, columns in sequence, each
-// lane's tableau in its own LDS column tab[l][q][lane].
+// Groups of CP_MEM + 1 .. BS_LANES members: one workgroup of BS_KMAX waves, wave k running
+// extrapolation column k for every member, so the columns advance side by side, one force
+// evaluation per pass, and an attempt takes at most 2 BS_KMAX + 1 passes.  A member has P
+// lanes (4 for groups of up to 16, 2 up to 32, else 1) that share its sources, sum every
+// P-th one and add the parts in a fixed tree.  Column k completes at pass 2(k + 1) and
+// extends each member's Neville row in place in LDS: it reads row k - 1, which column k - 1
+// wrote two passes before, and replaces it by row k, which column k + 1 reads two passes
+// later.  The tableau arithmetic and the accepted column (the first converged one) are those
+// of the sequential scheme.
+constexpr int WG_THREADS = BS_KMAX * BS_LANES;
+
+struct BsWgShared {
+    double pos[BS_KMAX][BS_LANES][3];          // each column's positions, for its pair forces
+    double m[BS_LANES], rc[BS_LANES], r01[BS_LANES], i09[BS_LANES];
+    double rcl[LEVELS_MAX - 1][BS_LANES];      // hierarchical levels 1..nlev-1
+    double tab[BS_KMAX][6][BS_LANES];          // Neville rows, extended in place
+    double err_last;                           // column BS_KMAX - 1's estimate
+    int32_t test[BS_LANES];
+    int32_t nlev;
+    int32_t kstar, kstar_att;                  // converged column and the attempt it ended
+};
+
+// One pass of column k for part `part` of member a's P lanes: the forces at z (when `on`),
+// between two barriers that every thread of the workgroup reaches.
 template <bool LV>
-__device__ bool bs_lanes(const BsMember &me, BsShared &S, double (*tab)[6][BS_LANES], double Y[6],
-                         double dt, double tol)
+__device__ void wg_forces(bool on, int k, int a, int part, int P, int nb, bool act, bool test, double mstar,
+                          double rc, double r01, double i09, BsWgShared &S, const double z[6], double d[6])
 {
+    if (part == 0) {
+        S.pos[k][a][0] = z[0];
+        S.pos[k][a][1] = z[1];
+        S.pos[k][a][2] = z[2];
+    }
+    __syncthreads();
+    if (on) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        if (part == 0) {
+            const double ri = inv_sqrt64(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
+            const double s = -mstar * (ri * ri) * ri;
+            ax = s * z[0];
+            ay = s * z[1];
+            az = s * z[2];
+        }
+#pragma unroll 1
+        for (int b = part; b < nb; b += P) {
+            if (b == a || (test && S.test[b])) continue;
+            const double dx = S.pos[k][b][0] - z[0];
+            const double dy = S.pos[k][b][1] - z[1];
+            const double dz = S.pos[k][b][2] - z[2];
+            const double q = sep2_rn(dx, dy, dz);
+            // r_crit,ab = max(r_crit,a, r_crit,b), with that member's derived constants
+            const bool own = rc >= S.rc[b];
+            const double rcab = own ? rc : S.rc[b];
+            if (!(q < sq_rn(rcab))) continue;
+            const double rq = inv_sqrt64(q);
+            double w = 1.0 - changeover_k((q * rq - (own ? r01 : S.r01[b])) * (own ? i09 : S.i09[b]));
+            if constexpr (LV) w *= deeper_levels<LV>(q * rq, q, S.nlev, &S.rcl[0][a], &S.rcl[0][b], BS_LANES);
+            const double t = S.m[b] * w * (rq * rq) * rq;
+            ax = fma(t, dx, ax);
+            ay = fma(t, dy, ay);
+            az = fma(t, dz, az);
+        }
+        for (int o = 1; o < P; o <<= 1) {
+            ax += __shfl_xor(ax, o, 64);
+            ay += __shfl_xor(ay, o, 64);
+            az += __shfl_xor(az, o, 64);
+        }
+        d[0] = act ? z[3] : 0.0;
+        d[1] = act ? z[4] : 0.0;
+        d[2] = act ? z[5] : 0.0;
+        d[3] = act ? ax : 0.0;
+        d[4] = act ? ay : 0.0;
+        d[5] = act ? az : 0.0;
+    }
+    __syncthreads(); // the next pass overwrites pos
+}
+
+template <bool LV>
+__device__ bool bs_workgroup(int k, int a, int part, int P, int nb, bool act, bool test, double mstar, double rc,
+                             double r01, double i09, BsWgShared &S, double Y[6], double dt, double tol)
+{
+    const int nsub = 2 * (k + 1);
+    const int lane = threadIdx.x & (BS_LANES - 1);
     double t = 0.0, H = dt;
     int attempts = 0;
     while (t < dt) {
-        const bool last = H >= (dt - t) * (1.0 - 0x1p-30);
+        const bool last = H >= (dt - t) * (1.0 - 0x1p-30); // ends the interval (exactly)
         if (last) H = dt - t;
         if (H < dt * 0x1p-40 || ++attempts > 20000) return false;
-        const double sr = wave_max(me.act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
-        const double sv = wave_max(me.act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        const double sr = wave_max(act ? sqrt(Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2]) : 0.0);
+        const double sv = wave_max(act ? sqrt(Y[3] * Y[3] + Y[4] * Y[4] + Y[5] * Y[5]) : 0.0);
+        const double h = H / nsub;
+        double zm[6], zc[6], T[6];
+        for (int q = 0; q < 6; ++q) zc[q] = zm[q] = T[q] = Y[q];
         int kstar = -1;
-        double err_last = 0.0;
-        double T[6];
 #pragma unroll 1
-        for (int k = 0; k < BS_KMAX; ++k) {
-            const int nsub = 2 * (k + 1);
-            const double h = H / nsub;
-            double zm[6], zc[6];
-            for (int q = 0; q < 6; ++q) zc[q] = zm[q] = Y[q];
-#pragma unroll 1
-            for (int i = 0; i <= nsub; ++i) {
-                double dd[6];
-                bs_forces<LV>(me, S, me.a, zc, dd);
-                if (i == 0) {
-                    for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
-                } else if (i < nsub) {
-                    for (int q = 0; q < 6; ++q) {
-                        const double tq = zm[q] + 2.0 * h * dd[q];
-                        zm[q] = zc[q];
-                        zc[q] = tq;
-                    }
-                } else {
-                    for (int q = 0; q < 6; ++q) T[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]);
-                }
-            }
-            // Neville: tab holds row k-1; replace it by row k in place (T(k, l-1) goes into
-            // slot l-1 once T(k-1, l-1) has been read from it)
-            double err = 0.0, dp = 0.0, dv = 0.0;
-#pragma unroll 1
-            for (int l = 1; l <= k; ++l) {
-                const double c = neville_c(k, l);
-                double old[6];
-                for (int q = 0; q < 6; ++q) old[q] = tab[l - 1][q][me.a];
-                for (int q = 0; q < 6; ++q) tab[l - 1][q][me.a] = T[q];
+        for (int i = 0; i <= 2 * BS_KMAX; ++i) {
+            double dd[6];
+            wg_forces<LV>(i <= nsub, k, a, part, P, nb, act, test, mstar, rc, r01, i09, S, zc, dd);
+            if (i == 0) {
+                for (int q = 0; q < 6; ++q) zc[q] = zm[q] + h * dd[q];
+            } else if (i < nsub) {
                 for (int q = 0; q < 6; ++q) {
-                    const double nx = T[q] + (T[q] - old[q]) * c;
-                    if (l == k) {
-                        if (q < 3) dp = fmax(dp, fabs(nx - T[q]));
-                        else dv = fmax(dv, fabs(nx - T[q]));
+                    const double tq = zm[q] + 2.0 * h * dd[q];
+                    zm[q] = zc[q];
+                    zc[q] = tq;
+                }
+            } else if (i == nsub) {
+                for (int q = 0; q < 6; ++q) T[q] = 0.5 * (zm[q] + zc[q] + h * dd[q]); // T(k, 0)
+                // Neville: row k - 1 is replaced by row k in place (T(k, l-1) goes into slot
+                // l-1 once T(k-1, l-1) has been read from it)
+                double dp = 0.0, dv = 0.0;
+#pragma unroll 1
+                for (int l = 1; l <= k; ++l) {
+                    const double c = neville_c(k, l);
+                    double old[6];
+                    for (int q = 0; q < 6; ++q) old[q] = S.tab[l - 1][q][a];
+                    if (part == 0)
+                        for (int q = 0; q < 6; ++q) S.tab[l - 1][q][a] = T[q];
+                    for (int q = 0; q < 6; ++q) {
+                        const double nx = T[q] + (T[q] - old[q]) * c;
+                        if (l == k) {
+                            if (q < 3) dp = fmax(dp, fabs(nx - T[q]));
+                            else dv = fmax(dv, fabs(nx - T[q]));
+                        }
+                        T[q] = nx;
                     }
-                    T[q] = nx;
+                }
+                if (part == 0)
+                    for (int q = 0; q < 6; ++q) S.tab[k][q][a] = T[q];
+                if (k > 0) {
+                    const double err = wave_max(act ? fmax(dp / sr, dv / sv) : 0.0);
+                    if (lane == 0) {
+                        if (err <= tol) {
+                            S.kstar = k;
+                            S.kstar_att = attempts;
+                        }
+                        if (k == BS_KMAX - 1) S.err_last = err;
+                    }
                 }
             }
-            for (int q = 0; q < 6; ++q) tab[k][q][me.a] = T[q];
-            if (k > 0) err = fmax(dp / sr, dv / sv);
-            if (k > 0) {
-                err = wave_max(me.act ? err : 0.0);
-                err_last = err;
-                if (err <= tol) {
-                    kstar = k;
-                    break;
-                }
+            if (i < 2 || (i & 1)) continue; // columns complete at even passes
+            __syncthreads();                // the completed column's verdict
+            if (S.kstar_att == attempts) {
+                kstar = S.kstar;
+                break;
             }
         }
         if (kstar >= 0) {
-            for (int q = 0; q < 6; ++q) Y[q] = T[q];
+            for (int q = 0; q < 6; ++q) Y[q] = S.tab[kstar][q][a];
             t = last ? dt : t + H;
             if (kstar <= 4) H = 2.0 * H;
             else if (kstar == BS_KMAX - 1) H = 0.5 * H;
         } else {
-            H = H * shrink_factor(err_last, tol);
+            H = H * shrink_factor(S.err_last, tol);
         }
+        __syncthreads(); // tab[kstar] and err_last are read before the next attempt writes them
     }
     return true;
 }
@@ -947,12 +1028,12 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
         if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
         return;
     }
-    const bool cols = nb <= CP_MEM;
-    const int k = cols ? lane / CP_MEM : 0;
+    if (nb > CP_MEM) return; // a workgroup of drift_wg_kernel integrates it
+    const int k = lane / CP_MEM;
     BsMember me;
-    me.a = cols ? lane % CP_MEM : lane;
+    me.a = lane % CP_MEM;
     me.nb = nb;
-    me.base = cols ? k * CP_MEM : 0;
+    me.base = k * CP_MEM;
     me.act = me.a < nb;
     const int ai = me.act ? me.a : 0;
     me.test = S.test[ai] != 0;
@@ -962,11 +1043,57 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
     me.i09 = S.i09[ai];
     const int b = members[k0 + ai];
     double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
-    const bool ok = cols ? bs_columns<LV>(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12)
-                         : bs_lanes<LV>(me, S, (double(*)[6][BS_LANES])tab, Y, dt, 1e-12);
+    const bool ok = bs_columns<LV>(me, k, S, (double(*)[BS_KMAX][CP_MEM][6])tab, Y, dt, 1e-12);
     // every lane has read its member's state before the first force evaluation's barrier
     if (me.act && k == 0) store_state(x, y, z, vx, vy, vz, b, Y);
     if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
+}
+
+// The encounter groups of CP_MEM + 1 .. BS_LANES members, one workgroup each (bs_workgroup);
+// the blocks of other groups return at once.
+template <bool LV>
+__global__ __launch_bounds__(WG_THREADS) void drift_wg_kernel(const int32_t *sys_of, const int32_t *sys_off,
+                                                              const int32_t *n_massive, const double *mstar,
+                                                              int n_total, double *x, double *y, double *z,
+                                                              double *vx, double *vy, double *vz, const double *m,
+                                                              const double *rc, double dt, const int32_t *members,
+                                                              const int32_t *group_start, const int32_t *n_groups,
+                                                              int32_t *flags, const double *rc_lv, int nlev)
+{
+    __shared__ BsWgShared S;
+    const int g = blockIdx.x;
+    if (g >= *n_groups) return;
+    const int k0 = group_start[g], nb = group_start[g + 1] - k0;
+    if (nb <= CP_MEM || nb > BS_LANES) return;
+    const int k = threadIdx.x / BS_LANES;
+    const int P = nb <= 16 ? 4 : (nb <= 32 ? 2 : 1);
+    const int a = (threadIdx.x % BS_LANES) / P, part = (threadIdx.x % BS_LANES) % P;
+    const double ms = mstar[sys_of[members[k0]]];
+    if (k == 0 && part == 0 && a < nb) {
+        const int b = members[k0 + a];
+        const int sb = sys_of[b];
+        S.m[a] = m[b];
+        S.rc[a] = rc[b];
+        S.r01[a] = 0.1 * rc[b];
+        S.i09[a] = 1.0 / (0.9 * rc[b]);
+        S.test[a] = b - sys_off[sb] >= n_massive[sb];
+        if constexpr (LV)
+            for (int l = 1; l < nlev; ++l) S.rcl[l - 1][a] = rc_lv[(size_t)(l - 1) * n_total + b];
+    }
+    if (threadIdx.x == 0) {
+        S.nlev = nlev;
+        S.kstar_att = 0;
+    }
+    __syncthreads();
+    const bool act = a < nb;
+    const int ai = act ? a : 0;
+    const int b = members[k0 + ai];
+    double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
+    const bool ok = bs_workgroup<LV>(k, a, part, P, nb, act, S.test[ai] != 0, ms, S.rc[ai], S.r01[ai], S.i09[ai], S,
+                                     Y, dt, 1e-12);
+    // every thread has read its member's state before the first force evaluation's barrier
+    if (act && k == 0 && part == 0) store_state(x, y, z, vx, vy, vz, b, Y);
+    if (!ok && threadIdx.x == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
 __global__ __launch_bounds__(256) void kepler_list_kernel(const int32_t *sys_of, const double *mstar,
@@ -1071,6 +1198,11 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
     kern<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy, vz, m,
                                         rc, dt, members, group_start, n_groups, member_slot, flags, big_groups,
                                         bs_blocks, rc_lv, nlev);
+    if (bs_blocks > 0) {
+        auto wg = nlev > 1 ? drift_wg_kernel<true> : drift_wg_kernel<false>;
+        wg<<<bs_blocks, WG_THREADS, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy,
+                                                 vz, m, rc, dt, members, group_start, n_groups, flags, rc_lv, nlev);
+    }
     return hipGetLastError();
 }
 
