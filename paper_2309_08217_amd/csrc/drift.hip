@@ -1049,51 +1049,81 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
     if (!ok && lane == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
-// The encounter groups of CP_MEM + 1 .. BS_LANES members, one workgroup each (bs_workgroup);
-// the blocks of other groups return at once.
+// The groups of CP_MEM + 1 .. BS_LANES members in group order, from one workgroup (a ballot
+// and a scan per round of 1024 groups): list[0] their number, list[1 + i] the groups.
+__global__ __launch_bounds__(1024) void wg_list_kernel(const int32_t *group_start, const int32_t *n_groups,
+                                                       int bs_blocks, int32_t *list)
+{
+    __shared__ int wsum[1024 / 64];
+    const int G = min(*n_groups, bs_blocks);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int base = 0;
+    for (int c = 0; c < G; c += 1024) {
+        const int g = c + (int)threadIdx.x;
+        const int nb = g < G ? group_start[g + 1] - group_start[g] : 0;
+        const bool med = nb > CP_MEM && nb <= BS_LANES;
+        const unsigned long long bal = __ballot(med);
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < 1024 / 64; ++w) {
+            off += w < wave ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        if (med) list[1 + base + off + __popcll(bal & ((1ull << lane) - 1))] = g;
+        base += tot;
+        __syncthreads(); // wsum is rewritten by the next round
+    }
+    if (threadIdx.x == 0) list[0] = base;
+}
+
+// The listed groups of CP_MEM + 1 .. BS_LANES members, one workgroup at a time each
+// (bs_workgroup).
 template <bool LV>
 __global__ __launch_bounds__(WG_THREADS) void drift_wg_kernel(const int32_t *sys_of, const int32_t *sys_off,
                                                               const int32_t *n_massive, const double *mstar,
                                                               int n_total, double *x, double *y, double *z,
                                                               double *vx, double *vy, double *vz, const double *m,
                                                               const double *rc, double dt, const int32_t *members,
-                                                              const int32_t *group_start, const int32_t *n_groups,
+                                                              const int32_t *group_start, const int32_t *list,
                                                               int32_t *flags, const double *rc_lv, int nlev)
 {
     __shared__ BsWgShared S;
-    const int g = blockIdx.x;
-    if (g >= *n_groups) return;
-    const int k0 = group_start[g], nb = group_start[g + 1] - k0;
-    if (nb <= CP_MEM || nb > BS_LANES) return;
-    const int k = threadIdx.x / BS_LANES;
-    const int P = nb <= 16 ? 4 : (nb <= 32 ? 2 : 1);
-    const int a = (threadIdx.x % BS_LANES) / P, part = (threadIdx.x % BS_LANES) % P;
-    const double ms = mstar[sys_of[members[k0]]];
-    if (k == 0 && part == 0 && a < nb) {
-        const int b = members[k0 + a];
-        const int sb = sys_of[b];
-        S.m[a] = m[b];
-        S.rc[a] = rc[b];
-        S.r01[a] = 0.1 * rc[b];
-        S.i09[a] = 1.0 / (0.9 * rc[b]);
-        S.test[a] = b - sys_off[sb] >= n_massive[sb];
-        if constexpr (LV)
-            for (int l = 1; l < nlev; ++l) S.rcl[l - 1][a] = rc_lv[(size_t)(l - 1) * n_total + b];
+    const int n_list = list[0];
+    for (int li = blockIdx.x; li < n_list; li += gridDim.x) {
+        const int g = list[1 + li];
+        const int k0 = group_start[g], nb = group_start[g + 1] - k0;
+        const int k = threadIdx.x / BS_LANES;
+        const int P = nb <= 16 ? 4 : (nb <= 32 ? 2 : 1);
+        const int a = (threadIdx.x % BS_LANES) / P, part = (threadIdx.x % BS_LANES) % P;
+        const double ms = mstar[sys_of[members[k0]]];
+        __syncthreads(); // the previous group's LDS is no longer read
+        if (k == 0 && part == 0 && a < nb) {
+            const int b = members[k0 + a];
+            const int sb = sys_of[b];
+            S.m[a] = m[b];
+            S.rc[a] = rc[b];
+            S.r01[a] = 0.1 * rc[b];
+            S.i09[a] = 1.0 / (0.9 * rc[b]);
+            S.test[a] = b - sys_off[sb] >= n_massive[sb];
+            if constexpr (LV)
+                for (int l = 1; l < nlev; ++l) S.rcl[l - 1][a] = rc_lv[(size_t)(l - 1) * n_total + b];
+        }
+        if (threadIdx.x == 0) {
+            S.nlev = nlev;
+            S.kstar_att = 0;
+        }
+        __syncthreads();
+        const bool act = a < nb;
+        const int ai = act ? a : 0;
+        const int b = members[k0 + ai];
+        double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
+        const bool ok = bs_workgroup<LV>(k, a, part, P, nb, act, S.test[ai] != 0, ms, S.rc[ai], S.r01[ai], S.i09[ai],
+                                         S, Y, dt, 1e-12);
+        // every thread has read its member's state before the first force evaluation's barrier
+        if (act && k == 0 && part == 0) store_state(x, y, z, vx, vy, vz, b, Y);
+        if (!ok && threadIdx.x == 0) atomicOr(flags, FLAG_NOCONVERGE);
     }
-    if (threadIdx.x == 0) {
-        S.nlev = nlev;
-        S.kstar_att = 0;
-    }
-    __syncthreads();
-    const bool act = a < nb;
-    const int ai = act ? a : 0;
-    const int b = members[k0 + ai];
-    double Y[6] = {x[b], y[b], z[b], vx[b], vy[b], vz[b]};
-    const bool ok = bs_workgroup<LV>(k, a, part, P, nb, act, S.test[ai] != 0, ms, S.rc[ai], S.r01[ai], S.i09[ai], S,
-                                     Y, dt, 1e-12);
-    // every thread has read its member's state before the first force evaluation's barrier
-    if (act && k == 0 && part == 0) store_state(x, y, z, vx, vy, vz, b, Y);
-    if (!ok && threadIdx.x == 0) atomicOr(flags, FLAG_NOCONVERGE);
 }
 
 __global__ __launch_bounds__(256) void kepler_list_kernel(const int32_t *sys_of, const double *mstar,
@@ -1184,8 +1214,8 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream, const double *rc_lv,
-                        int nlev, bool kepler)
+                        int32_t *flags, int big_groups, int bs_blocks, int32_t *wg_list, hipStream_t stream,
+                        const double *rc_lv, int nlev, bool kepler, const DriftSide *side)
 {
     if (L.n_total == 0) return hipSuccess;
     // one block per possible group: every group has >= 2 members; bs_blocks < 0: no group
@@ -1195,14 +1225,35 @@ hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double
     const int grid = bs_blocks + (kepler ? (L.n_total + BS_LANES - 1) / BS_LANES : 0);
     if (grid == 0) return hipSuccess;
     auto kern = nlev > 1 ? drift_kernel<true> : drift_kernel<false>;
+    auto wg = nlev > 1 ? drift_wg_kernel<true> : drift_wg_kernel<false>;
+    // the groups of 9..64 members: listed, then one workgroup each (1024 workgroups, or the
+    // largest number such groups can reach, walk the list); they run beside the launch of the
+    // smaller groups on the side stream when there is one and nothing is being captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (side && side->stream && bs_blocks > 0) {
+        const hipError_t e = hipStreamIsCapturing(stream, &cs);
+        if (e != hipSuccess) return e;
+    }
+    const bool fork = side && side->stream && bs_blocks > 0 && cs == hipStreamCaptureStatusNone;
+    const int wg_grid = std::max(1, std::min(1024, bs_blocks));
+    hipError_t e = hipSuccess;
+    if (bs_blocks > 0) wg_list_kernel<<<1, 1024, 0, stream>>>(group_start, n_groups, bs_blocks, wg_list);
+    if (fork) {
+        if ((e = hipEventRecord(side->fork, stream)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side->stream, side->fork, 0)) != hipSuccess) return e;
+        wg<<<wg_grid, WG_THREADS, 0, side->stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx,
+                                                     vy, vz, m, rc, dt, members, group_start, wg_list, flags, rc_lv,
+                                                     nlev);
+        if ((e = hipEventRecord(side->join, side->stream)) != hipSuccess) return e;
+    }
     kern<<<grid, BS_LANES, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy, vz, m,
                                         rc, dt, members, group_start, n_groups, member_slot, flags, big_groups,
                                         bs_blocks, rc_lv, nlev);
-    if (bs_blocks > 0) {
-        auto wg = nlev > 1 ? drift_wg_kernel<true> : drift_wg_kernel<false>;
-        wg<<<bs_blocks, WG_THREADS, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy,
-                                                 vz, m, rc, dt, members, group_start, n_groups, flags, rc_lv, nlev);
-    }
+    if (bs_blocks > 0 && !fork)
+        wg<<<wg_grid, WG_THREADS, 0, stream>>>(L.sys_of, L.sys_off, L.n_massive, L.mstar, L.n_total, x, y, z, vx, vy, vz,
+                                               m, rc, dt, members, group_start, wg_list, flags, rc_lv, nlev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (fork && (e = hipStreamWaitEvent(stream, side->join, 0)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

@@ -84,12 +84,14 @@ struct genga_ctx {
     int32_t *flags = nullptr;
     int32_t *lab = nullptr, *mark = nullptr, *members = nullptr, *group_start = nullptr;
     int32_t *n_groups = nullptr, *member_slot = nullptr;
+    int32_t *wg_list = nullptr; // groups of 9..64 members of a drift (their count first)
     double *epartial = nullptr;
     // grid-wide Bulirsch-Stoer for groups of more than CE_MAX_GROUP members (opt-in)
     int32_t large_groups = 0;
     BigBs big;
     int32_t *pin = nullptr;            // pinned host words for the per-attempt status reads
     hipStream_t big_stream = nullptr;  // private stream to capture one attempt
+    DriftSide side;                    // the drift's second stream (groups of 9..64 members)
     // the captured attempt, replayed on the caller's stream: one per tile-launch grid (a power
     // of two that covers the layout's tiles)
     hipGraphExec_t big_exec[32] = {};
@@ -214,6 +216,10 @@ struct genga_ctx {
 
     void release()
     {
+        if (side.stream) (void)hipStreamDestroy(side.stream);
+        if (side.fork) (void)hipEventDestroy(side.fork);
+        if (side.join) (void)hipEventDestroy(side.join);
+        side = DriftSide();
         dfree(L.sys_off);
         dfree(L.sys_of);
         dfree(L.mstar);
@@ -237,6 +243,7 @@ struct genga_ctx {
         dfree(group_start);
         dfree(n_groups);
         dfree(member_slot);
+        dfree(wg_list);
         dfree(epartial);
         dfree(kpart);
         dfree(import_bad);
@@ -377,6 +384,27 @@ int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s);
 // Sun drift (dt/2), Kepler / Bulirsch-Stoer (dt), Sun drift (dt/2).  With defer_shift the
 // last position shift is left to the next kick's source-record pass (only the momentum
 // partials are formed here); that kick must be given shift_tau = dt/2.
+
+// The drift's second stream and its events, made on first use outside graph capture; nullptr
+// while `s` is being captured or if making them fails (the drift's launches then stay on one
+// stream, with the same results).
+const DriftSide *drift_side(genga_ctx *ctx, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    DriftSide &d = ctx->side;
+    if (!d.stream) {
+        if (hipStreamCreateWithFlags(&d.stream, hipStreamNonBlocking) != hipSuccess) d.stream = nullptr;
+        if (d.stream && (hipEventCreateWithFlags(&d.fork, hipEventDisableTiming) != hipSuccess ||
+                         hipEventCreateWithFlags(&d.join, hipEventDisableTiming) != hipSuccess)) {
+            if (d.fork) (void)hipEventDestroy(d.fork);
+            (void)hipStreamDestroy(d.stream);
+            d = DriftSide();
+        }
+    }
+    return d.stream ? &d : nullptr;
+}
+
 int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, bool defer_shift = false)
 {
     const Layout &L = ctx->L;
@@ -408,7 +436,7 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
     }
     HIP_TRY(launch_drift(L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, dt, ctx->members,
                          ctx->group_start, ctx->n_groups, ctx->member_slot, ctx->flags, ctx->large_groups,
-                         bs_blocks, s));
+                         bs_blocks, ctx->wg_list, s, nullptr, 1, true, drift_side(ctx, s)));
     if (ctx->n_levels > 1) {
         const int rc = run_levels(ctx, b, dt, s);
         if (rc) return rc;
@@ -848,8 +876,8 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, double tau, hipStream_
                 // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members
                 // (the group count read on the device), the grid-wide path for larger ones
                 HIP_TRY(launch_drift(ctx->L, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, h, ctx->lv_mem,
-                                     ctx->lv_gs, &ctx->gw.hdr->G, ctx->member_slot, ctx->flags, 1, hd.G, s,
-                                     ctx->rc_lv, ctx->n_levels, false));
+                                     ctx->lv_gs, &ctx->gw.hdr->G, ctx->member_slot, ctx->flags, 1, hd.G, ctx->wg_list, s,
+                                     ctx->rc_lv, ctx->n_levels, false, drift_side(ctx, s)));
                 if (hd.max_nb > CE_MAX_GROUP) {
                     // rare: the groups and the parent order go to the host for the grid-wide path
                     std::vector<int32_t> cgs(hd.G + 1), cmem(hd.M), prev(T.M);
@@ -1183,6 +1211,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->group_start, (size_t)ctx->ce_cap + 1));
     HIP_TRY(dalloc(ctx->n_groups, 1));
     HIP_TRY(dalloc(ctx->member_slot, nt));
+    HIP_TRY(dalloc(ctx->wg_list, (size_t)std::max(ctx->ce_cap, n_total) / 2 + 2));
     HIP_TRY(dalloc(ctx->epartial, 9 * (size_t)ENERGY_SPLIT * max_items));
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
     HIP_TRY(dalloc(ctx->import_bad, 1));

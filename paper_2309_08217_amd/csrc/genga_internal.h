@@ -171,14 +171,24 @@ hipError_t launch_ce_groups(const Layout &L, const int32_t *pairs, const int32_t
                             int32_t *group_start, int32_t *n_groups, int32_t *member_slot,
                             int32_t *flags, hipStream_t stream);
 // Kepler drift of the bodies outside encounter groups and Bulirsch-Stoer of each group of up
-// to CE_MAX_GROUP members, in one launch; clears member_slot for the next step.  Larger groups
+// to CE_MAX_GROUP members (groups of 9 and more in a launch of their own, listed in wg_list:
+// [0] their number, then the groups; room for bs_blocks + 1); clears member_slot for the next
+// step.  Larger groups
 // are flagged (GENGA_ERR_CAPACITY) and Kepler-drifted, or, with big_groups != 0, left alone
 // for the grid-wide path below.
+// A second stream for the launch of the groups of 9..64 members, forked from and joined back
+// into the drift's stream by the two events (default priority; used only while the drift's
+// stream is not being captured into a graph, where the two launches stay in sequence).
+struct DriftSide {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
 hipError_t launch_drift(const Layout &L, double *x, double *y, double *z, double *vx, double *vy,
                         double *vz, const double *m, const double *rc, double dt, const int32_t *members,
                         const int32_t *group_start, const int32_t *n_groups, int32_t *member_slot,
-                        int32_t *flags, int big_groups, int bs_blocks, hipStream_t stream,
-                        const double *rc_lv = nullptr, int nlev = 1, bool kepler = true);
+                        int32_t *flags, int big_groups, int bs_blocks, int32_t *wg_list, hipStream_t stream,
+                        const double *rc_lv = nullptr, int nlev = 1, bool kepler = true,
+                        const DriftSide *side = nullptr);
 // Grid-wide union-find of the encounter pairs (large-group mode; the host reads lab back):
 // init (lab = body for the bodies of a pair), hook rounds (changed |= 1 while a round hooks),
 // compress (every member's lab = its root), slots (member_slot for members[0..n), lab = -1).
