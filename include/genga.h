@@ -154,7 +154,9 @@ int genga_tune_levels(genga_ctx *ctx, genga_bodies *b, double dt, double n1, dou
  * body i keeps m_i + m_j, the mass-weighted position and velocity and radius
  * (R_i^3 + R_j^3)^(1/3); body j gets m = 0 and status 1.  Then live bodies outside
  * [r_min, r_max] get m = 0 and status 2.  Bodies with m = 0 stay in the arrays (they exert no
- * force) until genga_compact.  At most 4096 colliding pairs per drift (more raise
+ * force) until genga_compact.  b->rcrit is the caller's and is left as it is: a merged body
+ * keeps its critical radius until the caller recomputes it with genga_rcrit (eq. (1) makes its
+ * Hill radius grow as m^(1/3)), e.g. after each step that reports a merger.  At most 4096 colliding pairs per drift (more raise
  * GENGA_ERR_CAPACITY).  mass = NULL turns collisions off.  0 <= r_min < r_max.  The launches
  * stay capturable; refused (GENGA_ERR_STATE) while a captured graph exists.  Synchronises. */
 int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *status, double r_min,
