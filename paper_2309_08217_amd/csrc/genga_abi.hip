@@ -103,8 +103,7 @@ struct genga_ctx {
     // host scratch of the grouping and tile ordering, kept so that the per-call vectors of
     // n_total entries are not allocated (and faulted in) again on every call
     std::vector<int32_t> h_lab, h_cnt, h_first;
-    std::vector<double> h_x, h_y;
-    std::vector<uint64_t> h_key, h_tmp;
+    OrderWork ow;                      // the device ring / azimuth ordering of the large groups
     // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
     int32_t n_levels = 1, n_sub = 1;
     double *rc_lv = nullptr;           // [n_levels - 1][n_total]
@@ -130,6 +129,7 @@ struct genga_ctx {
 
     void release_big()
     {
+        order_work_free(ow);
         dfree(big.k0);
         dfree(big.off);
         dfree(big.tiles);
@@ -495,6 +495,7 @@ int alloc_big(genga_ctx *ctx)
     }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
+    HIP_TRY(order_work_alloc(ctx->ow, (int)M));
     HIP_TRY(dalloc(b.off, G + 1));
     HIP_TRY(dalloc(b.tiles, (size_t)b.cap_T));
     HIP_TRY(dalloc(b.tfirst, G + 1));
@@ -659,52 +660,19 @@ int build_groups_large(genga_ctx *ctx, hipStream_t s)
     HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
-// The groups of gs / mem with at least min_nb members, each ordered so that 64 consecutive
-// members are close together and force tiles can skip distant tiles; cut into tiles of 64.
-// Without prev: by ring (equal-width bands of distance to the star, as many as make a tile of
-// 64 members about as wide as long), then by azimuth.  With prev (an order of bodies that
-// contains every member, e.g. the parent level's): in that order, which keeps its locality.
+// The groups of gs / mem with at least min_nb members, cut into tiles of 64, each group's
+// members ordered so that 64 consecutive ones are close together and force tiles can skip
+// distant tiles.  With prev (an order of bodies that contains every member, e.g. the parent
+// level's): in that order, which keeps its locality, into o.body.  Without: o.body is left
+// empty and the caller orders the members on the device (launch_ring_order: rings of distance
+// to the star, then azimuth).
 struct TileOrder {
     std::vector<int32_t> k0, off{0}, tfirst{0}, body;
     std::vector<int4> tiles;
 };
 
-// Ascending sort of distinct 64-bit keys: least-significant-digit radix, 8 bits per pass,
-// for long lists (a comparison sort of ~40000 keys costs milliseconds of host time per call);
-// the passes over the low 32 bits are skipped when the keys already ascend in them, since the
-// later passes are stable.
-static void sort_keys(std::vector<uint64_t> &key, std::vector<uint64_t> &tmp)
-{
-    const size_t n = key.size();
-    if (n < 1024) {
-        std::sort(key.begin(), key.end());
-        return;
-    }
-    bool low_sorted = true;
-    for (size_t i = 1; i < n && low_sorted; ++i) low_sorted = (uint32_t)key[i - 1] < (uint32_t)key[i];
-    tmp.resize(n);
-    for (int pass = low_sorted ? 4 : 0; pass < 8; ++pass) {
-        const int sh = 8 * pass;
-        size_t c[257] = {0};
-        for (size_t i = 0; i < n; ++i) ++c[((key[i] >> sh) & 255) + 1];
-        for (int d = 0; d < 256; ++d) c[d + 1] += c[d];
-        for (size_t i = 0; i < n; ++i) tmp[c[(key[i] >> sh) & 255]++] = key[i];
-        key.swap(tmp);
-    }
-}
-
-// a monotone stand-in for atan2(y, x) on [0, 4)
-static inline double pseudo_angle(double x, double y)
-{
-    const double s = std::fabs(x) + std::fabs(y);
-    if (!(s > 0.0)) return 0.0;
-    const double t = y / s; // in [-1, 1]
-    return x >= 0.0 ? (y >= 0.0 ? t : 4.0 + t) : 2.0 - t;
-}
-
-int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vector<int32_t> &gs,
-                const std::vector<int32_t> &mem, int min_nb, TileOrder &o,
-                const std::vector<int32_t> *prev = nullptr)
+int order_tiles(genga_ctx *ctx, const std::vector<int32_t> &gs, const std::vector<int32_t> &mem, int min_nb,
+                TileOrder &o, const std::vector<int32_t> *prev = nullptr)
 {
     const int ng = (int)gs.size() - 1;
     for (int g = 0; g < ng; ++g) {
@@ -719,10 +687,10 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
     for (size_t gi = 0; gi + 1 < o.tfirst.size(); ++gi)
         if (o.tfirst[gi + 1] - o.tfirst[gi] > BIG_TILES_PER_GROUP)
             return fail(GENGA_ERR_CAPACITY, "an encounter group of more than %d bodies", 64 * BIG_TILES_PER_GROUP);
-    if (o.k0.empty()) return GENGA_OK;
+    if (o.k0.empty() || !prev) return GENGA_OK;
     const size_t nt = (size_t)ctx->L.n_total;
     o.body.resize((size_t)o.off.back());
-    if (prev) {
+    {
         std::vector<int32_t> grp(nt, -1), fill(o.k0.size());
         for (size_t gi = 0; gi < o.k0.size(); ++gi) {
             for (int l = 0; l < o.off[gi + 1] - o.off[gi]; ++l) grp[mem[o.k0[gi] + l]] = (int32_t)gi;
@@ -732,39 +700,6 @@ int order_tiles(genga_ctx *ctx, genga_bodies *b, hipStream_t s, const std::vecto
             if (grp[bi] >= 0) o.body[fill[grp[bi]]++] = bi;
         for (size_t gi = 0; gi < o.k0.size(); ++gi)
             if (fill[gi] != o.off[gi + 1]) return fail(GENGA_ERR_STATE, "tile order misses group members");
-        return GENGA_OK;
-    }
-    std::vector<double> &hx = ctx->h_x, &hy = ctx->h_y;
-    hx.resize(nt);
-    hy.resize(nt);
-    HIP_TRY(hipMemcpyAsync(hx.data(), b->x, nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hy.data(), b->y, nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<uint64_t> &key = ctx->h_key, &tmp = ctx->h_tmp;
-    for (size_t gi = 0; gi < o.k0.size(); ++gi) {
-        const int nb = o.off[gi + 1] - o.off[gi];
-        double r0 = INFINITY, r1 = 0.0, rs = 0.0;
-        for (int l = 0; l < nb; ++l) {
-            const int32_t bi = mem[o.k0[gi] + l];
-            const double r = std::sqrt(hx[bi] * hx[bi] + hy[bi] * hy[bi]);
-            r0 = std::min(r0, r);
-            r1 = std::max(r1, r);
-            rs += r;
-        }
-        const double rmean = rs / nb, width = std::max(r1 - r0, 1e-300);
-        const int rings = std::max(1, (int)std::lround(std::sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
-        key.resize(nb);
-        for (int l = 0; l < nb; ++l) {
-            const int32_t bi = mem[o.k0[gi] + l];
-            const double r = std::sqrt(hx[bi] * hx[bi] + hy[bi] * hy[bi]);
-            const int ring = std::min(rings - 1, (int)((r - r0) / width * rings));
-            // (ring, azimuth) quantised into the high 32 bits, the body in the low ones
-            const double u = (ring + 0.25 * pseudo_angle(hx[bi], hy[bi])) / rings; // [0, 1]
-            const uint64_t q = (uint64_t)std::min(4294967295.0, std::max(0.0, u * 4294967295.0));
-            key[l] = q << 32 | (uint32_t)bi;
-        }
-        sort_keys(key, tmp);
-        for (int l = 0; l < nb; ++l) o.body[o.off[gi] + l] = (int32_t)(key[l] & 0xffffffffu);
     }
     return GENGA_OK;
 }
@@ -915,7 +850,7 @@ int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     T.G = T.M = T.n_tiles = T.n_multi = 0;
     if ((int)pgs.size() <= 1) return GENGA_OK;
     TileOrder o;
-    int rc = order_tiles(ctx, b, s, pgs, pmem, 2, o);
+    int rc = order_tiles(ctx, pgs, pmem, 2, o);
     if (rc) return rc;
     if ((int)o.k0.size() > ctx->lt_cap_G || o.off.back() > T.cap_M || (int)o.tiles.size() > ctx->lt_cap_T)
         return fail(GENGA_ERR_STATE, "level layout exceeds its allocation");
@@ -942,8 +877,10 @@ int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
     HIP_TRY(hipMemcpyAsync(T.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     if (!o.tiles.empty())
         HIP_TRY(hipMemcpyAsync(T.tiles, o.tiles.data(), o.tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s));
-    if (!o.body.empty())
-        HIP_TRY(hipMemcpyAsync(T.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // the members in ring / azimuth order, on the device (the group offsets in the large-group
+    // layout's k0, free until run_big_groups lays out its own)
+    HIP_TRY(hipMemcpyAsync(ctx->big.k0, o.k0.data(), o.k0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_ring_order(ctx->members, ctx->big.k0, T.off, T.G, T.M, b->x, b->y, ctx->ow, T.body, s));
     HIP_TRY(hipStreamSynchronize(s));
     return run_level(ctx, b, 1, dt, s);
 }
@@ -957,7 +894,7 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
     BigBs &bg = ctx->big;
     bg.G = bg.M = bg.n_tiles = 0;
     TileOrder o;
-    int rc = order_tiles(ctx, b, s, gs, mem_h, min_nb, o, prev);
+    int rc = order_tiles(ctx, gs, mem_h, min_nb, o, prev);
     if (rc) return rc;
     if (o.k0.empty()) return GENGA_OK;
     if ((int)o.k0.size() > bg.cap_G || o.off.back() > bg.cap_M || (int)o.tiles.size() > bg.cap_T)
@@ -972,7 +909,10 @@ int run_big_groups(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, co
     HIP_TRY(hipMemcpyAsync(bg.tfirst, o.tfirst.data(), o.tfirst.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     const int32_t dims[4] = {bg.G, bg.M, bg.n_tiles, 0};
     HIP_TRY(hipMemcpyAsync(bg.dims, dims, sizeof(dims), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(bg.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (prev)
+        HIP_TRY(hipMemcpyAsync(bg.body, o.body.data(), o.body.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    else
+        HIP_TRY(launch_ring_order(members_dev, bg.k0, bg.off, bg.G, bg.M, b->x, b->y, ctx->ow, bg.body, s));
     HIP_TRY(hipStreamSynchronize(s));
     const Layout &L = ctx->L;
     HIP_TRY(launch_big_setup(L, bg, members_dev, b->x, b->y, b->z, b->vx, b->vy, b->vz, b->m, b->rcrit, ctx->rc_lv,

@@ -351,6 +351,22 @@ struct GroupWork {
     int cap = 0;                                      // largest parent layout
 };
 hipError_t group_work_alloc(GroupWork &w, int cap);
+// The members of every group of a layout in ring / azimuth order about the star (the order the
+// force tiles want: 64 consecutive members close together): per group, equal-width rings of
+// distance to the star, as many as make a tile of 64 members about as wide as long, then the
+// azimuth; a stable radix sort of the keys (group, quantised ring + azimuth / 4) with the body
+// as value.  members[k0[gi] ..] are group gi's bodies, off[gi] its first slot in body_out.
+struct OrderWork {
+    uint64_t *keys = nullptr, *keys_sorted = nullptr; // [cap]
+    int32_t *vals = nullptr;                          // [cap]
+    void *temp = nullptr;
+    size_t temp_bytes = 0;
+    int cap = 0;
+};
+hipError_t order_work_alloc(OrderWork &w, int cap);
+void order_work_free(OrderWork &w);
+hipError_t launch_ring_order(const int32_t *members, const int32_t *k0, const int32_t *off, int n_groups, int M,
+                             const double *x, const double *y, OrderWork &w, int32_t *body_out, hipStream_t stream);
 void group_work_free(GroupWork &w);
 // With union_find: union-find of pairs (lab all -1 on entry; afterwards every body of a pair
 // holds its component's smallest body, the caller clears it); then the components' members in

@@ -150,6 +150,64 @@ int bits_for(uint64_t v)
     return b;
 }
 
+
+// a monotone stand-in for atan2(y, x) on [0, 4)
+__device__ __forceinline__ double pseudo_angle(double x, double y)
+{
+    const double s = fabs(x) + fabs(y);
+    if (!(s > 0.0)) return 0.0;
+    const double t = y / s; // in [-1, 1]
+    return x >= 0.0 ? (y >= 0.0 ? t : 4.0 + t) : 2.0 - t;
+}
+
+// Per layout group gi (one workgroup): its members' key (gi, ring, azimuth) and body.  The
+// rings are equal-width bands of distance to the star, as many as make a tile of 64 members
+// about as wide as long; the quantised (ring + azimuth / 4) / rings orders the members.
+__global__ __launch_bounds__(256) void ring_keys_kernel(const int32_t *members, const int32_t *k0, const int32_t *off,
+                                                        int n_groups, const double *x, const double *y, uint64_t *key,
+                                                        int32_t *val)
+{
+#pragma clang fp contract(off)
+    __shared__ double rmin[4], rmax[4], rsum[4];
+    for (int gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+        const int o = off[gi], nb = off[gi + 1] - o, m0 = k0[gi];
+        double r0 = INFINITY, r1 = 0.0, rs = 0.0;
+        for (int l = threadIdx.x; l < nb; l += 256) {
+            const int bi = members[m0 + l];
+            const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
+            r0 = fmin(r0, r);
+            r1 = fmax(r1, r);
+            rs += r;
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            r0 = fmin(r0, __shfl_xor(r0, d, 64));
+            r1 = fmax(r1, __shfl_xor(r1, d, 64));
+            rs += __shfl_xor(rs, d, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            rmin[threadIdx.x >> 6] = r0;
+            rmax[threadIdx.x >> 6] = r1;
+            rsum[threadIdx.x >> 6] = rs;
+        }
+        __syncthreads();
+        r0 = fmin(fmin(rmin[0], rmin[1]), fmin(rmin[2], rmin[3]));
+        r1 = fmax(fmax(rmax[0], rmax[1]), fmax(rmax[2], rmax[3]));
+        rs = (rsum[0] + rsum[1]) + (rsum[2] + rsum[3]);
+        const double rmean = rs / nb, width = fmax(r1 - r0, 1e-300);
+        const int rings = max(1, (int)lround(sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
+        for (int l = threadIdx.x; l < nb; l += 256) {
+            const int bi = members[m0 + l];
+            const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
+            const int ring = min(rings - 1, (int)((r - r0) / width * rings));
+            const double u = (ring + 0.25 * pseudo_angle(x[bi], y[bi])) / rings; // [0, 1]
+            const uint64_t q = (uint64_t)fmin(4294967295.0, fmax(0.0, u * 4294967295.0));
+            key[o + l] = (uint64_t)gi << 32 | q;
+            val[o + l] = bi;
+        }
+        __syncthreads(); // the partials are rewritten for the next group
+    }
+}
+
 } // namespace
 
 hipError_t group_work_alloc(GroupWork &w, int cap)
@@ -235,6 +293,42 @@ hipError_t launch_group_layout(const Layout &L, GroupWork &w, const int32_t *pai
                                                           out.tl);
     }
     return hipGetLastError();
+}
+
+hipError_t order_work_alloc(OrderWork &w, int cap)
+{
+    order_work_free(w);
+    w.cap = cap > 1 ? cap : 2;
+    const size_t n = (size_t)w.cap;
+    hipError_t e;
+    if ((e = hipMalloc((void **)&w.keys, n * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.keys_sorted, n * sizeof(uint64_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.vals, n * sizeof(int32_t))) != hipSuccess) return e;
+    int32_t *out = nullptr;
+    if ((e = rocprim::radix_sort_pairs(nullptr, w.temp_bytes, w.keys, w.keys_sorted, w.vals, out, (unsigned int)n, 0,
+                                       64)) != hipSuccess)
+        return e;
+    return hipMalloc(&w.temp, w.temp_bytes ? w.temp_bytes : 1);
+}
+
+void order_work_free(OrderWork &w)
+{
+    for (void *p : {(void *)w.keys, (void *)w.keys_sorted, (void *)w.vals, w.temp})
+        if (p) (void)hipFree(p);
+    w = OrderWork{};
+}
+
+hipError_t launch_ring_order(const int32_t *members, const int32_t *k0, const int32_t *off, int n_groups, int M,
+                             const double *x, const double *y, OrderWork &w, int32_t *body_out, hipStream_t stream)
+{
+    if (n_groups <= 0 || M <= 0) return hipSuccess;
+    if (M > w.cap) return hipErrorInvalidValue;
+    ring_keys_kernel<<<std::min(n_groups, 4096), 256, 0, stream>>>(members, k0, off, n_groups, x, y, w.keys, w.vals);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t bytes = w.temp_bytes;
+    return rocprim::radix_sort_pairs(w.temp, bytes, w.keys, w.keys_sorted, w.vals, body_out, (unsigned int)M, 0,
+                                     32 + bits_for((uint64_t)n_groups), stream);
 }
 
 } // namespace genga
