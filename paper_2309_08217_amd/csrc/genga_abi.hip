@@ -99,10 +99,8 @@ struct genga_ctx {
     int32_t *big_changed = nullptr;    // device word of the union-find rounds
     int32_t ce_cap = 0;                // members / group_start capacity
     std::vector<int32_t> gs_h;         // group_start copied to the host
-    std::vector<int32_t> mem_h;        // members copied to the host
     // host scratch of the grouping and tile ordering, kept so that the per-call vectors of
     // n_total entries are not allocated (and faulted in) again on every call
-    std::vector<int32_t> h_lab, h_cnt, h_first;
     OrderWork ow;                      // the device ring / azimuth ordering of the large groups
     // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
     int32_t n_levels = 1, n_sub = 1;
@@ -113,6 +111,7 @@ struct genga_ctx {
     int32_t *lv_pairs = nullptr, *lv_count = nullptr; // a level's pairs
     GroupWork gw;                      // device layout of a level's groups
     GroupHeader *ghdr = nullptr;       // pinned host copy of its header
+    int32_t *iota = nullptr;           // [n_total] 0, 1, ..: the body order, level 0's parent layout
     // collisions and removal (opt-in)
     CollideArgs col;
     int32_t pair_cap_req = 0;          // pair capacity asked for at genga_set_systems
@@ -130,6 +129,7 @@ struct genga_ctx {
     void release_big()
     {
         order_work_free(ow);
+        dfree(iota);
         dfree(big.k0);
         dfree(big.off);
         dfree(big.tiles);
@@ -441,7 +441,7 @@ int enqueue_drift(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s, boo
         const int rc = run_levels(ctx, b, dt, s);
         if (rc) return rc;
     } else if (ctx->large_groups) {
-        const int rc = run_big_groups(ctx, b, dt, s, ctx->gs_h, ctx->mem_h, ctx->members, CE_MAX_GROUP + 1);
+        const int rc = run_big_groups(ctx, b, dt, s, ctx->gs_h, {}, ctx->members, CE_MAX_GROUP + 1);
         if (rc) return rc;
     }
     if (defer_shift)
@@ -490,8 +490,16 @@ int alloc_big(genga_ctx *ctx)
         HIP_TRY(dalloc(ctx->lv_ng, 1));
         HIP_TRY(dalloc(ctx->lv_pairs, 2 * (size_t)ctx->pair_cap));
         HIP_TRY(dalloc(ctx->lv_count, 1));
+    }
+    {
+        // the groupings on the device (level 0's in body order, the levels' in their parent's)
+        const size_t nt = (size_t)std::max(ctx->L.n_total, 1);
         HIP_TRY(group_work_alloc(ctx->gw, (int)nt));
         if (!ctx->ghdr) HIP_TRY(hipHostMalloc((void **)&ctx->ghdr, sizeof(GroupHeader), hipHostMallocDefault));
+        std::vector<int32_t> id(nt);
+        for (size_t i = 0; i < nt; ++i) id[i] = (int32_t)i;
+        HIP_TRY(dalloc(ctx->iota, nt));
+        HIP_TRY(hipMemcpy(ctx->iota, id.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
@@ -548,116 +556,54 @@ int alloc_big(genga_ctx *ctx)
     return GENGA_OK;
 }
 
-// Groups of more than CE_MAX_GROUP members: read the group sizes (the one host round trip of
-// a step in this mode), lay the large groups out for the grid-wide path, and run attempts
-// until every group has reached dt.
-// Encounter groups in the large-group mode, without the one-workgroup limit: union-find of the
-// pairs on the device (hooking rounds until one changes nothing), labels read back, members
-// bucketed by root on the host (groups in order of their smallest member, members ascending,
-// as the one-workgroup kernel orders them) and sent back with group_start and n_groups.
-// Connected components of a pair list on the device (grid-wide union-find, labels read back,
-// bucketed on the host): gs / mem receive the groups (members ascending by body within each
-// group, groups by smallest member).  Leaves lab all -1 on the device, except with keep_lab
-// after a success: then the labels (the group's smallest member, -1 outside every pair) stay
-// for the caller, who clears them.  A group above the grid-wide path's limit is refused.
-int group_pairs(genga_ctx *ctx, const int32_t *pairs, const int32_t *count, int32_t cap,
-                std::vector<int32_t> &gs, std::vector<int32_t> &mem, hipStream_t s, bool strict,
-                bool keep_lab = false)
-{
-    const Layout &L = ctx->L;
-    const size_t nt = (size_t)L.n_total;
-    std::vector<int32_t> &lab = ctx->h_lab, &cnt = ctx->h_cnt, &first = ctx->h_first;
-    lab.resize(nt);
-    gs.assign(1, 0);
-    mem.clear();
-    // Rounds of (hook, compress) x 2 until a round changes nothing; compressing after each
-    // hook keeps the trees flat, so few rounds are needed.  The kernels read the pair count on
-    // the device, so the host waits once per checked round, for the count, the round's flag
-    // and the labels together; the first round (which links every pair) goes unchecked.
-    HIP_TRY(launch_uf_init(pairs, count, cap, ctx->lab, s));
-    for (int round = 0;; ++round) {
-        if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
-        ctx->pin[2] = 0;
-        HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
-        for (int rep = 0; rep < 2; ++rep) {
-            HIP_TRY(launch_uf_hook(pairs, count, cap, ctx->lab, ctx->big_changed, s));
-            HIP_TRY(launch_uf_compress(L, ctx->lab, s));
-        }
-        if (round == 0) continue;
-        HIP_TRY(hipMemcpyAsync(ctx->pin, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        if (nt > 0) HIP_TRY(hipMemcpyAsync(lab.data(), ctx->lab, nt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ctx->pin[2] == 0) break;
-    }
-    // with keep_lab the device labels stay for the caller, who clears them (on success)
-    if (nt > 0 && !keep_lab) HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s));
-    const auto refuse = [&](int status, const char *fmt, int a, int b) {
-        if (keep_lab && nt > 0) (void)hipMemsetAsync(ctx->lab, 0xff, nt * sizeof(int32_t), s);
-        gs.assign(1, 0);
-        mem.clear();
-        return fail(status, fmt, a, b);
-    };
-    // a list cut at its capacity has been flagged by the launch that filled it; strict: refuse
-    if (strict && ctx->pin[0] > cap)
-        return refuse(GENGA_ERR_CAPACITY, "%d encounter pairs exceed the capacity %d", ctx->pin[0], cap);
-    const int np = std::min(ctx->pin[0], cap);
-    if (np <= 0) return GENGA_OK;
-    // Labels are compressed to roots and a root is its group's smallest member, so scanning
-    // the bodies in ascending order meets every root before its other members: the roots get
-    // group numbers in that order (first[root]), one pass counts the members per group, and a
-    // second places them, ascending, after the prefix sum of the counts.
-    first.resize(nt);
-    cnt.clear();
-    for (size_t i = 0; i < nt; ++i) {
-        const int32_t r = lab[i];
-        if (r < 0) continue;
-        if (r == (int32_t)i) {
-            first[i] = (int32_t)cnt.size();
-            cnt.push_back(0);
-        }
-        ++cnt[first[r]];
-    }
-    const size_t ng = cnt.size();
-    gs.resize(ng + 1);
-    int32_t total = 0;
-    for (size_t g = 0; g < ng; ++g) {
-        if (cnt[g] > 64 * BIG_TILES_PER_GROUP)
-            return refuse(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", cnt[g],
-                          64 * BIG_TILES_PER_GROUP);
-        gs[g] = total;
-        total += cnt[g];
-        cnt[g] = gs[g]; // next free slot of group g
-    }
-    gs[ng] = total;
-    mem.resize((size_t)total);
-    for (size_t i = 0; i < nt; ++i) {
-        const int32_t r = lab[i];
-        if (r >= 0) mem[cnt[first[r]]++] = (int32_t)i;
-    }
-    return GENGA_OK;
-}
-
 // The encounter groups of the context's pair list, for the large-group mode: members /
 // group_start / n_groups on the device, member_slot set for the drift launch.
 int build_groups_large(genga_ctx *ctx, hipStream_t s)
 {
-    int rc = group_pairs(ctx, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->gs_h, ctx->mem_h, s, false);
+    // the components of the pair list laid out on the device in body order (groups by their
+    // smallest member, members ascending), and the header and group offsets read in one wait
+    const Layout &L = ctx->L;
+    const int nt = L.n_total;
+    GroupOut out;
+    out.body = ctx->members;
+    out.off = ctx->group_start;
+    const size_t ngs = (size_t)nt / 2 + 2; // groups have at least two members
+    std::vector<int32_t> &gs = ctx->gs_h;
+    const auto layout = [&](bool union_find) -> int {
+        HIP_TRY(launch_group_layout(L, ctx->gw, ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->iota, nt,
+                                    out, s, union_find));
+        gs.resize(ngs);
+        HIP_TRY(hipMemcpyAsync(ctx->ghdr, ctx->gw.hdr, sizeof(GroupHeader), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(gs.data(), ctx->group_start, ngs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return GENGA_OK;
+    };
+    int rc = layout(true);
     if (rc) return rc;
-    const int ng = (int)ctx->gs_h.size() - 1, nmem = (int)ctx->mem_h.size();
-    if (nmem > ctx->ce_cap) return fail(GENGA_ERR_STATE, "encounter members exceed their allocation");
-    ctx->pin[0] = ng;
-    ctx->pin[1] = nmem;
-    // uploads on the stream, one host wait (pin is rewritten by the next grouping)
-    if (nmem > 0) {
-        HIP_TRY(hipMemcpyAsync(ctx->members, ctx->mem_h.data(), nmem * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(ctx->group_start, ctx->gs_h.data(), ctx->gs_h.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, s));
+    // a union-find not settled within the enqueued rounds: checked rounds, then the layout again
+    for (int round = 0; ctx->ghdr->unconverged; ++round) {
+        if (round > 4096) return fail(GENGA_ERR_STATE, "union-find of the encounter pairs did not settle");
+        ctx->pin[2] = 0;
+        HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 2, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(launch_uf_hook(ctx->pairs, ctx->pair_count, ctx->pair_cap, ctx->lab, ctx->big_changed, s));
+            HIP_TRY(launch_uf_compress(L, ctx->lab, s));
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->pin + 2, ctx->big_changed, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ctx->pin[2] == 0 && (rc = layout(false))) return rc;
     }
-    HIP_TRY(hipMemcpyAsync(ctx->n_groups, ctx->pin, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ctx->big_changed, ctx->pin + 1, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(launch_uf_slots(nmem, ctx->members, ctx->big_changed, ctx->member_slot, ctx->lab, s));
+    const GroupHeader h = *ctx->ghdr;
+    if (h.max_nb > 64 * BIG_TILES_PER_GROUP) {
+        if (nt > 0) (void)hipMemsetAsync(ctx->lab, 0xff, (size_t)nt * sizeof(int32_t), s);
+        gs.assign(1, 0);
+        return fail(GENGA_ERR_CAPACITY, "an encounter group of %d bodies (at most %d)", h.max_nb,
+                    64 * BIG_TILES_PER_GROUP);
+    }
+    gs.resize((size_t)h.G + 1);
+    // the drift's group count and the members' slots (their labels back to -1)
+    HIP_TRY(hipMemcpyAsync(ctx->n_groups, &ctx->gw.hdr->G, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_uf_slots(nt, ctx->members, &ctx->gw.hdr->M, ctx->member_slot, ctx->lab, s));
     return GENGA_OK;
 }
 // The groups of gs / mem with at least min_nb members, cut into tiles of 64, each group's
@@ -845,12 +791,12 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, double tau, hipStream_
 // deeper levels inherit that order through the device layout.
 int run_levels(genga_ctx *ctx, genga_bodies *b, double dt, hipStream_t s)
 {
-    const std::vector<int32_t> &pgs = ctx->gs_h, &pmem = ctx->mem_h;
+    const std::vector<int32_t> &pgs = ctx->gs_h;
     LevelTiles &T = ctx->lt[0];
     T.G = T.M = T.n_tiles = T.n_multi = 0;
     if ((int)pgs.size() <= 1) return GENGA_OK;
     TileOrder o;
-    int rc = order_tiles(ctx, pgs, pmem, 2, o);
+    int rc = order_tiles(ctx, pgs, {}, 2, o);
     if (rc) return rc;
     if ((int)o.k0.size() > ctx->lt_cap_G || o.off.back() > T.cap_M || (int)o.tiles.size() > ctx->lt_cap_T)
         return fail(GENGA_ERR_STATE, "level layout exceeds its allocation");
