@@ -672,6 +672,18 @@ __global__ __launch_bounds__(256) void big_localize_kernel(BigBs b)
     }
 }
 
+// Group g's acceptance once column k (>= 1) has been decided: its column if it is the first
+// whose estimate meets tol, unless the attempt is void (a sub-step left the lists' bound).  On
+// the list path every launch that needs the verdict takes it itself, from the same words, and
+// one thread per group stores it in acc for the launches after it.
+__device__ __forceinline__ int decided(const BigBs &b, int g, int k, double tol)
+{
+    const int a = b.acc[g];
+    if (a >= 0 || k < 1 || b.done[g] || (b.skin && b.stale[g])) return a;
+    const unsigned long long e = b.err[g * BS_KMAX + k];
+    return (e != ~0ull && bitsd(e) <= tol) ? k : -1;
+}
+
 // What follows a member's pair sum in a sub-step: the star's pull, then the midpoint update of
 // OUT (modes 0 and 1, with the positions of OUT's source records) or, in mode 2, T(k, 0) and
 // the group's error estimate of column k.  Every lane of the wave calls it; `lead` marks the
@@ -846,14 +858,17 @@ __global__ __launch_bounds__(64 * BIG_LIST_LANES) __attribute__((amdgpu_waves_pe
 }
 
 // The first sub-step of column k >= 1 on the list path: the pair sums at Y are column 0's
-// (a0), so only the update runs, one thread per member.
-__global__ __launch_bounds__(GB_THREADS) void big_substep_start_kernel(BigBs b, int k, double *OUT, double *ROUT)
+// (a0), so only the update runs, one thread per member; it also takes column k - 1's verdict.
+__global__ __launch_bounds__(GB_THREADS) void big_substep_start_kernel(BigBs b, int k, double tol, double *OUT,
+                                                                      double *ROUT)
 {
     const int f = blockIdx.x * GB_THREADS + threadIdx.x;
     const bool valid = f < b.dims[1];
     const int fa = valid ? f : 0;
     const int g = b.grp[fa];
-    const bool act = valid && !b.done[g] && b.acc[g] < 0;
+    const int ka = decided(b, g, k - 1, tol); // column k - 1's verdict
+    if (valid && fa == b.off[g] && ka != b.acc[g]) b.acc[g] = ka;
+    const bool act = valid && !b.done[g] && ka < 0;
     const size_t M = (size_t)b.dims[1];
     const double *Y = b.Y;
     member_tail(b, k, 0, g, fa, act, act, Y[fa], Y[M + fa], Y[2 * M + fa], act ? b.a0[fa] : 0.0,
@@ -869,13 +884,14 @@ __global__ __launch_bounds__(64) void big_decide_kernel(BigBs b, int k, double t
     if (e != ~0ull && bitsd(e) <= tol) b.acc[g] = k;
 }
 
-// Accepted groups: Y = T(k*, k*).
-__global__ __launch_bounds__(GB_THREADS) void big_accept_kernel(BigBs b)
+// Accepted groups: Y = T(k*, k*) (the last column's verdict taken here).
+__global__ __launch_bounds__(GB_THREADS) void big_accept_kernel(BigBs b, double tol)
 {
     const int f = blockIdx.x * GB_THREADS + threadIdx.x;
     if (f >= b.dims[1]) return;
     const int g = b.grp[f];
-    const int ks = b.acc[g];
+    const int ks = decided(b, g, BS_KMAX - 1, tol);
+    if (f == b.off[g] && ks != b.acc[g]) b.acc[g] = ks;
     if (b.done[g] || ks < 0) return;
     const size_t M = (size_t)b.dims[1];
     for (int q = 0; q < 6; ++q) {
@@ -900,7 +916,7 @@ __global__ __launch_bounds__(GB_THREADS) void big_control_kernel(BigBs b, double
             ++active;
             continue;
         }
-        const int ks = b.acc[g];
+        const int ks = decided(b, g, BS_KMAX - 1, tol);
         // a rejected attempt leaves Y and the skins as they were and only shortens the step: the
         // next attempt keeps its lists (the prediction and its bound hold over any shorter step)
         if (b.skin) b.keep[g] = ks < 0;
@@ -995,7 +1011,7 @@ hipError_t launch_big_attempt(const BigBs &b, double tol, int32_t *flags, int ti
         substep<<<nt, GB_TILE * waves, 0, stream>>>(b, k, 2, buf[zc], buf[zm], nullptr, box[zc], nullptr);
         if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol); // the estimates came with T(k, 0)
     }
-    big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b, tol);
     big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);
     return hipGetLastError();
 }
@@ -1024,7 +1040,7 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
         if (k == 0)
             substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 0, 0, buf[0], buf[0], buf[1], rec[0], rec[1]);
         else
-            big_substep_start_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k, buf[1], rec[1]);
+            big_substep_start_kernel<<<gm, GB_THREADS, 0, stream>>>(b, k, tol, buf[1], rec[1]);
         int zc = 1, zm = 0;
         for (int i = 1; i < nsub; ++i) {
             const int out = zm == 0 ? 2 : zm;
@@ -1033,9 +1049,8 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
             zc = out;
         }
         substep<<<nt, 64 * BIG_LIST_LANES, 0, stream>>>(b, k, 2, nsub, buf[zc], buf[zm], nullptr, rec[zc], nullptr);
-        if (k > 0) big_decide_kernel<<<gg, 64, 0, stream>>>(b, k, tol);
     }
-    big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b);
+    big_accept_kernel<<<gm, GB_THREADS, 0, stream>>>(b, tol);
     big_control_kernel<<<1, GB_THREADS, 0, stream>>>(b, tol, flags);
     return hipGetLastError();
 }
