@@ -607,29 +607,36 @@ __global__ __launch_bounds__(64) void big_list_kernel(BigBs b)
 // its members' lists become the tile's slots, in tile order (more than BIG_LIST_SLOTS void the
 // attempt and send the step to the tile path), and each member's segments are written as one
 // run of slot positions, slot * 64 + the source's position in its tile.
-__global__ __launch_bounds__(256) void big_localize_kernel(BigBs b)
+constexpr int LOC_THREADS = 64 * BIG_LIST_SEGS; // one thread per (member, segment) of a tile
+
+__global__ __launch_bounds__(LOC_THREADS) void big_localize_kernel(BigBs b)
 {
-    static_assert(BIG_LIST_SEGS == 4 && BIG_LIST_SLOTS * 64 <= 65536, "four segments, 16-bit positions");
+    static_assert(BIG_LIST_SLOTS * 64 <= 65536, "16-bit slot positions");
     __shared__ int mark[BIG_TILES_PER_GROUP];
-    __shared__ int wsum[4];
+    __shared__ int wsum[LOC_THREADS / 64];
     for (int me = blockIdx.x; me < b.dims[2]; me += gridDim.x) {
         const int4 tile = b.tiles[me];
         const int g = tile.x;
         if (b.done[g] || b.keep[g]) continue; // the whole block
         const int o = b.off[g], nb = b.off[g + 1] - o, nt = b.tfirst[g + 1] - b.tfirst[g];
-        for (int i = threadIdx.x; i < nt; i += 256) mark[i] = 0;
+        for (int i = threadIdx.x; i < nt; i += LOC_THREADS) mark[i] = 0;
         __syncthreads();
-        const int m = threadIdx.x >> 2, s = threadIdx.x & 3;
+        const int m = threadIdx.x / BIG_LIST_SEGS, s = threadIdx.x % BIG_LIST_SEGS;
         const bool valid = m < tile.z;
         const int f = tile.y + (valid ? m : 0);
-        const int4 nn = reinterpret_cast<const int4 *>(b.nlen)[f];
-        const int len = valid ? (s == 0 ? nn.x : (s == 1 ? nn.y : (s == 2 ? nn.z : nn.w))) : 0;
-        const int start = s == 0 ? 0 : (s == 1 ? nn.x : (s == 2 ? nn.x + nn.y : nn.x + nn.y + nn.z));
+        const int32_t *nlen = b.nlen + (size_t)f * BIG_LIST_SEGS;
+        int start = 0, all = 0;
+        for (int q = 0; q < BIG_LIST_SEGS; ++q) {
+            const int l = nlen[q];
+            start += q < s ? l : 0;
+            all += l;
+        }
+        const int len = valid ? nlen[s] : 0;
         const int32_t *row = b.nl + (size_t)f * BIG_LIST_CAP + s * BIG_LIST_SEG;
         for (int e = 0; e < len; ++e) mark[(row[e] - o) >> 6] = 1;
         __syncthreads();
         // ordered compaction of the marks: thread t takes tiles [t per, (t + 1) per)
-        const int per = (nt + 255) / 256;
+        const int per = (nt + LOC_THREADS - 1) / LOC_THREADS;
         const int t0 = (int)threadIdx.x * per, t1 = min(t0 + per, nt);
         int cnt = 0;
         for (int i = t0; i < t1; ++i) cnt += mark[i];
@@ -642,7 +649,7 @@ __global__ __launch_bounds__(256) void big_localize_kernel(BigBs b)
         if (lane == 63) wsum[wave] = incl;
         __syncthreads();
         int pos = incl - cnt, total = 0;
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < LOC_THREADS / 64; ++w) {
             pos += w < wave ? wsum[w] : 0;
             total += wsum[w];
         }
@@ -667,7 +674,7 @@ __global__ __launch_bounds__(256) void big_localize_kernel(BigBs b)
             }
         }
         // a tile beyond the slots lists nothing (its attempt is void)
-        if (valid && s == 0) b.ltot[f] = total <= BIG_LIST_SLOTS ? nn.x + nn.y + nn.z + nn.w : 0;
+        if (valid && s == 0) b.ltot[f] = total <= BIG_LIST_SLOTS ? all : 0;
         __syncthreads(); // the marks are cleared for the next tile
     }
 }
@@ -1034,7 +1041,7 @@ hipError_t launch_big_attempt_list(const BigBs &b, double tol, int32_t *flags, i
         big_list_kernel<true><<<nl, 64, 0, stream>>>(b);
     else
         big_list_kernel<false><<<nl, 64, 0, stream>>>(b);
-    big_localize_kernel<<<nt, 256, 0, stream>>>(b);
+    big_localize_kernel<<<nt, LOC_THREADS, 0, stream>>>(b);
     for (int k = 0; k < BS_KMAX; ++k) {
         const int nsub = 2 * (k + 1);
         if (k == 0)

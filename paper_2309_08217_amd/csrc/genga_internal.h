@@ -260,7 +260,7 @@ struct BigBs {
     int32_t *ovf = nullptr;        // device word: a list exceeded BIG_LIST_CAP (the host falls back to tiles)
 };
 constexpr int BIG_TILES_PER_GROUP = 1024; // a workgroup of 1024 threads tests one source tile each
-constexpr int BIG_LIST_SEGS = 4;          // segments of a member's list (built by separate waves)
+constexpr int BIG_LIST_SEGS = 8;          // segments of a member's list (built by separate waves)
 constexpr int BIG_LIST_SEG = 128;         // sources per segment
 constexpr int BIG_LIST_CAP = BIG_LIST_SEGS * BIG_LIST_SEG; // sources per member on the list path
 constexpr int BIG_LIST_LANES = 8;         // lanes that share one member's list in a sub-step
