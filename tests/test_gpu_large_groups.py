@@ -16,18 +16,18 @@ FP64, FP32 = genga.GENGA_KICK_FP64, genga.GENGA_KICK_FP32
 DT5 = discs.DT_5_DAYS
 
 
-def dense_system(d, large=True):
+def dense_system(d, large=True, pair_capacity=0):
     rc = oracle.rcrit(d.state(), d.mstar, discs.DENSE_N1, discs.DENSE_N2, DT5)
-    s = System([d], rcrit=rc)
+    s = System([d], pair_capacity=pair_capacity, rcrit=rc)
     if large:
         genga.genga_set_large_groups(s.ctx.handle, True)
     return s
 
 
-def compare_drift(d, label):
-    s = dense_system(d)
+def compare_drift(d, label, pair_capacity=0):
+    s = dense_system(d, pair_capacity=pair_capacity)
     s.accel(FP64)                       # the encounter list of this state
-    pairs, cnt = s.encounter_list()
+    pairs, cnt = s.encounter_list(cap=pair_capacity or None)
     b0 = s.numpy_state()
     gid = oracle.groups(d.n, pairs)
     sizes = np.bincount(gid[gid >= 0])
@@ -224,6 +224,30 @@ def test_tight_binary_inside_a_large_group():
         st["v" + key][1] = v0[q] + vrel * w[q]
     st["m"][0] = st["m"][1] = m
     compare_drift(discs.Disc(**st, name="ring with binary"), "tight binary")
+
+
+def test_lists_over_capacity_fall_back_to_the_tile_path():
+    """1400 bodies on a jittered lattice 0.02 au across (spacing 5e-4 au), all inside each
+    other's r_crit (about 0.037 au here): every member would list the other 1399, more than a
+    list holds (8 segments of 128) and from more source tiles than a target tile stages (16),
+    so the steps' attempts run on the tile path.  The drift against the oracle's."""
+    d0 = discs.disc_dense(2000, seed=14)
+    st = d0.state()
+    rng = np.random.default_rng(5)
+    side = 38
+    n_c = 1400
+    ij = np.stack(np.meshgrid(np.arange(side), np.arange(side), indexing="ij"), -1).reshape(-1, 2)[:n_c]
+    spacing = 0.02 / side
+    off = np.zeros((n_c, 3))
+    off[:, :2] = (ij - side / 2) * spacing + rng.uniform(-0.1, 0.1, (n_c, 2)) * spacing
+    off[:, 2] = rng.uniform(-0.1, 0.1, n_c) * spacing
+    r0 = np.array([st["x"][0], st["y"][0], st["z"][0]])
+    v0 = np.array([st["vx"][0], st["vy"][0], st["vz"][0]])
+    for q, key in enumerate(("x", "y", "z")):
+        st[key][:n_c] = r0[q] + off[:, q]
+        st["v" + key][:n_c] = v0[q] * (1.0 + rng.normal(0.0, 1e-5, n_c))
+    # about 1.0e6 pairs: the list's default capacity (16 per body) is raised
+    compare_drift(discs.Disc(**st, name="clump"), "clump 1400", pair_capacity=1 << 21)
 
 
 def test_large_groups_with_test_bodies():
