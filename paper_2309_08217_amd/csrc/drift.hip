@@ -976,8 +976,12 @@ __global__ __launch_bounds__(BS_LANES) void drift_kernel(const int32_t *sys_of, 
                                                          int32_t *flags, int big_groups, int bs_blocks,
                                                          const double *rc_lv, int nlev)
 {
+    // the column path's two Neville rows; the small-group path's T(k, 0) table and Lagrange
+    // weights fit in the same space.  The block's LDS sets how many share a CU.
+    constexpr int TAB = 2 * BS_KMAX * CP_MEM * 6;
+    static_assert(BS_KMAX * 3 * 6 + 2 * BS_LANES <= TAB, "small-group tables fit");
     __shared__ BsShared S;
-    __shared__ double tab[BS_KMAX * 6 * BS_LANES];
+    __shared__ double tab[TAB];
     const int lane = threadIdx.x;
     if ((int)blockIdx.x >= bs_blocks) {
         const int i = (blockIdx.x - bs_blocks) * BS_LANES + lane;
