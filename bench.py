@@ -267,12 +267,19 @@ DENSE_WORKLOADS["dense_collisions_merging"] = (DENSE_WORKLOADS["dense"][0] + "; 
                                                "and removal inside 0.4 au / beyond 40 au", discs.disc_dense, (1, 1))
 
 
+# steps between two spatial sorts of the bodies in the dense runs (Keplerian shear mixes a
+# ring's azimuths by about a tile's width in some tens of 5-day steps)
+SORT_EVERY = 10
+
+
 def dense(torch, stream, which="dense", steps=10, warmup=2):
     """Encounter-dominated regime: a dense annulus (0.7-1 au, 2 Earth masses, 5-day step) with
     r_crit from the full eq. (1), n2 = 0.4, where the encounter groups span most of the disc;
     the grid-wide Bulirsch-Stoer path integrates them (host round trips per attempt, so eager
     steps only).  "dense": the 6600-body disc (one group of all bodies); "dense_40k": the
-    40322-body disc of the paper's high-resolution run."""
+    40322-body disc of the paper's high-resolution run.  The bodies are sorted in space
+    (genga_sort_bodies) after set-up and then every SORT_EVERY steps inside the timed
+    region."""
     from scipy.sparse import coo_matrix
     from scipy.sparse.csgraph import connected_components
     label, make, lv = DENSE_WORKLOADS[which]
@@ -288,6 +295,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     rc = torch.zeros_like(b.x)
     genga.genga_rcrit(ctx.handle, b, discs.DENSE_N1, discs.DENSE_N2, discs.DT_5_DAYS, rc)
     b.rcrit = rc
+    genga.genga_sort_bodies(ctx.handle, b)
     collide = which in COLLIDE_RADII_AU
     if collide:
         radius = torch.full((d.n,), COLLIDE_RADII_AU[which], dtype=torch.float64, device="cuda:0")
@@ -321,15 +329,33 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     sizes = np.bincount(lab)
     e0 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
     genga.genga_energy(ctx.handle, b, e0)
-    with torch.cuda.stream(stream):
-        genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, warmup, genga.GENGA_KICK_FP32, stream=stream)
+
+    def run(n):
+        # sort, then up to SORT_EVERY steps, until n steps are done
+        with torch.cuda.stream(stream):
+            k = 0
+            while k < n:
+                c = min(SORT_EVERY, n - k)
+                genga.genga_sort_bodies(ctx.handle, b, None, stream)
+                genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, c, genga.GENGA_KICK_FP32, stream=stream)
+                k += c
+
+    run(warmup)
     torch.cuda.synchronize()
     dead_before = int((col_status != 0).sum().item()) if collide else 0
     t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        genga.genga_step(ctx.handle, b, discs.DT_5_DAYS, steps, genga.GENGA_KICK_FP32, stream=stream)
+    run(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    # the sort alone (the state is already in order: the same work as any sort)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        for _ in range(10):
+            genga.genga_sort_bodies(ctx.handle, b, None, stream)
+        ev1.record(stream)
+    torch.cuda.synchronize()
+    sort_ms = ev0.elapsed_time(ev1) / 10
     e1 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
     genga.genga_energy(ctx.handle, b, e1)
     torch.cuda.synchronize()
@@ -348,6 +374,7 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
             "groups_above_64_at_start": int((sizes > 64).sum()),
             "steps": steps, "warmup": warmup, "steps_per_s": steps / t, "ms_per_step": 1e3 * t / steps,
             "kick_ms": kick_ms, "non_kick_ms_per_step": 1e3 * t / steps - kick_ms,
+            "sort_ms": sort_ms, "sort_every": SORT_EVERY,
             "dE_over_E": float(E1[0] / E0[0] - 1.0),
             "dL_over_L": float(np.linalg.norm(E1[1:]) / np.linalg.norm(E0[1:]) - 1.0),
             "status": status}

@@ -170,6 +170,24 @@ int genga_set_collisions(genga_ctx *ctx, double *mass, double *radius, int32_t *
  * *n_total_out (host).  Synchronises the device. */
 int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *status, int32_t *n_total_out);
 
+/* Reorder the bodies in space, in place: within each system the massive bodies, then the test
+ * bodies, each in order of ring (equal-width bands of distance to the star, as many as make 64
+ * consecutive bodies a patch about as wide as long) and azimuth, ties in the present order.
+ * The paper fixes no body order; every result is the same up to the rounding order of sums.
+ * What the order changes is speed where r_crit spans many neighbours: the kick's candidate
+ * pairs then come in dense runs instead of one lane in every wave, and the union-find of the
+ * encounter groups converges in fewer rounds.  Keplerian shear mixes the azimuths of a ring
+ * again within tens of orbits' fractions, so call it every few steps (between genga_step calls).
+ * Permuted: the bodies' x..vz, m and rcrit (the library writes m and rcrit: const in
+ * genga_bodies notwithstanding), the radius and status arrays of genga_set_collisions (and its
+ * mass array when it is not b->m), and the context's copy of the genga_set_levels radii.
+ * perm_out (device int32[n_total], may be NULL) receives the old index of the body now at
+ * each place, for the caller's own per-body data.  The context's encounter list no longer
+ * names these bodies (a standalone genga_encounter_list then refuses it, as after a drift).
+ * Enqueued on `stream`, no host synchronisation, no allocation (the work buffers come with
+ * genga_set_systems); calls that share the context must be ordered after it on that stream. */
+int genga_sort_bodies(genga_ctx *ctx, genga_bodies *b, int32_t *perm_out, void *stream);
+
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with
  * R_H,i = a_i (m_i / 3 Mstar)^(1/3), a_i the osculating semi-major axis of the body's
  * Kepler part (mu = Mstar, or |r_i| for an unbound body) and v_i = sqrt(Mstar/a_i).

@@ -36,7 +36,7 @@ GENGA_ACC_KAHAN32 = 1
 # every entry point of include/genga.h
 ENTRY_POINTS = (
     "genga_create", "genga_destroy", "genga_set_systems", "genga_set_test_bodies", "genga_set_large_groups",
-    "genga_set_levels", "genga_tune_levels", "genga_set_collisions", "genga_compact",
+    "genga_set_levels", "genga_tune_levels", "genga_set_collisions", "genga_compact", "genga_sort_bodies",
     "genga_rcrit", "genga_accel", "genga_accel_noalloc",
     "genga_kick", "genga_encounter_list", "genga_drift", "genga_energy", "genga_step",
     "genga_graph_capture", "genga_graph_launch", "genga_autotune", "genga_set_kick_shape",
@@ -77,6 +77,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "genga_set_levels": [vp, i32, i32, vp],
         "genga_set_collisions": [vp, vp, vp, vp, dbl, dbl],
         "genga_compact": [vp, bp, vp, vp, ctypes.POINTER(i32)],
+        "genga_sort_bodies": [vp, bp, vp, vp],
         "genga_tune_levels": [vp, bp, dbl, dbl, dbl, i32, i32, i32, ctypes.c_int, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), vp],
         "genga_rcrit": [vp, bp, dbl, dbl, dbl, vp, vp],
@@ -240,6 +241,13 @@ def genga_compact(ctx: int, b: Bodies, radius, status) -> int:
     n = ctypes.c_int32(0)
     _check(load_library().genga_compact(ctx, ctypes.byref(cb), _ptr(radius), _ptr(status), ctypes.byref(n)))
     return n.value
+
+
+def genga_sort_bodies(ctx: int, b: Bodies, perm_out=None, stream=None) -> None:
+    """Reorder the bodies in space in place (ring, then azimuth, per system and kind); perm_out
+    (int32 device tensor of n_total, optional) receives the old index of each new place."""
+    cb = b.c()
+    _check(load_library().genga_sort_bodies(ctx, ctypes.byref(cb), _ptr(perm_out), _stream(stream)))
 
 
 def genga_rcrit(ctx: int, b: Bodies, n1: float, n2: float, dt: float, rc_out, stream=None) -> None:

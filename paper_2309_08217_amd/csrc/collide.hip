@@ -181,7 +181,8 @@ __global__ __launch_bounds__(256) void collide_remove_kernel(CollideArgs c, int 
     }
 }
 
-__global__ __launch_bounds__(256) void gather_kernel(const int32_t *idx, int n, const double *src, double *dst)
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(const int32_t *idx, int n, const T *src, T *dst)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k < n) dst[k] = src[idx[k]];
@@ -192,7 +193,14 @@ __global__ __launch_bounds__(256) void gather_kernel(const int32_t *idx, int n, 
 hipError_t launch_gather(const int32_t *idx, int n, const double *src, double *dst, hipStream_t stream)
 {
     if (n <= 0) return hipSuccess;
-    gather_kernel<<<(n + 255) / 256, 256, 0, stream>>>(idx, n, src, dst);
+    gather_kernel<double><<<(n + 255) / 256, 256, 0, stream>>>(idx, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const int32_t *idx, int n, const int32_t *src, int32_t *dst, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    gather_kernel<int32_t><<<(n + 255) / 256, 256, 0, stream>>>(idx, n, src, dst);
     return hipGetLastError();
 }
 

@@ -102,6 +102,10 @@ struct genga_ctx {
     // host scratch of the grouping and tile ordering, kept so that the per-call vectors of
     // n_total entries are not allocated (and faulted in) again on every call
     OrderWork ow;                      // the device ring / azimuth ordering of the large groups
+    // genga_sort_bodies: its ordering work, the bounds of the sorted runs (the massive and the
+    // test bodies of each system: 2 n_sys + 1 offsets) and the permutation
+    OrderWork sw;
+    int32_t *sort_seg = nullptr, *sort_perm = nullptr;
     // hierarchical levels (with the large-group mode): levels 1..n_levels-1 and their radii
     int32_t n_levels = 1, n_sub = 1;
     double *rc_lv = nullptr;           // [n_levels - 1][n_total]
@@ -247,6 +251,9 @@ struct genga_ctx {
         dfree(epartial);
         dfree(kpart);
         dfree(import_bad);
+        order_work_free(sw);
+        dfree(sort_seg);
+        dfree(sort_perm);
         list_valid = false;
         dfree(col.list);
         dfree(col.count);
@@ -975,6 +982,13 @@ int upload_plan(genga_ctx *ctx)
     }
     HIP_TRY(hipMemcpy(ctx->item_first, first.data(), (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(ctx->L.n_massive, ctx->n_massive_h.data(), n_sys * sizeof(int32_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> seg(2 * (size_t)n_sys + 1);
+    for (int s = 0; s < n_sys; ++s) {
+        seg[2 * s] = ctx->sys_off_h[s];
+        seg[2 * s + 1] = ctx->sys_off_h[s] + ctx->n_massive_h[s];
+    }
+    seg[2 * n_sys] = ctx->sys_off_h[n_sys];
+    HIP_TRY(hipMemcpy(ctx->sort_seg, seg.data(), seg.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(hipDeviceSynchronize());
     return GENGA_OK;
 }
@@ -1102,6 +1116,9 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
     HIP_TRY(dalloc(ctx->import_bad, 1));
     HIP_TRY(hipMemset(ctx->import_bad, 0, sizeof(int32_t)));
+    HIP_TRY(order_work_alloc(ctx->sw, std::max(n_total, 1)));
+    HIP_TRY(dalloc(ctx->sort_seg, 2 * (size_t)n_sys + 1));
+    HIP_TRY(dalloc(ctx->sort_perm, std::max<size_t>(nt, 1)));
 
     HIP_TRY(hipMemcpy(ctx->L.sys_off, sys_off_host, (n_sys + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     if (nt) HIP_TRY(hipMemcpy(ctx->L.sys_of, sys_of.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -1360,6 +1377,41 @@ int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *stat
     if (col.mass && (rc = genga_set_collisions(ctx, col.mass, col.radius, col.status, col.r_min, col.r_max)))
         return rc;
     *n_total_out = nk;
+    return GENGA_OK;
+}
+
+int genga_sort_bodies(genga_ctx *ctx, genga_bodies *b, int32_t *perm_out, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = check_bodies(ctx, b, true, true))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last_stream = s;
+    ctx->list_valid = false; // the encounter list names bodies by their old places
+    const int n = ctx->L.n_total;
+    if (n == 0) return GENGA_OK;
+    // runs: the massive, then the test bodies of each system, each in ring / azimuth order
+    HIP_TRY(launch_ring_order(nullptr, ctx->sort_seg, ctx->sort_seg, 2 * ctx->L.n_sys, n, b->x, b->y, ctx->sw,
+                              ctx->sort_perm, s));
+    // every per-body array the context knows, staged through the kick's share buffer (at least
+    // 3 n_total doubles; no kick is in flight between calls on the context's stream)
+    double *tmp = ctx->kpart;
+    std::vector<double *> arr = {b->x, b->y, b->z, b->vx, b->vy, b->vz, const_cast<double *>(b->m),
+                                 const_cast<double *>(b->rcrit)};
+    if (ctx->col.mass && ctx->col.mass != b->m) arr.push_back(ctx->col.mass);
+    if (ctx->col.radius) arr.push_back(ctx->col.radius);
+    for (int k = 0; ctx->rc_lv && k + 1 < ctx->n_levels; ++k) arr.push_back(ctx->rc_lv + (size_t)k * n);
+    for (double *p : arr) {
+        HIP_TRY(launch_gather(ctx->sort_perm, n, p, tmp, s));
+        HIP_TRY(hipMemcpyAsync(p, tmp, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (ctx->col.status) {
+        int32_t *ti = reinterpret_cast<int32_t *>(tmp);
+        HIP_TRY(launch_gather(ctx->sort_perm, n, ctx->col.status, ti, s));
+        HIP_TRY(hipMemcpyAsync(ctx->col.status, ti, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    if (perm_out)
+        HIP_TRY(hipMemcpyAsync(perm_out, ctx->sort_perm, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     return GENGA_OK;
 }
 

@@ -365,6 +365,8 @@ struct OrderWork {
 };
 hipError_t order_work_alloc(OrderWork &w, int cap);
 void order_work_free(OrderWork &w);
+// Per group gi: its members members[k0[gi] ..] (members NULL: the bodies k0[gi], k0[gi] + 1, ..)
+// in ring / azimuth order into body_out[off[gi] ..], groups one after the other.
 hipError_t launch_ring_order(const int32_t *members, const int32_t *k0, const int32_t *off, int n_groups, int M,
                              const double *x, const double *y, OrderWork &w, int32_t *body_out, hipStream_t stream);
 void group_work_free(GroupWork &w);
@@ -396,6 +398,7 @@ hipError_t launch_collide_resolve(const CollideArgs &c, int n_total, double *x, 
 
 // dst[k] = src[idx[k]], k < n.
 hipError_t launch_gather(const int32_t *idx, int n, const double *src, double *dst, hipStream_t stream);
+hipError_t launch_gather(const int32_t *idx, int n, const int32_t *src, int32_t *dst, hipStream_t stream);
 
 hipError_t launch_energy(const Layout &L, const WorkItem *items, int32_t n_items, const double *x,
                          const double *y, const double *z, const double *vx, const double *vy,

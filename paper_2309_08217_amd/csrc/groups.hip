@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void ring_keys_kernel(const int32_t *members, 
         const int o = off[gi], nb = off[gi + 1] - o, m0 = k0[gi];
         double r0 = INFINITY, r1 = 0.0, rs = 0.0;
         for (int l = threadIdx.x; l < nb; l += 256) {
-            const int bi = members[m0 + l];
+            const int bi = members ? members[m0 + l] : m0 + l;
             const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
             r0 = fmin(r0, r);
             r1 = fmax(r1, r);
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void ring_keys_kernel(const int32_t *members, 
         const double rmean = rs / nb, width = fmax(r1 - r0, 1e-300);
         const int rings = max(1, (int)lround(sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
         for (int l = threadIdx.x; l < nb; l += 256) {
-            const int bi = members[m0 + l];
+            const int bi = members ? members[m0 + l] : m0 + l;
             const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
             const int ring = min(rings - 1, (int)((r - r0) / width * rings));
             const double u = (ring + 0.25 * pseudo_angle(x[bi], y[bi])) / rings; // [0, 1]
