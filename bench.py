@@ -347,6 +347,10 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
     run(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    e1 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    genga.genga_energy(ctx.handle, b, e1)
+    torch.cuda.synchronize()
+    status = genga.genga_poll_status(ctx.handle)
     # the sort alone (the state is already in order: the same work as any sort)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(stream):
@@ -356,10 +360,6 @@ def dense(torch, stream, which="dense", steps=10, warmup=2):
         ev1.record(stream)
     torch.cuda.synchronize()
     sort_ms = ev0.elapsed_time(ev1) / 10
-    e1 = torch.zeros(4, dtype=torch.float64, device="cuda:0")
-    genga.genga_energy(ctx.handle, b, e1)
-    torch.cuda.synchronize()
-    status = genga.genga_poll_status(ctx.handle)
     kick_ms = time_kicks(ctx, b, genga.GENGA_KICK_FP32, 10, torch, stream)
     E0, E1 = e0.cpu().numpy(), e1.cpu().numpy()
     ctx.close()

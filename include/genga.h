@@ -21,7 +21,7 @@
  *    genga_set_large_groups, genga_set_levels, genga_poll_status, genga_autotune, the graph
  *    calls, and genga_drift / genga_step while large groups are enabled, as documented.  Every launch
  *    sequence is otherwise capturable into a HIP graph (no memset nodes, no host round
- *    trips).
+ *    trips), except genga_sort_bodies, which refuses capture.
  *  - Return value: GENGA_OK (0) or a negative genga_status.  Errors knowable on the host
  *    (null pointer, bad enum, no layout set) return at once and enqueue nothing.
  *    Conditions found on the device (pair-list overflow, non-finite acceleration,
@@ -185,7 +185,9 @@ int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *stat
  * each place, for the caller's own per-body data.  The context's encounter list no longer
  * names these bodies (a standalone genga_encounter_list then refuses it, as after a drift).
  * Enqueued on `stream`, no host synchronisation, no allocation (the work buffers come with
- * genga_set_systems); calls that share the context must be ordered after it on that stream. */
+ * genga_set_systems); calls that share the context must be ordered after it on that stream.
+ * Not capturable: on a stream under graph capture it returns GENGA_ERR_STATE and enqueues
+ * nothing (its radix sort clears work memory with memset nodes). */
 int genga_sort_bodies(genga_ctx *ctx, genga_bodies *b, int32_t *perm_out, void *stream);
 
 /* Critical radius of every body, eq. (1): r_crit,i = max(n1 R_H,i, n2 dt v_i) with

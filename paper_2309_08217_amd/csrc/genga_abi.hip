@@ -1386,6 +1386,12 @@ int genga_sort_bodies(genga_ctx *ctx, genga_bodies *b, int32_t *perm_out, void *
     if (rc) return rc;
     if ((rc = check_bodies(ctx, b, true, true))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    // the radix sort is a library call that clears its work memory with memset nodes, which
+    // captured graphs must not hold
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(GENGA_ERR_STATE, "genga_sort_bodies cannot be captured into a graph");
     ctx->last_stream = s;
     ctx->list_valid = false; // the encounter list names bodies by their old places
     const int n = ctx->L.n_total;

@@ -181,3 +181,28 @@ def test_empty_system_and_stream():
     for k in ("x", "vx"):
         assert np.max(np.abs(got[k] - exp[k][p])) <= 1e-11
     s.close()
+
+
+def test_capture_is_refused():
+    """Under graph capture the sort refuses (its radix sort would record memset nodes) and
+    enqueues nothing: the bodies are unchanged."""
+    d = discs.disc_c1()
+    s = System([d])
+    torch = s.torch
+    before = s.numpy_state()
+    st = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    dummy = torch.zeros(4, device="cuda")
+    err = None
+    with torch.cuda.graph(g, stream=st):
+        dummy += 1.0
+        try:
+            genga.genga_sort_bodies(s.ctx.handle, s.b, None, st)
+        except genga.GengaError as e:
+            err = e
+    torch.cuda.synchronize()
+    assert err is not None and err.status == genga.GENGA_ERR_STATE
+    after = s.numpy_state()
+    for k in KEYS:
+        assert np.array_equal(after[k], before[k])
+    s.close()
