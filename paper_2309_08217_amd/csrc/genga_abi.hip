@@ -510,7 +510,7 @@ int alloc_big(genga_ctx *ctx)
     }
     const size_t M = (size_t)b.cap_M, G = (size_t)b.cap_G;
     HIP_TRY(dalloc(b.k0, G));
-    HIP_TRY(order_work_alloc(ctx->ow, (int)M));
+    HIP_TRY(order_work_alloc(ctx->ow, (int)std::max(M, G)));
     HIP_TRY(dalloc(b.off, G + 1));
     HIP_TRY(dalloc(b.tiles, (size_t)b.cap_T));
     HIP_TRY(dalloc(b.tfirst, G + 1));
@@ -1116,7 +1116,7 @@ int genga_set_systems(genga_ctx *ctx, int32_t n_sys, const int32_t *sys_off_host
     HIP_TRY(dalloc(ctx->kpart, (size_t)KICK_MAX_SPLIT * 3 * nt));
     HIP_TRY(dalloc(ctx->import_bad, 1));
     HIP_TRY(hipMemset(ctx->import_bad, 0, sizeof(int32_t)));
-    HIP_TRY(order_work_alloc(ctx->sw, std::max(n_total, 1)));
+    HIP_TRY(order_work_alloc(ctx->sw, std::max(n_total, 2 * n_sys)));
     HIP_TRY(dalloc(ctx->sort_seg, 2 * (size_t)n_sys + 1));
     HIP_TRY(dalloc(ctx->sort_perm, std::max<size_t>(nt, 1)));
 

@@ -359,6 +359,7 @@ hipError_t group_work_alloc(GroupWork &w, int cap);
 struct OrderWork {
     uint64_t *keys = nullptr, *keys_sorted = nullptr; // [cap]
     int32_t *vals = nullptr;                          // [cap]
+    uint64_t *bounds = nullptr;                       // [2 cap]: per group, smallest and largest distance
     void *temp = nullptr;
     size_t temp_bytes = 0;
     int cap = 0;
@@ -366,7 +367,8 @@ struct OrderWork {
 hipError_t order_work_alloc(OrderWork &w, int cap);
 void order_work_free(OrderWork &w);
 // Per group gi: its members members[k0[gi] ..] (members NULL: the bodies k0[gi], k0[gi] + 1, ..)
-// in ring / azimuth order into body_out[off[gi] ..], groups one after the other.
+// in ring / azimuth order into body_out[off[gi] ..], groups one after the other.  M (the
+// layout's size) and n_groups at most the work's capacity.
 hipError_t launch_ring_order(const int32_t *members, const int32_t *k0, const int32_t *off, int n_groups, int M,
                              const double *x, const double *y, OrderWork &w, int32_t *body_out, hipStream_t stream);
 void group_work_free(GroupWork &w);

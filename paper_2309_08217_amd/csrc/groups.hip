@@ -160,51 +160,94 @@ __device__ __forceinline__ double pseudo_angle(double x, double y)
     return x >= 0.0 ? (y >= 0.0 ? t : 4.0 + t) : 2.0 - t;
 }
 
-// Per layout group gi (one workgroup): its members' key (gi, ring, azimuth) and body.  The
-// rings are equal-width bands of distance to the star, as many as make a tile of 64 members
-// about as wide as long; the quantised (ring + azimuth / 4) / rings orders the members.
-__global__ __launch_bounds__(256) void ring_keys_kernel(const int32_t *members, const int32_t *k0, const int32_t *off,
-                                                        int n_groups, const double *x, const double *y, uint64_t *key,
-                                                        int32_t *val)
+// The group of layout position p: the last gi with off[gi] <= p (empty groups share their
+// offset with the next one and are passed over).
+__device__ __forceinline__ int group_of(const int32_t *off, int n_groups, int p)
+{
+    int lo = 0, hi = n_groups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int ring_body(const int32_t *members, const int32_t *k0, const int32_t *off, int gi,
+                                         int p)
+{
+    const int m = k0[gi] + (p - off[gi]);
+    return members ? members[m] : m;
+}
+
+__global__ __launch_bounds__(256) void ring_bounds_clear_kernel(int n_groups, uint64_t *bounds)
+{
+    for (int g = blockIdx.x * 256 + threadIdx.x; g < n_groups; g += gridDim.x * 256) {
+        bounds[2 * g] = 0x7ff0000000000000ull; // +inf: the smallest distance so far
+        bounds[2 * g + 1] = 0ull;              // +0
+    }
+}
+
+// Each group's smallest and largest distance to the star over the layout positions: a wave
+// whose lanes share one group reduces first; the atomics order the bit patterns, which for
+// non-negative doubles is the numeric order, so the result does not depend on the order.
+__global__ __launch_bounds__(256) void ring_bounds_kernel(const int32_t *members, const int32_t *k0,
+                                                          const int32_t *off, int n_groups, int M, const double *x,
+                                                          const double *y, uint64_t *bounds)
 {
 #pragma clang fp contract(off)
-    __shared__ double rmin[4], rmax[4], rsum[4];
-    for (int gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
-        const int o = off[gi], nb = off[gi + 1] - o, m0 = k0[gi];
-        double r0 = INFINITY, r1 = 0.0, rs = 0.0;
-        for (int l = threadIdx.x; l < nb; l += 256) {
-            const int bi = members ? members[m0 + l] : m0 + l;
-            const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
-            r0 = fmin(r0, r);
-            r1 = fmax(r1, r);
-            rs += r;
+    const int stride = gridDim.x * 256;
+    for (int base = blockIdx.x * 256; base < M; base += stride) {
+        const int p = base + (int)threadIdx.x;
+        const bool on = p < M;
+        const int gi = on ? group_of(off, n_groups, p) : 0;
+        double r0 = INFINITY, r1 = 0.0;
+        if (on) {
+            const int bi = ring_body(members, k0, off, gi, p);
+            r0 = r1 = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
         }
-        for (int d = 32; d > 0; d >>= 1) {
-            r0 = fmin(r0, __shfl_xor(r0, d, 64));
-            r1 = fmax(r1, __shfl_xor(r1, d, 64));
-            rs += __shfl_xor(rs, d, 64);
+        const int g0 = __builtin_amdgcn_readfirstlane(gi);
+        const unsigned long long act = __ballot(true);
+        if (__ballot(on && gi == g0) == act) {
+            for (int d = 32; d > 0; d >>= 1) {
+                r0 = fmin(r0, __shfl_xor(r0, d, 64));
+                r1 = fmax(r1, __shfl_xor(r1, d, 64));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                atomicMin((unsigned long long *)&bounds[2 * g0], (unsigned long long)__double_as_longlong(r0));
+                atomicMax((unsigned long long *)&bounds[2 * g0 + 1], (unsigned long long)__double_as_longlong(r1));
+            }
+        } else if (on) {
+            atomicMin((unsigned long long *)&bounds[2 * gi], (unsigned long long)__double_as_longlong(r0));
+            atomicMax((unsigned long long *)&bounds[2 * gi + 1], (unsigned long long)__double_as_longlong(r1));
         }
-        if ((threadIdx.x & 63) == 0) {
-            rmin[threadIdx.x >> 6] = r0;
-            rmax[threadIdx.x >> 6] = r1;
-            rsum[threadIdx.x >> 6] = rs;
-        }
-        __syncthreads();
-        r0 = fmin(fmin(rmin[0], rmin[1]), fmin(rmin[2], rmin[3]));
-        r1 = fmax(fmax(rmax[0], rmax[1]), fmax(rmax[2], rmax[3]));
-        rs = (rsum[0] + rsum[1]) + (rsum[2] + rsum[3]);
-        const double rmean = rs / nb, width = fmax(r1 - r0, 1e-300);
-        const int rings = max(1, (int)lround(sqrt(nb * width / (64.0 * 2.0 * M_PI * rmean))));
-        for (int l = threadIdx.x; l < nb; l += 256) {
-            const int bi = members ? members[m0 + l] : m0 + l;
-            const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
-            const int ring = min(rings - 1, (int)((r - r0) / width * rings));
-            const double u = (ring + 0.25 * pseudo_angle(x[bi], y[bi])) / rings; // [0, 1]
-            const uint64_t q = (uint64_t)fmin(4294967295.0, fmax(0.0, u * 4294967295.0));
-            key[o + l] = (uint64_t)gi << 32 | q;
-            val[o + l] = bi;
-        }
-        __syncthreads(); // the partials are rewritten for the next group
+    }
+}
+
+// Per layout position: the member's key (gi, ring, azimuth) and body.  The rings are
+// equal-width bands of distance to the star, as many as make a tile of 64 members about as
+// wide as long (the band's circumference taken at the middle of the group's range); the
+// quantised (ring + azimuth / 4) / rings orders the members.
+__global__ __launch_bounds__(256) void ring_keys_kernel(const int32_t *members, const int32_t *k0, const int32_t *off,
+                                                        int n_groups, int M, const double *x, const double *y,
+                                                        const uint64_t *bounds, uint64_t *key, int32_t *val)
+{
+#pragma clang fp contract(off)
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < M; p += gridDim.x * 256) {
+        const int gi = group_of(off, n_groups, p);
+        const int bi = ring_body(members, k0, off, gi, p);
+        const int nb = off[gi + 1] - off[gi];
+        const double r0 = __longlong_as_double((long long)bounds[2 * gi]);
+        const double r1 = __longlong_as_double((long long)bounds[2 * gi + 1]);
+        const double width = fmax(r1 - r0, 1e-300), rmid = fmax(0.5 * (r0 + r1), 1e-300);
+        const double nr = fmin(sqrt(nb * width / (64.0 * 2.0 * M_PI * rmid)), 1048576.0);
+        const int rings = max(1, (int)lround(nr));
+        const double r = sqrt(x[bi] * x[bi] + y[bi] * y[bi]);
+        const int ring = min(rings - 1, (int)((r - r0) / width * rings));
+        const double u = (ring + 0.25 * pseudo_angle(x[bi], y[bi])) / rings; // [0, 1]
+        const uint64_t q = (uint64_t)fmin(4294967295.0, fmax(0.0, u * 4294967295.0));
+        key[p] = (uint64_t)gi << 32 | q;
+        val[p] = bi;
     }
 }
 
@@ -304,6 +347,7 @@ hipError_t order_work_alloc(OrderWork &w, int cap)
     if ((e = hipMalloc((void **)&w.keys, n * sizeof(uint64_t))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&w.keys_sorted, n * sizeof(uint64_t))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&w.vals, n * sizeof(int32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&w.bounds, 2 * n * sizeof(uint64_t))) != hipSuccess) return e;
     int32_t *out = nullptr;
     if ((e = rocprim::radix_sort_pairs(nullptr, w.temp_bytes, w.keys, w.keys_sorted, w.vals, out, (unsigned int)n, 0,
                                        64)) != hipSuccess)
@@ -313,7 +357,7 @@ hipError_t order_work_alloc(OrderWork &w, int cap)
 
 void order_work_free(OrderWork &w)
 {
-    for (void *p : {(void *)w.keys, (void *)w.keys_sorted, (void *)w.vals, w.temp})
+    for (void *p : {(void *)w.keys, (void *)w.keys_sorted, (void *)w.vals, (void *)w.bounds, w.temp})
         if (p) (void)hipFree(p);
     w = OrderWork{};
 }
@@ -322,8 +366,11 @@ hipError_t launch_ring_order(const int32_t *members, const int32_t *k0, const in
                              const double *x, const double *y, OrderWork &w, int32_t *body_out, hipStream_t stream)
 {
     if (n_groups <= 0 || M <= 0) return hipSuccess;
-    if (M > w.cap) return hipErrorInvalidValue;
-    ring_keys_kernel<<<std::min(n_groups, 4096), 256, 0, stream>>>(members, k0, off, n_groups, x, y, w.keys, w.vals);
+    if (M > w.cap || n_groups > w.cap) return hipErrorInvalidValue;
+    const int grid = std::min((M + 255) / 256, 2048);
+    ring_bounds_clear_kernel<<<std::min((n_groups + 255) / 256, 256), 256, 0, stream>>>(n_groups, w.bounds);
+    ring_bounds_kernel<<<grid, 256, 0, stream>>>(members, k0, off, n_groups, M, x, y, w.bounds);
+    ring_keys_kernel<<<grid, 256, 0, stream>>>(members, k0, off, n_groups, M, x, y, w.bounds, w.keys, w.vals);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t bytes = w.temp_bytes;
