@@ -323,7 +323,7 @@ hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, d
 
 // Encounter groups of a level's pair list laid out on the device (groups.hip).  The host reads
 // only the header, once per grouping.
-constexpr int UF_ROUNDS = 4; // union-find rounds enqueued at once; more only if the last still hooked
+constexpr int UF_ROUNDS = 3; // union-find rounds enqueued at once; more only if the last still hooked
 struct GroupHeader {
     int32_t G, M;            // groups, members
     int32_t n_tiles, n_multi; // tiles of 64; of them in groups of several tiles
