@@ -1178,14 +1178,16 @@ hipError_t launch_momentum(const Layout &L, const double *vx, const double *vy, 
 hipError_t launch_uf_init(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
                           hipStream_t stream)
 {
-    uf_init_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab);
+    // 256 workgroups walk the pairs: a round that has nothing to do returns at once, and its
+    // launch costs less the fewer workgroups it dispatches
+    uf_init_kernel<<<256, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab);
     return hipGetLastError();
 }
 
 hipError_t launch_uf_hook(const int32_t *pairs, const int32_t *pair_count, int32_t pair_cap, int32_t *lab,
                           int32_t *changed, hipStream_t stream, const int32_t *run_if)
 {
-    uf_hook_kernel<<<1024, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab, changed, run_if);
+    uf_hook_kernel<<<256, 256, 0, stream>>>(pairs, pair_count, pair_cap, lab, changed, run_if);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ def test_host_side_argument_errors_without_gpu():
     assert lib.genga_encounter_list(None, None, None, 0, None, None) == genga.GENGA_ERR_ARG
     assert lib.genga_drift(None, None, 0.1, None, None, None) == genga.GENGA_ERR_ARG
     assert lib.genga_autotune(None, None, 1, None, None) == genga.GENGA_ERR_ARG
+    assert lib.genga_sort_bodies(None, None, None, None) == genga.GENGA_ERR_ARG
     assert b"null context" in lib.genga_last_error()
     assert lib.genga_set_systems(None, 1, None, None, 0) == genga.GENGA_ERR_ARG
     assert lib.genga_set_kick_shape(None, 1, 8, 1) == genga.GENGA_ERR_ARG
