@@ -176,14 +176,16 @@ int genga_compact(genga_ctx *ctx, genga_bodies *b, double *radius, int32_t *stat
  * The paper fixes no body order; every result is the same up to the rounding order of sums.
  * What the order changes is speed where r_crit spans many neighbours: the kick's candidate
  * pairs then come in dense runs instead of one lane in every wave, and the union-find of the
- * encounter groups converges in fewer rounds.  Keplerian shear mixes the azimuths of a ring
- * again within tens of orbits' fractions, so call it every few steps (between genga_step calls).
+ * encounter groups converges in fewer rounds.  Keplerian shear spreads each patch along its
+ * ring again (in a dense annulus at 0.7-1 au, by about a patch's width in some tens of 5-day
+ * steps), so call it every few steps, between genga_step calls.
  * Permuted: the bodies' x..vz, m and rcrit (the library writes m and rcrit: const in
  * genga_bodies notwithstanding), the radius and status arrays of genga_set_collisions (and its
  * mass array when it is not b->m), and the context's copy of the genga_set_levels radii.
  * perm_out (device int32[n_total], may be NULL) receives the old index of the body now at
  * each place, for the caller's own per-body data.  The context's encounter list no longer
- * names these bodies (a standalone genga_encounter_list then refuses it, as after a drift).
+ * names these bodies: asking for the last kick's list (genga_encounter_list with b = NULL)
+ * then returns GENGA_ERR_STATE, as after a drift.
  * Enqueued on `stream`, no host synchronisation, no allocation (the work buffers come with
  * genga_set_systems); calls that share the context must be ordered after it on that stream.
  * Not capturable: on a stream under graph capture it returns GENGA_ERR_STATE and enqueues
