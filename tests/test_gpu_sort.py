@@ -206,3 +206,24 @@ def test_capture_is_refused():
     for k in KEYS:
         assert np.array_equal(after[k], before[k])
     s.close()
+
+
+def test_empty_runs_between_systems():
+    """Three systems, the middle one empty and the last with 100 test bodies at its end: every
+    run (massive or test, empty ones included) maps onto itself and the arrays move with it,
+    so the search for a position's run passes over the empty runs."""
+    empty = discs.Disc(*(np.zeros(0) for _ in range(7)), name="empty")
+    ds = [discs.make_disc(700, 2.5, seed=51, name="a"), empty, discs.make_disc(500, 2.5, seed=52, name="b")]
+    s = System(ds)
+    nm = np.array([700, 0, 400], dtype=np.int32)
+    genga.genga_set_test_bodies(s.ctx.handle, nm)
+    before = s.numpy_state()
+    perm = sort(s)
+    assert np.array_equal(np.sort(perm), np.arange(s.n))
+    for a_, b_ in runs(s.off, nm):
+        assert np.all((perm[a_:b_] >= a_) & (perm[a_:b_] < b_)), (a_, b_)
+    after = s.numpy_state()
+    for k in KEYS:
+        assert np.array_equal(after[k], before[k][perm]), k
+    assert not np.array_equal(perm, np.arange(s.n))
+    s.close()
