@@ -130,16 +130,36 @@ __global__ __launch_bounds__(GL_THREADS) void group_tiles_kernel(const int32_t *
     const uint64_t e = tscan[g];
     const int mo = (int)(e >> 32), so = (int)(e & 0xffffffffu);
     const int tf = mo + so;
-    const int o = off[g], nb = off[g + 1] - o, nt = (nb + 63) / 64;
+    (void)so;
     tfirst[g] = tf;
-    for (int k = 0; k < nt; ++k) {
-        tiles[tf + k] = make_int4(g, o + 64 * k, min(64, nb - 64 * k), 0);
-        tl[nt > 1 ? mo + k : n_multi + so] = tf + k;
-    }
     if (g == G - 1) {
         tfirst[G] = n_tiles;
         hdr->n_tiles = n_tiles;
         hdr->n_multi = n_multi;
+    }
+}
+
+// The tiles themselves, one thread each (a group of many tiles would otherwise be one thread's
+// loop): tile t belongs to the last group whose first tile is at most t (every group has one).
+__global__ __launch_bounds__(GL_THREADS) void group_tile_fill_kernel(const int32_t *off, const GroupHeader *hdr,
+                                                                     const uint64_t *tscan, const int32_t *tfirst,
+                                                                     int4 *tiles, int32_t *tl, int Tcap)
+{
+    const int G = hdr->G, n_tiles = hdr->n_tiles, n_multi = hdr->n_multi;
+    if (G <= 0) return;
+    for (int t = blockIdx.x * GL_THREADS + threadIdx.x; t < min(n_tiles, Tcap); t += gridDim.x * GL_THREADS) {
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tfirst[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int g = lo, k = t - tfirst[g];
+        const int o = off[g], nb = off[g + 1] - o, nt = (nb + 63) / 64;
+        const uint64_t e = tscan[g];
+        const int mo = (int)(e >> 32), so = (int)(e & 0xffffffffu);
+        tiles[t] = make_int4(g, o + 64 * k, min(64, nb - 64 * k), 0);
+        tl[nt > 1 ? mo + k : n_multi + so] = t;
     }
 }
 
@@ -334,6 +354,9 @@ hipError_t launch_group_layout(const Layout &L, GroupWork &w, const int32_t *pai
             return e;
         group_tiles_kernel<<<ng, GL_THREADS, 0, stream>>>(out.off, w.hdr, Gcap, w.tv, w.tscan, out.tfirst, out.tiles,
                                                           out.tl);
+        // at most one tile per member
+        group_tile_fill_kernel<<<std::min(nb, 1024), GL_THREADS, 0, stream>>>(out.off, w.hdr, w.tscan, out.tfirst,
+                                                                              out.tiles, out.tl, Mp);
     }
     return hipGetLastError();
 }
