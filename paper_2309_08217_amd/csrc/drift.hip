@@ -1130,15 +1130,20 @@ __global__ __launch_bounds__(WG_THREADS) void drift_wg_kernel(const int32_t *sys
     }
 }
 
+// skip: labels read, then reset to -1 (the list holds every body whose label is set)
 __global__ __launch_bounds__(256) void kepler_list_kernel(const int32_t *sys_of, const double *mstar,
-                                                          const int32_t *list, int n, const int32_t *skip,
+                                                          const int32_t *list, int n, int32_t *skip,
                                                           double *x, double *y, double *z, double *vx,
                                                           double *vy, double *vz, double dt, int32_t *flags)
 {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const int i = list[k];
-    if (skip && skip[i] >= 0) return;
+    if (skip) {
+        const int s = skip[i];
+        skip[i] = -1;
+        if (s >= 0) return;
+    }
     double Y[6] = {x[i], y[i], z[i], vx[i], vy[i], vz[i]};
     if (!kepler_universal(Y[0], Y[1], Y[2], Y[3], Y[4], Y[5], mstar[sys_of[i]], dt)) atomicOr(flags, FLAG_KEPLER);
     store_state(x, y, z, vx, vy, vz, i, Y);
@@ -1148,7 +1153,7 @@ __global__ __launch_bounds__(256) void kepler_list_kernel(const int32_t *sys_of,
 
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
-                              hipStream_t stream, const int32_t *skip)
+                              hipStream_t stream, int32_t *skip)
 {
     if (n <= 0) return hipSuccess;
     kepler_list_kernel<<<(n + 255) / 256, 256, 0, stream>>>(L.sys_of, L.mstar, list, n, skip, x, y, z, vx, vy, vz,

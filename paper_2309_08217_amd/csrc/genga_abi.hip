@@ -750,15 +750,14 @@ int run_level(genga_ctx *ctx, genga_bodies *b, int level, double tau, hipStream_
     const bool deepest = level + 1 == ctx->n_levels;
     int rc;
     for (int sub = 0; sub < ctx->n_sub; ++sub) {
-        HIP_TRY(hipMemsetAsync(ctx->lv_count, 0, sizeof(int32_t), s));
+        // the emitting kick clears the pair count of the level
         if ((rc = level_kick(ctx, b, level, T, 0.5 * h, true, s))) return rc;
         if ((rc = group_level(ctx, level, T, deepest, s))) return rc;
         const GroupHeader hd = *ctx->ghdr;
-        // parent members in no pair of this level (device label -1): Kepler drift over h; then
-        // the labels are cleared
+        // parent members in no pair of this level (device label -1): Kepler drift over h; the
+        // same launch clears the labels (only parent members carry one)
         HIP_TRY(launch_kepler_list(ctx->L, T.body, T.M, b->x, b->y, b->z, b->vx, b->vy, b->vz, h, ctx->flags, s,
                                    ctx->lab));
-        HIP_TRY(hipMemsetAsync(ctx->lab, 0xff, (size_t)ctx->L.n_total * sizeof(int32_t), s));
         if (hd.G > 0) {
             if (deepest) {
                 // Bulirsch-Stoer with the product weight: one wave per group of up to 64 members

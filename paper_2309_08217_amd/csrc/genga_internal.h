@@ -313,13 +313,14 @@ struct LevelKickArgs {
 hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const double *m, const double *rc0,
                                     const double *rcl, int level, hipStream_t stream);
 // Gather the members' positions and tile boxes, then kick (waves: 8 or 16 per workgroup of a
-// multi-tile group's target tile).
+// multi-tile group's target tile).  An emitting kick starts its pair count from zero.
 hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
                              const double *z, int waves, hipStream_t stream);
-// Kepler drift over dt of the bodies list[0..n-1] (with skip: those with skip[body] < 0).
+// Kepler drift over dt of the bodies list[0..n-1] (with skip: those with skip[body] < 0; every
+// listed skip[body] is then reset to -1).
 hipError_t launch_kepler_list(const Layout &L, const int32_t *list, int32_t n, double *x, double *y,
                               double *z, double *vx, double *vy, double *vz, double dt, int32_t *flags,
-                              hipStream_t stream, const int32_t *skip = nullptr);
+                              hipStream_t stream, int32_t *skip = nullptr);
 
 // Encounter groups of a level's pair list laid out on the device (groups.hip).  The host reads
 // only the header, once per grouping.

@@ -57,9 +57,10 @@ __global__ __launch_bounds__(64) void level_tiles_setup_kernel(LevelTiles t, con
 
 // Positions of the members of each tile, and the tile's box.  One wave per tile.
 __global__ __launch_bounds__(64) void level_tiles_pos_kernel(LevelTiles t, const double *x, const double *y,
-                                                             const double *z)
+                                                             const double *z, int32_t *clear)
 {
     const int me = blockIdx.x;
+    if (clear && me == 0 && threadIdx.x == 0) *clear = 0; // the kick after this launch appends pairs
     const int4 tile = t.tiles[me];
     const bool v = (int)threadIdx.x < tile.z;
     const int f = tile.y + (v ? (int)threadIdx.x : 0);
@@ -319,8 +320,8 @@ hipError_t launch_level_tiles_setup(const Layout &L, const LevelTiles &t, const 
 hipError_t launch_level_kick(const LevelTiles &t, const LevelKickArgs &a, const double *x, const double *y,
                              const double *z, int waves, hipStream_t stream)
 {
-    if (t.n_tiles == 0) return hipSuccess;
-    level_tiles_pos_kernel<<<t.n_tiles, 64, 0, stream>>>(t, x, y, z);
+    if (t.n_tiles == 0) return a.emit ? hipMemsetAsync(a.pair_count, 0, sizeof(int32_t), stream) : hipSuccess;
+    level_tiles_pos_kernel<<<t.n_tiles, 64, 0, stream>>>(t, x, y, z, a.emit ? a.pair_count : nullptr);
     if (t.n_multi > 0) {
         if (waves == 16)
             level_tiles_kick_kernel<16><<<t.n_multi, LT_TILE * 16, 0, stream>>>(t, a);
