@@ -115,11 +115,12 @@ __global__ __launch_bounds__(GL_THREADS) void group_sizes_kernel(const int32_t *
     tv[g] = v;
 }
 
-// Tiles of 64 members, group by group (tfirst), and the launch list tl: the tiles of groups of
-// several tiles first (a workgroup each), then the tile of every group of one tile (a wave each).
-__global__ __launch_bounds__(GL_THREADS) void group_tiles_kernel(const int32_t *off, GroupHeader *hdr, int Gcap,
-                                                                 const uint64_t *tv, const uint64_t *tscan,
-                                                                 int32_t *tfirst, int4 *tiles, int32_t *tl)
+// Tiles of 64 members, group by group: each group's first tile (tfirst) and the header's tile
+// counts; group_tile_fill_kernel then writes the tiles and the launch list tl (the tiles of
+// groups of several tiles first, a workgroup each, then the tile of every group of one tile, a
+// wave each).
+__global__ __launch_bounds__(GL_THREADS) void group_tiles_kernel(GroupHeader *hdr, int Gcap, const uint64_t *tv,
+                                                                 const uint64_t *tscan, int32_t *tfirst)
 {
     const int g = blockIdx.x * GL_THREADS + threadIdx.x;
     if (g >= Gcap) return;
@@ -129,9 +130,7 @@ __global__ __launch_bounds__(GL_THREADS) void group_tiles_kernel(const int32_t *
     const int n_multi = (int)(tot >> 32), n_tiles = n_multi + (int)(tot & 0xffffffffu);
     const uint64_t e = tscan[g];
     const int mo = (int)(e >> 32), so = (int)(e & 0xffffffffu);
-    const int tf = mo + so;
-    (void)so;
-    tfirst[g] = tf;
+    tfirst[g] = mo + so;
     if (g == G - 1) {
         tfirst[G] = n_tiles;
         hdr->n_tiles = n_tiles;
@@ -352,8 +351,7 @@ hipError_t launch_group_layout(const Layout &L, GroupWork &w, const int32_t *pai
         if ((e = rocprim::exclusive_scan(w.temp, bytes, w.tv, w.tscan, (uint64_t)0, (size_t)Gcap,
                                          rocprim::plus<uint64_t>(), stream)) != hipSuccess)
             return e;
-        group_tiles_kernel<<<ng, GL_THREADS, 0, stream>>>(out.off, w.hdr, Gcap, w.tv, w.tscan, out.tfirst, out.tiles,
-                                                          out.tl);
+        group_tiles_kernel<<<ng, GL_THREADS, 0, stream>>>(w.hdr, Gcap, w.tv, w.tscan, out.tfirst);
         // at most one tile per member
         group_tile_fill_kernel<<<std::min(nb, 1024), GL_THREADS, 0, stream>>>(out.off, w.hdr, w.tscan, out.tfirst,
                                                                               out.tiles, out.tl, Mp);
